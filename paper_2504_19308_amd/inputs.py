@@ -1,0 +1,181 @@
+"""Seeded synthetic inputs for the approximate product.
+
+This module holds no arithmetic of the approximation method itself: it only
+draws test matrices.  Both the oracle-side tests and the GPU path are fed from
+here, so that the two sides see bit-identical operands.
+
+Generators follow the paper's appendix on matrix generation (Haar-distributed
+singular vectors, Alg. C.1): a Gaussian matrix is QR-factored and the columns
+of Q are multiplied by the signs of diag(R) (a zero sign counts as +1), which
+gives a Haar-distributed orthogonal factor.  The spectral-decay laws are the
+ones named for the workloads: exp(-i/20) with i = 0..n-1 (the Type-1 style
+index base of the appendix) and power laws i**-alpha with i = 1..n.
+
+Seeds: numpy PCG64 with ``seed = 42 + 100*config + 10*operand + stream``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def seed_of(config: int, operand: int, stream: int = 0) -> int:
+    return 42 + 100 * config + 10 * operand + stream
+
+
+def rng_of(config: int, operand: int, stream: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_of(config, operand, stream)))
+
+
+# ---------------------------------------------------------------------------
+# Haar factors (Alg. C.1)
+# ---------------------------------------------------------------------------
+def _sign_fixed_q(M, qr):
+    Q, R = qr(M)
+    d = np.sign(np.diag(R)) if isinstance(R, np.ndarray) else None
+    if d is None:  # torch path
+        import torch
+        d = torch.sign(torch.diagonal(R))
+        d = torch.where(d == 0, torch.ones_like(d), d)
+        return Q * d.unsqueeze(0)
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def haar_columns(rows: int, cols: int, rng: np.random.Generator, device=None):
+    """rows x cols matrix with orthonormal, Haar-distributed columns (cols <= rows).
+
+    With ``device`` set (a torch device string) the Gaussian draw still comes
+    from ``rng`` on the host; only the QR runs on that device in float64.  The
+    sign fix makes Q unique, so host and device results agree to rounding.
+    """
+    M = rng.standard_normal((rows, cols))
+    if device is None:
+        return _sign_fixed_q(M, np.linalg.qr)
+    import torch
+    Mt = torch.from_numpy(M).to(device=device, dtype=torch.float64)
+    return _sign_fixed_q(Mt, torch.linalg.qr)
+
+
+def spectral_matrix(m: int, n: int, sigma: np.ndarray, rng: np.random.Generator,
+                    device=None):
+    """Q1 diag(sigma) Q2^T with Haar Q1 (m x r), Q2 (n x r), r = len(sigma)."""
+    r = len(sigma)
+    Q1 = haar_columns(m, r, rng, device)
+    Q2 = haar_columns(n, r, rng, device)
+    if device is None:
+        return (Q1 * sigma[None, :]) @ Q2.T
+    import torch
+    s = torch.from_numpy(np.asarray(sigma, dtype=np.float64)).to(Q1.device)
+    return (Q1 * s.unsqueeze(0)) @ Q2.T
+
+
+def decay_exp(n: int, scale: float = 20.0) -> np.ndarray:
+    return np.exp(-np.arange(n, dtype=np.float64) / scale)
+
+
+def decay_power(n: int, alpha: float) -> np.ndarray:
+    return np.arange(1, n + 1, dtype=np.float64) ** (-alpha)
+
+
+# ---------------------------------------------------------------------------
+# Structured classes used for the circulant path
+# ---------------------------------------------------------------------------
+def toeplitz_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Toeplitz matrix from 2n-1 U(0,1) values: T[i,j] = v[i-j+n-1]."""
+    v = rng.random(2 * n - 1)
+    i = np.arange(n)
+    return v[(i[:, None] - i[None, :]) + n - 1]
+
+
+def planted_circulant(n: int, modes, rng: np.random.Generator, noise: float = 0.0):
+    """A = sum_k R_k D^k over the given frequency set with random real data.
+
+    Built entrywise in the spatial domain, with no FFT: for each mode k a real
+    random cycle profile c_k is drawn and A[p,q] += Re(c_k[(p-q)%n] w^{kq})
+    for the class {k, n-k} together, so A is real and its circulant content
+    sits on the planted classes only.  ``noise`` adds i.i.d. N(0, noise^2).
+    """
+    A = np.zeros((n, n))
+    p = np.arange(n)[:, None]
+    q = np.arange(n)[None, :]
+    for k in modes:
+        c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        term = c[(p - q) % n] * np.exp(2j * np.pi * k * q / n)
+        A += term.real
+    if noise:
+        A += noise * rng.standard_normal((n, n))
+    return A
+
+
+def sparse_overlay(m: int, n: int, frac: float, scale: float,
+                   rng: np.random.Generator):
+    """round(frac*m*n) distinct uniform positions with Laplace(0, scale) values.
+
+    Returns (flat_positions, values); positions are sorted ascending.
+    """
+    nnz = int(round(frac * m * n))
+    pos = np.sort(rng.choice(m * n, size=nnz, replace=False))
+    vals = rng.laplace(0.0, scale, size=nnz)
+    return pos, vals
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+@dataclass
+class Pair:
+    A: np.ndarray
+    B: np.ndarray
+    name: str
+
+
+def workload_c1(n: int = 256) -> Pair:
+    """n=256 square float64, sigma_i = exp(-i/20), plus 1e-3 N(0,1) noise."""
+    out = []
+    for operand in (0, 1):
+        rng = rng_of(1, operand)
+        M = spectral_matrix(n, n, decay_exp(n), rng)
+        M = M + 1e-3 * rng.standard_normal((n, n))
+        out.append(M)
+    return Pair(out[0], out[1], f"haar-exp20-noise n={n}")
+
+
+def workload_c2(n: int = 4096, device=None, with_sparse: bool = False,
+                frac: float = 0.01, lap_scale: float = 10.0) -> Pair:
+    """Square Haar operands with sigma_i = i^-1.5; optional 1% Laplace overlay."""
+    out = []
+    for operand in (0, 1):
+        rng = rng_of(2, operand)
+        M = spectral_matrix(n, n, decay_power(n, 1.5), rng, device)
+        if with_sparse:
+            pos, vals = sparse_overlay(n, n, frac, lap_scale, rng_of(2, operand, 1))
+            if device is None:
+                M = M.copy()
+                M.reshape(-1)[pos] += vals
+            else:
+                import torch
+                flat = M.reshape(-1)
+                flat[torch.from_numpy(pos).to(M.device)] += torch.from_numpy(vals).to(M.device)
+        out.append(M)
+    tag = "haar-pow1.5" + (f"+sparse{frac:g}" if with_sparse else "")
+    return Pair(out[0], out[1], f"{tag} n={n}")
+
+
+def workload_toeplitz(n: int) -> Pair:
+    A = toeplitz_uniform(n, rng_of(9, 0))
+    B = toeplitz_uniform(n, rng_of(9, 1))
+    return Pair(A, B, f"toeplitz-U01 n={n}")
+
+
+def gaussian(rows: int, cols: int, rng: np.random.Generator) -> np.ndarray:
+    return rng.standard_normal((rows, cols))
+
+
+def log2_int(n: int) -> int:
+    k = int(round(math.log2(n)))
+    if 1 << k != n:
+        raise ValueError(f"{n} is not a power of two")
+    return k
