@@ -1,0 +1,319 @@
+"""Benchmark: approximate product at n = 4096 (square float32 operands with
+Haar singular vectors and sigma_i = i^-1.5), against dense float32 GEMM.
+
+One step = one first-order approximate product M = Atil B + Delta A Btil of
+the primary variant (truncated SVD, rank 32 for both operands), with both
+decompositions made beforehand on the device and timed separately
+(decompose_ms; the paper treats the decomposition of a static operand as an
+offline step).  Every other variant of the workload (circulant K = 8/32/128,
+SVD rank 32/128, zeroth and first order, sparsified operands) is measured too
+and listed under "variants" with its error against the exact product.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
+MFMA_F32_PEAK = 157.3e12     # flop/s, dense FP32 matrix cores
+VALU_F32_PEAK = 78.6e12      # flop/s, FP32 vector FMA without packed-FP32 forms
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="run just one variant name (profiling)")
+    return ap.parse_args()
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+
+    def run(self, fn, reps, warm):
+        t = self.torch
+        for _ in range(warm):
+            fn()
+        t.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            a = t.cuda.Event(enable_timing=True)
+            b = t.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        return times
+
+
+def rel_err(M, exact64):
+    d = (M.double() - exact64)
+    return float(d.norm() / exact64.norm())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2504_19308_amd import Context, inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = "cuda"
+    n = args.n
+    t0 = time.time()
+    log(f"[bench] generating n={n} operands")
+    pair = inputs.workload_c2(n, device=dev)
+    A = pair.A.float().contiguous()
+    B = pair.B.float().contiguous()
+    exact = A.double() @ B.double()
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready {time.time() - t0:.1f}s")
+    tm = Timer(torch)
+    flops_equiv = 2.0 * n * n * n
+
+    # dense baselines on the same GPU
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B), 25, 5))
+    Ab, Bb = A.bfloat16(), B.bfloat16()
+    dense_bf16_ms = statistics.median(tm.run(lambda: torch.matmul(Ab, Bb), 25, 5))
+    log(f"[bench] dense fp32 {dense_ms:.3f} ms, bf16 {dense_bf16_ms:.3f} ms")
+
+    ctx = Context(0)
+
+    def decompose_timed(M, kind, K, **kw):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        d = ctx.decompose(M, kind, K, **kw)
+        torch.cuda.synchronize()
+        return d, (time.perf_counter() - a) * 1e3
+
+    out = torch.empty((n, n), dtype=torch.float32, device=dev)
+
+    # ---- primary variant: SVD rank 32, first order ---------------------------
+    kp = 32
+    dA, tA = decompose_timed(A, "tsvd", kp, seed=1)
+    dB, tB = decompose_timed(B, "tsvd", kp, seed=2)
+    step = lambda: ctx.approx_matmul(dA, B, dB, out=out)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    kt = ctx.timings()
+    ctx.set_timing(False)
+    # the event brackets add a little; time the same steps without them too
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    err_primary = rel_err(out, exact)
+    value = flops_equiv / (ms_step * 1e-3) / 1e12
+    log(f"[bench] primary tsvd k={kp} first order: {ms_step:.4f} ms/step, err {err_primary:.3e}")
+
+    # roofline of the dominant kernel (largest total time in the timed steps)
+    name, (kms, launches) = max(kt.items(), key=lambda kv: kv[1][0])
+    avg_s = kms / launches * 1e-3
+    kc = 2 * kp
+    shapes = {
+        # name: (bytes per launch, flops per launch)
+        "gemm_out": (4.0 * (n * kc + kc * n + n * n), 2.0 * n * n * kc),
+        "gemm_VtB": (4.0 * (n * kp + n * n), 2.0 * kp * n * n),
+        "gemm_AU": (4.0 * (n * n + n * kp), 2.0 * n * kp * n),
+    }
+    byts, fl = shapes.get(name, (float("nan"), float("nan")))
+    if fl / MFMA_F32_PEAK > byts / HBM_PEAK:
+        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["avg_us"] = avg_s * 1e6
+    roof["algorithmic_bytes"] = byts
+    roof["algorithmic_flops"] = fl
+    roof["per_kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in kt.items()}
+
+    variants = []
+    if not args.no_variants:
+        variants = run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, args.only, dA, dB)
+
+    cpu = None if args.no_cpu else cpu_baseline(pair, A, B, kp, flops_equiv)
+
+    rec = {
+        "metric": "approx-matmul TFLOP-equiv/s and speedup vs dense GEMM at <=1% rel. Frobenius error",
+        "value": value,
+        "unit": "TFLOP-equiv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"square n={n} float32 A,B = Q1 diag(i^-1.5) Q2^T (Haar Q, seeded); "
+                        f"first-order truncated-SVD product, rank {kp} for A and B",
+            "n": n, "variant": f"tsvd k={kp} first order",
+        },
+        "err_vs_exact": err_primary,
+        "dense_fp32_ms": dense_ms,
+        "dense_bf16_ms": dense_bf16_ms,
+        "speedup_vs_dense_fp32": dense_ms / ms_step,
+        "decompose_ms": {"A": tA, "B": tB},
+        "end_to_end": {
+            "ms": ms_step + tA + tB,
+            "tflop_equiv_s": flops_equiv / ((ms_step + tA + tB) * 1e-3) / 1e12,
+            "speedup_vs_dense_fp32": dense_ms / (ms_step + tA + tB),
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
+    n = A.shape[0]
+    res = []
+    out = torch.empty_like(A)
+    cache = {("tsvd", 32): (dA_tsvd32, dB_tsvd32)}
+
+    def dec(M, key, kind, K, **kw):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        d = ctx.decompose(M, kind, K, **kw)
+        torch.cuda.synchronize()
+        return d, (time.perf_counter() - a) * 1e3
+
+    def measure(name, dA, dB, Bm, dec_ms, ex):
+        if only and only != name:
+            return
+        fn = lambda: ctx.approx_matmul(dA, Bm, dB, out=out)
+        ms = statistics.median(tm.run(fn, 25, 5))
+        ctx.set_timing(True)
+        fn()
+        kt = ctx.timings()
+        ctx.set_timing(False)
+        err = rel_err(out, ex)
+        res.append({"name": name, "ms": ms, "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12,
+                    "speedup_vs_dense_fp32": dense_ms / ms, "err_vs_exact": err,
+                    "meets_1pct": err <= 0.01, "decompose_ms": dec_ms,
+                    "kernels_ms": {k: v[0] for k, v in kt.items()}})
+        log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
+
+    # circulant
+    for K in (8, 32, 128):
+        dA, ta = dec(A, None, "circulant", K)
+        dB, tb = dec(B, None, "circulant", K)
+        measure(f"circulant K={K} zeroth", dA, None, B, ta, exact)
+        measure(f"circulant K={K} first", dA, dB, B, ta + tb, exact)
+        del dA, dB
+    # truncated SVD
+    for k in (32, 128):
+        if ("tsvd", k) in cache:
+            dA, dB = cache[("tsvd", k)]
+            ta = tb = float("nan")
+        else:
+            dA, ta = dec(A, None, "tsvd", k, seed=1)
+            dB, tb = dec(B, None, "tsvd", k, seed=2)
+        measure(f"tsvd k={k} zeroth", dA, None, B, ta, exact)
+        measure(f"tsvd k={k} first", dA, dB, B, ta + tb, exact)
+    # sparsified operands: 1% Laplace(10) entries over the same low-rank decay
+    from paper_2504_19308_amd import inputs
+    sp = inputs.workload_c2(n, device="cuda", with_sparse=True)
+    As, Bs = sp.A.float().contiguous(), sp.B.float().contiguous()
+    ex_s = As.double() @ Bs.double()
+    for inner, K in (("tsvd", 32), ("circulant", 8)):
+        dA, ta = dec(As, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=3)
+        dB, tb = dec(Bs, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=4)
+        measure(f"sparse1%+{inner} K={K} zeroth", dA, None, Bs, ta, ex_s)
+        measure(f"sparse1%+{inner} K={K} first", dA, dB, Bs, ta + tb, ex_s)
+        del dA, dB
+    return res
+
+
+def cpu_baseline(pair, A, B, k, flops_equiv):
+    """The float64 oracle's first-order SVD product on 128 sampled output
+    columns (factors from the oracle's own exact float64 SVD of the operands
+    would cost minutes; the device factors are reused instead, so this times
+    the oracle's product step only)."""
+    import threadpoolctl
+    from oracle import tsvd as ot
+    import torch
+    ctx_dec = None
+    Ah = A.double().cpu().numpy()
+    Bh = B.double().cpu().numpy()
+    n = Ah.shape[0]
+    cols = np.sort(np.random.default_rng(0).choice(n, 128, replace=False))
+    # exact rank-k factors from the generator-free route: SVD of a k+16 sketch
+    # is not the oracle; use numpy's SVD of the projected operands instead
+    def factors(M):
+        rng = np.random.default_rng(1)
+        Q, _ = np.linalg.qr(M @ rng.standard_normal((n, k + 16)))
+        for _ in range(2):
+            Q, _ = np.linalg.qr(M @ (M.T @ Q))
+        U, s, Vt = np.linalg.svd(Q.T @ M, full_matrices=False)
+        return (Q @ U)[:, :k], s[:k], Vt[:k].T
+    UA, sA, VA = factors(Ah)
+    UB, sB, VB = factors(Bh)
+    decA = ot.TSVDDecomp(Ah, k, UA, sA, VA)
+    decB_cols = ot.TSVDDecomp(Bh[:, cols], k, UB, sB, VB[cols])
+    Bc = Bh[:, cols]
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    reps = 0
+    t = time.perf_counter()
+    while True:
+        M0 = ot.apply_zeroth(decA, Bc)
+        M1 = M0 + ot.apply_first_order_term(decB_cols, decA.residual_dense())
+        reps += 1
+        if time.perf_counter() - t > 10.0:
+            break
+    dt = (time.perf_counter() - t) / reps
+    sample_flops = 2.0 * n * n * len(cols)
+    return {"value": sample_flops / dt / 1e12, "unit": "TFLOP-equiv/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle first-order SVD product (float64, numpy) on {len(cols)} of {n} output "
+                      f"columns, rank {k}, {reps} repetitions over ~10 s; value scaled by the sampled "
+                      f"columns' dense-equivalent flops"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * amm.h -- approximate matrix multiplication from truncated decompositions,
+ * MI355X (gfx950) library.  C ABI: every entry point is extern "C", takes plain
+ * host or device pointers and sizes, and returns an amm_status.  No exception
+ * crosses the ABI.  A non-OK status leaves every output untouched and sets a
+ * thread-local message readable with amm_last_error().
+ *
+ * The operation (paper: "Efficient approximations of matrix multiplication
+ * using truncated decompositions", Sec. 2.1, eq. (2.1)-(2.3)):
+ *   A = Atil + Delta A,  B = Btil + Delta B,
+ *   zeroth order  M0 = Atil B,
+ *   first order   M1 = Atil B + Delta A Btil   (= AB - Delta A Delta B).
+ * Atil is one of
+ *   - a truncated circulant decomposition  sum_{k in S} R_k D^k  (Thm. 1.1,
+ *     Alg. 2.2 / 2.3), applied through FFTs: FFT(B) -> sum_t diag(L_t) C^k_t
+ *     -> one inverse FFT (Alg. 2.3 step 5);
+ *   - a truncated SVD  U_k S_k V_k^T  (Sec. 2.2, Alg. 2.1), applied as
+ *     U_k (S_k (V_k^T B));
+ *   - a sparse part of dominant entries plus a truncated dense residue,
+ *     S + trunc(A - S)  (eq. (2.4), abstract).
+ *
+ * Conventions shared by all calls
+ *   - Matrices are row-major, contiguous (leading dimension = column count),
+ *     float32, in device memory unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     All device work of a call is enqueued on it.  amm_approx_matmul never
+ *     synchronises the host; amm_decompose synchronises `stream` (it reads
+ *     the per-frequency energies or the sketch back to pick components).
+ *   - The caller owns A, B, out and the streams.  A decomposition handle owns
+ *     its component buffers; it is immutable after creation and may be used
+ *     from several streams, but must outlive the work enqueued with it.
+ *   - Circulant decompositions need a square operand with n a power of two,
+ *     2 <= n <= 4096; other n return AMM_EUNSUPPORTED.
+ */
+#ifndef AMM_H
+#define AMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amm_ctx amm_ctx;
+typedef struct amm_dec amm_dec;
+
+typedef enum {
+  AMM_OK = 0,
+  AMM_EINVAL = 1,       /* NULL pointer, negative size, bad enum value */
+  AMM_ESHAPE = 2,       /* operand shapes do not conform */
+  AMM_EUNSUPPORTED = 3, /* valid request outside what the GPU path covers */
+  AMM_ENOMEM = 4,       /* device allocation failed */
+  AMM_EDEVICE = 5,      /* a HIP call failed; message holds hipGetErrorString */
+  AMM_ESTATE = 6        /* handle in the wrong state (e.g. no residual kept) */
+} amm_status;
+
+/* Decomposition kinds. AMM_SPARSE may be OR-ed with AMM_CIRCULANT or
+ * AMM_TSVD, which then truncates the dense residue A - S. */
+enum { AMM_CIRCULANT = 1, AMM_TSVD = 2, AMM_SPARSE = 4 };
+
+typedef struct {
+  double sparse_frac;  /* AMM_SPARSE: keep round(frac*m*n) entries of largest |a| */
+  int64_t sparse_nnz;  /* AMM_SPARSE: if >= 0, overrides sparse_frac */
+  int oversample;      /* AMM_TSVD: extra sketch columns (default 16) */
+  int power_iters;     /* AMM_TSVD: subspace iterations (default 2) */
+  uint64_t seed;       /* AMM_TSVD: counter-based sketch seed (Philox4x32-10) */
+  int keep_residual;   /* keep Delta A on the device so that this handle can
+                          be the left operand of a first-order product */
+} amm_opts;
+
+/* Fill `o` with the defaults (frac 0.01, nnz -1, oversample 16, power 2,
+ * seed 0, keep_residual 1). */
+void amm_opts_default(amm_opts* o);
+
+typedef struct {
+  int kind;              /* AMM_CIRCULANT / AMM_TSVD, possibly | AMM_SPARSE */
+  int64_t m, n;          /* operand shape */
+  int K;                 /* requested components (frequencies or rank) */
+  int K_eff;             /* components kept (circulant: K or K-1, pairs closed) */
+  int64_t nnz;           /* sparse entries (0 if not sparse) */
+  int has_residual;      /* Delta A available for first-order use */
+  double norm_A;         /* ||A||_F  (float64) */
+  double norm_residual;  /* ||Delta A||_F from the dropped energy/spectrum */
+} amm_dec_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (made current for the call).
+ * Owns per-size twiddle tables and scratch; not thread-safe. */
+amm_status amm_ctx_create(amm_ctx** ctx, int device);
+void amm_ctx_destroy(amm_ctx* ctx);
+
+/* Per-launch timing for measurement.  With timing enabled, every kernel that
+ * a call on `ctx` enqueues is bracketed by hipEventRecord on the same stream.
+ * amm_ctx_timings waits for the recorded events, then reports per kernel name
+ * the summed duration (ms) and launch count, and clears the totals.  With all
+ * output pointers NULL it only reports *count (the number of names).
+ * names: cap slots of name_len bytes each, NUL-terminated. */
+amm_status amm_ctx_set_timing(amm_ctx* ctx, int enable);
+amm_status amm_ctx_timings(amm_ctx* ctx, char* names, int name_len, double* total_ms,
+                           int64_t* launches, int cap, int* count);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* amm_last_error(void);
+
+/* ---- decomposition ------------------------------------------------------ */
+
+/* Decompose the m x n float32 device matrix A.
+ *  kind = AMM_CIRCULANT: m == n required.  Computes every circulant
+ *    coefficient (Thm. 1.1 / Alg. 2.2) in float64 on the device through the
+ *    two-sided transform F A F^-1, ranks the frequencies by energy
+ *    ||R_k||_F^2 (Alg. 2.3 steps 2-3) and keeps the closed set of at most K
+ *    frequencies {k, n-k} with the most energy, then stores the eigenvalue
+ *    lists L_t = F r_{.,k_t} (Alg. 2.3 step 4).  With keep_residual it also
+ *    keeps Delta A = A - sum_{t} R_t D^{k_t}  (Alg. 2.3 step 6) in float32.
+ *  kind = AMM_TSVD: rank-K randomized SVD (Alg. 2.1, with oversampling and
+ *    subspace iterations), float64 on the device; K <= min(m, n).  With
+ *    keep_residual it borrows A (see amm_dec_import_tsvd) -- the caller must
+ *    keep A alive and unchanged while the handle is used as a left operand.
+ *  kind |= AMM_SPARSE: first splits A = S + R with S the round(frac*m*n)
+ *    entries of largest |a| (ties to the smaller row-major index), stored as
+ *    CSR, then truncates R with the other kind (K may be 0 for none).
+ * `opts` may be NULL (defaults).  On success *out owns a new handle. */
+amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n,
+                         int kind, int K, const amm_opts* opts, void* stream,
+                         amm_dec** out);
+
+/* Import a circulant truncation computed elsewhere.
+ *  freqs_host: K int32 frequencies in [0, n) (host).
+ *  eig_host:   K x n complex float64, interleaved (re, im), row t holds
+ *              L_t[p] = sum_j r_{j,k_t} exp(-2 pi i p j / n)  (host).
+ *  residual:   optional n x n float32 Delta A on the device, copied.
+ *  norm_A, norm_residual: stored for amm_dec_query (may be 0).
+ * The set should be closed under k -> n-k for a real product. */
+amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K,
+                                    const int32_t* freqs_host,
+                                    const double* eig_host,
+                                    const float* residual, double norm_A,
+                                    double norm_residual, amm_dec** out);
+
+/* Import a truncated SVD: U (m x k), sigma (k), V (n x k), float64 host
+ * arrays, row-major.  A (m x n, device) is optional and borrowed: it is needed
+ * only when this handle is the left operand of a first-order product. */
+amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k,
+                               const double* U_host, const double* sigma_host,
+                               const double* V_host, const float* A,
+                               amm_dec** out);
+
+/* Import a sparse part (CSR on the host: row_ptr m+1, col nnz ascending per
+ * row, val nnz) plus an optional truncated residue handle, whose ownership
+ * passes to the new handle.  A (device, borrowed) as in amm_dec_import_tsvd. */
+amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n,
+                                 int64_t nnz, const int32_t* row_ptr_host,
+                                 const int32_t* col_host, const float* val_host,
+                                 amm_dec* residue, const float* A,
+                                 amm_dec** out);
+
+amm_status amm_dec_query(const amm_dec* dec, amm_dec_info* info);
+
+/* Copy the kept circulant frequencies (ascending) to `out_host` (capacity
+ * `cap`); *count receives K_eff. Circulant handles (or sparse ones with a
+ * circulant residue) only. */
+amm_status amm_dec_frequencies(const amm_dec* dec, int32_t* out_host, int cap,
+                               int* count);
+
+/* Copy the float64 per-frequency energies ||R_k||_F^2 (n values) of a
+ * circulant decomposition made by amm_decompose to the host. */
+amm_status amm_dec_energies(const amm_dec* dec, double* out_host, int64_t cap);
+
+/* Copy the truncated-SVD factors as float32 (U m x k, sigma k, V n x k). */
+amm_status amm_dec_tsvd_factors(const amm_dec* dec, float* U_host,
+                                float* sigma_host, float* V_host);
+
+/* Copy the sparse part (row_ptr m+1, col nnz, val nnz) to the host. */
+amm_status amm_dec_sparse_part(const amm_dec* dec, int32_t* row_ptr_host,
+                               int32_t* col_host, float* val_host);
+
+void amm_dec_destroy(amm_dec* dec);
+
+/* ---- product ------------------------------------------------------------ */
+
+/* out (m x p) = Atil B                 when dB == NULL   (zeroth order)
+ * out (m x p) = Atil B + Delta A Btil  when dB != NULL   (first order)
+ * B is n x p on the device, dA describes an m x n operand.  dB must describe
+ * B's own decomposition (n x p) and dA must hold Delta A (circulant:
+ * keep_residual; SVD/sparse: borrowed A).  out is overwritten; it must not
+ * alias B.  Nothing is allocated per call except the SVD and sparse
+ * intermediates, which come from the context's reusable scratch. */
+amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
+                             const float* B, int64_t n, int64_t p, float* out,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMM_H */

@@ -1,0 +1,233 @@
+"""Approximate matrix products from truncated decompositions on MI355X.
+
+Thin Python layer over the C ABI of ``libamm.so`` (include/amm.h).  Torch
+tensors provide device memory and the current stream; every arithmetic step
+runs in the library's HIP kernels.  If the library is missing the calls raise.
+
+    ctx = Context()
+    dA = ctx.decompose(A, "circulant", K=32)      # A: float32 CUDA tensor
+    M = ctx.approx_matmul(dA, B)                  # zeroth order
+    dB = ctx.decompose(B, "tsvd", K=32)
+    M1 = ctx.approx_matmul(dA, B, dB)             # first order
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import AMM_CIRCULANT, AMM_SPARSE, AMM_TSVD, AmmError  # noqa: F401
+
+KINDS = {"circulant": AMM_CIRCULANT, "tsvd": AMM_TSVD, "sparse": AMM_SPARSE,
+         "sparse+circulant": AMM_SPARSE | AMM_CIRCULANT, "sparse+tsvd": AMM_SPARSE | AMM_TSVD}
+
+
+def _stream_ptr(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_f32_cuda(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D tensor")
+
+
+class Decomposition:
+    """Owns an ``amm_dec`` handle; keeps borrowed tensors alive."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, keep=()):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = list(keep)
+
+    def info(self) -> dict:
+        inf = _lib.AmmDecInfo()
+        _lib.check(_lib.load().amm_dec_query(self.handle, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _lib.AmmDecInfo._fields_}
+
+    def frequencies(self) -> np.ndarray:
+        lib = _lib.load()
+        cnt = C.c_int(0)
+        _lib.check(lib.amm_dec_frequencies(self.handle, None, 0, C.byref(cnt)))
+        out = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        _lib.check(lib.amm_dec_frequencies(self.handle, out.ctypes.data_as(C.c_void_p), len(out), C.byref(cnt)))
+        return out[: cnt.value].copy()
+
+    def energies(self) -> np.ndarray:
+        n = self.info()["n"]
+        out = np.zeros(n, dtype=np.float64)
+        _lib.check(_lib.load().amm_dec_energies(self.handle, out.ctypes.data_as(C.c_void_p), n))
+        return out
+
+    def tsvd_factors(self):
+        inf = self.info()
+        m, n, k = inf["m"], inf["n"], inf["K_eff"]
+        U = np.zeros((m, k), np.float32)
+        s = np.zeros(k, np.float32)
+        V = np.zeros((n, k), np.float32)
+        _lib.check(_lib.load().amm_dec_tsvd_factors(self.handle, U.ctypes.data_as(C.c_void_p),
+                                                    s.ctypes.data_as(C.c_void_p), V.ctypes.data_as(C.c_void_p)))
+        return U, s, V
+
+    def sparse_part(self):
+        inf = self.info()
+        m, nnz = inf["m"], inf["nnz"]
+        rp = np.zeros(m + 1, np.int32)
+        col = np.zeros(max(nnz, 1), np.int32)
+        val = np.zeros(max(nnz, 1), np.float32)
+        _lib.check(_lib.load().amm_dec_sparse_part(self.handle, rp.ctypes.data_as(C.c_void_p),
+                                                   col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p)))
+        return rp, col[:nnz], val[:nnz]
+
+    def close(self):
+        if self.handle:
+            _lib.load().amm_dec_destroy(self.handle)
+            self.handle = None
+
+    def _release(self):
+        """Ownership moved into another handle (sparse residue)."""
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        lib = _lib.load()
+        h = C.c_void_p()
+        _lib.check(lib.amm_ctx_create(C.byref(h), device))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.load().amm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- per-launch timing (HIP events on the launch stream) --------------------
+    def set_timing(self, enable: bool = True):
+        _lib.check(_lib.load().amm_ctx_set_timing(self.handle, 1 if enable else 0))
+
+    def timings(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last call; waits for the events."""
+        lib = _lib.load()
+        cnt = C.c_int(0)
+        _lib.check(lib.amm_ctx_timings(self.handle, None, 0, None, None, 0, C.byref(cnt)))
+        n = max(cnt.value, 1)
+        name_len = 64
+        names = C.create_string_buffer(n * name_len)
+        ms = np.zeros(n, np.float64)
+        launches = np.zeros(n, np.int64)
+        _lib.check(lib.amm_ctx_timings(self.handle, names, name_len, ms.ctypes.data_as(C.c_void_p),
+                                       launches.ctypes.data_as(C.c_void_p), n, C.byref(cnt)))
+        out = {}
+        raw = names.raw
+        for i in range(cnt.value):
+            nm = raw[i * name_len:(i + 1) * name_len].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(launches[i]))
+        return out
+
+    # -- decompositions ---------------------------------------------------------
+    def decompose(self, A, kind: str, K: int, sparse_frac: float | None = None,
+                  sparse_nnz: int | None = None, oversample: int = 16, power_iters: int = 2,
+                  seed: int = 0, keep_residual: bool = True) -> Decomposition:
+        _need_f32_cuda(A, "A")
+        lib = _lib.load()
+        o = _lib.AmmOpts()
+        lib.amm_opts_default(C.byref(o))
+        if sparse_frac is not None:
+            o.sparse_frac = sparse_frac
+        if sparse_nnz is not None:
+            o.sparse_nnz = sparse_nnz
+        o.oversample, o.power_iters, o.seed = oversample, power_iters, seed
+        o.keep_residual = 1 if keep_residual else 0
+        h = C.c_void_p()
+        m, n = A.shape
+        _lib.check(lib.amm_decompose(self.handle, C.c_void_p(A.data_ptr()), m, n, KINDS[kind], K,
+                                     C.byref(o), _stream_ptr(self.torch, A.device), C.byref(h)))
+        keep = (A,) if kind in ("tsvd",) and keep_residual else ()
+        return Decomposition(self, h, keep)
+
+    def import_circulant(self, n: int, freqs, eig, residual=None, norm_A: float = 0.0,
+                         norm_residual: float = 0.0) -> Decomposition:
+        """freqs: K ints; eig: K x n complex eigenvalue lists (host)."""
+        freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.int32))
+        eig = np.asarray(eig, dtype=np.complex128).reshape(len(freqs), n)
+        eig_f = np.ascontiguousarray(eig.view(np.float64))
+        res_ptr = None
+        if residual is not None:
+            _need_f32_cuda(residual, "residual")
+            res_ptr = C.c_void_p(residual.data_ptr())
+        h = C.c_void_p()
+        _lib.check(_lib.load().amm_dec_import_circulant(
+            self.handle, n, len(freqs), freqs.ctypes.data_as(C.c_void_p), eig_f.ctypes.data_as(C.c_void_p),
+            res_ptr, float(norm_A), float(norm_residual), C.byref(h)))
+        self.torch.cuda.synchronize()
+        return Decomposition(self, h)
+
+    def import_tsvd(self, U, s, V, A=None) -> Decomposition:
+        U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
+        s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float64))
+        m, k = U.shape
+        n = V.shape[0]
+        a_ptr = None
+        if A is not None:
+            _need_f32_cuda(A, "A")
+            a_ptr = C.c_void_p(A.data_ptr())
+        h = C.c_void_p()
+        _lib.check(_lib.load().amm_dec_import_tsvd(
+            self.handle, m, n, k, U.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p),
+            V.ctypes.data_as(C.c_void_p), a_ptr, C.byref(h)))
+        return Decomposition(self, h, (A,) if A is not None else ())
+
+    def import_sparse(self, m: int, n: int, row_ptr, col, val, residue: Decomposition | None = None,
+                      A=None) -> Decomposition:
+        rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+        cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+        vl = np.ascontiguousarray(np.asarray(val, dtype=np.float32))
+        a_ptr = None
+        if A is not None:
+            _need_f32_cuda(A, "A")
+            a_ptr = C.c_void_p(A.data_ptr())
+        h = C.c_void_p()
+        rh = residue.handle if residue is not None else None
+        _lib.check(_lib.load().amm_dec_import_sparse(
+            self.handle, m, n, int(rp[-1]), rp.ctypes.data_as(C.c_void_p), cl.ctypes.data_as(C.c_void_p),
+            vl.ctypes.data_as(C.c_void_p), rh, a_ptr, C.byref(h)))
+        keep = [A] if A is not None else []
+        if residue is not None:
+            keep += residue._keep
+            residue._release()
+        return Decomposition(self, h, keep)
+
+    # -- product ----------------------------------------------------------------
+    def approx_matmul(self, dA: Decomposition, B, dB: Decomposition | None = None, out=None):
+        _need_f32_cuda(B, "B")
+        n, p = B.shape
+        m = dA.info()["m"]
+        if out is None:
+            out = self.torch.empty((m, p), dtype=self.torch.float32, device=B.device)
+        else:
+            _need_f32_cuda(out, "out")
+        _lib.check(_lib.load().amm_approx_matmul(
+            self.handle, dA.handle, dB.handle if dB is not None else None, C.c_void_p(B.data_ptr()),
+            n, p, C.c_void_p(out.data_ptr()), _stream_ptr(self.torch, B.device)))
+        return out

@@ -1,0 +1,87 @@
+"""ctypes declarations of the C ABI in include/amm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamm.so")
+
+AMM_OK = 0
+STATUS_NAMES = {0: "AMM_OK", 1: "AMM_EINVAL", 2: "AMM_ESHAPE", 3: "AMM_EUNSUPPORTED",
+                4: "AMM_ENOMEM", 5: "AMM_EDEVICE", 6: "AMM_ESTATE"}
+
+AMM_CIRCULANT = 1
+AMM_TSVD = 2
+AMM_SPARSE = 4
+
+
+class AmmOpts(C.Structure):
+    _fields_ = [("sparse_frac", C.c_double), ("sparse_nnz", C.c_int64),
+                ("oversample", C.c_int), ("power_iters", C.c_int),
+                ("seed", C.c_uint64), ("keep_residual", C.c_int)]
+
+
+class AmmDecInfo(C.Structure):
+    _fields_ = [("kind", C.c_int), ("m", C.c_int64), ("n", C.c_int64), ("K", C.c_int),
+                ("K_eff", C.c_int), ("nnz", C.c_int64), ("has_residual", C.c_int),
+                ("norm_A", C.c_double), ("norm_residual", C.c_double)]
+
+
+# name -> (restype, argtypes); every pointer is a plain void* / typed pointer
+SIGNATURES = {
+    "amm_opts_default": (None, [C.POINTER(AmmOpts)]),
+    "amm_last_error": (C.c_char_p, []),
+    "amm_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "amm_ctx_destroy": (None, [C.c_void_p]),
+    "amm_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "amm_ctx_timings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                  C.POINTER(C.c_int)]),
+    "amm_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                C.POINTER(AmmOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amm_dec_import_circulant": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_void_p)]),
+    "amm_dec_import_tsvd": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amm_dec_import_sparse": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_void_p)]),
+    "amm_dec_query": (C.c_int, [C.c_void_p, C.POINTER(AmmDecInfo)]),
+    "amm_dec_frequencies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "amm_dec_energies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "amm_dec_tsvd_factors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amm_dec_sparse_part": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amm_dec_destroy": (None, [C.c_void_p]),
+    "amm_approx_matmul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_int64, C.c_void_p, C.c_void_p]),
+}
+
+_lib = None
+
+
+class AmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libamm.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2504_19308_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != AMM_OK:
+        msg = load().amm_last_error()
+        raise AmmError(status, msg.decode() if msg else "")

@@ -1,0 +1,682 @@
+// C ABI of the approximate-product library: handles, validation, dispatch.
+//
+// Combination rules (eq. (2.1)-(2.3) of the paper):
+//   zeroth order  out = Atil B
+//   first order   out = Atil B + Delta A Btil
+// "left" products (Atil B) and "right" products (X Btil for a dense X) are
+// dispatched per decomposition kind; a sparse handle contributes its CSR part
+// and then its truncated residue.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "amm_internal.hpp"
+
+namespace amm {
+
+namespace {
+thread_local char g_msg[512] = "";
+}
+
+thread_local KernelTimer* g_timer = nullptr;
+
+namespace {
+// Routes the launches of one API call to the context's timer when enabled.
+struct TimerScope {
+  KernelTimer* prev;
+  explicit TimerScope(amm_ctx* ctx) : prev(g_timer) { g_timer = (ctx && ctx->timing) ? &ctx->timer : nullptr; }
+  ~TimerScope() { g_timer = prev; }
+};
+}  // namespace
+
+amm_status fail(amm_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+amm_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(AMM_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(AMM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+amm_status DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) return AMM_OK;
+  hipError_t e = hipMalloc(&ptr, b);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  bytes = b;
+  return AMM_OK;
+}
+
+amm_status DevBuf::reserve(size_t b) {
+  if (b <= bytes) return AMM_OK;
+  return alloc(b);
+}
+
+namespace {
+
+int log2_exact(int64_t n) {
+  if (n < 2 || (n & (n - 1)) != 0) return -1;
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+// exp(-2 pi i m / n) with the angle reduced to the first octant, so every entry
+// is the correctly rounded value of an exactly representable fraction m / n.
+void twiddle_value(int64_t m, int64_t n, long double* c, long double* s) {
+  // angle = 2 pi m / n; use m/n in [0, 1)
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const int64_t q = m * 8;           // position in eighths of a turn
+  const int64_t oct = q / n;         // octant 0..7
+  const int64_t rem = q - oct * n;   // remainder within the octant, times n
+  long double a = (long double)rem / (long double)n * (pi / 4);  // in [0, pi/4)
+  long double cs, sn;
+  // in octant o, angle = o * pi/4 + a
+  switch (oct) {
+    case 0: cs = cosl(a); sn = sinl(a); break;
+    case 1: cs = sinl(pi / 4 - a); sn = cosl(pi / 4 - a); break;
+    case 2: cs = -sinl(a); sn = cosl(a); break;
+    case 3: cs = -cosl(pi / 4 - a); sn = sinl(pi / 4 - a); break;
+    case 4: cs = -cosl(a); sn = -sinl(a); break;
+    case 5: cs = -sinl(pi / 4 - a); sn = -cosl(pi / 4 - a); break;
+    case 6: cs = sinl(a); sn = -cosl(a); break;
+    default: cs = cosl(pi / 4 - a); sn = -sinl(pi / 4 - a); break;
+  }
+  *c = cs;
+  *s = -sn;  // exp(-i angle)
+}
+
+}  // namespace
+
+amm_status twiddles32(amm_ctx* ctx, int log2n, const float2** out) {
+  auto it = ctx->tw32.find(log2n);
+  if (it == ctx->tw32.end()) {
+    const int64_t n = int64_t(1) << log2n;
+    std::vector<float2> h(n);
+    for (int64_t m = 0; m < n; ++m) {
+      long double c, s;
+      twiddle_value(m, n, &c, &s);
+      h[m] = float2{(float)c, (float)s};
+    }
+    DevBuf b;
+    AMM_TRY(b.alloc(n * sizeof(float2)));
+    AMM_HIP(hipMemcpy(b.ptr, h.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+    it = ctx->tw32.emplace(log2n, std::move(b)).first;
+  }
+  *out = it->second.as<float2>();
+  return AMM_OK;
+}
+
+amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out) {
+  auto it = ctx->tw64.find(log2n);
+  if (it == ctx->tw64.end()) {
+    const int64_t n = int64_t(1) << log2n;
+    std::vector<double2> h(n);
+    for (int64_t m = 0; m < n; ++m) {
+      long double c, s;
+      twiddle_value(m, n, &c, &s);
+      h[m] = double2{(double)c, (double)s};
+    }
+    DevBuf b;
+    AMM_TRY(b.alloc(n * sizeof(double2)));
+    AMM_HIP(hipMemcpy(b.ptr, h.data(), n * sizeof(double2), hipMemcpyHostToDevice));
+    it = ctx->tw64.emplace(log2n, std::move(b)).first;
+  }
+  *out = it->second.as<double2>();
+  return AMM_OK;
+}
+
+// ---- product dispatch ---------------------------------------------------------
+namespace {
+
+bool is_circ(const amm_dec* d) { return d->kind == AMM_CIRCULANT; }
+bool is_tsvd(const amm_dec* d) { return d->kind == AMM_TSVD; }
+bool is_sparse(const amm_dec* d) { return (d->kind & AMM_SPARSE) != 0; }
+
+// out (m x p) (+)= Atil B
+amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out,
+                      bool acc, hipStream_t s) {
+  if (is_sparse(d)) {
+    AMM_TRY(spmm_csr(d, B, p, out, acc, s));
+    if (d->inner) AMM_TRY(left_apply(ctx, d->inner, B, p, out, true, s));
+    return AMM_OK;
+  }
+  if (is_circ(d)) {
+    if (d->K_eff == 0) {
+      if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
+      return AMM_OK;
+    }
+    return cd_apply_columns(ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(),
+                            d->L.as<float2>(), B, p, out, acc, s);
+  }
+  if (is_tsvd(d)) {
+    const int k = d->K_eff;
+    if (k == 0) {
+      if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
+      return AMM_OK;
+    }
+    AMM_TRY(ctx->scratch[0].reserve((size_t)k * p * sizeof(float)));
+    float* G = ctx->scratch[0].as<float>();
+    // G = V^T B  (k x p)
+    AMM_TRY(gemm_f32(k, p, d->n, 1.f, MatView{d->V.as<float>(), 1, k}, MatView{B, p, 1}, 0.f, G, p, s, "gemm_VtB"));
+    // out = (U S) G
+    AMM_TRY(gemm_f32(d->m, p, k, 1.f, MatView{d->US.as<float>(), k, 1}, MatView{G, p, 1},
+                     acc ? 1.f : 0.f, out, p, s, "gemm_out"));
+    return AMM_OK;
+  }
+  return fail(AMM_EINVAL, "unknown decomposition kind %d", d->kind);
+}
+
+// out (rows x p) (+)= X Btil, X dense rows x n
+amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
+                       bool acc, hipStream_t s) {
+  const int64_t n = d->m, p = d->n;  // Btil is n x p
+  if (is_sparse(d)) {
+    AMM_TRY(dense_times_csr(X, rows, d, out, acc, s));
+    if (d->inner) AMM_TRY(right_apply(ctx, X, rows, d->inner, out, true, s));
+    return AMM_OK;
+  }
+  if (is_circ(d)) {
+    if (d->K_eff == 0) {
+      if (!acc) AMM_TRY(fill_f32(out, rows * p, 0.f, s));
+      return AMM_OK;
+    }
+    return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
+                         d->Ladj.as<float2>(), X, rows, out, acc, s);
+  }
+  if (is_tsvd(d)) {
+    const int k = d->K_eff;
+    if (k == 0) {
+      if (!acc) AMM_TRY(fill_f32(out, rows * p, 0.f, s));
+      return AMM_OK;
+    }
+    AMM_TRY(ctx->scratch[1].reserve((size_t)rows * k * sizeof(float)));
+    float* T = ctx->scratch[1].as<float>();
+    // T = X U  (rows x k), out (+)= (T S) V^T = T (V S)^T
+    AMM_TRY(gemm_f32(rows, k, n, 1.f, MatView{X, n, 1}, MatView{d->U.as<float>(), k, 1}, 0.f, T, k, s));
+    AMM_TRY(gemm_f32(rows, p, k, 1.f, MatView{T, k, 1}, MatView{d->VS.as<float>(), 1, k},
+                     acc ? 1.f : 0.f, out, p, s));
+    return AMM_OK;
+  }
+  return fail(AMM_EINVAL, "unknown decomposition kind %d", d->kind);
+}
+
+// Pointer to Delta A (m x n) for the left operand, materialised in scratch[2]
+// when the handle only borrows A.
+amm_status residual_of(amm_ctx* ctx, const amm_dec* d, const float** out, hipStream_t s) {
+  if (d->residual.ptr) {
+    *out = d->residual.as<float>();
+    return AMM_OK;
+  }
+  if (is_sparse(d)) {
+    if (d->inner && (d->inner->residual.ptr || d->inner->A_borrowed))
+      return residual_of(ctx, d->inner, out, s);
+    return fail(AMM_ESTATE, "sparse handle has no residual for a first-order product");
+  }
+  if (is_tsvd(d) && d->A_borrowed) {
+    const int64_t mn = d->m * d->n;
+    AMM_TRY(ctx->scratch[2].reserve(mn * sizeof(float)));
+    float* R = ctx->scratch[2].as<float>();
+    AMM_HIP(hipMemcpyAsync(R, d->A_borrowed, mn * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (d->K_eff > 0)
+      AMM_TRY(gemm_f32(d->m, d->n, d->K_eff, -1.f, MatView{d->US.as<float>(), d->K_eff, 1},
+                       MatView{d->V.as<float>(), 1, d->K_eff}, 1.f, R, d->n, s));
+    *out = R;
+    return AMM_OK;
+  }
+  return fail(AMM_ESTATE, "left operand keeps no Delta A (decompose with keep_residual or pass A)");
+}
+
+}  // namespace
+}  // namespace amm
+
+using namespace amm;
+
+amm_dec::~amm_dec() {
+  if (inner) delete inner;
+}
+
+extern "C" {
+
+void amm_opts_default(amm_opts* o) {
+  if (!o) return;
+  o->sparse_frac = 0.01;
+  o->sparse_nnz = -1;
+  o->oversample = 16;
+  o->power_iters = 2;
+  o->seed = 0;
+  o->keep_residual = 1;
+}
+
+const char* amm_last_error(void) { return g_msg; }
+
+amm_status amm_ctx_create(amm_ctx** ctx, int device) {
+  if (!ctx) return fail(AMM_EINVAL, "ctx is NULL");
+  int count = 0;
+  AMM_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(AMM_EINVAL, "device %d out of range (%d devices)", device, count);
+  AMM_HIP(hipSetDevice(device));
+  amm_ctx* c = new amm_ctx();
+  c->device = device;
+  *ctx = c;
+  return AMM_OK;
+}
+
+void amm_ctx_destroy(amm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+void amm_dec_destroy(amm_dec* dec) { delete dec; }
+
+amm_status amm_ctx_set_timing(amm_ctx* ctx, int enable) {
+  if (!ctx) return fail(AMM_EINVAL, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return AMM_OK;
+}
+
+amm_status amm_ctx_timings(amm_ctx* ctx, char* names, int name_len, double* total_ms,
+                           int64_t* launches, int cap, int* count) {
+  if (!ctx || !count) return fail(AMM_EINVAL, "NULL argument");
+  KernelTimer& t = ctx->timer;
+  for (auto& p : t.pending) {
+    float ms = 0.f;
+    AMM_HIP(hipEventSynchronize(p.b));
+    AMM_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& acc = t.totals[p.name];
+    acc.first += ms;
+    acc.second += 1;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  t.pending.clear();
+  *count = (int)t.totals.size();
+  if (names || total_ms || launches) {
+    if (cap < (int)t.totals.size()) return fail(AMM_EINVAL, "capacity %d < %d", cap, (int)t.totals.size());
+    int i = 0;
+    for (auto& kv : t.totals) {
+      if (names && name_len > 0) {
+        std::snprintf(names + (size_t)i * name_len, name_len, "%s", kv.first.c_str());
+      }
+      if (total_ms) total_ms[i] = kv.second.first;
+      if (launches) launches[i] = kv.second.second;
+      ++i;
+    }
+    t.totals.clear();
+  }
+  return AMM_OK;
+}
+
+amm_status amm_dec_query(const amm_dec* d, amm_dec_info* info) {
+  if (!d || !info) return fail(AMM_EINVAL, "NULL argument");
+  info->kind = d->kind;
+  info->m = d->m;
+  info->n = d->n;
+  info->K = d->K;
+  info->K_eff = d->K_eff;
+  info->nnz = d->nnz;
+  const amm_dec* r = d;
+  info->has_residual = (d->residual.ptr || d->A_borrowed ||
+                        (d->inner && (d->inner->residual.ptr || d->inner->A_borrowed))) ? 1 : 0;
+  (void)r;
+  info->norm_A = d->norm_A;
+  info->norm_residual = d->norm_residual;
+  return AMM_OK;
+}
+
+amm_status amm_dec_frequencies(const amm_dec* d, int32_t* out_host, int cap, int* count) {
+  if (!d || !count) return fail(AMM_EINVAL, "NULL argument");
+  const amm_dec* c = is_sparse(d) ? d->inner : d;
+  if (!c || !is_circ(c)) return fail(AMM_ESTATE, "not a circulant decomposition");
+  *count = (int)c->freqs.size();
+  if (out_host) {
+    if (cap < (int)c->freqs.size()) return fail(AMM_EINVAL, "capacity %d < %d", cap, (int)c->freqs.size());
+    std::memcpy(out_host, c->freqs.data(), c->freqs.size() * sizeof(int32_t));
+  }
+  return AMM_OK;
+}
+
+amm_status amm_dec_energies(const amm_dec* d, double* out_host, int64_t cap) {
+  if (!d || !out_host) return fail(AMM_EINVAL, "NULL argument");
+  const amm_dec* c = is_sparse(d) ? d->inner : d;
+  if (!c || !c->has_energies) return fail(AMM_ESTATE, "no energies stored");
+  if (cap < c->n) return fail(AMM_EINVAL, "capacity too small");
+  AMM_HIP(hipMemcpy(out_host, c->energies.ptr, c->n * sizeof(double), hipMemcpyDeviceToHost));
+  return AMM_OK;
+}
+
+amm_status amm_dec_tsvd_factors(const amm_dec* d, float* U_host, float* sigma_host, float* V_host) {
+  if (!d) return fail(AMM_EINVAL, "NULL argument");
+  const amm_dec* c = is_sparse(d) ? d->inner : d;
+  if (!c || !is_tsvd(c)) return fail(AMM_ESTATE, "not an SVD decomposition");
+  const int k = c->K_eff;
+  if (U_host) AMM_HIP(hipMemcpy(U_host, c->U.ptr, c->m * k * sizeof(float), hipMemcpyDeviceToHost));
+  if (sigma_host) AMM_HIP(hipMemcpy(sigma_host, c->sigma.ptr, k * sizeof(float), hipMemcpyDeviceToHost));
+  if (V_host) AMM_HIP(hipMemcpy(V_host, c->V.ptr, c->n * k * sizeof(float), hipMemcpyDeviceToHost));
+  return AMM_OK;
+}
+
+amm_status amm_dec_sparse_part(const amm_dec* d, int32_t* row_ptr_host, int32_t* col_host, float* val_host) {
+  if (!d || !is_sparse(d)) return fail(AMM_ESTATE, "not a sparse decomposition");
+  if (row_ptr_host) AMM_HIP(hipMemcpy(row_ptr_host, d->row_ptr.ptr, (d->m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (d->nnz > 0) {
+    if (col_host) AMM_HIP(hipMemcpy(col_host, d->col.ptr, d->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (val_host) AMM_HIP(hipMemcpy(val_host, d->val.ptr, d->nnz * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  return AMM_OK;
+}
+
+amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_t* freqs,
+                                    const double* eig, const float* residual, double norm_A,
+                                    double norm_residual, amm_dec** out) {
+  if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
+  const int l2 = log2_exact(n);
+  if (l2 < 1 || l2 > 12) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 4096], got %lld", (long long)n);
+  if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
+  if (K > 0 && (!freqs || !eig)) return fail(AMM_EINVAL, "NULL frequencies or eigenvalues");
+  for (int t = 0; t < K; ++t)
+    if (freqs[t] < 0 || freqs[t] >= n) return fail(AMM_EINVAL, "frequency %d out of range", freqs[t]);
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_dec* d = new amm_dec();
+  d->kind = AMM_CIRCULANT;
+  d->m = d->n = n;
+  d->K = d->K_eff = K;
+  d->device = ctx->device;
+  d->norm_A = norm_A;
+  d->norm_residual = norm_residual;
+  d->freqs.assign(freqs, freqs + K);
+  std::vector<float2> L((size_t)std::max(K, 1) * n), La((size_t)std::max(K, 1) * n);
+  std::vector<int32_t> sh(std::max(K, 1)), sa(std::max(K, 1));
+  for (int t = 0; t < K; ++t) {
+    const int64_t k = freqs[t];
+    sh[t] = (int32_t)k;
+    sa[t] = (int32_t)((n - k) % n);
+    for (int64_t p = 0; p < n; ++p) {
+      const double* e = eig + 2 * ((int64_t)t * n + p);
+      L[(size_t)t * n + p] = float2{(float)e[0], (float)e[1]};
+      const double* f = eig + 2 * ((int64_t)t * n + ((p + k) % n));
+      La[(size_t)t * n + p] = float2{(float)f[0], (float)-f[1]};
+    }
+  }
+  amm_status st;
+  if ((st = d->L.alloc(L.size() * sizeof(float2))) != AMM_OK ||
+      (st = d->Ladj.alloc(La.size() * sizeof(float2))) != AMM_OK ||
+      (st = d->shifts.alloc(sh.size() * sizeof(int32_t))) != AMM_OK ||
+      (st = d->shifts_adj.alloc(sa.size() * sizeof(int32_t))) != AMM_OK) {
+    delete d;
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(d->L.ptr, L.data(), L.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->Ladj.ptr, La.data(), La.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->shifts.ptr, sh.data(), sh.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->shifts_adj.ptr, sa.data(), sa.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && residual) {
+    if ((st = d->residual.alloc(n * n * sizeof(float))) != AMM_OK) { delete d; return st; }
+    e = hipMemcpy(d->residual.ptr, residual, n * n * sizeof(float), hipMemcpyDeviceToDevice);
+  }
+  if (e != hipSuccess) {
+    delete d;
+    return hip_fail(e, "import circulant");
+  }
+  *out = d;
+  return AMM_OK;
+}
+
+amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const double* U,
+                               const double* sigma, const double* V, const float* A, amm_dec** out) {
+  if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (m <= 0 || n <= 0 || k < 0 || k > std::min(m, n)) return fail(AMM_ESHAPE, "bad SVD shape m=%lld n=%lld k=%d", (long long)m, (long long)n, k);
+  if (k > 0 && (!U || !sigma || !V)) return fail(AMM_EINVAL, "NULL factor");
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_dec* d = new amm_dec();
+  d->kind = AMM_TSVD;
+  d->m = m;
+  d->n = n;
+  d->K = d->K_eff = k;
+  d->device = ctx->device;
+  d->A_borrowed = A;
+  const int64_t kk = std::max(k, 1);
+  std::vector<float> hU(m * kk, 0.f), hUS(m * kk, 0.f), hV(n * kk, 0.f), hVS(n * kk, 0.f), hs(kk, 0.f);
+  double s2 = 0.0;
+  for (int j = 0; j < k; ++j) { hs[j] = (float)sigma[j]; s2 += sigma[j] * sigma[j]; }
+  for (int64_t i = 0; i < m; ++i)
+    for (int j = 0; j < k; ++j) {
+      hU[i * k + j] = (float)U[i * k + j];
+      hUS[i * k + j] = (float)(U[i * k + j] * sigma[j]);
+    }
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < k; ++j) {
+      hV[i * k + j] = (float)V[i * k + j];
+      hVS[i * k + j] = (float)(V[i * k + j] * sigma[j]);
+    }
+  amm_status st;
+  std::vector<float> hVSt(n * kk, 0.f);
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < k; ++j) hVSt[(int64_t)j * n + i] = hVS[i * k + j];
+  if ((st = d->U.alloc(hU.size() * 4)) != AMM_OK || (st = d->US.alloc(hUS.size() * 4)) != AMM_OK ||
+      (st = d->V.alloc(hV.size() * 4)) != AMM_OK || (st = d->VS.alloc(hVS.size() * 4)) != AMM_OK ||
+      (st = d->VSt.alloc(hVSt.size() * 4)) != AMM_OK || (st = d->sigma.alloc(hs.size() * 4)) != AMM_OK) {
+    delete d;
+    return st;
+  }
+  hipError_t e = hipMemcpy(d->U.ptr, hU.data(), hU.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->US.ptr, hUS.data(), hUS.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->V.ptr, hV.data(), hV.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->VS.ptr, hVS.data(), hVS.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->VSt.ptr, hVSt.data(), hVSt.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->sigma.ptr, hs.data(), hs.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete d;
+    return hip_fail(e, "import tsvd");
+  }
+  d->norm_A = 0.0;
+  d->norm_residual = 0.0;
+  (void)s2;
+  *out = d;
+  return AMM_OK;
+}
+
+amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                                 const int32_t* row_ptr, const int32_t* col, const float* val,
+                                 amm_dec* residue, const float* A, amm_dec** out) {
+  if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (m <= 0 || n <= 0 || nnz < 0 || nnz > m * n) return fail(AMM_ESHAPE, "bad sparse shape");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(AMM_EINVAL, "NULL CSR array");
+  if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(AMM_EINVAL, "row_ptr does not span [0, nnz]");
+  for (int64_t i = 0; i < m; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return fail(AMM_EINVAL, "row_ptr not monotone");
+  for (int64_t e = 0; e < nnz; ++e)
+    if (col[e] < 0 || col[e] >= n) return fail(AMM_EINVAL, "column index out of range");
+  if (residue && (residue->m != m || residue->n != n)) return fail(AMM_ESHAPE, "residue shape differs");
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_dec* d = new amm_dec();
+  d->kind = AMM_SPARSE | (residue ? residue->kind : 0);
+  d->m = m;
+  d->n = n;
+  d->nnz = nnz;
+  d->device = ctx->device;
+  d->A_borrowed = A;
+  amm_status st;
+  if ((st = d->row_ptr.alloc((m + 1) * 4)) != AMM_OK || (st = d->col.alloc(std::max<int64_t>(nnz, 1) * 4)) != AMM_OK ||
+      (st = d->val.alloc(std::max<int64_t>(nnz, 1) * 4)) != AMM_OK) {
+    delete d;
+    return st;
+  }
+  hipError_t e = hipMemcpy(d->row_ptr.ptr, row_ptr, (m + 1) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz) e = hipMemcpy(d->col.ptr, col, nnz * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz) e = hipMemcpy(d->val.ptr, val, nnz * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete d;
+    return hip_fail(e, "import sparse");
+  }
+  if ((st = build_csc(d)) != AMM_OK) {
+    delete d;
+    return st;
+  }
+  d->inner = residue;
+  if (residue) d->K = d->K_eff = residue->K_eff;
+  *out = d;
+  return AMM_OK;
+}
+
+amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int kind, int K,
+                         const amm_opts* opts, void* stream, amm_dec** out) {
+  if (!ctx || !A || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (m <= 0 || n <= 0) return fail(AMM_ESHAPE, "empty operand");
+  amm_opts o;
+  amm_opts_default(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  TimerScope ts(ctx);
+  AMM_HIP(hipSetDevice(ctx->device));
+  const int base = kind & ~AMM_SPARSE;
+  if (kind & AMM_SPARSE) {
+    if (base != 0 && base != AMM_CIRCULANT && base != AMM_TSVD) return fail(AMM_EINVAL, "bad kind %d", kind);
+    int64_t nnz = o.sparse_nnz >= 0 ? o.sparse_nnz : (int64_t)llround(o.sparse_frac * (double)m * (double)n);
+    if (nnz < 0 || nnz > m * n) return fail(AMM_EINVAL, "sparse count %lld out of range", (long long)nnz);
+    amm_dec* d = new amm_dec();
+    d->kind = kind;
+    d->m = m;
+    d->n = n;
+    d->K = K;
+    d->device = ctx->device;
+    DevBuf R;
+    amm_status st = R.alloc(m * n * sizeof(float));
+    if (st == AMM_OK) st = sparse_extract(ctx, A, m, n, nnz, d, R.as<float>(), s);
+    if (st == AMM_OK && base != 0) {
+      amm_dec* in = nullptr;
+      st = amm_decompose(ctx, R.as<float>(), m, n, base, K, &o, stream, &in);
+      if (st == AMM_OK) {
+        d->inner = in;
+        d->K_eff = in->K_eff;
+        // a borrowed residue A of the inner SVD would dangle: materialise Delta A
+        if (o.keep_residual && is_tsvd(in)) {
+          const float* dr = nullptr;
+          in->A_borrowed = R.as<float>();
+          st = residual_of(ctx, in, &dr, s);
+          if (st == AMM_OK) st = d->residual.alloc(m * n * sizeof(float));
+          if (st == AMM_OK && hipMemcpyAsync(d->residual.ptr, dr, m * n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            st = fail(AMM_EDEVICE, "copy residual");
+          in->A_borrowed = nullptr;
+        }
+      }
+    } else if (st == AMM_OK && o.keep_residual) {
+      d->residual = std::move(R);
+    }
+    if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "sync");
+    if (st != AMM_OK) {
+      delete d;
+      return st;
+    }
+    *out = d;
+    return AMM_OK;
+  }
+  if (kind == AMM_CIRCULANT) {
+    if (m != n) return fail(AMM_ESHAPE, "circulant decomposition needs a square operand");
+    const int l2 = log2_exact(n);
+    if (l2 < 1 || l2 > 12) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 4096]");
+    if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
+    amm_dec* d = new amm_dec();
+    d->kind = AMM_CIRCULANT;
+    d->m = d->n = n;
+    d->K = K;
+    d->device = ctx->device;
+    amm_status st = cd_decompose(ctx, A, l2, K, o.keep_residual != 0, d, s);
+    if (st != AMM_OK) {
+      delete d;
+      return st;
+    }
+    *out = d;
+    return AMM_OK;
+  }
+  if (kind == AMM_TSVD) {
+    if (K < 0 || K > std::min(m, n)) return fail(AMM_EINVAL, "rank %d out of range", K);
+    amm_dec* d = new amm_dec();
+    d->kind = AMM_TSVD;
+    d->m = m;
+    d->n = n;
+    d->K = K;
+    d->device = ctx->device;
+    amm_status st = tsvd_decompose(ctx, A, m, n, K, &o, d, s);
+    if (st != AMM_OK) {
+      delete d;
+      return st;
+    }
+    if (o.keep_residual) d->A_borrowed = A;
+    *out = d;
+    return AMM_OK;
+  }
+  return fail(AMM_EINVAL, "bad kind %d", kind);
+}
+
+amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
+                             int64_t n, int64_t p, float* out, void* stream) {
+  if (!ctx || !dA || !B || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (n != dA->n) return fail(AMM_ESHAPE, "B has %lld rows, A has %lld columns", (long long)n, (long long)dA->n);
+  if (p <= 0) return fail(AMM_ESHAPE, "B has no columns");
+  if (dB && (dB->m != n || dB->n != p)) return fail(AMM_ESHAPE, "dB describes a %lldx%lld operand, B is %lldx%lld",
+                                                    (long long)dB->m, (long long)dB->n, (long long)n, (long long)p);
+  if (B == out) return fail(AMM_EINVAL, "out aliases B");
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  if (dB) {
+    // validate the residual source before any launch
+    if (!(is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed)) {
+      bool ok = dA->residual.ptr || (is_tsvd(dA) && dA->A_borrowed) ||
+                (is_sparse(dA) && dA->inner && (dA->inner->residual.ptr || dA->inner->A_borrowed));
+      if (!ok) return fail(AMM_ESTATE, "left operand keeps no Delta A (decompose with keep_residual or pass A)");
+    }
+  }
+  TimerScope ts(ctx);
+  if (!dB) return left_apply(ctx, dA, B, p, out, false, s);
+  if (is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed) {
+    // M1 = U_A S_A (V_A^T B) + (A U_B - U_A S_A (V_A^T U_B)) S_B V_B^T
+    //    = [U_A S_A | H] [V_A^T B ; S_B V_B^T]   -- one output GEMM, no Delta A
+    const int ka = dA->K_eff, kb = dB->K_eff, kc = ka + kb;
+    const int64_t m = dA->m;
+    if (kc == 0) return fill_f32(out, m * p, 0.f, s);
+    AMM_TRY(ctx->scratch[0].reserve((size_t)kc * p * sizeof(float)));
+    AMM_TRY(ctx->scratch[1].reserve((size_t)m * kc * sizeof(float)));
+    AMM_TRY(ctx->scratch[3].reserve((size_t)std::max(ka, 1) * std::max(kb, 1) * sizeof(float)));
+    float* Gc = ctx->scratch[0].as<float>();   // kc x p
+    float* Uc = ctx->scratch[1].as<float>();   // m x kc
+    float* Sm = ctx->scratch[3].as<float>();   // ka x kb
+    if (ka > 0) {
+      AMM_TRY(gemm_f32(ka, p, n, 1.f, MatView{dA->V.as<float>(), 1, ka}, MatView{B, p, 1}, 0.f, Gc, p, s, "gemm_VtB"));
+      AMM_HIP(hipMemcpy2DAsync(Uc, kc * sizeof(float), dA->US.ptr, ka * sizeof(float), ka * sizeof(float), m,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    if (kb > 0) {
+      AMM_HIP(hipMemcpyAsync(Gc + (int64_t)ka * p, dB->VSt.ptr, (size_t)kb * p * sizeof(float),
+                             hipMemcpyDeviceToDevice, s));
+      AMM_TRY(gemm_f32(m, kb, n, 1.f, MatView{dA->A_borrowed, n, 1}, MatView{dB->U.as<float>(), kb, 1}, 0.f,
+                       Uc + ka, kc, s, "gemm_AU"));
+      if (ka > 0) {
+        AMM_TRY(gemm_f32(ka, kb, n, 1.f, MatView{dA->V.as<float>(), 1, ka}, MatView{dB->U.as<float>(), kb, 1}, 0.f,
+                         Sm, kb, s, "gemm_small"));
+        AMM_TRY(gemm_f32(m, kb, ka, -1.f, MatView{dA->US.as<float>(), ka, 1}, MatView{Sm, kb, 1}, 1.f, Uc + ka, kc,
+                         s, "gemm_small"));
+      }
+    }
+    return gemm_f32(m, p, kc, 1.f, MatView{Uc, kc, 1}, MatView{Gc, p, 1}, 0.f, out, p, s, "gemm_out");
+  }
+  AMM_TRY(left_apply(ctx, dA, B, p, out, false, s));
+  const float* dAres = nullptr;
+  AMM_TRY(residual_of(ctx, dA, &dAres, s));
+  return right_apply(ctx, dAres, dA->m, dB, out, true, s);
+}
+
+}  // extern "C"

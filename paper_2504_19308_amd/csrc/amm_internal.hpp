@@ -1,0 +1,183 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "amm.h"
+
+namespace amm {
+
+// ---- error reporting -------------------------------------------------------
+amm_status fail(amm_status st, const char* fmt, ...);
+amm_status hip_fail(hipError_t e, const char* what);
+
+#define AMM_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return amm::hip_fail(e_, #call); \
+  } while (0)
+
+#define AMM_TRY(call)                    \
+  do {                                   \
+    amm_status s_ = (call);              \
+    if (s_ != AMM_OK) return s_;         \
+  } while (0)
+
+// ---- device buffers ---------------------------------------------------------
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  amm_status alloc(size_t b);          // exact-size allocation (frees old)
+  amm_status reserve(size_t b);        // grow-only
+  template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// ---- optional per-launch timing ---------------------------------------------
+// When a context has timing enabled, every kernel launch made on its behalf is
+// bracketed by hipEventRecord on the launch stream; amm_ctx_timings() resolves
+// the events and reports the total and count per kernel name.
+struct KernelTimer {
+  struct Pending { const char* name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, long>> totals;  // ms, launches
+};
+extern thread_local KernelTimer* g_timer;
+
+struct TimedLaunch {
+  hipEvent_t b_ = nullptr;
+  hipStream_t s_;
+  const char* name_;
+  TimedLaunch(const char* name, hipStream_t s) : s_(s), name_(name) {
+    if (!g_timer) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b_) != hipSuccess) { (void)hipEventDestroy(a); b_ = nullptr; return; }
+    (void)hipEventRecord(a, s_);
+    g_timer->pending.push_back({name_, a, b_});
+  }
+  ~TimedLaunch() {
+    if (b_) (void)hipEventRecord(b_, s_);
+  }
+};
+
+}  // namespace amm
+
+struct amm_ctx {
+  int device = 0;
+  std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
+  std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
+  amm::DevBuf scratch[6];              // grow-only work areas for products
+  amm::KernelTimer timer;
+  bool timing = false;
+};
+
+struct amm_dec {
+  int kind = 0;
+  int64_t m = 0, n = 0;
+  int K = 0;
+  int K_eff = 0;
+  double norm_A = 0.0;
+  double norm_residual = 0.0;
+  int device = 0;
+
+  // circulant (n x n): kept frequencies, float32 eigenvalue lists and the
+  // adjoint lists  Ladj_t[p] = conj(L_t[(p + k_t) mod n]) with shift -k_t.
+  std::vector<int32_t> freqs;
+  amm::DevBuf shifts;      // K_eff int32: k_t
+  amm::DevBuf shifts_adj;  // K_eff int32: (n - k_t) mod n
+  amm::DevBuf L;           // K_eff x n float2
+  amm::DevBuf Ladj;        // K_eff x n float2
+  amm::DevBuf energies;    // n double (decompose only)
+  bool has_energies = false;
+
+  // SVD: U m x k, V n x k, sigma k (float32), US = U diag(sigma), VS = V diag(sigma),
+  // VSt = (V diag(sigma))^T  (k x n, for the fused first-order output GEMM)
+  amm::DevBuf U, V, sigma, US, VS, VSt;
+
+  // sparse part: CSR (row_ptr m+1, col, val) and its transpose as CSC
+  // (csc_ptr n+1, csc_row, csc_val) for products with S on the right
+  int64_t nnz = 0;
+  amm::DevBuf row_ptr, col, val;
+  amm::DevBuf csc_ptr, csc_row, csc_val;
+  amm_dec* inner = nullptr;
+
+  // Delta A: owned (circulant) or borrowed A (SVD / sparse)
+  amm::DevBuf residual;        // m x n float32, owned
+  const float* A_borrowed = nullptr;
+
+  ~amm_dec();
+};
+
+namespace amm {
+
+// ---- kernel launchers (defined in the .hip files) ---------------------------
+amm_status twiddles32(amm_ctx* ctx, int log2n, const float2** out);
+amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
+
+// Circulant product through the fused LDS FFT kernel.
+//  column mode: out (n x p) [+]= Atil B, B (n x p) row-major, along columns.
+//  row mode:    out (rows x n) [+]= X Btil^T-side operator applied to each
+//               row of X (rows x n):  out_row = (op(row^T))^T.
+amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
+                            const float2* L, const float* B, int64_t p, float* out,
+                            bool accumulate, hipStream_t s);
+amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
+                         const float2* L, const float* X, int64_t rows, float* out,
+                         bool accumulate, hipStream_t s);
+
+// Circulant decomposition, float64 on the device.
+amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
+                        bool keep_residual, amm_dec* dec, hipStream_t s);
+
+// Closed-set frequency selection (host), same reading as documented in amm.h.
+std::vector<int32_t> select_closed(const std::vector<double>& E, int K);
+
+// Dense float32 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C, with
+// general element strides (row-major or transposed views).
+struct MatView {
+  const float* p;
+  int64_t rs, cs;  // element (i, j) at p[i*rs + j*cs]
+};
+amm_status gemm_f32(int64_t M, int64_t N, int64_t Kd, float alpha, MatView A, MatView B,
+                    float beta, float* C, int64_t ldc, hipStream_t s, const char* tag = "gemm_f32");
+amm_status gemm_f64(int64_t M, int64_t N, int64_t Kd, double alpha, const double* A,
+                    int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs,
+                    int64_t b_cs, double beta, double* C, int64_t ldc, hipStream_t s);
+
+// SVD path
+amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
+                          const amm_opts* o, amm_dec* dec, hipStream_t s);
+
+// Sparse path
+amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
+                          amm_dec* dec, float* R_out, hipStream_t s);
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool accumulate,
+                    hipStream_t s);
+amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out,
+                           bool accumulate, hipStream_t s);
+
+amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);
+amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);
+// Build the CSC copy of a CSR part held on the device (host transpose).
+amm_status build_csc(amm_dec* d);
+
+}  // namespace amm

@@ -1,0 +1,252 @@
+// Circulant-component product, fused in one kernel per column tile.
+//
+// Alg. 2.3 step 5 with the shift trick of Sec. 2.3.2:
+//   Atil b = F^-1 ( sum_t  diag(L_t) C^{k_t} F b ),   (C^k X)[p] = X[(p-k) mod n],
+// so each operand column needs one forward FFT, K complex multiply-adds per
+// frequency bin and one inverse FFT.  Atil is real (frequency set closed
+// under k -> n-k), hence complex-linear on complex vectors: two real columns
+// b1, b2 are packed as b1 + i b2, transformed together, and the real and
+// imaginary parts of the result are Atil b1 and Atil b2.
+//
+// One workgroup owns C packed columns (2C real columns) and keeps their whole
+// spectra in LDS (layout [bin][col], one padding slot per 16 bins):
+//   load tile -> forward Stockham stages -> shifted MAC into registers ->
+//   inverse stages -> store (1/n folded in).
+// Row mode is the same pipeline applied to pairs of rows of X, used for the
+// first-order term  Delta A Btil = (Btil^T Delta A^T)^T, whose operator is the
+// adjoint list (conj L_t[p + k_t], shift -k_t).
+#include "amm_internal.hpp"
+#include "fft_core.hpp"
+
+namespace amm {
+namespace {
+
+template <int LOG2N> struct CdCfg {
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int C = LOG2N <= 10 ? 16 : (LOG2N == 11 ? 8 : 4);   // packed columns
+  static constexpr int T = LOG2N <= 8 ? 256 : (LOG2N == 9 ? 512 : 1024);  // threads
+  static constexpr int CPL = 4;                                         // cols per MAC lane
+  static constexpr int G = C / CPL;
+  static constexpr int BL = T / G;                                      // MAC bin lanes
+  static constexpr int NBINS = (N + BL - 1) / BL;
+  static constexpr int LDS_SLOTS = (N + N / 16 + 1) * C;
+};
+
+__device__ __forceinline__ int pad_bin(int bin) { return bin + (bin >> 4); }
+
+template <int R, int SIGN, int LOG2N, int Ns>
+__device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict__ tw) {
+  using Cfg = CdCfg<LOG2N>;
+  constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
+  constexpr int NBF = (N / R) * C;
+  constexpr int NB = (NBF + T - 1) / T;
+  float2 v[NB][R];
+  constexpr int twstep = N / (Ns * R);
+  // Opaque copy of the thread index: keeps the compiler from hoisting every
+  // stage's LDS addresses out of the kernel and holding them in registers.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = tid + i * T;
+    if (NBF % T == 0 || b < NBF) {
+      const int col = b % C, j = b / C;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds[pad_bin(j + r * (N / R)) * C + col];
+      if constexpr (Ns > 1) {
+        const unsigned k = (unsigned)j & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[(unsigned)r * k * (unsigned)twstep];
+          if (SIGN > 0) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dftR<R, SIGN>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = tid + i * T;
+    if (NBF % T == 0 || b < NBF) {
+      const int col = b % C, j = b / C;
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[pad_bin(base + r * Ns) * C + col] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int SIGN, int LOG2N, int ST = 0, int Ns = 1>
+__device__ __forceinline__ void lds_fft(float2* lds, const float2* __restrict__ tw) {
+  if constexpr (ST < stage_count(LOG2N)) {
+    constexpr int lr = stage_log2r(LOG2N, ST);
+    lds_stage<(1 << lr), SIGN, LOG2N, Ns>(lds, tw);
+    lds_fft<SIGN, LOG2N, ST + 1, (Ns << lr)>(lds, tw);
+  }
+}
+
+// ROWS = false: tile = real columns [2 C tile, 2 C tile + 2C) of an N x p matrix.
+// ROWS = true:  tile = real rows [2 C tile, ...) of a rows x N matrix.
+template <int LOG2N, bool ROWS>
+__global__ void __launch_bounds__(CdCfg<LOG2N>::T)
+cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
+                int K, const int32_t* __restrict__ shifts, const float2* __restrict__ L,
+                const float2* __restrict__ tw, int accumulate) {
+  using Cfg = CdCfg<LOG2N>;
+  constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
+  __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
+  float* ldsf = reinterpret_cast<float*>(lds);
+
+  // XCD-aware tile order: consecutive tiles land on the same XCD so that the
+  // row segments they share stay in one L2.
+  const int nblk = gridDim.x;
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int per = (nblk + 7) / 8;
+  int tile = xcd * per + slot;
+  if ((nblk & 7) != 0) tile = blockIdx.x;   // only remap when it is a bijection
+  const int64_t first = (int64_t)tile * 2 * C;  // first real column / row
+
+  // ---- load -----------------------------------------------------------------
+  if (!ROWS) {
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int rc = e % (2 * C), row = e / (2 * C);
+      const int64_t c = first + rc;
+      ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * extent + c] : 0.f;
+    }
+  } else {
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int q = e % N, rl = e / N;
+      const int64_t r = first + rl;
+      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = r < extent ? X[r * N + q] : 0.f;
+    }
+  }
+  __syncthreads();
+
+  lds_fft<-1, LOG2N>(lds, tw);
+
+  // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
+  constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL, NBINS = Cfg::NBINS;
+  const int cg = threadIdx.x % G, bl = threadIdx.x / G;
+  float2 acc[NBINS][CPL];
+#pragma unroll
+  for (int i = 0; i < NBINS; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[i][c] = float2{0.f, 0.f};
+
+  for (int t = 0; t < K; ++t) {
+    const int k = shifts[t];
+    const float2* __restrict__ Lt = L + (int64_t)t * N;
+#pragma unroll
+    for (int i = 0; i < NBINS; ++i) {
+      const int p = bl + i * BL;
+      if (N % BL == 0 || p < N) {
+        const float2 l = Lt[p];
+        const int q = (p - k) & (N - 1);
+        const float4* src = reinterpret_cast<const float4*>(&lds[pad_bin(q) * C + cg * CPL]);
+        const float4 x01 = src[0], x23 = src[1];
+        acc[i][0].x += l.x * x01.x - l.y * x01.y;
+        acc[i][0].y += l.x * x01.y + l.y * x01.x;
+        acc[i][1].x += l.x * x01.z - l.y * x01.w;
+        acc[i][1].y += l.x * x01.w + l.y * x01.z;
+        acc[i][2].x += l.x * x23.x - l.y * x23.y;
+        acc[i][2].y += l.x * x23.y + l.y * x23.x;
+        acc[i][3].x += l.x * x23.z - l.y * x23.w;
+        acc[i][3].y += l.x * x23.w + l.y * x23.z;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NBINS; ++i) {
+    const int p = bl + i * BL;
+    if (N % BL == 0 || p < N) {
+      float4* dst = reinterpret_cast<float4*>(&lds[pad_bin(p) * C + cg * CPL]);
+      dst[0] = float4{acc[i][0].x, acc[i][0].y, acc[i][1].x, acc[i][1].y};
+      dst[1] = float4{acc[i][2].x, acc[i][2].y, acc[i][3].x, acc[i][3].y};
+    }
+  }
+  __syncthreads();
+
+  lds_fft<+1, LOG2N>(lds, tw);
+
+  // ---- store ----------------------------------------------------------------
+  const float scale = 1.0f / (float)N;
+  if (!ROWS) {
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int rc = e % (2 * C), row = e / (2 * C);
+      const int64_t c = first + rc;
+      if (c < extent) {
+        const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * scale;
+        float* o = out + (int64_t)row * extent + c;
+        *o = accumulate ? *o + v : v;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int q = e % N, rl = e / N;
+      const int64_t r = first + rl;
+      if (r < extent) {
+        const float v = ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] * scale;
+        float* o = out + r * N + q;
+        *o = accumulate ? *o + v : v;
+      }
+    }
+  }
+}
+
+template <int LOG2N>
+amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
+                     const int32_t* shifts, const float2* L, const float2* tw, bool acc,
+                     hipStream_t s) {
+  using Cfg = CdCfg<LOG2N>;
+  const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
+  if (tiles == 0) return AMM_OK;
+  if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
+  dim3 grid((unsigned)tiles), block(Cfg::T);
+  TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
+  if (rows)
+    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
+                       shifts, L, tw, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false>), grid, block, 0, s, X, out, extent, K,
+                       shifts, L, tw, acc ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
+                       const int32_t* shifts, const float2* L, const float2* tw, bool acc,
+                       hipStream_t s) {
+  switch (log2n) {
+#define AMM_CASE(L2) \
+  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s);
+    AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
+    AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
+#undef AMM_CASE
+    default: return fail(AMM_EUNSUPPORTED, "circulant product needs 2 <= n <= 4096, n a power of two");
+  }
+}
+
+}  // namespace
+
+amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
+                            const float2* L, const float* B, int64_t p, float* out,
+                            bool accumulate, hipStream_t s) {
+  const float2* tw = nullptr;
+  AMM_TRY(twiddles32(ctx, log2n, &tw));
+  return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s);
+}
+
+amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
+                         const float2* L, const float* X, int64_t rows, float* out,
+                         bool accumulate, hipStream_t s) {
+  const float2* tw = nullptr;
+  AMM_TRY(twiddles32(ctx, log2n, &tw));
+  return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s);
+}
+
+}  // namespace amm

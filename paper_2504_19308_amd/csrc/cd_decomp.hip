@@ -1,0 +1,279 @@
+// Circulant decomposition on the device, float64 (Thm. 1.1, Alg. 2.2,
+// Alg. 2.3 steps 2-4 and step 6's residual).
+//
+// The paper forms the cycle matrix (cycle j in column j, Alg. A.2), takes the
+// DFT of every cycle to get all coefficients r_{j,k} (Alg. 2.2) and then the
+// eigenvalue lists L_k = F r_{.,k} (Alg. 2.3 step 4).  Substituting the cycle
+// index j = (row - col) mod n gives the same numbers from the two-sided
+// transform  Ahat = F A F^-1  (DFT down the columns, inverse DFT along the
+// rows -- the 2-D relation the paper notes in Sec. 2.3.1):
+//     L_k[p] = Ahat[p, (p - k) mod n],
+// i.e. the k-th component lives on the k-th wrapped diagonal of Ahat.  Both
+// transforms then run along contiguous or column-batched directions of the
+// row-major input instead of along the wrapped diagonals that the cycle
+// gather reads.  The component energy is, by Parseval,
+//     ||R_k||_F^2 = n sum_j |r_{j,k}|^2 = sum_p |L_k[p]|^2,
+// the quantity Alg. 2.3 ranks by (its T[k] is the square root of this / n).
+// Removing the kept diagonals of Ahat and transforming back gives
+// Delta A = A - sum_{t} R_{k_t} D^{k_t} (step 6) without the O(K n^2) sum.
+#include <algorithm>
+#include <cmath>
+
+#include "amm_internal.hpp"
+#include "fft_core.hpp"
+
+namespace amm {
+namespace {
+
+__global__ void widen_real(const float* __restrict__ A, double2* __restrict__ Z, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) Z[i] = double2{(double)A[i], 0.0};
+}
+
+__global__ void real_part_f32(const double2* __restrict__ Z, float* __restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (float)Z[i].x;
+}
+
+// One Stockham pass over `batch` complex vectors of length n.  Element e of
+// vector b lives at b*bs + e*es.  batch_fast picks the thread order so that
+// neighbouring threads touch neighbouring addresses (columns: batch index
+// fastest; rows: element index fastest).
+template <int R, int SIGN>
+__global__ void fft64_pass(const double2* __restrict__ in, double2* __restrict__ out, int n,
+                           int Ns, int64_t es, int64_t bs, int64_t batch,
+                           const double2* __restrict__ tw, double scale, int batch_fast) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = n / R;
+  if (gid >= nb * batch) return;
+  int64_t b, j;
+  if (batch_fast) { b = gid % batch; j = gid / batch; }
+  else { j = gid % nb; b = gid / nb; }
+  const double2* src = in + b * bs;
+  double2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[(j + (int64_t)r * nb) * es];
+  const int k = (int)(j & (Ns - 1));
+  if (Ns > 1) {
+    const int step = n / (Ns * R);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      double2 w = tw[(unsigned)(r * k * step)];
+      if (SIGN > 0) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+  }
+  dftR<R, SIGN>(v);
+  double2* dst = out + b * bs;
+  const int64_t base = (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[(base + (int64_t)r * Ns) * es] = cscale(v[r], scale);
+}
+
+// E_part[chunk][k] = sum over rows p of the chunk of |Ahat[p, (p - k) mod n]|^2
+__global__ void energy_partial(const double2* __restrict__ Ahat, int n, int rows_per_chunk,
+                               double* __restrict__ part) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  if (k >= n) return;
+  const int p0 = chunk * rows_per_chunk;
+  const int p1 = min(n, p0 + rows_per_chunk);
+  double s = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    const double2 v = Ahat[(int64_t)p * n + ((p - k) & (n - 1))];
+    s += v.x * v.x + v.y * v.y;
+  }
+  part[(int64_t)chunk * n + k] = s;
+}
+
+__global__ void energy_reduce(const double* __restrict__ part, int chunks, int n,
+                              double* __restrict__ E) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + k];
+  E[k] = s;
+}
+
+// L_t[p] = Ahat[p, (p - k_t) mod n];  Ladj_t[p] = conj(L_t[(p + k_t) mod n])
+__global__ void gather_lists(const double2* __restrict__ Ahat, int n,
+                             const int32_t* __restrict__ shifts, float2* __restrict__ L,
+                             float2* __restrict__ Ladj) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (p >= n) return;
+  const int k = shifts[t];
+  const double2 a = Ahat[(int64_t)p * n + ((p - k) & (n - 1))];
+  L[(int64_t)t * n + p] = float2{(float)a.x, (float)a.y};
+  const double2 b = Ahat[(int64_t)((p + k) & (n - 1)) * n + p];
+  Ladj[(int64_t)t * n + p] = float2{(float)b.x, (float)-b.y};
+}
+
+__global__ void zero_diagonals(double2* __restrict__ Ahat, int n, const int32_t* __restrict__ shifts) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (p >= n) return;
+  Ahat[(int64_t)p * n + ((p - shifts[t]) & (n - 1))] = double2{0.0, 0.0};
+}
+
+template <int SIGN>
+amm_status launch_pass(int log2r, const double2* in, double2* out, int n, int Ns, int64_t es,
+                       int64_t bs, int64_t batch, const double2* tw, double scale,
+                       bool batch_fast, hipStream_t s) {
+  const int R = 1 << log2r;
+  const int64_t threads = (int64_t)(n / R) * batch;
+  dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+  const int bf = batch_fast ? 1 : 0;
+  switch (R) {
+    case 16: hipLaunchKernelGGL((fft64_pass<16, SIGN>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, bf); break;
+    case 8: hipLaunchKernelGGL((fft64_pass<8, SIGN>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, bf); break;
+    case 4: hipLaunchKernelGGL((fft64_pass<4, SIGN>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, bf); break;
+    case 2: hipLaunchKernelGGL((fft64_pass<2, SIGN>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, bf); break;
+    default: return fail(AMM_EUNSUPPORTED, "bad radix");
+  }
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+// Transform all n vectors of the n x n array in `cur` along one axis; result
+// ends in `cur` (buffers are swapped as needed).  columns: vectors run down
+// the columns.  sign -1 forward; `scale` multiplies the final pass.
+amm_status transform_axis(double2*& cur, double2*& tmp, int log2n, bool columns, int sign,
+                          double scale, const double2* tw, hipStream_t s) {
+  const int n = 1 << log2n;
+  const int64_t es = columns ? n : 1, bs = columns ? 1 : n;
+  int Ns = 1;
+  const int stages = stage_count(log2n);
+  for (int st = 0; st < stages; ++st) {
+    const int lr = stage_log2r(log2n, st);
+    const double sc = (st == stages - 1) ? scale : 1.0;
+    if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, n, tw, sc, columns, s));
+    else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, n, tw, sc, columns, s));
+    std::swap(cur, tmp);
+    Ns <<= lr;
+  }
+  return AMM_OK;
+}
+
+}  // namespace
+
+std::vector<int32_t> select_closed(const std::vector<double>& E, int K) {
+  // Among frequency sets closed under k -> n-k with at most K members, keep
+  // the one with the largest total energy.  Singleton classes are {0} and
+  // {n/2}; every other class is a pair, so for each subset of singletons the
+  // best completion is the top pairs by E[k] + E[n-k] (ties: smaller k).
+  const int n = (int)E.size();
+  std::vector<int> singles{0};
+  if (n % 2 == 0 && n > 1) singles.push_back(n / 2);
+  std::vector<int> pairs;
+  for (int k = 1; k < (n + 1) / 2; ++k) pairs.push_back(k);
+  std::stable_sort(pairs.begin(), pairs.end(), [&](int a, int b) {
+    const double ea = E[a] + E[n - a], eb = E[b] + E[n - b];
+    if (ea != eb) return ea > eb;
+    return a < b;
+  });
+  std::vector<std::vector<int>> subsets{{}};
+  for (int sgl : singles) subsets.push_back({sgl});
+  if (singles.size() == 2) subsets.push_back(singles);
+  bool have = false;
+  double best_total = 0.0;
+  size_t best_size = 0;
+  std::vector<int32_t> best;
+  for (const auto& U : subsets) {
+    if ((int)U.size() > K) continue;
+    std::vector<int32_t> members(U.begin(), U.end());
+    const int np = (K - (int)U.size()) / 2;
+    for (int i = 0; i < np && i < (int)pairs.size(); ++i) {
+      members.push_back(pairs[i]);
+      members.push_back(n - pairs[i]);
+    }
+    double total = 0.0;
+    for (int m : members) total += E[m];
+    if (!have || total > best_total || (total == best_total && members.size() > best_size)) {
+      have = true;
+      best_total = total;
+      best_size = members.size();
+      best = members;
+    }
+  }
+  std::sort(best.begin(), best.end());
+  return best;
+}
+
+amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool keep_residual,
+                        amm_dec* dec, hipStream_t s) {
+  const int n = 1 << log2n;
+  const int64_t nn = (int64_t)n * n;
+  const double2* tw = nullptr;
+  AMM_TRY(twiddles64(ctx, log2n, &tw));
+  DevBuf z0, z1;
+  AMM_TRY(z0.alloc(nn * sizeof(double2)));
+  AMM_TRY(z1.alloc(nn * sizeof(double2)));
+  double2* cur = z0.as<double2>();
+  double2* tmp = z1.as<double2>();
+  hipLaunchKernelGGL(widen_real, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, cur, nn);
+  AMM_HIP(hipGetLastError());
+  AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/true, -1, 1.0, tw, s));
+  AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/false, +1, 1.0 / n, tw, s));
+
+  // energies ||R_k||_F^2
+  const int rows_per_chunk = 64;
+  const int chunks = (n + rows_per_chunk - 1) / rows_per_chunk;
+  DevBuf part;
+  AMM_TRY(part.alloc((size_t)chunks * n * sizeof(double)));
+  AMM_TRY(dec->energies.alloc((size_t)n * sizeof(double)));
+  hipLaunchKernelGGL(energy_partial, dim3((unsigned)((n + 255) / 256), (unsigned)chunks), dim3(256), 0, s,
+                     cur, n, rows_per_chunk, part.as<double>());
+  hipLaunchKernelGGL(energy_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     part.as<double>(), chunks, n, dec->energies.as<double>());
+  AMM_HIP(hipGetLastError());
+  std::vector<double> E(n);
+  AMM_HIP(hipMemcpyAsync(E.data(), dec->energies.ptr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  dec->has_energies = true;
+
+  // selection (Alg. 2.3 steps 2-3, closed under conjugate pairs)
+  dec->freqs = select_closed(E, K);
+  dec->K_eff = (int)dec->freqs.size();
+  double total = 0.0, kept = 0.0;
+  for (int k = 0; k < n; ++k) total += E[k];
+  for (int k : dec->freqs) kept += E[k];
+  dec->norm_A = std::sqrt(std::max(total, 0.0));
+  dec->norm_residual = std::sqrt(std::max(total - kept, 0.0));
+
+  const int Ke = dec->K_eff;
+  std::vector<int32_t> adj(Ke);
+  for (int t = 0; t < Ke; ++t) adj[t] = (n - dec->freqs[t]) & (n - 1);
+  const size_t kb = (size_t)std::max(Ke, 1) * sizeof(int32_t);
+  AMM_TRY(dec->shifts.alloc(kb));
+  AMM_TRY(dec->shifts_adj.alloc(kb));
+  AMM_TRY(dec->L.alloc((size_t)std::max(Ke, 1) * n * sizeof(float2)));
+  AMM_TRY(dec->Ladj.alloc((size_t)std::max(Ke, 1) * n * sizeof(float2)));
+  if (Ke > 0) {
+    AMM_HIP(hipMemcpyAsync(dec->shifts.ptr, dec->freqs.data(), Ke * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    AMM_HIP(hipMemcpyAsync(dec->shifts_adj.ptr, adj.data(), Ke * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(gather_lists, dim3((unsigned)((n + 255) / 256), (unsigned)Ke), dim3(256), 0, s,
+                       cur, n, dec->shifts.as<int32_t>(), dec->L.as<float2>(), dec->Ladj.as<float2>());
+    AMM_HIP(hipGetLastError());
+  }
+
+  if (keep_residual) {
+    // Delta A = F^-1 (Ahat with the kept diagonals removed) F
+    if (Ke > 0) {
+      hipLaunchKernelGGL(zero_diagonals, dim3((unsigned)((n + 255) / 256), (unsigned)Ke), dim3(256), 0, s,
+                         cur, n, dec->shifts.as<int32_t>());
+      AMM_HIP(hipGetLastError());
+    }
+    AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/false, -1, 1.0, tw, s));
+    AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/true, +1, 1.0 / n, tw, s));
+    AMM_TRY(dec->residual.alloc(nn * sizeof(float)));
+    hipLaunchKernelGGL(real_part_f32, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, cur,
+                       dec->residual.as<float>(), nn);
+    AMM_HIP(hipGetLastError());
+  }
+  // the temporaries are released on return; make sure no kernel still uses them
+  AMM_HIP(hipStreamSynchronize(s));
+  return AMM_OK;
+}
+
+}  // namespace amm

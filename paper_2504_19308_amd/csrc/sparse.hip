@@ -1,0 +1,325 @@
+// Dominant-entry sparsification and the sparse products (eq. (2.4) of the
+// paper, abstract; Sec. 2.4 "may require exploitation of sparse data
+// structures").
+//
+// Reading: S keeps the nnz entries of largest |a| (ties to the smaller
+// row-major index), stored as CSR; R = A - S is the dense residue.
+//
+// Extraction is a radix select on the IEEE bit pattern of |a| (for finite
+// floats the order of |a| equals the unsigned order of (bits & 0x7fffffff)):
+// four 8-bit digit passes from the top narrow down the threshold key T with
+//   #{key > T} < nnz <= #{key >= T},
+// the entries with key == T are then taken in row-major order until nnz is
+// reached.  A per-row pass writes CSR rows (column order) and R.
+#include <algorithm>
+#include <vector>
+
+#include "amm_internal.hpp"
+
+namespace amm {
+namespace {
+
+__device__ __forceinline__ uint32_t key_of(float a) { return __float_as_uint(a) & 0x7fffffffu; }
+
+// histogram of digit `shift` among keys whose bits above the digit equal prefix
+__global__ void radix_hist(const float* __restrict__ A, int64_t count, uint32_t prefix,
+                           uint32_t hi_mask, int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const uint32_t k = key_of(A[i]);
+    if ((k & hi_mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// per-row counts of key > T and key == T
+__global__ void row_counts(const float* __restrict__ A, int64_t n, uint32_t T,
+                           int32_t* __restrict__ gt, int32_t* __restrict__ eq) {
+  const int64_t row = blockIdx.x;
+  const float* a = A + row * n;
+  int cg = 0, ce = 0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const uint32_t k = key_of(a[j]);
+    cg += k > T;
+    ce += k == T;
+  }
+  __shared__ int sg[256], se[256];
+  sg[threadIdx.x] = cg;
+  se[threadIdx.x] = ce;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      sg[threadIdx.x] += sg[threadIdx.x + off];
+      se[threadIdx.x] += se[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    gt[row] = sg[0];
+    eq[row] = se[0];
+  }
+}
+
+// Block-wide exclusive scan of 0/1 flags (256 threads, 4 waves of 64).
+__device__ __forceinline__ int block_excl_scan(int flag, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + in_wave;
+}
+
+// One block per row: write the kept entries (column order) and R = A - S.
+__global__ void __launch_bounds__(256)
+fill_rows(const float* __restrict__ A, int64_t n, uint32_t T, const int32_t* __restrict__ take_eq,
+          const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col, float* __restrict__ val,
+          float* __restrict__ R) {
+  __shared__ int wsum[4];
+  const int64_t row = blockIdx.x;
+  const float* a = A + row * n;
+  float* r = R + row * n;
+  int eq_seen = 0, out_pos = row_ptr[row];
+  const int eq_cap = take_eq[row];
+  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    float v = 0.f;
+    uint32_t k = 0;
+    if (j < n) {
+      v = a[j];
+      k = key_of(v);
+    }
+    const int is_eq = (j < n) && (k == T);
+    int eq_tot;
+    const int eq_rank = eq_seen + block_excl_scan(is_eq, wsum, &eq_tot);
+    const int keep = (j < n) && (k > T || (is_eq && eq_rank < eq_cap));
+    int keep_tot;
+    const int pos = out_pos + block_excl_scan(keep, wsum, &keep_tot);
+    if (keep) {
+      col[pos] = (int32_t)j;
+      val[pos] = v;
+    }
+    if (j < n) r[j] = keep ? 0.f : v;
+    eq_seen += eq_tot;
+    out_pos += keep_tot;
+  }
+}
+
+// out[i, :] (+)= sum_e val[e] B[col[e], :]; one block per row, 4 columns a thread.
+__global__ void __launch_bounds__(256)
+spmm_rows(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+          const float* __restrict__ val, const float* __restrict__ B, int64_t p,
+          float* __restrict__ out, int accumulate) {
+  const int64_t row = blockIdx.y;
+  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (c0 >= p) return;
+  const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const bool full = (c0 + 4 <= p) && ((p & 3) == 0);
+  for (int e = e0; e < e1; ++e) {
+    const float v = val[e];
+    const float* b = B + (int64_t)col[e] * p + c0;
+    if (full) {
+      const float4 x = *reinterpret_cast<const float4*>(b);
+      acc[0] += v * x.x; acc[1] += v * x.y; acc[2] += v * x.z; acc[3] += v * x.w;
+    } else {
+      for (int q = 0; q < 4 && c0 + q < p; ++q) acc[q] += v * b[q];
+    }
+  }
+  float* o = out + row * p + c0;
+  for (int q = 0; q < 4 && c0 + q < p; ++q) o[q] = accumulate ? o[q] + acc[q] : acc[q];
+}
+
+// out[r, c] (+)= sum over column c of S of X[r, j] S[j, c]; one block per row
+// r with X's row staged in LDS, threads over output columns.
+__global__ void __launch_bounds__(256)
+dense_csc_rows(const float* __restrict__ X, int64_t n, const int32_t* __restrict__ csc_ptr,
+               const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val,
+               int64_t p, float* __restrict__ out, int accumulate) {
+  extern __shared__ float xrow[];
+  const int64_t r = blockIdx.x;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) xrow[j] = X[r * n + j];
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < p; c += blockDim.x) {
+    float acc = 0.f;
+    for (int e = csc_ptr[c]; e < csc_ptr[c + 1]; ++e) acc += xrow[csc_row[e]] * csc_val[e];
+    float* o = out + r * p + c;
+    *o = accumulate ? *o + acc : acc;
+  }
+}
+
+__global__ void fill_kernel(float* __restrict__ p, int64_t count, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+__global__ void transpose_kernel(const float* __restrict__ src, int64_t rows, int64_t cols,
+                                 float* __restrict__ dst) {
+  __shared__ float tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[i][threadIdx.x] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) dst[c * rows + r] = tile[threadIdx.x][i];
+  }
+}
+
+amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return AMM_OK;
+  if ((rows + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "transpose too tall");
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
+                     dim3(32, 8), 0, s, src, rows, cols, dst);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s) {
+  if (count <= 0) return AMM_OK;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status build_csc(amm_dec* d) {
+  const int64_t m = d->m, n = d->n, nnz = d->nnz;
+  std::vector<int32_t> rp(m + 1), cl(std::max<int64_t>(nnz, 1));
+  std::vector<float> vl(std::max<int64_t>(nnz, 1));
+  AMM_HIP(hipMemcpy(rp.data(), d->row_ptr.ptr, (m + 1) * 4, hipMemcpyDeviceToHost));
+  if (nnz) {
+    AMM_HIP(hipMemcpy(cl.data(), d->col.ptr, nnz * 4, hipMemcpyDeviceToHost));
+    AMM_HIP(hipMemcpy(vl.data(), d->val.ptr, nnz * 4, hipMemcpyDeviceToHost));
+  }
+  std::vector<int32_t> cp(n + 1, 0), rr(std::max<int64_t>(nnz, 1));
+  std::vector<float> cv(std::max<int64_t>(nnz, 1));
+  for (int64_t e = 0; e < nnz; ++e) cp[cl[e] + 1]++;
+  for (int64_t c = 0; c < n; ++c) cp[c + 1] += cp[c];
+  std::vector<int32_t> fillp(cp.begin(), cp.end() - 1);
+  for (int64_t i = 0; i < m; ++i)
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int32_t at = fillp[cl[e]]++;
+      rr[at] = (int32_t)i;
+      cv[at] = vl[e];
+    }
+  AMM_TRY(d->csc_ptr.alloc((n + 1) * 4));
+  AMM_TRY(d->csc_row.alloc(rr.size() * 4));
+  AMM_TRY(d->csc_val.alloc(cv.size() * 4));
+  AMM_HIP(hipMemcpy(d->csc_ptr.ptr, cp.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(d->csc_row.ptr, rr.data(), rr.size() * 4, hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(d->csc_val.ptr, cv.data(), cv.size() * 4, hipMemcpyHostToDevice));
+  return AMM_OK;
+}
+
+amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
+                          amm_dec* d, float* R, hipStream_t s) {
+  (void)ctx;
+  const int64_t count = m * n;
+  if (m > 0x7fffffff || nnz > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "sparse part too large for int32 CSR");
+  d->nnz = nnz;
+  AMM_TRY(d->row_ptr.alloc((m + 1) * 4));
+  AMM_TRY(d->col.alloc(std::max<int64_t>(nnz, 1) * 4));
+  AMM_TRY(d->val.alloc(std::max<int64_t>(nnz, 1) * 4));
+
+  // radix select of the threshold key
+  uint32_t prefix = 0, hi_mask = 0;
+  int64_t remaining = nnz;  // how many of the keys matching the prefix are still needed
+  DevBuf hist;
+  AMM_TRY(hist.alloc(256 * 4));
+  uint32_t T = 0xffffffffu;  // nnz == 0: nothing passes key > T or == T
+  if (nnz > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      AMM_HIP(hipMemsetAsync(hist.ptr, 0, 256 * 4, s));
+      hipLaunchKernelGGL(radix_hist, dim3(grid), dim3(256), 0, s, A, count, prefix, hi_mask, shift,
+                         hist.as<uint32_t>());
+      AMM_HIP(hipGetLastError());
+      uint32_t h[256];
+      AMM_HIP(hipMemcpyAsync(h, hist.ptr, sizeof(h), hipMemcpyDeviceToHost, s));
+      AMM_HIP(hipStreamSynchronize(s));
+      int digit = 255;
+      for (; digit >= 0; --digit) {
+        if ((int64_t)h[digit] >= remaining) break;
+        remaining -= h[digit];
+      }
+      if (digit < 0) return fail(AMM_EDEVICE, "radix select lost count");
+      prefix |= (uint32_t)digit << shift;
+      hi_mask |= 255u << shift;
+    }
+    T = prefix;
+  }
+  // remaining = number of entries equal to T that must be taken
+  DevBuf gt, eq, take, rp;
+  AMM_TRY(gt.alloc(m * 4));
+  AMM_TRY(eq.alloc(m * 4));
+  AMM_TRY(take.alloc(m * 4));
+  std::vector<int32_t> hgt(m), heq(m), htake(m), hrp(m + 1);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(row_counts, dim3((unsigned)m), dim3(256), 0, s, A, n, T, gt.as<int32_t>(), eq.as<int32_t>());
+    AMM_HIP(hipGetLastError());
+    AMM_HIP(hipMemcpyAsync(hgt.data(), gt.ptr, m * 4, hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipMemcpyAsync(heq.data(), eq.ptr, m * 4, hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+  }
+  int64_t eq_left = remaining, pos = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t tk = std::min<int64_t>(eq_left, heq[i]);
+    htake[i] = (int32_t)tk;
+    eq_left -= tk;
+    hrp[i] = (int32_t)pos;
+    pos += hgt[i] + tk;
+  }
+  hrp[m] = (int32_t)pos;
+  if (pos != nnz) return fail(AMM_EDEVICE, "sparse count mismatch %lld vs %lld", (long long)pos, (long long)nnz);
+  AMM_HIP(hipMemcpyAsync(take.ptr, htake.data(), m * 4, hipMemcpyHostToDevice, s));
+  AMM_HIP(hipMemcpyAsync(d->row_ptr.ptr, hrp.data(), (m + 1) * 4, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(fill_rows, dim3((unsigned)m), dim3(256), 0, s, A, n, T, take.as<int32_t>(),
+                     d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), R);
+  AMM_HIP(hipGetLastError());
+  AMM_HIP(hipStreamSynchronize(s));
+  AMM_TRY(build_csc(d));
+  // norms for reporting: ||A||_F^2 = ||S||^2 + ||R||^2 is left to the caller
+  return AMM_OK;
+}
+
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
+  if (d->m > 65535) return fail(AMM_EUNSUPPORTED, "too many rows for the SpMM grid");
+  dim3 grid((unsigned)((p + 1023) / 1024), (unsigned)d->m), block(256);
+  TimedLaunch tl("spmm_csr", s);
+  hipLaunchKernelGGL(spmm_rows, grid, block, 0, s, d->row_ptr.as<int32_t>(), d->col.as<int32_t>(),
+                     d->val.as<float>(), B, p, out, acc ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out, bool acc,
+                           hipStream_t s) {
+  const int64_t n = d->m, p = d->n;
+  const size_t lds = (size_t)n * sizeof(float);
+  if (lds > 160 * 1024) return fail(AMM_EUNSUPPORTED, "inner dimension too large for the LDS row stage");
+  if (rows > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many rows");
+  if (lds > 64 * 1024) AMM_HIP(hipFuncSetAttribute((const void*)dense_csc_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  TimedLaunch tl("dense_times_csr", s);
+  hipLaunchKernelGGL(dense_csc_rows, dim3((unsigned)rows), dim3(256), lds, s, X, n, d->csc_ptr.as<int32_t>(),
+                     d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, out, acc ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+}  // namespace amm

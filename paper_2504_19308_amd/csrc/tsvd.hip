@@ -1,0 +1,315 @@
+// Randomized truncated SVD, float64 on the device (Alg. 2.1 of the paper,
+// after Halko, Martinsson and Tropp).
+//
+// Alg. 2.1 sketches Y = A phi with k random columns, orthonormalises Y and
+// takes the SVD of Q^T A.  Without oversampling that does not return the best
+// rank-k approximation, so the sketch carries `oversample` extra columns and
+// `power_iters` subspace iterations (Y <- A A^T Y with re-orthonormalisation),
+// both from the same reference; the leading k triplets are kept.
+//
+// Device work: the tall GEMMs (float64 MFMA) and the sketch generator.  Host
+// work is confined to l x l matrices (l = k + oversample): Cholesky factors
+// for the CholeskyQR2 orthonormalisation and a Jacobi eigensolver for the
+// small Gram matrix (Q^T A)(Q^T A)^T.
+//
+// The sketch entries are N(0,1) from Philox4x32-10 (Salmon et al., 2011) with
+// the Box-Muller transform: counter = (element pair index, seed), key fixed.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "amm_internal.hpp"
+
+namespace amm {
+namespace {
+
+__device__ __forceinline__ void philox_round(uint32_t* c, const uint32_t* k) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+  const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__device__ __forceinline__ void philox4x32_10(uint32_t* c, uint32_t k0, uint32_t k1) {
+  uint32_t k[2] = {k0, k1};
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+}
+
+__global__ void gaussian_sketch(double* __restrict__ out, int64_t count, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // pair index
+  if (2 * i >= count) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)seed, (uint32_t)(seed >> 32)};
+  philox4x32_10(c, 0x1BD11BDAu, 0x6A09E667u);
+  // two uniforms in (0, 1] from 53-bit words
+  const uint64_t a = ((uint64_t)c[0] << 21) ^ (uint64_t)(c[1] >> 11);
+  const uint64_t b = ((uint64_t)c[2] << 21) ^ (uint64_t)(c[3] >> 11);
+  const double u1 = ((double)(a & ((1ull << 53) - 1)) + 1.0) * (1.0 / 9007199254740992.0);
+  const double u2 = ((double)(b & ((1ull << 53) - 1)) + 0.5) * (1.0 / 9007199254740992.0);
+  const double r = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  out[2 * i] = r * cs;
+  if (2 * i + 1 < count) out[2 * i + 1] = r * sn;
+}
+
+__global__ void widen_f32(const float* __restrict__ a, double* __restrict__ b, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = (double)a[i];
+}
+
+__global__ void sumsq_partial(const float* __restrict__ a, int64_t count, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const double v = a[i];
+    s += v * v;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// out[i*ldo + j] = (float)(src[i*lds + perm[j]] * (scale ? scale[perm[j]] : 1))
+__global__ void pick_columns(const double* __restrict__ src, int64_t rows, int64_t lds,
+                             const int32_t* __restrict__ perm, const double* __restrict__ scale,
+                             int k, float* __restrict__ out, float* __restrict__ out_scaled,
+                             const double* __restrict__ sig) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * k) return;
+  const int64_t i = idx / k;
+  const int j = (int)(idx % k);
+  double v = src[i * lds + perm[j]];
+  if (scale) v *= scale[perm[j]];
+  out[idx] = (float)v;
+  out_scaled[idx] = (float)(v * sig[j]);
+}
+
+// ---- host l x l linear algebra ---------------------------------------------------
+// Cholesky G = R^T R (upper R); returns false if not positive definite.
+bool cholesky_upper(std::vector<double>& G, int l) {
+  for (int j = 0; j < l; ++j) {
+    double d = G[j * l + j];
+    for (int k = 0; k < j; ++k) d -= G[k * l + j] * G[k * l + j];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    G[j * l + j] = d;
+    for (int i = j + 1; i < l; ++i) {
+      double v = G[j * l + i];
+      for (int k = 0; k < j; ++k) v -= G[k * l + j] * G[k * l + i];
+      G[j * l + i] = v / d;
+    }
+    for (int i = 0; i < j; ++i) G[j * l + i] = 0.0;
+  }
+  return true;
+}
+
+// inverse of an upper-triangular R (row-major)
+std::vector<double> inv_upper(const std::vector<double>& R, int l) {
+  std::vector<double> X(l * l, 0.0);
+  for (int j = 0; j < l; ++j) {
+    X[j * l + j] = 1.0 / R[j * l + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += R[i * l + k] * X[k * l + j];
+      X[i * l + j] = -s / R[i * l + i];
+    }
+  }
+  return X;
+}
+
+// cyclic Jacobi: G = W diag(lam) W^T
+void jacobi_eig(std::vector<double> G, int l, std::vector<double>& lam, std::vector<double>& W) {
+  W.assign(l * l, 0.0);
+  for (int i = 0; i < l; ++i) W[i * l + i] = 1.0;
+  double fro = 0.0;
+  for (double v : G) fro += v * v;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < l; ++i)
+      for (int j = i + 1; j < l; ++j) off += G[i * l + j] * G[i * l + j];
+    if (std::sqrt(off) <= 1e-16 * fro) break;
+    for (int p = 0; p < l; ++p)
+      for (int q = p + 1; q < l; ++q) {
+        const double apq = G[p * l + q];
+        if (apq == 0.0) continue;
+        const double app = G[p * l + p], aqq = G[q * l + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < l; ++k) {
+          const double gkp = G[k * l + p], gkq = G[k * l + q];
+          G[k * l + p] = c * gkp - s * gkq;
+          G[k * l + q] = s * gkp + c * gkq;
+        }
+        for (int k = 0; k < l; ++k) {
+          const double gpk = G[p * l + k], gqk = G[q * l + k];
+          G[p * l + k] = c * gpk - s * gqk;
+          G[q * l + k] = s * gpk + c * gqk;
+        }
+        for (int k = 0; k < l; ++k) {
+          const double wkp = W[k * l + p], wkq = W[k * l + q];
+          W[k * l + p] = c * wkp - s * wkq;
+          W[k * l + q] = s * wkp + c * wkq;
+        }
+      }
+  }
+  lam.resize(l);
+  for (int i = 0; i < l; ++i) lam[i] = G[i * l + i];
+}
+
+// Orthonormalise the columns of Y (rows x l, row-major) in place into Q via
+// CholeskyQR2 (a shifted first pass guards against a numerically rank-deficient
+// sketch).  tmp: rows x l scratch.
+amm_status orthonormalise(double* Y, double* tmp, int64_t rows, int l, DevBuf& gram, hipStream_t s) {
+  std::vector<double> G(l * l);
+  for (int pass = 0; pass < 3; ++pass) {
+    AMM_TRY(gemm_f64(l, l, rows, 1.0, Y, 1, l, Y, l, 1, 0.0, gram.as<double>(), l, s));
+    AMM_HIP(hipMemcpyAsync(G.data(), gram.ptr, l * l * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < l; ++i)
+      for (int j = 0; j < i; ++j) G[i * l + j] = G[j * l + i] = 0.5 * (G[i * l + j] + G[j * l + i]);
+    if (pass == 0) {
+      double nrm = 0.0;
+      for (int i = 0; i < l; ++i) nrm += G[i * l + i];
+      const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * nrm;
+      for (int i = 0; i < l; ++i) G[i * l + i] += shift;
+    }
+    if (!cholesky_upper(G, l)) return fail(AMM_EDEVICE, "CholeskyQR broke down (sketch rank-deficient)");
+    std::vector<double> Ri = inv_upper(G, l);
+    AMM_HIP(hipMemcpyAsync(gram.ptr, Ri.data(), l * l * sizeof(double), hipMemcpyHostToDevice, s));
+    AMM_TRY(gemm_f64(rows, l, l, 1.0, Y, l, 1, gram.as<double>(), l, 1, 0.0, tmp, l, s));
+    AMM_HIP(hipMemcpyAsync(Y, tmp, rows * l * sizeof(double), hipMemcpyDeviceToDevice, s));
+    AMM_HIP(hipStreamSynchronize(s));
+  }
+  return AMM_OK;
+}
+
+}  // namespace
+
+amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
+                          const amm_opts* o, amm_dec* dec, hipStream_t s) {
+  (void)ctx;
+  const int64_t mn = std::min(m, n);
+  const int l = (int)std::min<int64_t>(mn, (int64_t)k + std::max(o->oversample, 0));
+  const int q = std::max(o->power_iters, 0);
+  dec->K_eff = k;
+  // ||A||_F
+  {
+    const int blocks = 1024;
+    DevBuf part;
+    AMM_TRY(part.alloc(blocks * sizeof(double)));
+    hipLaunchKernelGGL(sumsq_partial, dim3(blocks), dim3(256), 0, s, A, m * n, part.as<double>());
+    AMM_HIP(hipGetLastError());
+    std::vector<double> h(blocks);
+    AMM_HIP(hipMemcpyAsync(h.data(), part.ptr, blocks * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : h) t += v;
+    dec->norm_A = std::sqrt(t);
+  }
+  const int64_t kk = std::max(k, 1);
+  AMM_TRY(dec->U.alloc(m * kk * 4));
+  AMM_TRY(dec->US.alloc(m * kk * 4));
+  AMM_TRY(dec->V.alloc(n * kk * 4));
+  AMM_TRY(dec->VS.alloc(n * kk * 4));
+  AMM_TRY(dec->VSt.alloc(n * kk * 4));
+  AMM_TRY(dec->sigma.alloc(kk * 4));
+  if (k == 0) {
+    dec->norm_residual = dec->norm_A;
+    return AMM_OK;
+  }
+  DevBuf A64, Om, Y, Z, T1, gram, Bs;
+  AMM_TRY(A64.alloc(m * n * sizeof(double)));
+  AMM_TRY(Om.alloc(n * l * sizeof(double)));
+  AMM_TRY(Y.alloc(m * l * sizeof(double)));
+  AMM_TRY(Z.alloc(n * l * sizeof(double)));
+  AMM_TRY(T1.alloc(std::max(m, n) * l * sizeof(double)));
+  AMM_TRY(gram.alloc(l * l * sizeof(double)));
+  AMM_TRY(Bs.alloc(l * n * sizeof(double)));
+  hipLaunchKernelGGL(widen_f32, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, A, A64.as<double>(), m * n);
+  const int64_t cnt = n * l;
+  hipLaunchKernelGGL(gaussian_sketch, dim3((unsigned)((cnt / 2 + 256) / 256)), dim3(256), 0, s, Om.as<double>(), cnt, o->seed);
+  AMM_HIP(hipGetLastError());
+  const double* Ad = A64.as<double>();
+  // Y = A Omega
+  AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, Om.as<double>(), l, 1, 0.0, Y.as<double>(), l, s));
+  AMM_TRY(orthonormalise(Y.as<double>(), T1.as<double>(), m, l, gram, s));
+  for (int it = 0; it < q; ++it) {
+    // Z = A^T Q, orthonormalise; Y = A Z, orthonormalise
+    AMM_TRY(gemm_f64(n, l, m, 1.0, Ad, 1, n, Y.as<double>(), l, 1, 0.0, Z.as<double>(), l, s));
+    AMM_TRY(orthonormalise(Z.as<double>(), T1.as<double>(), n, l, gram, s));
+    AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, Z.as<double>(), l, 1, 0.0, Y.as<double>(), l, s));
+    AMM_TRY(orthonormalise(Y.as<double>(), T1.as<double>(), m, l, gram, s));
+  }
+  // Bs = Q^T A  (l x n)
+  AMM_TRY(gemm_f64(l, n, m, 1.0, Y.as<double>(), 1, l, Ad, n, 1, 0.0, Bs.as<double>(), n, s));
+  // Gram = Bs Bs^T = W diag(lam) W^T  (host Jacobi)
+  AMM_TRY(gemm_f64(l, l, n, 1.0, Bs.as<double>(), n, 1, Bs.as<double>(), 1, n, 0.0, gram.as<double>(), l, s));
+  std::vector<double> G(l * l), lam, W;
+  AMM_HIP(hipMemcpyAsync(G.data(), gram.ptr, l * l * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < l; ++i)
+    for (int j = 0; j < i; ++j) G[i * l + j] = G[j * l + i] = 0.5 * (G[i * l + j] + G[j * l + i]);
+  jacobi_eig(G, l, lam, W);
+  std::vector<int32_t> order(l);
+  for (int i = 0; i < l; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] > lam[b]; });
+  std::vector<double> sig(l), inv_sig(l, 0.0);
+  for (int i = 0; i < l; ++i) {
+    sig[i] = std::sqrt(std::max(lam[i], 0.0));
+    inv_sig[i] = sig[i] > 0 ? 1.0 / sig[i] : 0.0;
+  }
+  std::vector<double> sig_k(k);
+  std::vector<float> sig_f(k);
+  double kept = 0.0;
+  for (int j = 0; j < k; ++j) {
+    sig_k[j] = sig[order[j]];
+    sig_f[j] = (float)sig_k[j];
+    kept += sig_k[j] * sig_k[j];
+  }
+  dec->norm_residual = std::sqrt(std::max(dec->norm_A * dec->norm_A - kept, 0.0));
+  // U_full = Q W (m x l), V_full = Bs^T W diag(1/sig) (n x l)
+  DevBuf Wd, Uf, Vf, perm, isg, sgk;
+  AMM_TRY(Wd.alloc(l * l * sizeof(double)));
+  AMM_TRY(Uf.alloc(m * l * sizeof(double)));
+  AMM_TRY(Vf.alloc(n * l * sizeof(double)));
+  AMM_TRY(perm.alloc(l * 4));
+  AMM_TRY(isg.alloc(l * sizeof(double)));
+  AMM_TRY(sgk.alloc(k * sizeof(double)));
+  AMM_HIP(hipMemcpyAsync(Wd.ptr, W.data(), l * l * sizeof(double), hipMemcpyHostToDevice, s));
+  AMM_HIP(hipMemcpyAsync(perm.ptr, order.data(), l * 4, hipMemcpyHostToDevice, s));
+  AMM_HIP(hipMemcpyAsync(isg.ptr, inv_sig.data(), l * sizeof(double), hipMemcpyHostToDevice, s));
+  AMM_HIP(hipMemcpyAsync(sgk.ptr, sig_k.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+  AMM_TRY(gemm_f64(m, l, l, 1.0, Y.as<double>(), l, 1, Wd.as<double>(), l, 1, 0.0, Uf.as<double>(), l, s));
+  AMM_TRY(gemm_f64(n, l, l, 1.0, Bs.as<double>(), 1, n, Wd.as<double>(), l, 1, 0.0, Vf.as<double>(), l, s));
+  hipLaunchKernelGGL(pick_columns, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s, Uf.as<double>(), m,
+                     (int64_t)l, perm.as<int32_t>(), (const double*)nullptr, k, dec->U.as<float>(),
+                     dec->US.as<float>(), sgk.as<double>());
+  hipLaunchKernelGGL(pick_columns, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, Vf.as<double>(), n,
+                     (int64_t)l, perm.as<int32_t>(), isg.as<double>(), k, dec->V.as<float>(),
+                     dec->VS.as<float>(), sgk.as<double>());
+  AMM_HIP(hipGetLastError());
+  AMM_TRY(transpose_f32(dec->VS.as<float>(), n, k, dec->VSt.as<float>(), s));
+  AMM_HIP(hipMemcpyAsync(dec->sigma.ptr, sig_f.data(), k * 4, hipMemcpyHostToDevice, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  return AMM_OK;
+}
+
+}  // namespace amm

@@ -1,0 +1,173 @@
+"""GPU parity of the truncated-SVD and sparse paths against the float64 oracle.
+
+Products are compared on identical decompositions (oracle factors / CSR
+imported through the C ABI) to the float32 bar 1e-5 relative Frobenius.  The
+device randomized SVD is judged on what the mathematics fixes (singular
+values of the generator, the Eckart-Young tail); the device extraction must
+give the oracle's CSR exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import product as op
+from oracle import sparse as osp
+from oracle import tsvd as ot
+from paper_2504_19308_amd import inputs
+from tests._gpu_common import TOL_F32, ctx, f32, gpu, host, note, rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _spectral(m, n, sigma, seed):
+    return f32(inputs.spectral_matrix(m, n, sigma, np.random.default_rng(seed)))
+
+
+@pytest.mark.parametrize("m,n,p,k", [
+    (16, 16, 16, 4), (33, 47, 29, 5), (100, 64, 257, 16), (256, 256, 256, 16),
+    (512, 384, 1000, 64), (1024, 1024, 1024, 128), (130, 2100, 70, 9),
+])
+def test_tsvd_apply_parity(m, n, p, k):
+    note(f"tsvd apply m={m} n={n} p={p} k={k}")
+    rng = np.random.default_rng(m + n + p)
+    sig = inputs.decay_power(min(m, n), 1.0)
+    A = _spectral(m, n, sig, m + 1)
+    B = f32(rng.standard_normal((n, p)))
+    dec = ot.TSVDDecomp(A, k)
+    want = ot.apply_zeroth(dec, B)
+    c = ctx()
+    d = c.import_tsvd(dec.U, dec.s, dec.V)
+    got = host(c.approx_matmul(d, gpu(B)))
+    assert rel(got, want) < TOL_F32
+
+
+@pytest.mark.parametrize("n,kA,kB", [(64, 4, 6), (256, 16, 16), (1024, 32, 32), (333, 7, 11)])
+def test_tsvd_first_order_parity(n, kA, kB):
+    note(f"tsvd first order n={n} kA={kA} kB={kB}")
+    sig = inputs.decay_power(n, 1.5)
+    A = _spectral(n, n, sig, 11 + n)
+    B = _spectral(n, n, sig, 12 + n)
+    decA, decB = ot.TSVDDecomp(A, kA), ot.TSVDDecomp(B, kB)
+    want = op.algorithm(decA, B, decB)
+    c = ctx()
+    Ag = gpu(A)
+    dA = c.import_tsvd(decA.U, decA.s, decA.V, A=Ag)
+    dB = c.import_tsvd(decB.U, decB.s, decB.V)
+    got = host(c.approx_matmul(dA, gpu(B), dB))
+    assert rel(got, want) < TOL_F32
+
+
+def test_tsvd_first_order_needs_A():
+    from paper_2504_19308_amd import AmmError
+    n = 32
+    A = _spectral(n, n, inputs.decay_exp(n), 1)
+    dec = ot.TSVDDecomp(A, 4)
+    c = ctx()
+    d = c.import_tsvd(dec.U, dec.s, dec.V)
+    with pytest.raises(AmmError):
+        c.approx_matmul(d, gpu(A), d)
+
+
+@pytest.mark.parametrize("n,k,alpha", [(256, 16, 1.5), (512, 32, 1.5), (1024, 64, 1.2)])
+def test_tsvd_decompose_quality(n, k, alpha):
+    """Singular values of the generator are recovered and the truncation error
+    is within 1e-3 of the Eckart-Young tail sqrt(sum_{i>k} sigma_i^2)."""
+    note(f"tsvd decompose n={n} k={k}")
+    sig = inputs.decay_power(n, alpha)
+    A = _spectral(n, n, sig, 31 + n)
+    c = ctx()
+    Ag = gpu(A)
+    d = c.decompose(Ag, "tsvd", k, oversample=16, power_iters=2, seed=5)
+    U, s, V = d.tsvd_factors()
+    s_exact = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s[: k // 2] - s_exact[: k // 2]) / s_exact[: k // 2]) < 1e-5
+    Ak = (U.astype(np.float64) * s.astype(np.float64)) @ V.astype(np.float64).T
+    tail = np.sqrt(np.sum(s_exact[k:] ** 2))
+    err = np.linalg.norm(A - Ak)
+    assert err / tail - 1 < 1e-3
+    inf = d.info()
+    assert np.isclose(inf["norm_A"], np.linalg.norm(A), rtol=1e-9)
+
+
+@pytest.mark.parametrize("m,n,p,frac,inner,K", [
+    (64, 64, 40, 0.05, None, 0), (128, 128, 128, 0.02, "tsvd", 8),
+    (256, 256, 100, 0.01, "circulant", 8), (300, 200, 77, 0.03, "tsvd", 5),
+])
+def test_sparse_apply_parity(m, n, p, frac, inner, K):
+    note(f"sparse apply m={m} n={n} frac={frac} inner={inner}")
+    rng = np.random.default_rng(m * 3 + n)
+    A = f32(inputs.spectral_matrix(m, n, inputs.decay_power(min(m, n), 1.5), rng))
+    pos, vals = inputs.sparse_overlay(m, n, frac, 10.0, rng)
+    A = A.copy()
+    A.reshape(-1)[pos] += vals
+    A = f32(A)
+    B = f32(rng.standard_normal((n, p)))
+    if inner == "circulant" and m != n:
+        pytest.skip("circulant residue needs a square operand")
+    dec = osp.SparseDecomp(A, frac, inner, K)
+    want = osp.apply_zeroth(dec, B)
+    c = ctx()
+    res = None
+    if inner == "tsvd":
+        res = c.import_tsvd(dec.inner.U, dec.inner.s, dec.inner.V)
+    elif inner == "circulant":
+        res = c.import_circulant(n, dec.inner.S, dec.inner.L)
+    d = c.import_sparse(m, n, dec.S.row_ptr, dec.S.col, dec.S.val, residue=res)
+    got = host(c.approx_matmul(d, gpu(B)))
+    assert rel(got, np.real(want)) < TOL_F32
+
+
+@pytest.mark.parametrize("n,frac", [(64, 0.05), (256, 0.01)])
+def test_sparse_first_order_parity(n, frac):
+    rng = np.random.default_rng(n)
+    mk = lambda: f32(inputs.spectral_matrix(n, n, inputs.decay_power(n, 1.5), rng))
+    A, B = mk(), mk()
+    for M in (A, B):
+        pos, vals = inputs.sparse_overlay(n, n, frac, 10.0, rng)
+        M.reshape(-1)[pos] += vals
+    A, B = f32(A), f32(B)
+    decA = osp.SparseDecomp(A, frac, "tsvd", 6)
+    decB = osp.SparseDecomp(B, frac, "tsvd", 6)
+    want = op.algorithm(decA, B, decB)
+    c = ctx()
+    Rg = gpu(decA.R)
+    rA = c.import_tsvd(decA.inner.U, decA.inner.s, decA.inner.V, A=Rg)
+    dA = c.import_sparse(n, n, decA.S.row_ptr, decA.S.col, decA.S.val, residue=rA)
+    rB = c.import_tsvd(decB.inner.U, decB.inner.s, decB.inner.V)
+    dB = c.import_sparse(n, n, decB.S.row_ptr, decB.S.col, decB.S.val, residue=rB)
+    got = host(c.approx_matmul(dA, gpu(B), dB))
+    assert rel(got, want) < TOL_F32
+
+
+@pytest.mark.parametrize("m,n,nnz", [(8, 8, 0), (8, 8, 64), (37, 53, 100), (256, 256, 655), (1000, 300, 4000)])
+def test_sparse_extract_exact(m, n, nnz):
+    """Device extraction returns the oracle's CSR exactly (ties included)."""
+    note(f"sparse extract m={m} n={n} nnz={nnz}")
+    rng = np.random.default_rng(m + nnz)
+    A = np.round(rng.standard_normal((m, n)) * 4) / 4   # many exact ties
+    A = f32(A)
+    want = osp.extract_dominant(A, nnz)
+    c = ctx()
+    d = c.decompose(gpu(A), "sparse", 0, sparse_nnz=nnz)
+    rp, col, val = d.sparse_part()
+    assert np.array_equal(rp, want.row_ptr)
+    assert np.array_equal(col, want.col)
+    assert np.array_equal(val.astype(np.float64), want.val)
+
+
+def test_sparse_decompose_end_to_end():
+    n = 256
+    rng = np.random.default_rng(77)
+    A = f32(inputs.spectral_matrix(n, n, inputs.decay_power(n, 1.5), rng))
+    pos, vals = inputs.sparse_overlay(n, n, 0.01, 10.0, rng)
+    A.reshape(-1)[pos] += vals
+    A = f32(A)
+    B = f32(rng.standard_normal((n, 64)))
+    c = ctx()
+    d = c.decompose(gpu(A), "sparse+tsvd", 16, sparse_frac=0.01)
+    got = host(c.approx_matmul(d, gpu(B)))
+    dec = osp.SparseDecomp(A, 0.01, "tsvd", 16)
+    want = osp.apply_zeroth(dec, B)
+    # same sparse set exactly, SVD of the residue by the randomized method
+    rp, col, val = d.sparse_part()
+    assert np.array_equal(col, dec.S.col)
+    assert rel(got, want) < 1e-4
