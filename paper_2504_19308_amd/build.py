@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamm.so")
 
-SOURCES = ["amm_api.cpp", "cd_apply.hip", "cd_decomp.hip", "gemm.hip", "sparse.hip", "tsvd.hip"]
+SOURCES = ["amm_api.cpp", "cd_apply.hip", "cd_decomp.hip", "gemm.hip", "sparse.hip", "tsvd.hip", "tsvd_apply.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -44,29 +44,32 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
         raise RuntimeError("hipcc not found")
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    procs = []
-    objs = []
+    pending = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
-        objs.append(obj)
         cmd = [HIPCC, *FLAGS]
         if src.endswith(".cpp"):
             cmd += ["-x", "hip"]
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
-        if len([p for _, p in procs if p.poll() is None]) >= jobs:
-            for _, p in procs:
-                p.wait()
-    failed = False
-    for cmd, p in procs:
-        out, err = p.communicate()
-        if p.returncode != 0:
-            failed = True
-            sys.stderr.write(" ".join(cmd) + "\n" + out + err)
+        pending.append((src, obj, cmd))
+    # compiler output goes to a log file per source (a full pipe would block)
+    running, done, failed = [], [], []
+    while pending or running:
+        while pending and len(running) < jobs:
+            src, obj, cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            logf = open(os.path.join(objdir, src + ".log"), "w")
+            running.append((src, obj, cmd, logf, subprocess.Popen(cmd, stdout=logf, stderr=subprocess.STDOUT)))
+        src, obj, cmd, logf, proc = running.pop(0)
+        rc = proc.wait()
+        logf.close()
+        (done if rc == 0 else failed).append((src, obj, cmd))
     if failed:
-        raise RuntimeError("HIP compilation failed")
+        for src, _, cmd in failed:
+            sys.stderr.write(" ".join(cmd) + "\n" + open(os.path.join(objdir, src + ".log")).read())
+        raise RuntimeError("HIP compilation failed: " + ", ".join(f[0] for f in failed))
+    objs = [os.path.join(objdir, src.rsplit(".", 1)[0] + ".o") for src in SOURCES]
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -137,6 +137,13 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out) {
   return AMM_OK;
 }
 
+amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const float* US, const float* V,
+                         float* dst, hipStream_t s) {
+  AMM_HIP(hipMemcpyAsync(dst, A, m * n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (k > 0) AMM_TRY(gemm_f32(m, n, k, -1.f, MatView{US, k, 1}, MatView{V, 1, k}, 1.f, dst, n, s, "gemm_residual"));
+  return AMM_OK;
+}
+
 // ---- product dispatch ---------------------------------------------------------
 namespace {
 
@@ -168,6 +175,12 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     }
     AMM_TRY(ctx->scratch[0].reserve((size_t)k * p * sizeof(float)));
     float* G = ctx->scratch[0].as<float>();
+    if (!acc && tsvd_fast_shapes(d->m, d->n, p, k, 0)) {
+      const size_t gp = (size_t)4 * k * p;
+      AMM_TRY(ctx->scratch[4].reserve(gp * sizeof(float)));
+      return tsvd_fast_product(d->m, d->n, p, k, 0, d->V.as<float>(), d->US.as<float>(), B, nullptr,
+                               nullptr, nullptr, ctx->scratch[4].as<float>(), gp, nullptr, 0, out, s);
+    }
     // G = V^T B  (k x p)
     AMM_TRY(gemm_f32(k, p, d->n, 1.f, MatView{d->V.as<float>(), 1, k}, MatView{B, p, 1}, 0.f, G, p, s, "gemm_VtB"));
     // out = (U S) G
@@ -485,6 +498,15 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
   d->norm_A = 0.0;
   d->norm_residual = 0.0;
   (void)s2;
+  if (A) {
+    amm_status st2 = d->residual.alloc(m * n * sizeof(float));
+    if (st2 == AMM_OK) st2 = tsvd_residual(A, m, n, k, d->US.as<float>(), d->V.as<float>(), d->residual.as<float>(), 0);
+    if (st2 == AMM_OK && hipDeviceSynchronize() != hipSuccess) st2 = fail(AMM_EDEVICE, "residual");
+    if (st2 != AMM_OK) {
+      delete d;
+      return st2;
+    }
+  }
   *out = d;
   return AMM_OK;
 }
@@ -562,16 +584,8 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
       if (st == AMM_OK) {
         d->inner = in;
         d->K_eff = in->K_eff;
-        // a borrowed residue A of the inner SVD would dangle: materialise Delta A
-        if (o.keep_residual && is_tsvd(in)) {
-          const float* dr = nullptr;
-          in->A_borrowed = R.as<float>();
-          st = residual_of(ctx, in, &dr, s);
-          if (st == AMM_OK) st = d->residual.alloc(m * n * sizeof(float));
-          if (st == AMM_OK && hipMemcpyAsync(d->residual.ptr, dr, m * n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            st = fail(AMM_EDEVICE, "copy residual");
-          in->A_borrowed = nullptr;
-        }
+        // R is a temporary: the inner handle keeps its own Delta R, never R
+        in->A_borrowed = nullptr;
       }
     } else if (st == AMM_OK && o.keep_residual) {
       d->residual = std::move(R);
@@ -611,6 +625,11 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     d->K = K;
     d->device = ctx->device;
     amm_status st = tsvd_decompose(ctx, A, m, n, K, &o, d, s);
+    if (st == AMM_OK && o.keep_residual) {
+      st = d->residual.alloc(m * n * sizeof(float));
+      if (st == AMM_OK) st = tsvd_residual(A, m, n, K, d->US.as<float>(), d->V.as<float>(), d->residual.as<float>(), s);
+      if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "residual");
+    }
     if (st != AMM_OK) {
       delete d;
       return st;
@@ -642,6 +661,18 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   }
   TimerScope ts(ctx);
   if (!dB) return left_apply(ctx, dA, B, p, out, false, s);
+  if (is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed && dB->residual.ptr &&
+      tsvd_fast_shapes(dA->m, n, p, dA->K_eff, dB->K_eff)) {
+    // M1 = U_A S_A (V_A^T Delta B) + (A U_B)(S_B V_B^T): two panels, one output GEMM
+    const int ka = dA->K_eff, kb = dB->K_eff;
+    const int64_t m = dA->m;
+    const size_t gp = (size_t)4 * std::max(ka, 1) * p, hp = (size_t)4 * std::max(kb, 1) * m;
+    AMM_TRY(ctx->scratch[4].reserve(gp * sizeof(float)));
+    AMM_TRY(ctx->scratch[5].reserve(hp * sizeof(float)));
+    return tsvd_fast_product(m, n, p, ka, kb, dA->V.as<float>(), dA->US.as<float>(), dB->residual.as<float>(),
+                             dA->A_borrowed, dB->U.as<float>(), dB->VSt.as<float>(), ctx->scratch[4].as<float>(),
+                             gp, ctx->scratch[5].as<float>(), hp, out, s);
+  }
   if (is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed) {
     // M1 = U_A S_A (V_A^T B) + (A U_B - U_A S_A (V_A^T U_B)) S_B V_B^T
     //    = [U_A S_A | H] [V_A^T B ; S_B V_B^T]   -- one output GEMM, no Delta A

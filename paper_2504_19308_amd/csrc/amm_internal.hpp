@@ -163,7 +163,16 @@ amm_status gemm_f64(int64_t M, int64_t N, int64_t Kd, double alpha, const double
                     int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs,
                     int64_t b_cs, double beta, double* C, int64_t ldc, hipStream_t s);
 
-// SVD path
+// SVD path: skinny panels and the short-K output GEMM (tsvd_apply.hip)
+bool tsvd_fast_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb);
+int tsvd_fast_splits(int64_t tiles, int64_t n);
+amm_status tsvd_fast_product(int64_t m, int64_t n, int64_t p, int ka, int kb, const float* V_A,
+                             const float* US_A, const float* Y, const float* X, const float* U_B,
+                             const float* VSt_B, float* Gp, size_t gp_floats, float* H,
+                             size_t h_floats, float* out, hipStream_t s);
+// Delta A = A - (U S) V^T into dst (m x n)
+amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const float* US, const float* V,
+                         float* dst, hipStream_t s);
 amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
                           const amm_opts* o, amm_dec* dec, hipStream_t s);
 

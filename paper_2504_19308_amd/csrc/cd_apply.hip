@@ -34,7 +34,15 @@ template <int LOG2N> struct CdCfg {
 
 __device__ __forceinline__ int pad_bin(int bin) { return bin + (bin >> 4); }
 
-template <int R, int SIGN, int LOG2N, int Ns>
+// LDS slot of (bin, col): the C packed columns of a bin sit together
+// ([bin][col], one padding slot per 16 bins) in both modes.
+template <int LOG2N, bool ROWS>
+__device__ __forceinline__ int slot(int bin, int col) {
+  using Cfg = CdCfg<LOG2N>;
+  return pad_bin(bin) * Cfg::C + col;
+}
+
+template <int R, int SIGN, int LOG2N, int Ns, bool ROWS>
 __device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict__ tw) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
@@ -52,7 +60,7 @@ __device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict_
     if (NBF % T == 0 || b < NBF) {
       const int col = b % C, j = b / C;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lds[pad_bin(j + r * (N / R)) * C + col];
+      for (int r = 0; r < R; ++r) v[i][r] = lds[slot<LOG2N, ROWS>(j + r * (N / R), col)];
       if constexpr (Ns > 1) {
         const unsigned k = (unsigned)j & (Ns - 1);
 #pragma unroll
@@ -74,18 +82,18 @@ __device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict_
       const int k = j & (Ns - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[pad_bin(base + r * Ns) * C + col] = v[i][r];
+      for (int r = 0; r < R; ++r) lds[slot<LOG2N, ROWS>(base + r * Ns, col)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-template <int SIGN, int LOG2N, int ST = 0, int Ns = 1>
+template <int SIGN, int LOG2N, bool ROWS, int ST = 0, int Ns = 1>
 __device__ __forceinline__ void lds_fft(float2* lds, const float2* __restrict__ tw) {
   if constexpr (ST < stage_count(LOG2N)) {
     constexpr int lr = stage_log2r(LOG2N, ST);
-    lds_stage<(1 << lr), SIGN, LOG2N, Ns>(lds, tw);
-    lds_fft<SIGN, LOG2N, ST + 1, (Ns << lr)>(lds, tw);
+    lds_stage<(1 << lr), SIGN, LOG2N, Ns, ROWS>(lds, tw);
+    lds_fft<SIGN, LOG2N, ROWS, ST + 1, (Ns << lr)>(lds, tw);
   }
 }
 
@@ -95,7 +103,7 @@ template <int LOG2N, bool ROWS>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const float2* __restrict__ L,
-                const float2* __restrict__ tw, int accumulate) {
+                const float2* __restrict__ tw, int accumulate, int vec4) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
@@ -111,26 +119,60 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   const int64_t first = (int64_t)tile * 2 * C;  // first real column / row
 
   // ---- load -----------------------------------------------------------------
+  // All global loads of a thread are issued before its first LDS store.
   if (!ROWS) {
-    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
-      const int rc = e % (2 * C), row = e / (2 * C);
-      const int64_t c = first + rc;
-      ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * extent + c] : 0.f;
+    if (vec4) {
+      constexpr int V = 2 * C / 4;                       // float4 per row
+      constexpr int TOT = N * V, NL = (TOT + T - 1) / T;
+      float4 r[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int e = threadIdx.x + q * T;
+        const int row = e / V, v = e % V;
+        const int64_t c = first + 4 * v;
+        r[q] = (e < TOT && c < extent) ? *reinterpret_cast<const float4*>(X + (int64_t)row * extent + c)
+                                       : float4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int e = threadIdx.x + q * T;
+        if (e < TOT) *reinterpret_cast<float4*>(&lds[pad_bin(e / V) * C + 2 * (e % V)]) = r[q];
+      }
+    } else {
+      for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+        const int rc = e % (2 * C), row = e / (2 * C);
+        const int64_t c = first + rc;
+        ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * extent + c] : 0.f;
+      }
     }
   } else {
-    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
-      const int q = e % N, rl = e / N;
-      const int64_t r = first + rl;
-      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = r < extent ? X[r * N + q] : 0.f;
+    constexpr int TOT = N * 2 * C, NL = (TOT + T - 1) / T;
+    float r[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * T;
+      const int qq = e % N, rl = e / N;
+      const int64_t row = first + rl;
+      r[q] = (e < TOT && row < extent) ? X[row * N + qq] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * T;
+      if (e < TOT) {
+        const int qq = e % N, rl = e / N;
+        ldsf[slot<LOG2N, true>(qq, rl >> 1) * 2 + (rl & 1)] = r[q];
+      }
     }
   }
   __syncthreads();
 
-  lds_fft<-1, LOG2N>(lds, tw);
+  lds_fft<-1, LOG2N, ROWS>(lds, tw);
 
   // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
   constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL, NBINS = Cfg::NBINS;
-  const int cg = threadIdx.x % G, bl = threadIdx.x / G;
+  // lanes = (bin, column group); the 4 packed columns of a group are read as 2 float4
+  const int cg = threadIdx.x % G;
+  const int bl = threadIdx.x / G;
   float2 acc[NBINS][CPL];
 #pragma unroll
   for (int i = 0; i < NBINS; ++i)
@@ -146,16 +188,18 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       if (N % BL == 0 || p < N) {
         const float2 l = Lt[p];
         const int q = (p - k) & (N - 1);
+        float2 x[CPL];
         const float4* src = reinterpret_cast<const float4*>(&lds[pad_bin(q) * C + cg * CPL]);
         const float4 x01 = src[0], x23 = src[1];
-        acc[i][0].x += l.x * x01.x - l.y * x01.y;
-        acc[i][0].y += l.x * x01.y + l.y * x01.x;
-        acc[i][1].x += l.x * x01.z - l.y * x01.w;
-        acc[i][1].y += l.x * x01.w + l.y * x01.z;
-        acc[i][2].x += l.x * x23.x - l.y * x23.y;
-        acc[i][2].y += l.x * x23.y + l.y * x23.x;
-        acc[i][3].x += l.x * x23.z - l.y * x23.w;
-        acc[i][3].y += l.x * x23.w + l.y * x23.z;
+        x[0] = float2{x01.x, x01.y};
+        x[1] = float2{x01.z, x01.w};
+        x[2] = float2{x23.x, x23.y};
+        x[3] = float2{x23.z, x23.w};
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          acc[i][c].x += l.x * x[c].x - l.y * x[c].y;
+          acc[i][c].y += l.x * x[c].y + l.y * x[c].x;
+        }
       }
     }
   }
@@ -171,27 +215,51 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   }
   __syncthreads();
 
-  lds_fft<+1, LOG2N>(lds, tw);
+  lds_fft<+1, LOG2N, ROWS>(lds, tw);
 
   // ---- store ----------------------------------------------------------------
   const float scale = 1.0f / (float)N;
   if (!ROWS) {
-    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
-      const int rc = e % (2 * C), row = e / (2 * C);
-      const int64_t c = first + rc;
-      if (c < extent) {
-        const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * scale;
-        float* o = out + (int64_t)row * extent + c;
-        *o = accumulate ? *o + v : v;
+    if (vec4) {
+      constexpr int V = 2 * C / 4;
+      constexpr int TOT = N * V, NL = (TOT + T - 1) / T;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int e = threadIdx.x + q * T;
+        const int row = e / V, v = e % V;
+        const int64_t c = first + 4 * v;
+        if (e < TOT && c < extent) {
+          float4 y = *reinterpret_cast<const float4*>(&lds[pad_bin(row) * C + 2 * v]);
+          y = float4{y.x * scale, y.y * scale, y.z * scale, y.w * scale};
+          float4* o = reinterpret_cast<float4*>(out + (int64_t)row * extent + c);
+          if (accumulate) {
+            const float4 z = *o;
+            y = float4{y.x + z.x, y.y + z.y, y.z + z.z, y.w + z.w};
+          }
+          *o = y;
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+        const int rc = e % (2 * C), row = e / (2 * C);
+        const int64_t c = first + rc;
+        if (c < extent) {
+          const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * scale;
+          float* o = out + (int64_t)row * extent + c;
+          *o = accumulate ? *o + v : v;
+        }
       }
     }
   } else {
-    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
-      const int q = e % N, rl = e / N;
-      const int64_t r = first + rl;
-      if (r < extent) {
-        const float v = ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] * scale;
-        float* o = out + r * N + q;
+    constexpr int TOT = N * 2 * C, NL = (TOT + T - 1) / T;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = threadIdx.x + q * T;
+      const int qq = e % N, rl = e / N;
+      const int64_t row = first + rl;
+      if (e < TOT && row < extent) {
+        const float v = ldsf[slot<LOG2N, true>(qq, rl >> 1) * 2 + (rl & 1)] * scale;
+        float* o = out + row * N + qq;
         *o = accumulate ? *o + v : v;
       }
     }
@@ -208,12 +276,14 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
   if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
   dim3 grid((unsigned)tiles), block(Cfg::T);
   TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
+  // float4 path: whole float4 groups inside a row and 16-byte aligned rows
+  const int vec4 = (!rows && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
   if (rows)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0);
+                       shifts, L, tw, acc ? 1 : 0, 0);
   else
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0);
+                       shifts, L, tw, acc ? 1 : 0, vec4);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }

@@ -125,14 +125,15 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A, i
     }
   }
 
-  // D layout of v_mfma_*_16x16x4: lane l, element r -> row 4*(l/16)+r, col l%16
+  // D layout, lane l, element r, col l%16:  f32 16x16x4 -> row 4*(l/16) + r;
+  // f64 16x16x4 -> row 4*r + l/16 (checked on gfx950 with a lane probe)
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = m0 + wm + a * 16 + lk * 4 + r;
+        const int64_t gi = m0 + wm + a * 16 + (sizeof(T) == 4 ? lk * 4 + r : r * 4 + lk);
         const int64_t gj = n0 + wn + b * 16 + li;
         if (gi < M && gj < N) {
           const T v = alpha * acc[a][b][r];

@@ -117,7 +117,9 @@ fill_rows(const float* __restrict__ A, int64_t n, uint32_t T, const int32_t* __r
   }
 }
 
-// out[i, :] (+)= sum_e val[e] B[col[e], :]; one block per row, 4 columns a thread.
+// S B with S in CSR: one block per output row; each thread owns 4 adjacent
+// columns and walks the row's stored entries, gathering rows of B (coalesced
+// float4 reads shared by the block).
 __global__ void __launch_bounds__(256)
 spmm_rows(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
           const float* __restrict__ val, const float* __restrict__ B, int64_t p,
@@ -142,22 +144,49 @@ spmm_rows(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
   for (int q = 0; q < 4 && c0 + q < p; ++q) o[q] = accumulate ? o[q] + acc[q] : acc[q];
 }
 
-// out[r, c] (+)= sum over column c of S of X[r, j] S[j, c]; one block per row
-// r with X's row staged in LDS, threads over output columns.
+// X S with S in CSC (the transpose's CSR): one workgroup owns R rows of X,
+// staged in LDS as [j][R+1]; threads over output columns gather X[., j] for
+// the stored entries of their column.  Writes are coalesced along columns.
+template <int R>
 __global__ void __launch_bounds__(256)
-dense_csc_rows(const float* __restrict__ X, int64_t n, const int32_t* __restrict__ csc_ptr,
-               const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val,
-               int64_t p, float* __restrict__ out, int accumulate) {
-  extern __shared__ float xrow[];
-  const int64_t r = blockIdx.x;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) xrow[j] = X[r * n + j];
+dense_csc_slab(const float* __restrict__ X, int64_t rows, int64_t n, const int32_t* __restrict__ csc_ptr,
+               const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val, int64_t p,
+               float* __restrict__ out, int accumulate) {
+  extern __shared__ float xs[];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  for (int64_t e = threadIdx.x; e < n * R; e += blockDim.x) {
+    const int r = (int)(e / n);
+    const int64_t j = e % n;
+    xs[j * (R + 1) + r] = (r0 + r < rows) ? X[(r0 + r) * n + j] : 0.f;
+  }
   __syncthreads();
   for (int64_t c = threadIdx.x; c < p; c += blockDim.x) {
-    float acc = 0.f;
-    for (int e = csc_ptr[c]; e < csc_ptr[c + 1]; ++e) acc += xrow[csc_row[e]] * csc_val[e];
-    float* o = out + r * p + c;
-    *o = accumulate ? *o + acc : acc;
+    float acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.f;
+    const int e1 = csc_ptr[c + 1];
+    for (int e = csc_ptr[c]; e < e1; ++e) {
+      const float v = csc_val[e];
+      const float* x = xs + (int64_t)csc_row[e] * (R + 1);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += v * x[q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (r0 + q < rows) {
+        float* o = out + (r0 + q) * p + c;
+        *o = accumulate ? *o + acc[q] : acc[q];
+      }
   }
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+// largest R in {8, 4, 2, 1} whose [n][R+1] slab fits in LDS (0: none fits)
+int slab_width(int64_t n) {
+  for (int R = 8; R >= 1; R /= 2)
+    if ((size_t)n * (R + 1) * sizeof(float) <= LDS_MAX) return R;
+  return 0;
 }
 
 __global__ void fill_kernel(float* __restrict__ p, int64_t count, float v) {
@@ -298,6 +327,13 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   return AMM_OK;
 }
 
+template <typename K>
+amm_status set_lds(K kernel, size_t lds) {
+  if (lds > 64 * 1024)
+    AMM_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return AMM_OK;
+}
+
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
   if (d->m > 65535) return fail(AMM_EUNSUPPORTED, "too many rows for the SpMM grid");
   dim3 grid((unsigned)((p + 1023) / 1024), (unsigned)d->m), block(256);
@@ -311,13 +347,21 @@ amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, boo
 amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out, bool acc,
                            hipStream_t s) {
   const int64_t n = d->m, p = d->n;
-  const size_t lds = (size_t)n * sizeof(float);
-  if (lds > 160 * 1024) return fail(AMM_EUNSUPPORTED, "inner dimension too large for the LDS row stage");
-  if (rows > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many rows");
-  if (lds > 64 * 1024) AMM_HIP(hipFuncSetAttribute((const void*)dense_csc_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int R = slab_width(n);
+  if (R == 0) return fail(AMM_EUNSUPPORTED, "inner dimension too large for the LDS row stage");
+  const int64_t blocks = (rows + R - 1) / R;
+  if (blocks > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many rows");
+  const size_t lds = (size_t)n * (R + 1) * sizeof(float);
   TimedLaunch tl("dense_times_csr", s);
-  hipLaunchKernelGGL(dense_csc_rows, dim3((unsigned)rows), dim3(256), lds, s, X, n, d->csc_ptr.as<int32_t>(),
-                     d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, out, acc ? 1 : 0);
+#define AMM_DCSC(RR)                                                                                      \
+  case RR:                                                                                                \
+    AMM_TRY(set_lds(dense_csc_slab<RR>, lds));                                                            \
+    hipLaunchKernelGGL(dense_csc_slab<RR>, dim3((unsigned)blocks), dim3(256), lds, s, X, rows, n,         \
+                       d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, out, \
+                       acc ? 1 : 0);                                                                      \
+    break;
+  switch (R) { AMM_DCSC(8) AMM_DCSC(4) AMM_DCSC(2) AMM_DCSC(1) }
+#undef AMM_DCSC
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
