@@ -146,22 +146,10 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       }
     }
   } else {
-    constexpr int TOT = N * 2 * C, NL = (TOT + T - 1) / T;
-    float r[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = threadIdx.x + q * T;
-      const int qq = e % N, rl = e / N;
-      const int64_t row = first + rl;
-      r[q] = (e < TOT && row < extent) ? X[row * N + qq] : 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = threadIdx.x + q * T;
-      if (e < TOT) {
-        const int qq = e % N, rl = e / N;
-        ldsf[slot<LOG2N, true>(qq, rl >> 1) * 2 + (rl & 1)] = r[q];
-      }
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int q = e % N, rl = e / N;
+      const int64_t r = first + rl;
+      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = r < extent ? X[r * N + q] : 0.f;
     }
   }
   __syncthreads();
@@ -251,15 +239,12 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       }
     }
   } else {
-    constexpr int TOT = N * 2 * C, NL = (TOT + T - 1) / T;
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = threadIdx.x + q * T;
-      const int qq = e % N, rl = e / N;
-      const int64_t row = first + rl;
-      if (e < TOT && row < extent) {
-        const float v = ldsf[slot<LOG2N, true>(qq, rl >> 1) * 2 + (rl & 1)] * scale;
-        float* o = out + row * N + qq;
+    for (int e = threadIdx.x; e < N * 2 * C; e += T) {
+      const int q = e % N, rl = e / N;
+      const int64_t r = first + rl;
+      if (r < extent) {
+        const float v = ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] * scale;
+        float* o = out + r * N + q;
         *o = accumulate ? *o + v : v;
       }
     }
