@@ -191,6 +191,24 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
                              const float* B, int64_t n, int64_t p, float* out,
                              void* stream);
 
+/* ---- backward ------------------------------------------------------------ */
+
+/* Gradients of Y = Wtil X (Wtil: the truncation held by dW, m x n; X: n x p;
+ * dY: m x p, all device float32) with the truncation structure frozen -- the
+ * kept circulant frequencies, the singular subspaces U_k and V_k, and the
+ * sparse pattern are constants, so Wtil = P(W) with P linear:
+ *   dX  = Wtil^T dY          (n x p)   written when dX != NULL,
+ *   dWo = P^T(dY X^T)        (m x n)   written when dWo != NULL.
+ * For the circulant and SVD kinds P is an orthogonal projection (the
+ * Frobenius orthogonality of the components, Rem. 1.2 of the paper; the
+ * orthonormal singular subspaces), so P^T = P.  The circulant gradient is
+ * formed from the column spectra of dY and X without the m x n product
+ * dY X^T.  Circulant dWo needs p even.  Outputs are overwritten and must not
+ * alias the inputs. */
+amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X,
+                                      const float* dY, int64_t p, float* dX, float* dWo,
+                                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

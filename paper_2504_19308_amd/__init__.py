@@ -218,6 +218,24 @@ class Context:
             residue._release()
         return Decomposition(self, h, keep)
 
+    # -- backward ---------------------------------------------------------------
+    def approx_matmul_backward(self, dW: Decomposition, X, dY, need_dx: bool = True, need_dw: bool = True):
+        """(dX, dW) for Y = Wtil X with the truncation structure frozen."""
+        _need_f32_cuda(X, "X")
+        _need_f32_cuda(dY, "dY")
+        inf = dW.info()
+        m, n = inf["m"], inf["n"]
+        p = X.shape[1]
+        if X.shape[0] != n or tuple(dY.shape) != (m, p):
+            raise ValueError("shape mismatch")
+        dX = self.torch.empty((n, p), dtype=self.torch.float32, device=X.device) if need_dx else None
+        dWo = self.torch.empty((m, n), dtype=self.torch.float32, device=X.device) if need_dw else None
+        _lib.check(_lib.load().amm_approx_matmul_backward(
+            self.handle, dW.handle, C.c_void_p(X.data_ptr()), C.c_void_p(dY.data_ptr()), p,
+            C.c_void_p(dX.data_ptr()) if dX is not None else None,
+            C.c_void_p(dWo.data_ptr()) if dWo is not None else None, _stream_ptr(self.torch, X.device)))
+        return dX, dWo
+
     # -- product ----------------------------------------------------------------
     def approx_matmul(self, dA: Decomposition, B, dB: Decomposition | None = None, out=None):
         _need_f32_cuda(B, "B")
@@ -231,3 +249,39 @@ class Context:
             self.handle, dA.handle, dB.handle if dB is not None else None, C.c_void_p(B.data_ptr()),
             n, p, C.c_void_p(out.data_ptr()), _stream_ptr(self.torch, B.device)))
         return out
+
+
+def _make_autograd():
+    import torch
+
+    class ApproxLinearFunction(torch.autograd.Function):
+        """Y = P(W) X through the library, P frozen at the decomposition `dec`
+        of W's current value; backward gives dX = P(W)^T dY, dW = P^T(dY X^T)."""
+
+        @staticmethod
+        def forward(fctx, W, X, amm_ctx, dec):
+            fctx.save_for_backward(X)
+            fctx.amm = (amm_ctx, dec)
+            return amm_ctx.approx_matmul(dec, X.contiguous())
+
+        @staticmethod
+        def backward(fctx, gY):
+            (X,) = fctx.saved_tensors
+            amm_ctx, dec = fctx.amm
+            dX, dW = amm_ctx.approx_matmul_backward(dec, X.contiguous(), gY.contiguous(),
+                                                    need_dx=fctx.needs_input_grad[1],
+                                                    need_dw=fctx.needs_input_grad[0])
+            return dW, dX, None, None
+
+    return ApproxLinearFunction
+
+
+_AUTOGRAD = None
+
+
+def approx_linear(W, X, ctx: "Context", dec: Decomposition):
+    """Differentiable Y = Wtil X (Wtil from `dec`, a decomposition of W)."""
+    global _AUTOGRAD
+    if _AUTOGRAD is None:
+        _AUTOGRAD = _make_autograd()
+    return _AUTOGRAD.apply(W, X, ctx, dec)

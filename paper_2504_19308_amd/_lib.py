@@ -54,6 +54,8 @@ SIGNATURES = {
     "amm_dec_destroy": (None, [C.c_void_p]),
     "amm_approx_matmul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_int64, C.c_void_p, C.c_void_p]),
+    "amm_approx_matmul_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                             C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

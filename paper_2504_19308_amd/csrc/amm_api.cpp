@@ -476,12 +476,16 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
       hVS[i * k + j] = (float)(V[i * k + j] * sigma[j]);
     }
   amm_status st;
-  std::vector<float> hVSt(n * kk, 0.f);
+  std::vector<float> hVSt(n * kk, 0.f), hVt(n * kk, 0.f);
   for (int64_t i = 0; i < n; ++i)
-    for (int j = 0; j < k; ++j) hVSt[(int64_t)j * n + i] = hVS[i * k + j];
+    for (int j = 0; j < k; ++j) {
+      hVSt[(int64_t)j * n + i] = hVS[i * k + j];
+      hVt[(int64_t)j * n + i] = hV[i * k + j];
+    }
   if ((st = d->U.alloc(hU.size() * 4)) != AMM_OK || (st = d->US.alloc(hUS.size() * 4)) != AMM_OK ||
       (st = d->V.alloc(hV.size() * 4)) != AMM_OK || (st = d->VS.alloc(hVS.size() * 4)) != AMM_OK ||
-      (st = d->VSt.alloc(hVSt.size() * 4)) != AMM_OK || (st = d->sigma.alloc(hs.size() * 4)) != AMM_OK) {
+      (st = d->VSt.alloc(hVSt.size() * 4)) != AMM_OK || (st = d->Vt.alloc(hVt.size() * 4)) != AMM_OK ||
+      (st = d->sigma.alloc(hs.size() * 4)) != AMM_OK) {
     delete d;
     return st;
   }
@@ -490,6 +494,7 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
   if (e == hipSuccess) e = hipMemcpy(d->V.ptr, hV.data(), hV.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d->VS.ptr, hVS.data(), hVS.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d->VSt.ptr, hVSt.data(), hVSt.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d->Vt.ptr, hVt.data(), hVt.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d->sigma.ptr, hs.data(), hs.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete d;
@@ -708,6 +713,25 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   const float* dAres = nullptr;
   AMM_TRY(residual_of(ctx, dA, &dAres, s));
   return right_apply(ctx, dAres, dA->m, dB, out, true, s);
+}
+
+amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X, const float* dY,
+                                      int64_t p, float* dX, float* dW_out, void* stream) {
+  if (!ctx || !dW || !X || !dY) return fail(AMM_EINVAL, "NULL argument");
+  if (p <= 0) return fail(AMM_ESHAPE, "X has no columns");
+  if (!dX && !dW_out) return AMM_OK;
+  if (dX && (dX == dY || dX == X)) return fail(AMM_EINVAL, "dX aliases an input");
+  if (dW_out && (dW_out == dY || dW_out == X)) return fail(AMM_EINVAL, "dW aliases an input");
+  const amm_dec* c = dW;
+  while (c) {
+    if (c->kind == AMM_CIRCULANT && (c->m != c->n)) return fail(AMM_ESHAPE, "circulant handle not square");
+    if (c->kind == AMM_TSVD && !c->Vt.ptr && dW_out) return fail(AMM_ESTATE, "SVD handle lacks V^T");
+    c = c->inner;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  TimerScope ts(ctx);
+  return approx_backward(ctx, dW, X, dY, p, dX, dW_out, s);
 }
 
 }  // extern "C"

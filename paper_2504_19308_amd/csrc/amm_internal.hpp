@@ -111,7 +111,7 @@ struct amm_dec {
 
   // SVD: U m x k, V n x k, sigma k (float32), US = U diag(sigma), VS = V diag(sigma),
   // VSt = (V diag(sigma))^T  (k x n, for the fused first-order output GEMM)
-  amm::DevBuf U, V, sigma, US, VS, VSt;
+  amm::DevBuf U, V, sigma, US, VS, VSt, Vt;
 
   // sparse part: CSR (row_ptr m+1, col, val) and its transpose as CSC
   // (csc_ptr n+1, csc_row, csc_val) for products with S on the right
@@ -144,6 +144,11 @@ amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
                          bool accumulate, hipStream_t s);
 
+// Forward spectra of the packed column pairs of B (n x p, p even): spec
+// (n x p floats) holds complex bin values at [p][2c], [p][2c + 1].
+amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t p, float* spec,
+                               hipStream_t s);
+
 // Circulant decomposition, float64 on the device.
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s);
@@ -170,6 +175,16 @@ amm_status tsvd_fast_product(int64_t m, int64_t n, int64_t p, int ka, int kb, co
                              const float* US_A, const float* Y, const float* X, const float* U_B,
                              const float* VSt_B, float* Gp, size_t gp_floats, float* H,
                              size_t h_floats, float* out, hipStream_t s);
+// Skinny and short-K products on the matrix cores (shapes: see tsvd_apply.hip)
+amm_status panel_full(int a, int64_t n_red, const float* X, const float* Y, int64_t ncols, float* C,
+                      hipStream_t s);
+bool panel_full_ok(int a, int64_t ncols);
+amm_status gemm_short(int64_t M, int64_t N, int K, const float* A, const float* B, float* C, hipStream_t s);
+bool gemm_short_ok(int64_t M, int64_t N, int K);
+// Raw CSR x dense: out (rows x p) (+)= S B
+amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
+                    const float* B, int64_t p, float* out, bool accumulate, hipStream_t s);
+
 // Delta A = A - (U S) V^T into dst (m x n)
 amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const float* US, const float* V,
                          float* dst, hipStream_t s);
@@ -186,6 +201,8 @@ amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float
 
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);
+amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
+                           float* dX, float* dW, hipStream_t s);
 // Build the CSC copy of a CSR part held on the device (host transpose).
 amm_status build_csc(amm_dec* d);
 

@@ -99,7 +99,10 @@ __device__ __forceinline__ void lds_fft(float2* lds, const float2* __restrict__ 
 
 // ROWS = false: tile = real columns [2 C tile, 2 C tile + 2C) of an N x p matrix.
 // ROWS = true:  tile = real rows [2 C tile, ...) of a rows x N matrix.
-template <int LOG2N, bool ROWS>
+// SPEC = true (column mode only): store the forward spectrum of each packed
+// column pair instead of the product, unscaled, in the same row-major slots
+// (bin p, pair c) -> out[p * extent + 2c + {re, im}].
+template <int LOG2N, bool ROWS, bool SPEC = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const float2* __restrict__ L,
@@ -156,6 +159,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 
   lds_fft<-1, LOG2N, ROWS>(lds, tw);
 
+  if constexpr (!SPEC) {
   // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
   constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL, NBINS = Cfg::NBINS;
   // lanes = (bin, column group); the 4 packed columns of a group are read as 2 float4
@@ -204,9 +208,10 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   __syncthreads();
 
   lds_fft<+1, LOG2N, ROWS>(lds, tw);
+  }
 
   // ---- store ----------------------------------------------------------------
-  const float scale = 1.0f / (float)N;
+  const float scale = SPEC ? 1.0f : 1.0f / (float)N;
   if (!ROWS) {
     if (vec4) {
       constexpr int V = 2 * C / 4;
@@ -254,16 +259,19 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 template <int LOG2N>
 amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
                      const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                     hipStream_t s) {
+                     hipStream_t s, bool spec = false) {
   using Cfg = CdCfg<LOG2N>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
   if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
   dim3 grid((unsigned)tiles), block(Cfg::T);
-  TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
+  TimedLaunch tl(spec ? "cd_spectrum" : (rows ? "cd_apply_rows" : "cd_apply_columns"), s);
   // float4 path: whole float4 groups inside a row and 16-byte aligned rows
   const int vec4 = (!rows && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
-  if (rows)
+  if (spec)
+    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
+                       shifts, L, tw, 0, vec4);
+  else if (rows)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
                        shifts, L, tw, acc ? 1 : 0, 0);
   else
@@ -275,10 +283,10 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
 
 amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
                        const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                       hipStream_t s) {
+                       hipStream_t s, bool spec = false) {
   switch (log2n) {
 #define AMM_CASE(L2) \
-  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s);
+  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
 #undef AMM_CASE
@@ -294,6 +302,13 @@ amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shift
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
   return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s);
+}
+
+amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t p, float* spec,
+                               hipStream_t s) {
+  const float2* tw = nullptr;
+  AMM_TRY(twiddles32(ctx, log2n, &tw));
+  return dispatch_cd(false, log2n, B, spec, p, 0, nullptr, nullptr, tw, false, s, true);
 }
 
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,

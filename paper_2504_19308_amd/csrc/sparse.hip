@@ -334,14 +334,19 @@ amm_status set_lds(K kernel, size_t lds) {
   return AMM_OK;
 }
 
-amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
-  if (d->m > 65535) return fail(AMM_EUNSUPPORTED, "too many rows for the SpMM grid");
-  dim3 grid((unsigned)((p + 1023) / 1024), (unsigned)d->m), block(256);
+amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
+                    const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
+  if (rows > 65535) return fail(AMM_EUNSUPPORTED, "too many rows for the SpMM grid");
+  if (rows <= 0 || p <= 0) return AMM_OK;
+  dim3 grid((unsigned)((p + 1023) / 1024), (unsigned)rows), block(256);
   TimedLaunch tl("spmm_csr", s);
-  hipLaunchKernelGGL(spmm_rows, grid, block, 0, s, d->row_ptr.as<int32_t>(), d->col.as<int32_t>(),
-                     d->val.as<float>(), B, p, out, acc ? 1 : 0);
+  hipLaunchKernelGGL(spmm_rows, grid, block, 0, s, row_ptr, col, val, B, p, out, acc ? 1 : 0);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
+}
+
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
+  return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s);
 }
 
 amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out, bool acc,

@@ -230,6 +230,7 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   AMM_TRY(dec->V.alloc(n * kk * 4));
   AMM_TRY(dec->VS.alloc(n * kk * 4));
   AMM_TRY(dec->VSt.alloc(n * kk * 4));
+  AMM_TRY(dec->Vt.alloc(n * kk * 4));
   AMM_TRY(dec->sigma.alloc(kk * 4));
   if (k == 0) {
     dec->norm_residual = dec->norm_A;
@@ -307,6 +308,7 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
                      dec->VS.as<float>(), sgk.as<double>());
   AMM_HIP(hipGetLastError());
   AMM_TRY(transpose_f32(dec->VS.as<float>(), n, k, dec->VSt.as<float>(), s));
+  AMM_TRY(transpose_f32(dec->V.as<float>(), n, k, dec->Vt.as<float>(), s));
   AMM_HIP(hipMemcpyAsync(dec->sigma.ptr, sig_f.data(), k * 4, hipMemcpyHostToDevice, s));
   AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;

@@ -391,4 +391,33 @@ amm_status tsvd_fast_product(int64_t m, int64_t n, int64_t p, int ka, int kb, co
 
 int tsvd_fast_splits(int64_t tiles, int64_t n) { return pick_splits(tiles, n); }
 
+namespace {
+bool rank_supported(int a) { return a == 16 || a == 32 || a == 48 || a == 64 || a == 128; }
+}
+
+bool panel_full_ok(int a, int64_t ncols) { return rank_supported(a) && ncols % G_TB == 0 && ncols > 0; }
+
+// C (a x ncols, row-major) = X^T Y, X n_red x a, Y n_red x ncols; one reduction split
+amm_status panel_full(int a, int64_t n_red, const float* X, const float* Y, int64_t ncols, float* C,
+                      hipStream_t s) {
+  if (!panel_full_ok(a, ncols)) return fail(AMM_EUNSUPPORTED, "panel shape");
+  PanelJob g{X, Y, ncols, n_red, (int)(ncols / G_TB), 1, C, ncols, 1, 0};
+  PanelJob h{};
+  return dispatch_panel(a, 0, g, h, s);
+}
+
+bool gemm_short_ok(int64_t M, int64_t N, int K) { return M % OT == 0 && N % OT == 0 && K % 4 == 0 && K > 0 && M > 0 && N > 0; }
+
+// C (M x N) = A (M x K) B (K x N), all row-major and contiguous
+amm_status gemm_short(int64_t M, int64_t N, int K, const float* A, const float* B, float* C, hipStream_t s) {
+  if (!gemm_short_ok(M, N, K)) return fail(AMM_EUNSUPPORTED, "short-K GEMM shape");
+  const int64_t tiles = (M / OT) * (N / OT);
+  TimedLaunch tl("gemm_out", s);
+  hipLaunchKernelGGL(out_kernel, dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, 0, A, (int64_t)K,
+                     (const float*)nullptr, (int64_t)0, 1, (int64_t)0, B, N, 1, (int64_t)0,
+                     (const float*)nullptr, (int64_t)0, C, N);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
 }  // namespace amm
