@@ -44,6 +44,7 @@ extern "C" {
 
 typedef struct amm_ctx amm_ctx;
 typedef struct amm_dec amm_dec;
+typedef struct amm_batch_plan amm_batch_plan;
 
 typedef enum {
   AMM_OK = 0,
@@ -190,6 +191,31 @@ void amm_dec_destroy(amm_dec* dec);
 amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
                              const float* B, int64_t n, int64_t p, float* out,
                              void* stream);
+
+/* ---- batches of products ---------------------------------------------------- */
+
+/* Plan `count` zeroth-order products out_i = Atil_i B_i of truncated-SVD
+ * handles that share one rank k (16, 32, 48, 64 or 128) -- e.g. the linear
+ * layers of a model -- executed as two launches for the whole batch: one
+ * covering every V_i^T B_i reduction and one covering every output tile.
+ * Shapes: m_i and p_i multiples of 128, n_i a multiple of 4; up to 256
+ * entries.  B[i] (n_i x p[i]) and out[i] (m_i x p[i]) are device pointers bound
+ * to the plan: later runs read and write the same buffers (the caller keeps
+ * them alive and does not overlap runs of one plan).  Creation times several
+ * reduction-split policies on `stream` (out_i are written while tuning),
+ * keeps the fastest, and captures the two launches in a HIP graph. */
+amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA,
+                                 const float* const* B, const int64_t* p, float* const* out,
+                                 void* stream, amm_batch_plan** plan);
+/* Run the plan on `stream`; use_graph != 0 replays the captured graph
+ * (ignored while the context has timing enabled: then the launches are
+ * issued directly so that they can be timed). */
+amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream);
+/* Chosen split policy (target workgroups), launch sizes and the tuned time
+ * of one run in ms. */
+amm_status amm_batch_info(const amm_batch_plan* plan, int* target_blocks, int* panel_blocks,
+                          int* out_blocks, double* tuned_ms);
+void amm_batch_plan_destroy(amm_batch_plan* plan);
 
 /* ---- backward ------------------------------------------------------------ */
 

@@ -100,6 +100,35 @@ class Decomposition:
             pass
 
 
+class BatchPlan:
+    """A planned batch of products; keeps its handles and buffers alive."""
+
+    def __init__(self, ctx, handle, decs, Bs, outs):
+        self.ctx, self.handle = ctx, handle
+        self.decs, self.Bs, self.outs = decs, Bs, outs
+
+    def run(self, use_graph: bool = True):
+        _lib.check(_lib.load().amm_batch_run(self.handle, 1 if use_graph else 0,
+                                             _stream_ptr(self.ctx.torch, self.Bs[0].device)))
+        return self.outs
+
+    def info(self) -> dict:
+        t, pb, ob, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        _lib.check(_lib.load().amm_batch_info(self.handle, C.byref(t), C.byref(pb), C.byref(ob), C.byref(ms)))
+        return {"target_blocks": t.value, "panel_blocks": pb.value, "out_blocks": ob.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if self.handle:
+            _lib.load().amm_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, device: int = 0):
         import torch
@@ -217,6 +246,26 @@ class Context:
             keep += residue._keep
             residue._release()
         return Decomposition(self, h, keep)
+
+    # -- batches ----------------------------------------------------------------
+    def batch_plan(self, decs, Bs, outs=None) -> "BatchPlan":
+        """Plan out_i = Atil_i B_i for truncated-SVD handles of one rank."""
+        count = len(decs)
+        if outs is None:
+            outs = [self.torch.empty((d.info()["m"], b.shape[1]), dtype=self.torch.float32, device=b.device)
+                    for d, b in zip(decs, Bs)]
+        for b in Bs:
+            _need_f32_cuda(b, "B")
+        for o in outs:
+            _need_f32_cuda(o, "out")
+        hd = (C.c_void_p * count)(*[d.handle for d in decs])
+        hb = (C.c_void_p * count)(*[b.data_ptr() for b in Bs])
+        hp = (C.c_int64 * count)(*[b.shape[1] for b in Bs])
+        ho = (C.c_void_p * count)(*[o.data_ptr() for o in outs])
+        h = C.c_void_p()
+        _lib.check(_lib.load().amm_batch_plan_create(self.handle, count, hd, hb, hp, ho,
+                                                     _stream_ptr(self.torch, Bs[0].device), C.byref(h)))
+        return BatchPlan(self, h, list(decs), list(Bs), list(outs))
 
     # -- backward ---------------------------------------------------------------
     def approx_matmul_backward(self, dW: Decomposition, X, dY, need_dx: bool = True, need_dw: bool = True):

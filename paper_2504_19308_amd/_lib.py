@@ -54,6 +54,12 @@ SIGNATURES = {
     "amm_dec_destroy": (None, [C.c_void_p]),
     "amm_approx_matmul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_int64, C.c_void_p, C.c_void_p]),
+    "amm_batch_plan_create": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amm_batch_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "amm_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double)]),
+    "amm_batch_plan_destroy": (None, [C.c_void_p]),
     "amm_approx_matmul_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_void_p, C.c_void_p, C.c_void_p]),
 }

@@ -260,6 +260,12 @@ amm_dec::~amm_dec() {
   if (inner) delete inner;
 }
 
+amm_batch_plan::~amm_batch_plan() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (own) (void)hipStreamDestroy(own);
+}
+
 extern "C" {
 
 void amm_opts_default(amm_opts* o) {
@@ -732,6 +738,104 @@ amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const flo
   AMM_HIP(hipSetDevice(ctx->device));
   TimerScope ts(ctx);
   return approx_backward(ctx, dW, X, dY, p, dX, dW_out, s);
+}
+
+amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA, const float* const* B,
+                                 const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
+  if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
+  if (count <= 0 || count > batch_max_items()) return fail(AMM_EINVAL, "batch size %d out of [1, %d]", count, batch_max_items());
+  int k = -1;
+  for (int i = 0; i < count; ++i) {
+    const amm_dec* d = dA[i];
+    if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
+    if (d->kind != AMM_TSVD) return fail(AMM_EUNSUPPORTED, "batch entries must be truncated-SVD handles");
+    if (k < 0) k = d->K_eff;
+    if (d->K_eff != k) return fail(AMM_EUNSUPPORTED, "batch entries must share one rank");
+    if (!batch_item_ok(d->m, d->n, p[i], k))
+      return fail(AMM_EUNSUPPORTED, "entry %d: shape %lldx%lld by %lld columns, rank %d not on the batched path", i,
+                  (long long)d->m, (long long)d->n, (long long)p[i], k);
+  }
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_batch_plan* bp = new amm_batch_plan();
+  bp->ctx = ctx;
+  bp->k = k;
+  for (int i = 0; i < count; ++i)
+    bp->items.push_back({dA[i]->m, dA[i]->n, p[i], dA[i]->V.as<float>(), dA[i]->US.as<float>(), B[i], out[i]});
+  hipStream_t s = (hipStream_t)stream;
+  // autotune the reduction split policy: time each candidate on the caller's stream
+  const int candidates[] = {256, 512, 1024, 2048, 4096};
+  double best = 1e30;
+  int best_t = 1024;
+  hipEvent_t e0, e1;
+  AMM_HIP(hipEventCreate(&e0));
+  AMM_HIP(hipEventCreate(&e1));
+  amm_status st = AMM_OK;
+  for (int t : candidates) {
+    if ((st = batch_build(bp, t)) != AMM_OK) break;
+    if ((st = batch_launch(bp, s)) != AMM_OK) break;  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && st == AMM_OK; ++r) st = batch_launch(bp, s);
+    (void)hipEventRecord(e1, s);
+    if (st != AMM_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(AMM_EDEVICE, "tuning"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) { best = ms; best_t = t; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == AMM_OK) st = batch_build(bp, best_t);
+  bp->tuned_ms = best / 3.0;
+  // capture the two launches once; runs replay the graph
+  if (st == AMM_OK && hipStreamCreateWithFlags(&bp->own, hipStreamNonBlocking) != hipSuccess) st = fail(AMM_EDEVICE, "stream");
+  if (st == AMM_OK) {
+    KernelTimer* saved = g_timer;
+    g_timer = nullptr;
+    if (hipStreamBeginCapture(bp->own, hipStreamCaptureModeThreadLocal) != hipSuccess) st = fail(AMM_EDEVICE, "capture");
+    if (st == AMM_OK) {
+      amm_status ls = batch_launch(bp, bp->own);
+      hipError_t ce = hipStreamEndCapture(bp->own, &bp->graph);
+      if (ls != AMM_OK) st = ls;
+      else if (ce != hipSuccess) st = hip_fail(ce, "hipStreamEndCapture");
+    }
+    if (st == AMM_OK && hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
+      st = fail(AMM_EDEVICE, "hipGraphInstantiate");
+    g_timer = saved;
+  }
+  if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "sync");
+  if (st != AMM_OK) {
+    delete bp;
+    return st;
+  }
+  *plan = bp;
+  return AMM_OK;
+}
+
+amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream) {
+  if (!plan) return fail(AMM_EINVAL, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  TimerScope ts(plan->ctx);
+  if (use_graph && plan->exec && !g_timer) {
+    AMM_HIP(hipGraphLaunch(plan->exec, s));
+    return AMM_OK;
+  }
+  return batch_launch(plan, s);
+}
+
+amm_status amm_batch_info(const amm_batch_plan* plan, int* target_blocks, int* panel_blocks, int* out_blocks,
+                          double* tuned_ms) {
+  if (!plan) return fail(AMM_EINVAL, "NULL plan");
+  if (target_blocks) *target_blocks = plan->target_blocks;
+  if (panel_blocks) *panel_blocks = plan->panel_blocks;
+  if (out_blocks) *out_blocks = plan->out_blocks;
+  if (tuned_ms) *tuned_ms = plan->tuned_ms;
+  return AMM_OK;
+}
+
+void amm_batch_plan_destroy(amm_batch_plan* plan) {
+  if (!plan) return;
+  if (plan->own) (void)hipStreamSynchronize(plan->own);
+  delete plan;
 }
 
 }  // extern "C"

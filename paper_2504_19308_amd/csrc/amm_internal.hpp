@@ -127,6 +127,32 @@ struct amm_dec {
   ~amm_dec();
 };
 
+struct amm_batch_plan {
+  struct Item {
+    int64_t m, n, p;
+    const float* V;    // n x k
+    const float* US;   // m x k
+    const float* B;    // n x p
+    float* out;        // m x p
+  };
+  amm_ctx* ctx = nullptr;
+  int k = 0;
+  std::vector<Item> items;
+  std::vector<int> splits;
+  int target_blocks = 0;
+  int panel_blocks = 0, out_blocks = 0;
+  amm::DevBuf partials, tables;
+  void* pjobs = nullptr;
+  void* ojobs = nullptr;
+  int* pstart = nullptr;
+  int* ostart = nullptr;
+  hipStream_t own = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double tuned_ms = 0.0;
+  ~amm_batch_plan();
+};
+
 namespace amm {
 
 // ---- kernel launchers (defined in the .hip files) ---------------------------
@@ -203,6 +229,11 @@ amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);
 amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                            float* dX, float* dW, hipStream_t s);
+// Batched truncated-SVD products (tsvd_apply.hip)
+amm_status batch_build(amm_batch_plan* bp, int target_blocks);
+amm_status batch_launch(amm_batch_plan* bp, hipStream_t s);
+bool batch_item_ok(int64_t m, int64_t n, int64_t p, int k);
+int batch_max_items();
 // Build the CSC copy of a CSR part held on the device (host transpose).
 amm_status build_csc(amm_dec* d);
 

@@ -205,15 +205,29 @@ constexpr int OAS = OKC + 4, OBS = OT + 16;
 
 // A2 and B1 may each be the sum of `a2s` / `b1s` partial slabs (split
 // reductions of the panel launch), added here in a fixed order.
-__global__ void __launch_bounds__(256)
-out_kernel(int64_t M, int64_t N, int K1, int K2, const float* __restrict__ A1, int64_t lda1,
-           const float* __restrict__ A2, int64_t lda2, int a2s, int64_t a2_stride,
-           const float* __restrict__ B1, int64_t ldb1, int b1s, int64_t b1_stride,
-           const float* __restrict__ B2, int64_t ldb2, float* __restrict__ C, int64_t ldc) {
-  __shared__ __align__(16) float As[OT * OAS];
-  __shared__ __align__(16) float Bs[OKC * OBS];
+struct OutJob {
+  int64_t M, N;
+  int K1, K2;
+  const float* A1; int64_t lda1;
+  const float* A2; int64_t lda2; int a2s; int64_t a2_stride;
+  const float* B1; int64_t ldb1; int b1s; int64_t b1_stride;
+  const float* B2; int64_t ldb2;
+  float* C; int64_t ldc;
+};
+
+__device__ __forceinline__ void out_tile(const OutJob& jb, int tile, float* As, float* Bs) {
+  const int64_t M = jb.M, N = jb.N;
+  const int K1 = jb.K1, K2 = jb.K2;
+  const float* __restrict__ A1 = jb.A1;
+  const float* __restrict__ A2 = jb.A2;
+  const float* __restrict__ B1 = jb.B1;
+  const float* __restrict__ B2 = jb.B2;
+  float* __restrict__ C = jb.C;
+  const int64_t lda1 = jb.lda1, lda2 = jb.lda2, ldb1 = jb.ldb1, ldb2 = jb.ldb2, ldc = jb.ldc;
+  const int a2s = jb.a2s, b1s = jb.b1s;
+  const int64_t a2_stride = jb.a2_stride, b1_stride = jb.b1_stride;
+  (void)M;
   const int ntn = (int)(N / OT);
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t m0 = (int64_t)(tile / ntn) * OT, n0 = (int64_t)(tile % ntn) * OT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -302,6 +316,53 @@ out_kernel(int64_t M, int64_t N, int K1, int K2, const float* __restrict__ A1, i
         C[(m0 + wm + a * 16 + lk * 4 + r) * ldc + n0 + wn + b * 16 + li] = acc[a][b][r];
 }
 
+__global__ void __launch_bounds__(256) out_kernel(OutJob jb) {
+  __shared__ __align__(16) float As[OT * OAS];
+  __shared__ __align__(16) float Bs[OKC * OBS];
+  out_tile(jb, xcd_tile(blockIdx.x, gridDim.x), As, Bs);
+}
+
+// ---- batches: one launch covers the tiles of many products --------------------
+// Block b belongs to the job j with start[j] <= b < start[j + 1] (start has
+// count + 1 entries); the search is over a short table in LDS.
+constexpr int MAX_BATCH = 256;
+
+__device__ __forceinline__ int find_job(const int* __restrict__ start, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int A>
+__global__ void __launch_bounds__(256)
+panel_batch_kernel(const PanelJob* __restrict__ jobs, const int* __restrict__ start, int count) {
+  __shared__ __align__(16) float smem[PanelCfg<A, G_TB>::SMEM_ALL];
+  __shared__ int st[MAX_BATCH + 1];
+  for (int i = threadIdx.x; i <= count; i += blockDim.x) st[i] = start[i];
+  __syncthreads();
+  const int b = blockIdx.x;
+  const int j = find_job(st, count, b);
+  const PanelJob jb = jobs[j];
+  panel_tile<A, G_TB, true>(jb, b - st[j], st[j + 1] - st[j], smem);
+}
+
+__global__ void __launch_bounds__(256)
+out_batch_kernel(const OutJob* __restrict__ jobs, const int* __restrict__ start, int count) {
+  __shared__ __align__(16) float As[OT * OAS];
+  __shared__ __align__(16) float Bs[OKC * OBS];
+  __shared__ int st[MAX_BATCH + 1];
+  for (int i = threadIdx.x; i <= count; i += blockDim.x) st[i] = start[i];
+  __syncthreads();
+  const int b = blockIdx.x;
+  const int j = find_job(st, count, b);
+  const OutJob jb = jobs[j];
+  out_tile(jb, xcd_tile(b - st[j], st[j + 1] - st[j]), As, Bs);
+}
+
 template <int AG, int AH>
 amm_status launch_panel2(const PanelJob& g, const PanelJob& h, hipStream_t s) {
   const int64_t nb = (AG > 0 ? (int64_t)g.ntiles * g.splits : 0) + (AH > 0 ? (int64_t)h.ntiles * h.splits : 0);
@@ -382,9 +443,9 @@ amm_status tsvd_fast_product(int64_t m, int64_t n, int64_t p, int ka, int kb, co
   const int64_t tiles = (m / OT) * (p / OT);
   if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "output too large");
   TimedLaunch tl("gemm_out", s);
-  hipLaunchKernelGGL(out_kernel, dim3((unsigned)tiles), dim3(256), 0, s, m, p, ka, kb, US_A, (int64_t)ka,
-                     (const float*)H, (int64_t)kb, hs, (int64_t)kb * m, (const float*)Gp, p, gs,
-                     (int64_t)ka * p, VSt_B, p, out, p);
+  OutJob oj{m, p, ka, kb, US_A, (int64_t)ka, H, (int64_t)kb, hs, (int64_t)kb * m, Gp, p, gs,
+            (int64_t)ka * p, VSt_B, p, out, p};
+  hipLaunchKernelGGL(out_kernel, dim3((unsigned)tiles), dim3(256), 0, s, oj);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -413,11 +474,99 @@ amm_status gemm_short(int64_t M, int64_t N, int K, const float* A, const float* 
   if (!gemm_short_ok(M, N, K)) return fail(AMM_EUNSUPPORTED, "short-K GEMM shape");
   const int64_t tiles = (M / OT) * (N / OT);
   TimedLaunch tl("gemm_out", s);
-  hipLaunchKernelGGL(out_kernel, dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, 0, A, (int64_t)K,
-                     (const float*)nullptr, (int64_t)0, 1, (int64_t)0, B, N, 1, (int64_t)0,
-                     (const float*)nullptr, (int64_t)0, C, N);
+  OutJob oj{M, N, K, 0, A, (int64_t)K, nullptr, 0, 1, 0, B, N, 1, 0, nullptr, 0, C, N};
+  hipLaunchKernelGGL(out_kernel, dim3((unsigned)tiles), dim3(256), 0, s, oj);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
+
+
+// ---- batch plans ---------------------------------------------------------------
+namespace {
+
+template <int A>
+amm_status launch_panel_batch(const PanelJob* jobs, const int* start, int count, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((panel_batch_kernel<A>), dim3((unsigned)blocks), dim3(256), 0, s, jobs, start, count);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status panel_batch(int a, const PanelJob* jobs, const int* start, int count, int blocks, hipStream_t s) {
+  switch (a) {
+    case 16: return launch_panel_batch<16>(jobs, start, count, blocks, s);
+    case 32: return launch_panel_batch<32>(jobs, start, count, blocks, s);
+    case 48: return launch_panel_batch<48>(jobs, start, count, blocks, s);
+    case 64: return launch_panel_batch<64>(jobs, start, count, blocks, s);
+    case 128: return launch_panel_batch<128>(jobs, start, count, blocks, s);
+    default: return fail(AMM_EUNSUPPORTED, "batch rank %d", a);
+  }
+}
+
+}  // namespace
+
+amm_status batch_build(amm_batch_plan* bp, int target_blocks) {
+  const int count = (int)bp->items.size();
+  std::vector<PanelJob> pj(count);
+  std::vector<OutJob> oj(count);
+  std::vector<int> ps(count + 1, 0), os(count + 1, 0);
+  std::vector<int> splits(count);
+  size_t part_floats = 0;
+  int64_t total_tiles = 0;
+  for (auto& it : bp->items) total_tiles += it.p / G_TB;
+  for (int i = 0; i < count; ++i) {
+    const auto& it = bp->items[i];
+    const int tiles = (int)(it.p / G_TB);
+    int sp = 1;
+    while (sp < 8 && total_tiles * sp * 2 <= target_blocks && it.n / (sp * 2) >= 256 && it.n % (8 * sp) == 0) sp *= 2;
+    splits[i] = sp;
+    part_floats += (size_t)sp * bp->k * it.p;
+    ps[i + 1] = ps[i] + tiles * sp;
+    os[i + 1] = os[i] + (int)((it.m / OT) * (it.p / OT));
+  }
+  AMM_TRY(bp->partials.reserve(part_floats * sizeof(float)));
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    const auto& it = bp->items[i];
+    float* G = bp->partials.as<float>() + off;
+    off += (size_t)splits[i] * bp->k * it.p;
+    pj[i] = PanelJob{it.V, it.B, it.p, it.n, (int)(it.p / G_TB), splits[i], G, it.p, 1, (int64_t)bp->k * it.p};
+    oj[i] = OutJob{it.m, it.p, bp->k, 0, it.US, (int64_t)bp->k, nullptr, 0, 1, 0, G, it.p, splits[i],
+                   (int64_t)bp->k * it.p, nullptr, 0, it.out, it.p};
+  }
+  AMM_TRY(bp->tables.reserve(count * (sizeof(PanelJob) + sizeof(OutJob)) + 2 * (count + 1) * sizeof(int) + 64));
+  char* base = bp->tables.as<char>();
+  bp->pjobs = base;
+  bp->ojobs = base + count * sizeof(PanelJob);
+  bp->pstart = reinterpret_cast<int*>(base + count * (sizeof(PanelJob) + sizeof(OutJob)));
+  bp->ostart = bp->pstart + count + 1;
+  AMM_HIP(hipMemcpy(bp->pjobs, pj.data(), count * sizeof(PanelJob), hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(bp->ojobs, oj.data(), count * sizeof(OutJob), hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(bp->pstart, ps.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(bp->ostart, os.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
+  bp->panel_blocks = ps[count];
+  bp->out_blocks = os[count];
+  bp->splits = splits;
+  bp->target_blocks = target_blocks;
+  return AMM_OK;
+}
+
+amm_status batch_launch(amm_batch_plan* bp, hipStream_t s) {
+  const int count = (int)bp->items.size();
+  {
+    TimedLaunch tl("batch_panel", s);
+    AMM_TRY(panel_batch(bp->k, reinterpret_cast<const PanelJob*>(bp->pjobs), bp->pstart, count, bp->panel_blocks, s));
+  }
+  TimedLaunch tl("batch_out", s);
+  hipLaunchKernelGGL(out_batch_kernel, dim3((unsigned)bp->out_blocks), dim3(256), 0, s,
+                     reinterpret_cast<const OutJob*>(bp->ojobs), (const int*)bp->ostart, count);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+bool batch_item_ok(int64_t m, int64_t n, int64_t p, int k) {
+  return tsvd_fast_shapes(m, n, p, k, 0) && p % G_TB == 0 && k > 0;
+}
+
+int batch_max_items() { return MAX_BATCH; }
 
 }  // namespace amm
