@@ -28,7 +28,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 MFMA_F32_PEAK = 157.3e12     # flop/s, dense FP32 matrix cores
-VALU_F32_PEAK = 78.6e12      # flop/s, FP32 vector FMA without packed-FP32 forms
+VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz; no packed-FP32 forms
+
+
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised
+# in profiles/tsvd_first_order_n4096.md (KiB per dispatch, n = 4096, rank 32),
+# with the scale factors a 256 MiB elementwise copy gave (FETCH x2.0, WRITE x1.0).
+# A figure is reported only while the kernel source still has the hash it had
+# when the counters were taken.
+TRAFFIC = {
+    "gemm_out": {"fetch_kib": 21827.6, "write_kib": 65539.5, "src": "paper_2504_19308_amd/csrc/tsvd_apply.hip",
+                 "sha16": "d68d9cb3ff0a4a7a"},
+    "panel": {"fetch_kib": 71525.8, "write_kib": 4096.0, "src": "paper_2504_19308_amd/csrc/tsvd_apply.hip",
+              "sha16": "d68d9cb3ff0a4a7a"},
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def traffic_bytes(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["src"])
+    try:
+        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if sha != t["sha16"]:
+        return None
+    return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
 
 
 def log(msg):
@@ -45,7 +74,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="run just one variant name (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference for byte counters)")
+                    help="also run a plain 256 MiB elementwise copy kernel (reference for byte counters)")
     return ap.parse_args()
 
 
@@ -164,7 +193,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_bytes(name)
     roof["kernel"] = name
     roof["avg_us"] = avg_s * 1e6
     roof["algorithmic_bytes"] = byts
@@ -176,7 +205,7 @@ def main():
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).normal_()
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            torch.neg(src, out=dst)    # one elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
         del src, dst
 
@@ -221,6 +250,38 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False):
+    """Roofline fraction of one kernel launch of a variant (algorithmic bytes
+    and flops; the larger of the two times at peak decides the bound)."""
+    import math as _m
+    if name in ("cd_apply_columns", "cd_apply_rows"):
+        byts = 2.0 * n * p * 4 + K * n * 8
+        fl = p * n * (5.0 * _m.log2(n) + 4.0 * K)
+        peak_fl = VALU_F32_PEAK
+    elif name == "panel":
+        # zeroth: V^T B streams B; first order: also A against U_B
+        byts = 4.0 * n * p * (2 if first else 1)
+        fl = 2.0 * k * n * p * (2 if first else 1)
+        peak_fl = MFMA_F32_PEAK
+    elif name == "gemm_out":
+        # short-K product writing the m x p result; K = k (zeroth) or 2k (first)
+        byts = 4.0 * n * p
+        fl = 2.0 * n * p * k * (2 if first else 1)
+        peak_fl = MFMA_F32_PEAK
+    elif name in ("spmm_csr", "dense_times_csr"):
+        byts = 8.0 * nnz + 4.0 * 2 * n * p
+        fl = 2.0 * nnz * p
+        peak_fl = VALU_F32_PEAK
+    else:
+        return None
+    t = ms_per_launch * 1e-3
+    if fl / peak_fl > byts / HBM_PEAK:
+        return {"kernel": name, "bound": "alu" if peak_fl == VALU_F32_PEAK else "mfma",
+                "achieved": fl / t / 1e12, "peak": peak_fl / 1e12, "unit": "TFLOP/s", "frac": fl / t / peak_fl}
+    return {"kernel": name, "bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": byts / t / HBM_PEAK}
+
+
 def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
     n = A.shape[0]
     res = []
@@ -234,7 +295,8 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         torch.cuda.synchronize()
         return d, (time.perf_counter() - a) * 1e3
 
-    def measure(name, dA, dB, Bm, dec_ms, ex):
+    def measure(name, dA, dB, Bm, dec_ms, ex, K=0, k=0, nnz=0):
+        first = dB is not None
         if only and only != name:
             return
         fn = lambda: ctx.approx_matmul(dA, Bm, dB, out=out)
@@ -244,41 +306,154 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         kt = ctx.timings()
         ctx.set_timing(False)
         err = rel_err(out, ex)
+        roofs = [r for r in (kernel_roof(kn, v[0] / v[1], n, n, K=K, k=k, nnz=nnz, first=first) for kn, v in kt.items()) if r]
         res.append({"name": name, "ms": ms, "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12,
                     "speedup_vs_dense_fp32": dense_ms / ms, "err_vs_exact": err,
                     "meets_1pct": err <= 0.01, "decompose_ms": dec_ms,
-                    "kernels_ms": {k: v[0] for k, v in kt.items()}})
+                    "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    # circulant
-    for K in (8, 32, 128):
-        dA, ta = dec(A, None, "circulant", K)
-        dB, tb = dec(B, None, "circulant", K)
-        measure(f"circulant K={K} zeroth", dA, None, B, ta, exact)
-        measure(f"circulant K={K} first", dA, dB, B, ta + tb, exact)
-        del dA, dB
-    # truncated SVD
-    for k in (32, 128):
-        if ("tsvd", k) in cache:
-            dA, dB = cache[("tsvd", k)]
-            ta = tb = float("nan")
-        else:
-            dA, ta = dec(A, None, "tsvd", k, seed=1)
-            dB, tb = dec(B, None, "tsvd", k, seed=2)
-        measure(f"tsvd k={k} zeroth", dA, None, B, ta, exact)
-        measure(f"tsvd k={k} first", dA, dB, B, ta + tb, exact)
-    # sparsified operands: 1% Laplace(10) entries over the same low-rank decay
-    from paper_2504_19308_amd import inputs
-    sp = inputs.workload_c2(n, device="cuda", with_sparse=True)
-    As, Bs = sp.A.float().contiguous(), sp.B.float().contiguous()
-    ex_s = As.double() @ Bs.double()
-    for inner, K in (("tsvd", 32), ("circulant", 8)):
-        dA, ta = dec(As, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=3)
-        dB, tb = dec(Bs, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=4)
-        measure(f"sparse1%+{inner} K={K} zeroth", dA, None, Bs, ta, ex_s)
-        measure(f"sparse1%+{inner} K={K} first", dA, dB, Bs, ta + tb, ex_s)
-        del dA, dB
+    if not only or only not in ("batch", "layer"):
+        # circulant
+        for K in (8, 32, 128):
+            dA, ta = dec(A, None, "circulant", K)
+            dB, tb = dec(B, None, "circulant", K)
+            K_eff = dA.info()["K_eff"]
+            measure(f"circulant K={K} zeroth", dA, None, B, ta, exact, K=K_eff)
+            measure(f"circulant K={K} first", dA, dB, B, ta + tb, exact, K=K_eff)
+            del dA, dB
+        # truncated SVD
+        for k in (32, 128):
+            if ("tsvd", k) in cache:
+                dA, dB = cache[("tsvd", k)]
+                ta = tb = float("nan")
+            else:
+                dA, ta = dec(A, None, "tsvd", k, seed=1)
+                dB, tb = dec(B, None, "tsvd", k, seed=2)
+            measure(f"tsvd k={k} zeroth", dA, None, B, ta, exact, k=k)
+            measure(f"tsvd k={k} first", dA, dB, B, ta + tb, exact, k=k)
+        # sparsified operands: 1% Laplace(10) entries over the same low-rank decay
+        from paper_2504_19308_amd import inputs
+        sp = inputs.workload_c2(n, device="cuda", with_sparse=True)
+        As, Bs = sp.A.float().contiguous(), sp.B.float().contiguous()
+        ex_s = As.double() @ Bs.double()
+        for inner, K in (("tsvd", 32), ("circulant", 8)):
+            dA, ta = dec(As, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=3)
+            dB, tb = dec(Bs, None, f"sparse+{inner}", K, sparse_frac=0.01, seed=4)
+            nz = dA.info()["nnz"]
+            measure(f"sparse1%+{inner} K={K} zeroth", dA, None, Bs, ta, ex_s, K=K, k=K, nnz=nz)
+            measure(f"sparse1%+{inner} K={K} first", dA, dB, Bs, ta + tb, ex_s, K=K, k=K, nnz=nz)
+            del dA, dB
+        del As, Bs, ex_s
+        torch.cuda.empty_cache()
+    if not only or only == "batch":
+        res.append(batch_workload(torch, ctx, tm))
+    if not only or only == "layer":
+        res.append(layer_workload(torch, ctx, tm))
     return res
+
+
+def batch_workload(torch, ctx, tm, k=128, pcols=2048, count=64):
+    """64 uneven pairs (shape i mod 3 of 4096x4096, 11008x4096, 4096x11008),
+    A_i = Q1 diag(i^-1) Q2^T with Haar factors, B_i 2048 columns of N(0,1);
+    rank-128 truncated-SVD products, all in one planned batch (graph replay).
+    The exact top-128 singular triplets of A_i are its generator's leading
+    factors, imported directly.  The first pair of each shape is generated in
+    full (r = min(m, n) Haar columns) and its error measured against
+    A_i B_i in float64; the other pairs need only their 128 leading columns."""
+    from paper_2504_19308_amd import inputs
+    shapes = [(4096, 4096), (11008, 4096), (4096, 11008)]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.seed_of(3, 1))
+    decs, Bs, flops = [], [], 0.0
+    exact = {}
+    t0 = time.time()
+    for i in range(count):
+        m, n = shapes[i % 3]
+        rng = inputs.rng_of(3, 0, i)
+        full = i < 3
+        r = min(m, n) if full else k
+        sig = inputs.decay_power(min(m, n), 1.0)
+        Q1 = inputs.haar_columns(m, r, rng, device="cuda")
+        Q2 = inputs.haar_columns(n, r, rng, device="cuda")
+        decs.append(ctx.import_tsvd(Q1[:, :k].cpu().numpy(), sig[:k], Q2[:, :k].cpu().numpy()))
+        Bs.append(torch.randn((n, pcols), generator=g, device="cuda", dtype=torch.float32))
+        if full:
+            s64 = torch.from_numpy(sig).cuda()
+            exact[i] = (Q1 * s64) @ (Q2.t() @ Bs[-1].double())
+        del Q1, Q2
+        flops += 2.0 * m * n * pcols
+    torch.cuda.synchronize()
+    log(f"[bench] batch inputs {time.time() - t0:.1f}s")
+    plan = ctx.batch_plan(decs, Bs)
+    ms = statistics.median(tm.run(lambda: plan.run(use_graph=True), 20, 3))
+    errs = {f"{shapes[i][0]}x{shapes[i][1]}": rel_err(plan.outs[i], exact[i]) for i in exact}
+    ms_eager = statistics.median(tm.run(lambda: plan.run(use_graph=False), 20, 3))
+    ctx.set_timing(True)
+    plan.run(use_graph=False)
+    kt = ctx.timings()
+    ctx.set_timing(False)
+    del exact
+    # dense FP32 baseline: the same 64 products with torch.matmul
+    dense = []
+    for (m, n) in shapes:
+        Ad = torch.randn((m, n), device="cuda")
+        Bd = torch.randn((n, pcols), device="cuda")
+        dense.append(statistics.median(tm.run(lambda: torch.matmul(Ad, Bd), 10, 2)))
+        del Ad, Bd
+    dense_ms = sum(dense[i % 3] for i in range(count))
+    info = plan.info()
+    worst = max(errs.values())
+    rec = {"name": f"batch {count} uneven pairs tsvd k={k} zeroth (graph)", "ms": ms, "ms_eager": ms_eager,
+           "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+           "dense_fp32_ms": dense_ms, "err_vs_exact": errs, "meets_1pct": worst <= 0.01,
+           "plan": info, "kernels_ms": {kn: v[0] for kn, v in kt.items()},
+           "precision": "float32 factors and activations"}
+    log(f"[bench] batch: {ms:.3f} ms (eager {ms_eager:.3f}), dense {dense_ms:.3f} ms, err {errs}")
+    plan.close()
+    del decs, Bs
+    torch.cuda.empty_cache()
+    return rec
+
+
+def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
+    """Differentiable layer Y = approx(W) X, W 4096x4096 with sigma_i = i^-1.2,
+    X 4096x8192 and dY N(0,1): forward + backward (dX, dW), truncated SVD of
+    rank 128 with the structure frozen; dense FP32 forward + 2 backward GEMMs
+    as the baseline."""
+    from paper_2504_19308_amd import inputs
+    W = inputs.spectral_matrix(n, n, inputs.decay_power(n, 1.2), inputs.rng_of(4, 0), device="cuda").float()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.seed_of(4, 1))
+    X = torch.randn((n, pcols), generator=g, device="cuda")
+    dY = torch.randn((n, pcols), generator=g, device="cuda")
+    t0 = time.perf_counter()
+    d = ctx.decompose(W, "tsvd", k, seed=7)
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - t0) * 1e3
+    Y = torch.empty((n, pcols), device="cuda")
+
+    def step():
+        ctx.approx_matmul(d, X, out=Y)
+        ctx.approx_matmul_backward(d, X, dY)
+
+    ms = statistics.median(tm.run(step, 10, 3))
+    ctx.set_timing(True)
+    step()
+    kt = ctx.timings()
+    ctx.set_timing(False)
+    dense_ms = statistics.median(tm.run(lambda: (W @ X, W.t() @ dY, dY @ X.t()), 5, 2))
+    exact = W.double() @ X.double()
+    err = float((Y.double() - exact).norm() / exact.norm())
+    flops = 3 * 2.0 * n * n * pcols
+    rec = {"name": f"layer fwd+bwd tsvd k={k} (W {n}x{n}, X {n}x{pcols})", "ms": ms,
+           "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+           "dense_fp32_ms": dense_ms, "forward_err_vs_exact": err, "decompose_ms": dec_ms,
+           "kernels_ms": {kn: v[0] for kn, v in kt.items()}}
+    log(f"[bench] layer fwd+bwd: {ms:.3f} ms, dense {dense_ms:.3f} ms, fwd err {err:.3e}")
+    del W, X, dY, Y, exact
+    torch.cuda.empty_cache()
+    return rec
 
 
 def cpu_baseline(pair, A, B, k, flops_equiv):
