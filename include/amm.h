@@ -30,7 +30,7 @@
  *     its component buffers; it is immutable after creation and may be used
  *     from several streams, but must outlive the work enqueued with it.
  *   - Circulant decompositions need a square operand with n a power of two,
- *     2 <= n <= 4096; other n return AMM_EUNSUPPORTED.
+ *     2 <= n <= 16384; other n return AMM_EUNSUPPORTED.
  */
 #ifndef AMM_H
 #define AMM_H

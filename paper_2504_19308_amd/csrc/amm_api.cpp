@@ -402,7 +402,7 @@ amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_
                                     double norm_residual, amm_dec** out) {
   if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
   const int l2 = log2_exact(n);
-  if (l2 < 1 || l2 > 12) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 4096], got %lld", (long long)n);
+  if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384], got %lld", (long long)n);
   if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
   if (K > 0 && (!freqs || !eig)) return fail(AMM_EINVAL, "NULL frequencies or eigenvalues");
   for (int t = 0; t < K; ++t)
@@ -612,7 +612,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
   if (kind == AMM_CIRCULANT) {
     if (m != n) return fail(AMM_ESHAPE, "circulant decomposition needs a square operand");
     const int l2 = log2_exact(n);
-    if (l2 < 1 || l2 > 12) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 4096]");
+    if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384]");
     if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
     amm_dec* d = new amm_dec();
     d->kind = AMM_CIRCULANT;

@@ -23,9 +23,11 @@ namespace {
 
 template <int LOG2N> struct CdCfg {
   static constexpr int N = 1 << LOG2N;
-  static constexpr int C = LOG2N <= 10 ? 16 : (LOG2N == 11 ? 8 : 4);   // packed columns
+  // packed columns per workgroup: the spectra of a tile fill ~139 KiB of LDS
+  // from n = 4096 up (n = 16384 holds a single packed column pair)
+  static constexpr int C = LOG2N <= 10 ? 16 : (LOG2N >= 12 ? (1 << (14 - LOG2N)) : 8);
   static constexpr int T = LOG2N <= 8 ? 256 : (LOG2N == 9 ? 512 : 1024);  // threads
-  static constexpr int CPL = 4;                                         // cols per MAC lane
+  static constexpr int CPL = C < 4 ? C : 4;                             // cols per MAC lane
   static constexpr int G = C / CPL;
   static constexpr int BL = T / G;                                      // MAC bin lanes
   static constexpr int NBINS = (N + BL - 1) / BL;
@@ -124,8 +126,8 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   // ---- load -----------------------------------------------------------------
   // All global loads of a thread are issued before its first LDS store.
   if (!ROWS) {
-    if (vec4) {
-      constexpr int V = 2 * C / 4;                       // float4 per row
+    if (2 * C >= 4 && vec4) {
+      constexpr int V = 2 * C >= 4 ? 2 * C / 4 : 1;      // float4 per row
       constexpr int TOT = N * V, NL = (TOT + T - 1) / T;
       float4 r[NL];
 #pragma unroll
@@ -181,12 +183,20 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
         const float2 l = Lt[p];
         const int q = (p - k) & (N - 1);
         float2 x[CPL];
-        const float4* src = reinterpret_cast<const float4*>(&lds[pad_bin(q) * C + cg * CPL]);
-        const float4 x01 = src[0], x23 = src[1];
-        x[0] = float2{x01.x, x01.y};
-        x[1] = float2{x01.z, x01.w};
-        x[2] = float2{x23.x, x23.y};
-        x[3] = float2{x23.z, x23.w};
+        const float2* src = &lds[pad_bin(q) * C + cg * CPL];
+        if constexpr (CPL == 4) {
+          const float4 x01 = reinterpret_cast<const float4*>(src)[0], x23 = reinterpret_cast<const float4*>(src)[1];
+          x[0] = float2{x01.x, x01.y};
+          x[1] = float2{x01.z, x01.w};
+          x[2] = float2{x23.x, x23.y};
+          x[3] = float2{x23.z, x23.w};
+        } else if constexpr (CPL == 2) {
+          const float4 x01 = reinterpret_cast<const float4*>(src)[0];
+          x[0] = float2{x01.x, x01.y};
+          x[1] = float2{x01.z, x01.w};
+        } else {
+          x[0] = src[0];
+        }
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
           acc[i][c].x += l.x * x[c].x - l.y * x[c].y;
@@ -200,9 +210,9 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   for (int i = 0; i < NBINS; ++i) {
     const int p = bl + i * BL;
     if (N % BL == 0 || p < N) {
-      float4* dst = reinterpret_cast<float4*>(&lds[pad_bin(p) * C + cg * CPL]);
-      dst[0] = float4{acc[i][0].x, acc[i][0].y, acc[i][1].x, acc[i][1].y};
-      dst[1] = float4{acc[i][2].x, acc[i][2].y, acc[i][3].x, acc[i][3].y};
+      float2* dst = &lds[pad_bin(p) * C + cg * CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) dst[c] = acc[i][c];
     }
   }
   __syncthreads();
@@ -213,8 +223,8 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   // ---- store ----------------------------------------------------------------
   const float scale = SPEC ? 1.0f : 1.0f / (float)N;
   if (!ROWS) {
-    if (vec4) {
-      constexpr int V = 2 * C / 4;
+    if (2 * C >= 4 && vec4) {
+      constexpr int V = 2 * C >= 4 ? 2 * C / 4 : 1;
       constexpr int TOT = N * V, NL = (TOT + T - 1) / T;
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
@@ -267,7 +277,8 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
   dim3 grid((unsigned)tiles), block(Cfg::T);
   TimedLaunch tl(spec ? "cd_spectrum" : (rows ? "cd_apply_rows" : "cd_apply_columns"), s);
   // float4 path: whole float4 groups inside a row and 16-byte aligned rows
-  const int vec4 = (!rows && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
+  const int vec4 = (!rows && 2 * Cfg::C >= 4 && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 &&
+                    ((uintptr_t)out % 16) == 0) ? 1 : 0;
   if (spec)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
                        shifts, L, tw, 0, vec4);
@@ -289,8 +300,9 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t
   case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
+    AMM_CASE(13) AMM_CASE(14)
 #undef AMM_CASE
-    default: return fail(AMM_EUNSUPPORTED, "circulant product needs 2 <= n <= 4096, n a power of two");
+    default: return fail(AMM_EUNSUPPORTED, "circulant product needs 2 <= n <= 16384, n a power of two");
   }
 }
 

@@ -90,24 +90,69 @@ def toeplitz_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
     return v[(i[:, None] - i[None, :]) + n - 1]
 
 
-def planted_circulant(n: int, modes, rng: np.random.Generator, noise: float = 0.0):
+def planted_circulant(n: int, modes, rng: np.random.Generator, noise: float = 0.0,
+                      device=None, profiles=None):
     """A = sum_k R_k D^k over the given frequency set with random real data.
 
-    Built entrywise in the spatial domain, with no FFT: for each mode k a real
-    random cycle profile c_k is drawn and A[p,q] += Re(c_k[(p-q)%n] w^{kq})
+    Built entrywise in the spatial domain, with no FFT: for each mode k a
+    random complex cycle profile c_k is drawn and A[p,q] += Re(c_k[(p-q)%n] w^{kq})
     for the class {k, n-k} together, so A is real and its circulant content
     sits on the planted classes only.  ``noise`` adds i.i.d. N(0, noise^2).
+    With ``device`` the same draws are combined by torch on that device
+    (float64); ``profiles`` (a list) receives the drawn c_k.
     """
-    A = np.zeros((n, n))
-    p = np.arange(n)[:, None]
-    q = np.arange(n)[None, :]
-    for k in modes:
-        c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-        term = c[(p - q) % n] * np.exp(2j * np.pi * k * q / n)
-        A += term.real
+    cs = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in modes]
+    if profiles is not None:
+        profiles.extend(cs)
+    if device is None:
+        A = np.zeros((n, n))
+        p = np.arange(n)[:, None]
+        q = np.arange(n)[None, :]
+        for k, c in zip(modes, cs):
+            term = c[(p - q) % n] * np.exp(2j * np.pi * k * q / n)
+            A += term.real
+        if noise:
+            A += noise * rng.standard_normal((n, n))
+        return A
+    import torch
+    idx = torch.arange(n, device=device)
+    diff = (idx[:, None] - idx[None, :]) % n
+    A = torch.zeros((n, n), dtype=torch.float64, device=device)
+    for k, c in zip(modes, cs):
+        ct = torch.from_numpy(c).to(device)
+        ph = torch.exp(2j * np.pi * ((k * idx) % n).to(torch.float64) / n)
+        A += (ct[diff] * ph[None, :]).real
+    del diff
     if noise:
-        A += noise * rng.standard_normal((n, n))
+        A += noise * torch.from_numpy(rng.standard_normal((n, n))).to(device)
     return A
+
+
+def real_circulant_lists(n: int, S, rng: np.random.Generator) -> np.ndarray:
+    """Random eigenvalue lists (len(S) x n, complex) of a real truncated
+    circulant decomposition on the closed frequency set S: the member n-k of
+    a pair gets L_{n-k}[p] = conj(L_k[-p]); the self-paired 0 and n/2 are
+    made to satisfy it themselves."""
+    S = [int(k) for k in S]
+    pos = {k: t for t, k in enumerate(S)}
+    L = np.zeros((len(S), n), dtype=np.complex128)
+    neg = (-np.arange(n)) % n
+    done = set()
+    for k in S:
+        if k in done:
+            continue
+        kk = (n - k) % n
+        if kk not in pos:
+            raise ValueError("frequency set is not closed under k -> n-k")
+        v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        if kk == k:
+            v = 0.5 * (v + np.conj(v[neg]))
+            L[pos[k]] = v
+        else:
+            L[pos[k]] = v
+            L[pos[kk]] = np.conj(v[neg])
+        done.update((k, kk))
+    return L
 
 
 def sparse_overlay(m: int, n: int, frac: float, scale: float,
