@@ -350,6 +350,55 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         res.append(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
         res.append(layer_workload(torch, ctx, tm))
+    if not only or only == "c5":
+        res.extend(c5_workload(torch, ctx, tm))
+    return res
+
+
+def c5_workload(torch, ctx, tm, n=16384, K=64, ncols=256):
+    """n = 16384 operands S + R (0.5 % Laplace(20) entries over a rank-1024
+    decay), A and B decomposed as S + circulant_64(R); zeroth- and first-order
+    products over all 16384 columns; the error against AB in float64 on 256
+    sampled columns."""
+    from paper_2504_19308_amd import inputs
+    t0 = time.time()
+    pair = inputs.workload_c5(n, device="cuda")
+    A = pair.A.float().contiguous()
+    B = pair.B.float().contiguous()
+    del pair
+    torch.cuda.empty_cache()
+    cols = torch.from_numpy(np.sort(np.random.default_rng(inputs.seed_of(5, 9)).choice(n, ncols, replace=False))).cuda()
+    exact = A.double() @ B[:, cols].double()
+    torch.cuda.synchronize()
+    log(f"[bench] c5 inputs {time.time() - t0:.1f}s")
+    decs = []
+    for M, seed in ((A, 1), (B, 2)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        decs.append(ctx.decompose(M, "sparse+circulant", K, sparse_frac=0.005))
+        torch.cuda.synchronize()
+        decs[-1].ms = (time.perf_counter() - a) * 1e3
+    dA, dB = decs
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    flops = 2.0 * n ** 3
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 3, 1))
+    res = []
+    for name, d2 in (("zeroth", None), ("first", dB)):
+        fn = lambda: ctx.approx_matmul(dA, B, d2, out=out)
+        ms = statistics.median(tm.run(fn, 5, 2))
+        ctx.set_timing(True)
+        fn()
+        kt = ctx.timings()
+        ctx.set_timing(False)
+        err = rel_err(out[:, cols], exact)
+        res.append({"name": f"n={n} sparse0.5%+circulant K={K} {name}", "ms": ms,
+                    "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+                    "dense_fp32_ms": dense_ms, "err_vs_exact_sampled": err, "meets_1pct": err <= 0.01,
+                    "decompose_ms": dA.ms + (dB.ms if d2 is not None else 0.0), "nnz": dA.info()["nnz"],
+                    "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
+        log(f"[bench] c5 {name}: {ms:.3f} ms (dense {dense_ms:.3f}), err {err:.3e}, kernels {res[-1]['kernels_ms']}")
+    del A, B, exact, out, dA, dB, decs
+    torch.cuda.empty_cache()
     return res
 
 

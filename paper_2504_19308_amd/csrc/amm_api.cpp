@@ -196,7 +196,7 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
                        bool acc, hipStream_t s) {
   const int64_t n = d->m, p = d->n;  // Btil is n x p
   if (is_sparse(d)) {
-    AMM_TRY(dense_times_csr(X, rows, d, out, acc, s));
+    AMM_TRY(dense_times_csr(ctx, X, rows, d, out, acc, s));
     if (d->inner) AMM_TRY(right_apply(ctx, X, rows, d->inner, out, true, s));
     return AMM_OK;
   }

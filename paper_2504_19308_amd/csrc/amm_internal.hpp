@@ -85,7 +85,7 @@ struct amm_ctx {
   int device = 0;
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[6];              // grow-only work areas for products
+  amm::DevBuf scratch[8];              // grow-only work areas for products
   amm::KernelTimer timer;
   bool timing = false;
 };
@@ -222,7 +222,7 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
                           amm_dec* dec, float* R_out, hipStream_t s);
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool accumulate,
                     hipStream_t s);
-amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out,
+amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                            bool accumulate, hipStream_t s);
 
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);

@@ -117,76 +117,89 @@ fill_rows(const float* __restrict__ A, int64_t n, uint32_t T, const int32_t* __r
   }
 }
 
-// S B with S in CSR: one block per output row; each thread owns 4 adjacent
-// columns and walks the row's stored entries, gathering rows of B (coalesced
-// float4 reads shared by the block).
+// S B with S in CSR.  B is cut into slices of 64 columns; a block owns one
+// slice of 16 output rows, each row handled by 16 lanes holding 4 adjacent
+// columns, which walk the row's stored entries and gather the matching 256-byte
+// slice rows of B (4 gathers in flight, summed in entry order).  Blocks are
+// dealt so that every XCD sweeps whole slices: all rows of a slice run on one
+// XCD, whose L2 then holds that slice of B (n x 256 bytes) while it is reused
+// by every stored entry.
+constexpr int SW = 64;    // columns per slice
+constexpr int RPB = 16;   // rows per block
+
 __global__ void __launch_bounds__(256)
-spmm_rows(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-          const float* __restrict__ val, const float* __restrict__ B, int64_t p,
-          float* __restrict__ out, int accumulate) {
-  const int64_t row = blockIdx.y;
-  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (c0 >= p) return;
+spmm_slices(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+            const float* __restrict__ val, const float* __restrict__ B, int64_t rows, int64_t p,
+            float* __restrict__ out, int accumulate, int nslices, int rgroups, int vec) {
+  const int bid = blockIdx.x;
+  int slice, rg;
+  if ((nslices & 7) == 0) {
+    const int xcd = bid & 7, local = bid >> 3;
+    slice = xcd * (nslices >> 3) + local / rgroups;
+    rg = local % rgroups;
+  } else {
+    slice = bid / rgroups;
+    rg = bid % rgroups;
+  }
+  const int64_t row = (int64_t)rg * RPB + (threadIdx.x >> 4);
+  const int64_t c0 = (int64_t)slice * SW + (threadIdx.x & 15) * 4;
+  if (row >= rows || c0 >= p) return;
   const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  const bool full = (c0 + 4 <= p) && ((p & 3) == 0);
-  for (int e = e0; e < e1; ++e) {
-    const float v = val[e];
-    const float* b = B + (int64_t)col[e] * p + c0;
-    if (full) {
-      const float4 x = *reinterpret_cast<const float4*>(b);
-      acc[0] += v * x.x; acc[1] += v * x.y; acc[2] += v * x.z; acc[3] += v * x.w;
-    } else {
+  float* o = out + row * p + c0;
+  if (vec) {  // p % 4 == 0 and 16-byte aligned B / out: c0 + 3 < p
+    float4 acc{0.f, 0.f, 0.f, 0.f};
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      float v[4];
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = val[e + u];
+        x[u] = *reinterpret_cast<const float4*>(B + (int64_t)col[e + u] * p + c0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc.x += v[u] * x[u].x; acc.y += v[u] * x[u].y; acc.z += v[u] * x[u].z; acc.w += v[u] * x[u].w;
+      }
+    }
+    for (; e < e1; ++e) {
+      const float v = val[e];
+      const float4 x = *reinterpret_cast<const float4*>(B + (int64_t)col[e] * p + c0);
+      acc.x += v * x.x; acc.y += v * x.y; acc.z += v * x.z; acc.w += v * x.w;
+    }
+    if (accumulate) {
+      const float4 z = *reinterpret_cast<const float4*>(o);
+      acc = float4{acc.x + z.x, acc.y + z.y, acc.z + z.z, acc.w + z.w};
+    }
+    *reinterpret_cast<float4*>(o) = acc;
+  } else {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int e = e0; e < e1; ++e) {
+      const float v = val[e];
+      const float* b = B + (int64_t)col[e] * p + c0;
       for (int q = 0; q < 4 && c0 + q < p; ++q) acc[q] += v * b[q];
     }
+    for (int q = 0; q < 4 && c0 + q < p; ++q) o[q] = accumulate ? o[q] + acc[q] : acc[q];
   }
-  float* o = out + row * p + c0;
-  for (int q = 0; q < 4 && c0 + q < p; ++q) o[q] = accumulate ? o[q] + acc[q] : acc[q];
 }
 
-// X S with S in CSC (the transpose's CSR): one workgroup owns R rows of X,
-// staged in LDS as [j][R+1]; threads over output columns gather X[., j] for
-// the stored entries of their column.  Writes are coalesced along columns.
-template <int R>
-__global__ void __launch_bounds__(256)
-dense_csc_slab(const float* __restrict__ X, int64_t rows, int64_t n, const int32_t* __restrict__ csc_ptr,
-               const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val, int64_t p,
-               float* __restrict__ out, int accumulate) {
-  extern __shared__ float xs[];
-  const int64_t r0 = (int64_t)blockIdx.x * R;
-  for (int64_t e = threadIdx.x; e < n * R; e += blockDim.x) {
-    const int r = (int)(e / n);
-    const int64_t j = e % n;
-    xs[j * (R + 1) + r] = (r0 + r < rows) ? X[(r0 + r) * n + j] : 0.f;
+// out (cols x rows) (+)= Y^T for Y rows x cols, through 32 x 33 LDS tiles
+__global__ void transpose_acc_kernel(const float* __restrict__ Y, int64_t rows, int64_t cols,
+                                     float* __restrict__ out, int accumulate) {
+  __shared__ float tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[i][threadIdx.x] = Y[r * cols + c];
   }
   __syncthreads();
-  for (int64_t c = threadIdx.x; c < p; c += blockDim.x) {
-    float acc[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = 0.f;
-    const int e1 = csc_ptr[c + 1];
-    for (int e = csc_ptr[c]; e < e1; ++e) {
-      const float v = csc_val[e];
-      const float* x = xs + (int64_t)csc_row[e] * (R + 1);
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += v * x[q];
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) {
+      float* o = out + c * rows + r;
+      *o = accumulate ? *o + tile[threadIdx.x][i] : tile[threadIdx.x][i];
     }
-#pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (r0 + q < rows) {
-        float* o = out + (r0 + q) * p + c;
-        *o = accumulate ? *o + acc[q] : acc[q];
-      }
   }
-}
-
-constexpr size_t LDS_MAX = 160 * 1024;
-
-// largest R in {8, 4, 2, 1} whose [n][R+1] slab fits in LDS (0: none fits)
-int slab_width(int64_t n) {
-  for (int R = 8; R >= 1; R /= 2)
-    if ((size_t)n * (R + 1) * sizeof(float) <= LDS_MAX) return R;
-  return 0;
 }
 
 __global__ void fill_kernel(float* __restrict__ p, int64_t count, float v) {
@@ -327,20 +340,15 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   return AMM_OK;
 }
 
-template <typename K>
-amm_status set_lds(K kernel, size_t lds) {
-  if (lds > 64 * 1024)
-    AMM_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  return AMM_OK;
-}
-
 amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
                     const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
-  if (rows > 65535) return fail(AMM_EUNSUPPORTED, "too many rows for the SpMM grid");
   if (rows <= 0 || p <= 0) return AMM_OK;
-  dim3 grid((unsigned)((p + 1023) / 1024), (unsigned)rows), block(256);
+  const int64_t nslices = (p + SW - 1) / SW, rgroups = (rows + RPB - 1) / RPB;
+  if (nslices * rgroups > 0x7fffffff || rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
+  const int vec = (p % 4 == 0 && ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
   TimedLaunch tl("spmm_csr", s);
-  hipLaunchKernelGGL(spmm_rows, grid, block, 0, s, row_ptr, col, val, B, p, out, acc ? 1 : 0);
+  hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, row_ptr, col, val, B, rows,
+                     p, out, acc ? 1 : 0, (int)nslices, (int)rgroups, vec);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -349,24 +357,31 @@ amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, boo
   return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s);
 }
 
-amm_status dense_times_csr(const float* X, int64_t rows, const amm_dec* d, float* out, bool acc,
-                           hipStream_t s) {
+// out (rows x p) (+)= X S for X rows x n and S n x p sparse:
+//   (X S)^T = S^T X^T, and S^T in CSR is S in CSC, so the product is the row
+//   gather above on X^T, transposed back into out.
+amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
+                           bool acc, hipStream_t s) {
   const int64_t n = d->m, p = d->n;
-  const int R = slab_width(n);
-  if (R == 0) return fail(AMM_EUNSUPPORTED, "inner dimension too large for the LDS row stage");
-  const int64_t blocks = (rows + R - 1) / R;
-  if (blocks > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many rows");
-  const size_t lds = (size_t)n * (R + 1) * sizeof(float);
+  if (rows <= 0 || p <= 0) return AMM_OK;
+  if ((rows + 31) / 32 > 65535 || (p + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "sparse operand too large");
+  AMM_TRY(ctx->scratch[6].reserve((size_t)n * rows * sizeof(float)));
+  AMM_TRY(ctx->scratch[7].reserve((size_t)p * rows * sizeof(float)));
+  float* Xt = ctx->scratch[6].as<float>();
+  float* Y = ctx->scratch[7].as<float>();
   TimedLaunch tl("dense_times_csr", s);
-#define AMM_DCSC(RR)                                                                                      \
-  case RR:                                                                                                \
-    AMM_TRY(set_lds(dense_csc_slab<RR>, lds));                                                            \
-    hipLaunchKernelGGL(dense_csc_slab<RR>, dim3((unsigned)blocks), dim3(256), lds, s, X, rows, n,         \
-                       d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, out, \
-                       acc ? 1 : 0);                                                                      \
-    break;
-  switch (R) { AMM_DCSC(8) AMM_DCSC(4) AMM_DCSC(2) AMM_DCSC(1) }
-#undef AMM_DCSC
+  AMM_TRY(transpose_f32(X, rows, n, Xt, s));
+  {
+    const int64_t nslices = (rows + SW - 1) / SW, rgroups = (p + RPB - 1) / RPB;
+    if (nslices * rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
+    const int vec = (rows % 4 == 0) ? 1 : 0;   // scratch buffers are 256-byte aligned
+    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, d->csc_ptr.as<int32_t>(),
+                       d->csc_row.as<int32_t>(), d->csc_val.as<float>(), Xt, p, rows, Y, 0, (int)nslices,
+                       (int)rgroups, vec);
+    AMM_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((rows + 31) / 32), (unsigned)((p + 31) / 32)),
+                     dim3(32, 8), 0, s, Y, p, rows, out, acc ? 1 : 0);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }

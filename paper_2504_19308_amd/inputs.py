@@ -209,6 +209,28 @@ def workload_c2(n: int = 4096, device=None, with_sparse: bool = False,
     return Pair(out[0], out[1], f"{tag} n={n}")
 
 
+def workload_c5(n: int = 16384, rank: int = 1024, frac: float = 0.005, lap_scale: float = 20.0,
+                device=None) -> Pair:
+    """Square operands S + R: R = Q1 diag(i^-1.5, i = 1..rank) Q2^T with thin
+    Haar factors (the energy beyond rank 1024 of the full law is ~4e-7 of the
+    total), S = round(frac n^2) Laplace(0, lap_scale) entries at uniform
+    positions."""
+    out = []
+    for operand in (0, 1):
+        rng = rng_of(5, operand)
+        M = spectral_matrix(n, n, decay_power(rank, 1.5), rng, device)
+        pos, vals = sparse_overlay(n, n, frac, lap_scale, rng_of(5, operand, 1))
+        if device is None:
+            M = M.copy()
+            M.reshape(-1)[pos] += vals
+        else:
+            import torch
+            flat = M.reshape(-1)
+            flat[torch.from_numpy(pos).to(M.device)] += torch.from_numpy(vals).to(M.device)
+        out.append(M)
+    return Pair(out[0], out[1], f"haar-pow1.5-r{rank}+sparse{frac:g}-laplace{lap_scale:g} n={n}")
+
+
 def workload_toeplitz(n: int) -> Pair:
     A = toeplitz_uniform(n, rng_of(9, 0))
     B = toeplitz_uniform(n, rng_of(9, 1))
