@@ -65,3 +65,43 @@ def test_batch_rejects_mixed_ranks():
     d2, B2, _ = _batch(c, 16, 128, 1, seed=2)
     with pytest.raises(AmmError):
         c.batch_plan(d1 + d2, B1 + B2)
+
+
+class _Factors:
+    """Given truncated-SVD factors (what the oracle's product reads)."""
+
+    def __init__(self, U, s, V):
+        self.U, self.s, self.V = U, s, V
+
+
+def test_batch_full_size_sampled():
+    """The 64-pair uneven batch at full size (4096 x 4096, 11008 x 4096,
+    4096 x 11008 by pair index mod 3; rank 128; 2048 columns), replayed as a
+    graph like the benchmark; every pair checked on sampled output columns."""
+    torch = torch_cuda()
+    note("batch full size 64 pairs")
+    shapes = [(4096, 4096), (11008, 4096), (4096, 11008)]
+    k, p, count = 128, 2048, 64
+    c = ctx()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.seed_of(3, 1))
+    decs, Bs, facs = [], [], []
+    for i in range(count):
+        m, n = shapes[i % 3]
+        rng = inputs.rng_of(3, 0, i)
+        sig = inputs.decay_power(min(m, n), 1.0)[:k]
+        U = inputs.haar_columns(m, k, rng, device="cuda").cpu().numpy()
+        V = inputs.haar_columns(n, k, rng, device="cuda").cpu().numpy()
+        decs.append(c.import_tsvd(U, sig, V))
+        # the factors the library holds are float32: the oracle uses the same
+        facs.append(_Factors(f32(U), f32(sig), f32(V)))
+        Bs.append(torch.randn((n, p), generator=g, device="cuda", dtype=torch.float32))
+    plan = c.batch_plan(decs, Bs)
+    plan.run(use_graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(64)
+    for i in range(count):
+        cols = np.sort(rng.choice(p, 6, replace=False))
+        want = ot.apply_zeroth(facs[i], Bs[i][:, cols].double().cpu().numpy())
+        got = plan.outs[i][:, cols].double().cpu().numpy()
+        assert rel(got, want) < TOL_F32, f"pair {i}"

@@ -145,3 +145,32 @@ def test_dense_times_sparse_ragged(n, k, nnz):
     dB = c.import_sparse(n, n, S.row_ptr, S.col, S.val)
     got = c.approx_matmul(dA, torch.from_numpy(Bm.astype(np.float32)).cuda(), dB)
     assert rel(got.double().cpu().numpy(), want) < TOL_F32
+
+
+def test_c5_first_order_identity_sampled():
+    """The full first-order product of the n = 16384 workload (both operands
+    decomposed on the device as S + circulant_64(R)) satisfies
+    M1 = A B - Delta A Delta B (eq. (2.1)-(2.3)) on sampled columns, with
+    Btil e_j and Atil (Delta B e_j) from the library's own zeroth-order
+    products and everything else in float64."""
+    torch = torch_cuda()
+    note("c5 first-order identity")
+    pair = inputs.workload_c5(N, device="cuda")
+    A = pair.A.float().contiguous()
+    B = pair.B.float().contiguous()
+    del pair
+    torch.cuda.empty_cache()
+    c = ctx()
+    dA = c.decompose(A, "sparse+circulant", 64, sparse_frac=FRAC)
+    dB = c.decompose(B, "sparse+circulant", 64, sparse_frac=FRAC)
+    M1 = c.approx_matmul(dA, B, dB)
+    cols = torch.from_numpy(np.sort(np.random.default_rng(5).choice(N, 32, replace=False))).cuda()
+    E = torch.zeros((N, len(cols)), device="cuda", dtype=torch.float32)
+    E[cols, torch.arange(len(cols), device="cuda")] = 1.0
+    Bhat = c.approx_matmul(dB, E)                   # Btil[:, cols]
+    dBc = B[:, cols].double() - Bhat.double()      # Delta B[:, cols]
+    AhatdB = c.approx_matmul(dA, dBc.float().contiguous()).double()
+    A64 = A.double()
+    want = A64 @ B[:, cols].double() - (A64 @ dBc - AhatdB)
+    got = M1[:, cols].double()
+    assert float((got - want).norm() / want.norm()) < TOL_F32
