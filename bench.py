@@ -347,7 +347,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         del As, Bs, ex_s
         torch.cuda.empty_cache()
     if not only or only == "batch":
-        res.append(batch_workload(torch, ctx, tm))
+        res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
         res.append(layer_workload(torch, ctx, tm))
     if not only or only == "c5":
@@ -460,9 +460,35 @@ def batch_workload(torch, ctx, tm, k=128, pcols=2048, count=64):
            "precision": "float32 factors and activations"}
     log(f"[bench] batch: {ms:.3f} ms (eager {ms_eager:.3f}), dense {dense_ms:.3f} ms, err {errs}")
     plan.close()
-    del decs, Bs
+    # the same batch with bfloat16 activations and components (float32 accumulation)
+    B16 = [b.bfloat16() for b in Bs]
+    del Bs
     torch.cuda.empty_cache()
-    return rec
+    plan16 = ctx.batch_plan(decs, B16)
+    ms16 = statistics.median(tm.run(lambda: plan16.run(use_graph=True), 20, 3))
+    ctx.set_timing(True)
+    plan16.run(use_graph=False)
+    kt16 = ctx.timings()
+    ctx.set_timing(False)
+    dense16 = []
+    for (m, n) in shapes:
+        Ad = torch.randn((m, n), device="cuda").bfloat16()
+        Bd = torch.randn((n, pcols), device="cuda").bfloat16()
+        dense16.append(statistics.median(tm.run(lambda: torch.matmul(Ad, Bd), 10, 2)))
+        del Ad, Bd
+    dense16_ms = sum(dense16[i % 3] for i in range(count))
+    byts = sum(2.0 * it_n * pcols + 4.0 * it_m * pcols for (it_m, it_n) in (shapes[i % 3] for i in range(count)))
+    rec16 = {"name": f"batch {count} uneven pairs tsvd k={k} zeroth bf16 components (graph)", "ms": ms16,
+             "tflop_equiv_s": flops / (ms16 * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms16,
+             "speedup_vs_dense_bf16": dense16_ms / ms16, "dense_bf16_ms": dense16_ms,
+             "hbm_bytes_algorithmic": byts, "hbm_frac": byts / (ms16 * 1e-3) / HBM_PEAK,
+             "plan": plan16.info(), "kernels_ms": {kn: v[0] for kn, v in kt16.items()},
+             "precision": "bfloat16 factors and activations, float32 accumulation and output"}
+    log(f"[bench] batch bf16: {ms16:.3f} ms, dense bf16 {dense16_ms:.3f} ms, HBM frac {rec16['hbm_frac']:.2f}")
+    plan16.close()
+    del decs, B16
+    torch.cuda.empty_cache()
+    return [rec, rec16]
 
 
 def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):

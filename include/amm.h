@@ -207,6 +207,17 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
 amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA,
                                  const float* const* B, const int64_t* p, float* const* out,
                                  void* stream, amm_batch_plan** plan);
+/* The same plan with bfloat16 components and float32 accumulation: B[i] are
+ * bfloat16 device matrices (n_i x p[i], row-major, caller-owned and bound to
+ * the plan), the plan keeps bfloat16 copies V_i^T and U_i S_i of each
+ * handle's factors (rounded to nearest even), and out[i] are float32.  The
+ * intermediate V_i^T B_i is accumulated in float32 and enters the second
+ * product as a hi + lo pair of bfloat16 values, so the rounding of the stored
+ * components is the only bfloat16 loss.  Shapes: rank 32, 64 or 128, m_i and
+ * p[i] multiples of 128, n_i a multiple of 32; up to 256 entries. */
+amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* const* dA,
+                                      const void* const* B, const int64_t* p, float* const* out,
+                                      void* stream, amm_batch_plan** plan);
 /* Run the plan on `stream`; use_graph != 0 replays the captured graph
  * (ignored while the context has timing enabled: then the launches are
  * issued directly so that they can be timed). */

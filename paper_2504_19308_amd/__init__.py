@@ -249,13 +249,23 @@ class Context:
 
     # -- batches ----------------------------------------------------------------
     def batch_plan(self, decs, Bs, outs=None) -> "BatchPlan":
-        """Plan out_i = Atil_i B_i for truncated-SVD handles of one rank."""
+        """Plan out_i = Atil_i B_i for truncated-SVD handles of one rank.  With
+        bfloat16 B_i the plan uses bfloat16 components (factors rounded once,
+        float32 accumulation and outputs)."""
         count = len(decs)
+        torch = self.torch
+        bf16 = all(b.dtype == torch.bfloat16 for b in Bs)
+        if not bf16 and any(b.dtype == torch.bfloat16 for b in Bs):
+            raise ValueError("B_i must be all float32 or all bfloat16")
         if outs is None:
-            outs = [self.torch.empty((d.info()["m"], b.shape[1]), dtype=self.torch.float32, device=b.device)
+            outs = [torch.empty((d.info()["m"], b.shape[1]), dtype=torch.float32, device=b.device)
                     for d, b in zip(decs, Bs)]
         for b in Bs:
-            _need_f32_cuda(b, "B")
+            if bf16:
+                if not (b.is_cuda and b.is_contiguous()):
+                    raise ValueError("B must be a contiguous CUDA bfloat16 tensor")
+            else:
+                _need_f32_cuda(b, "B")
         for o in outs:
             _need_f32_cuda(o, "out")
         hd = (C.c_void_p * count)(*[d.handle for d in decs])
@@ -263,8 +273,8 @@ class Context:
         hp = (C.c_int64 * count)(*[b.shape[1] for b in Bs])
         ho = (C.c_void_p * count)(*[o.data_ptr() for o in outs])
         h = C.c_void_p()
-        _lib.check(_lib.load().amm_batch_plan_create(self.handle, count, hd, hb, hp, ho,
-                                                     _stream_ptr(self.torch, Bs[0].device), C.byref(h)))
+        create = _lib.load().amm_batch_plan_create_bf16 if bf16 else _lib.load().amm_batch_plan_create
+        _lib.check(create(self.handle, count, hd, hb, hp, ho, _stream_ptr(torch, Bs[0].device), C.byref(h)))
         return BatchPlan(self, h, list(decs), list(Bs), list(outs))
 
     # -- backward ---------------------------------------------------------------

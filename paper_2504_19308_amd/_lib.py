@@ -56,6 +56,8 @@ SIGNATURES = {
                                     C.c_int64, C.c_void_p, C.c_void_p]),
     "amm_batch_plan_create": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amm_batch_plan_create_bf16": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]),
     "amm_batch_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "amm_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_double)]),

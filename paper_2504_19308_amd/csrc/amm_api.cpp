@@ -740,60 +740,49 @@ amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const flo
   return approx_backward(ctx, dW, X, dY, p, dX, dW_out, s);
 }
 
-amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA, const float* const* B,
-                                 const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
-  if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
-  if (count <= 0 || count > batch_max_items()) return fail(AMM_EINVAL, "batch size %d out of [1, %d]", count, batch_max_items());
-  int k = -1;
-  for (int i = 0; i < count; ++i) {
-    const amm_dec* d = dA[i];
-    if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
-    if (d->kind != AMM_TSVD) return fail(AMM_EUNSUPPORTED, "batch entries must be truncated-SVD handles");
-    if (k < 0) k = d->K_eff;
-    if (d->K_eff != k) return fail(AMM_EUNSUPPORTED, "batch entries must share one rank");
-    if (!batch_item_ok(d->m, d->n, p[i], k))
-      return fail(AMM_EUNSUPPORTED, "entry %d: shape %lldx%lld by %lld columns, rank %d not on the batched path", i,
-                  (long long)d->m, (long long)d->n, (long long)p[i], k);
-  }
-  AMM_HIP(hipSetDevice(ctx->device));
-  amm_batch_plan* bp = new amm_batch_plan();
-  bp->ctx = ctx;
-  bp->k = k;
-  for (int i = 0; i < count; ++i)
-    bp->items.push_back({dA[i]->m, dA[i]->n, p[i], dA[i]->V.as<float>(), dA[i]->US.as<float>(), B[i], out[i]});
-  hipStream_t s = (hipStream_t)stream;
-  // autotune the reduction split policy: time each candidate on the caller's stream
+}  // extern "C"
+
+namespace {
+
+amm_status plan_build(amm_batch_plan* bp, int t) { return bp->bf16 ? batch_build_bf16(bp, t) : batch_build(bp, t); }
+amm_status plan_launch(amm_batch_plan* bp, hipStream_t s) { return bp->bf16 ? batch_launch_bf16(bp, s) : batch_launch(bp, s); }
+
+// Autotune the reduction split policy by timing each candidate on the caller's
+// stream, then capture the two launches once on a plan-owned stream; runs
+// replay the graph.  Deletes the plan on failure.
+amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan) {
   const int candidates[] = {256, 512, 1024, 2048, 4096};
   double best = 1e30;
   int best_t = 1024;
   hipEvent_t e0, e1;
-  AMM_HIP(hipEventCreate(&e0));
-  AMM_HIP(hipEventCreate(&e1));
   amm_status st = AMM_OK;
-  for (int t : candidates) {
-    if ((st = batch_build(bp, t)) != AMM_OK) break;
-    if ((st = batch_launch(bp, s)) != AMM_OK) break;  // warm-up
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && st == AMM_OK; ++r) st = batch_launch(bp, s);
-    (void)hipEventRecord(e1, s);
-    if (st != AMM_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(AMM_EDEVICE, "tuning"); break; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) { best = ms; best_t = t; }
+  if (hipEventCreate(&e0) != hipSuccess) st = fail(AMM_EDEVICE, "event");
+  if (st == AMM_OK && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); st = fail(AMM_EDEVICE, "event"); }
+  if (st == AMM_OK) {
+    for (int t : candidates) {
+      if ((st = plan_build(bp, t)) != AMM_OK) break;
+      if ((st = plan_launch(bp, s)) != AMM_OK) break;  // warm-up
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && st == AMM_OK; ++r) st = plan_launch(bp, s);
+      (void)hipEventRecord(e1, s);
+      if (st != AMM_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(AMM_EDEVICE, "tuning"); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_t = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st == AMM_OK) st = batch_build(bp, best_t);
+  if (st == AMM_OK) st = plan_build(bp, best_t);
   bp->tuned_ms = best / 3.0;
-  // capture the two launches once; runs replay the graph
   if (st == AMM_OK && hipStreamCreateWithFlags(&bp->own, hipStreamNonBlocking) != hipSuccess) st = fail(AMM_EDEVICE, "stream");
   if (st == AMM_OK) {
     KernelTimer* saved = g_timer;
     g_timer = nullptr;
     if (hipStreamBeginCapture(bp->own, hipStreamCaptureModeThreadLocal) != hipSuccess) st = fail(AMM_EDEVICE, "capture");
     if (st == AMM_OK) {
-      amm_status ls = batch_launch(bp, bp->own);
+      amm_status ls = plan_launch(bp, bp->own);
       hipError_t ce = hipStreamEndCapture(bp->own, &bp->graph);
       if (ls != AMM_OK) st = ls;
       else if (ce != hipSuccess) st = hip_fail(ce, "hipStreamEndCapture");
@@ -811,6 +800,71 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
   return AMM_OK;
 }
 
+// shared argument checks: one rank, truncated-SVD handles, shapes on the path
+amm_status plan_check(int count, const amm_dec* const* dA, const void* const* B, const int64_t* p,
+                      float* const* out, bool bf16, int* k_out) {
+  if (count <= 0 || count > batch_max_items()) return fail(AMM_EINVAL, "batch size %d out of [1, %d]", count, batch_max_items());
+  int k = -1;
+  for (int i = 0; i < count; ++i) {
+    const amm_dec* d = dA[i];
+    if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
+    if (d->kind != AMM_TSVD) return fail(AMM_EUNSUPPORTED, "batch entries must be truncated-SVD handles");
+    if (k < 0) k = d->K_eff;
+    if (d->K_eff != k) return fail(AMM_EUNSUPPORTED, "batch entries must share one rank");
+    const bool ok = bf16 ? batch_item_ok_bf16(d->m, d->n, p[i], k) : batch_item_ok(d->m, d->n, p[i], k);
+    if (!ok)
+      return fail(AMM_EUNSUPPORTED, "entry %d: shape %lldx%lld by %lld columns, rank %d not on the batched path", i,
+                  (long long)d->m, (long long)d->n, (long long)p[i], k);
+  }
+  *k_out = k;
+  return AMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA, const float* const* B,
+                                 const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
+  if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
+  int k = 0;
+  AMM_TRY(plan_check(count, dA, reinterpret_cast<const void* const*>(B), p, out, false, &k));
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_batch_plan* bp = new amm_batch_plan();
+  bp->ctx = ctx;
+  bp->k = k;
+  for (int i = 0; i < count; ++i)
+    bp->items.push_back({dA[i]->m, dA[i]->n, p[i], dA[i]->V.as<float>(), dA[i]->US.as<float>(), B[i], out[i]});
+  return plan_finish(bp, (hipStream_t)stream, plan);
+}
+
+amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* const* dA, const void* const* B,
+                                      const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
+  if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
+  int k = 0;
+  AMM_TRY(plan_check(count, dA, B, p, out, true, &k));
+  AMM_HIP(hipSetDevice(ctx->device));
+  amm_batch_plan* bp = new amm_batch_plan();
+  bp->ctx = ctx;
+  bp->k = k;
+  bp->bf16 = true;
+  std::vector<const float*> V, US;
+  for (int i = 0; i < count; ++i) {
+    amm_batch_plan::Item it{dA[i]->m, dA[i]->n, p[i], nullptr, nullptr, nullptr, out[i]};
+    it.B16 = B[i];
+    bp->items.push_back(it);
+    V.push_back(dA[i]->V.as<float>());
+    US.push_back(dA[i]->US.as<float>());
+  }
+  hipStream_t s = (hipStream_t)stream;
+  amm_status st = batch_convert_bf16(bp, V, US, s);
+  if (st != AMM_OK) {
+    delete bp;
+    return st;
+  }
+  return plan_finish(bp, s, plan);
+}
+
 amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream) {
   if (!plan) return fail(AMM_EINVAL, "NULL plan");
   hipStream_t s = (hipStream_t)stream;
@@ -819,7 +873,7 @@ amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream) {
     AMM_HIP(hipGraphLaunch(plan->exec, s));
     return AMM_OK;
   }
-  return batch_launch(plan, s);
+  return plan_launch(plan, s);
 }
 
 amm_status amm_batch_info(const amm_batch_plan* plan, int* target_blocks, int* panel_blocks, int* out_blocks,

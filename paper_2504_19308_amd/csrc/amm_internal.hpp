@@ -134,9 +134,14 @@ struct amm_batch_plan {
     const float* US;   // m x k
     const float* B;    // n x p
     float* out;        // m x p
+    const void* B16 = nullptr;   // bfloat16 plans: B (n x p), V^T (k x n), U S (m x k)
+    const void* Vt16 = nullptr;
+    const void* US16 = nullptr;
   };
   amm_ctx* ctx = nullptr;
   int k = 0;
+  bool bf16 = false;            // bfloat16 components, float32 accumulation
+  amm::DevBuf fac16;            // plan-owned bfloat16 factor copies
   std::vector<Item> items;
   std::vector<int> splits;
   int target_blocks = 0;
@@ -234,6 +239,11 @@ amm_status batch_build(amm_batch_plan* bp, int target_blocks);
 amm_status batch_launch(amm_batch_plan* bp, hipStream_t s);
 bool batch_item_ok(int64_t m, int64_t n, int64_t p, int k);
 int batch_max_items();
+bool batch_item_ok_bf16(int64_t m, int64_t n, int64_t p, int k);
+amm_status batch_convert_bf16(amm_batch_plan* bp, const std::vector<const float*>& V,
+                              const std::vector<const float*>& US, hipStream_t s);
+amm_status batch_build_bf16(amm_batch_plan* bp, int target_blocks);
+amm_status batch_launch_bf16(const amm_batch_plan* bp, hipStream_t s);
 // Build the CSC copy of a CSR part held on the device (host transpose).
 amm_status build_csc(amm_dec* d);
 

@@ -47,3 +47,12 @@ def rel(x, y):
 def note(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def bf16(x):
+    """Round to bfloat16 (nearest, ties to even) through float32, as float64:
+    the exact values a bfloat16 operand holds (finite inputs)."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    b = a.view(np.uint32).astype(np.uint64)
+    r = (((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
