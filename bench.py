@@ -32,15 +32,14 @@ VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2
 
 
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised
-# in profiles/tsvd_first_order_n4096.md (KiB per dispatch, n = 4096, rank 32),
+# in profiles/ (KiB per dispatch, n = 4096, rank 32),
 # with the scale factors a 256 MiB elementwise copy gave (FETCH x2.0, WRITE x1.0).
 # A figure is reported only while the kernel source still has the hash it had
 # when the counters were taken.
 TRAFFIC = {
-    "gemm_out": {"fetch_kib": 21827.6, "write_kib": 65539.5, "src": "paper_2504_19308_amd/csrc/tsvd_apply.hip",
-                 "sha16": "d68d9cb3ff0a4a7a"},
-    "panel": {"fetch_kib": 71525.8, "write_kib": 4096.0, "src": "paper_2504_19308_amd/csrc/tsvd_apply.hip",
-              "sha16": "d68d9cb3ff0a4a7a"},
+    # kernel tag: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch and the source they were taken on
+    "panel": {"fetch_kib": None, "write_kib": None, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip", "sha16": ""},
+    "gemm_out": {"fetch_kib": None, "write_kib": None, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip", "sha16": ""},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -55,7 +54,7 @@ def traffic_bytes(kernel):
         sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if sha != t["sha16"]:
+    if sha != t["sha16"] or t["fetch_kib"] is None:
         return None
     return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
 

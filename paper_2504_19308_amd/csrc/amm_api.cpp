@@ -175,6 +175,12 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     }
     AMM_TRY(ctx->scratch[0].reserve((size_t)k * p * sizeof(float)));
     float* G = ctx->scratch[0].as<float>();
+    if (!acc && tsvd_split_shapes(d->m, d->n, p, k, 0)) {
+      const size_t need = tsvd_split_scratch(d->m, d->n, p, k, 0);
+      AMM_TRY(ctx->scratch[4].reserve(need * sizeof(float)));
+      return tsvd_split_product(d->m, d->n, p, k, 0, d->V.as<float>(), d->US.as<float>(), B, nullptr, nullptr,
+                                nullptr, ctx->scratch[4].as<float>(), need, out, s);
+    }
     if (!acc && tsvd_fast_shapes(d->m, d->n, p, k, 0)) {
       const size_t gp = (size_t)4 * k * p;
       AMM_TRY(ctx->scratch[4].reserve(gp * sizeof(float)));
@@ -672,6 +678,15 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   }
   TimerScope ts(ctx);
   if (!dB) return left_apply(ctx, dA, B, p, out, false, s);
+  if (is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed && dB->residual.ptr &&
+      tsvd_split_shapes(dA->m, n, p, dA->K_eff, dB->K_eff)) {
+    // M1 = U_A S_A (V_A^T Delta B) + (A U_B)(S_B V_B^T): panels, reduce, split output GEMM
+    const size_t need = tsvd_split_scratch(dA->m, n, p, dA->K_eff, dB->K_eff);
+    AMM_TRY(ctx->scratch[4].reserve(need * sizeof(float)));
+    return tsvd_split_product(dA->m, n, p, dA->K_eff, dB->K_eff, dA->V.as<float>(), dA->US.as<float>(),
+                              dB->residual.as<float>(), dA->A_borrowed, dB->U.as<float>(), dB->VS.as<float>(),
+                              ctx->scratch[4].as<float>(), need, out, s);
+  }
   if (is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed && dB->residual.ptr &&
       tsvd_fast_shapes(dA->m, n, p, dA->K_eff, dB->K_eff)) {
     // M1 = U_A S_A (V_A^T Delta B) + (A U_B)(S_B V_B^T): two panels, one output GEMM

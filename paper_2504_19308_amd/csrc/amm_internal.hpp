@@ -201,6 +201,11 @@ amm_status gemm_f64(int64_t M, int64_t N, int64_t Kd, double alpha, const double
 
 // SVD path: skinny panels and the short-K output GEMM (tsvd_apply.hip)
 bool tsvd_fast_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb);
+bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb);
+size_t tsvd_split_scratch(int64_t m, int64_t n, int64_t p, int ka, int kb);
+amm_status tsvd_split_product(int64_t m, int64_t n, int64_t p, int ka, int kb, const float* V_A, const float* US_A,
+                              const float* Y, const float* X, const float* U_B, const float* VS_B, float* scratch,
+                              size_t scratch_floats, float* out, hipStream_t s);
 int tsvd_fast_splits(int64_t tiles, int64_t n);
 amm_status tsvd_fast_product(int64_t m, int64_t n, int64_t p, int ka, int kb, const float* V_A,
                              const float* US_A, const float* Y, const float* X, const float* U_B,

@@ -196,3 +196,72 @@ def test_sparse_decompose_end_to_end():
     rp, col, val = d.sparse_part()
     assert np.array_equal(col, dec.S.col)
     assert rel(got, want) < 1e-4
+
+
+@pytest.mark.parametrize("n,ka,kb", [(256, 32, 32), (512, 64, 32), (640, 32, 64), (1024, 64, 64), (384, 32, 0)])
+def test_tsvd_split_path_first_order(n, ka, kb):
+    """Shapes of the three-launch path (direct panels, reduction, output GEMM
+    on split bfloat16 operands): float32 accuracy against the oracle."""
+    note(f"tsvd split path n={n} ka={ka} kb={kb}")
+    sig = inputs.decay_power(n, 1.5)
+    A = _spectral(n, n, sig, 21 + n)
+    B = _spectral(n, n, sig, 22 + n)
+    decA = ot.TSVDDecomp(A, ka)
+    c = ctx()
+    Ag, Bg = gpu(A), gpu(B)
+    dA = c.import_tsvd(decA.U, decA.s, decA.V, A=Ag)
+    if kb == 0:
+        got = host(c.approx_matmul(dA, Bg))
+        want = ot.apply_zeroth(decA, B)
+    else:
+        decB = ot.TSVDDecomp(B, kb)
+        dB = c.import_tsvd(decB.U, decB.s, decB.V, A=Bg)
+        got = host(c.approx_matmul(dA, Bg, dB))
+        want = op.algorithm(decA, B, decB)
+    assert rel(got, want) < TOL_F32
+
+
+@pytest.mark.parametrize("m,n,p,k", [(128, 128, 128, 32), (384, 640, 256, 64), (256, 1024, 768, 32)])
+def test_tsvd_split_path_zeroth_rect(m, n, p, k):
+    note(f"tsvd split zeroth m={m} n={n} p={p} k={k}")
+    rng = np.random.default_rng(m + n + p + k)
+    A = _spectral(m, n, inputs.decay_power(min(m, n), 1.0), k + 1)
+    B = f32(rng.standard_normal((n, p)))
+    dec = ot.TSVDDecomp(A, k)
+    c = ctx()
+    d = c.import_tsvd(dec.U, dec.s, dec.V)
+    assert rel(host(c.approx_matmul(d, gpu(B))), ot.apply_zeroth(dec, B)) < TOL_F32
+
+
+def test_tsvd_first_order_full_size_sampled():
+    """The benchmark's step at full size (n = 4096, rank 32 for A and B, the
+    generator's exact leading factors imported), checked on sampled columns."""
+    torch = torch_cuda()
+    n, k = 4096, 32
+    note("tsvd first order full size")
+    sig = inputs.decay_power(n, 1.5)
+    facs, mats = [], []
+    for operand in (0, 1):
+        rng = inputs.rng_of(2, operand)
+        Q1 = inputs.haar_columns(n, n, rng, device="cuda")
+        Q2 = inputs.haar_columns(n, n, rng, device="cuda")
+        s64 = torch.from_numpy(sig).cuda()
+        mats.append(((Q1 * s64) @ Q2.t()).float().contiguous())
+        facs.append((Q1[:, :k].cpu().numpy(), sig[:k], Q2[:, :k].cpu().numpy()))
+        del Q1, Q2
+    A, B = mats
+    c = ctx()
+    dA = c.import_tsvd(*facs[0], A=A)
+    dB = c.import_tsvd(*facs[1], A=B)
+    out = c.approx_matmul(dA, B, dB)
+    torch.cuda.synchronize()
+    cols = np.sort(np.random.default_rng(9).choice(n, 24, replace=False))
+    Ah = A.double().cpu().numpy()
+    Bc = B[:, cols].double().cpu().numpy()
+    UA, sA, VA = (f32(x) for x in facs[0])
+    UB, sB, VB = (f32(x) for x in facs[1])
+    decA = ot.TSVDDecomp(Ah, k, U=UA, s=sA, V=VA)
+    Btil_c = (UB * sB[None, :]) @ VB[cols].T
+    want = ot.apply_zeroth(decA, Bc) + decA.residual_dense() @ Btil_c
+    got = out[:, cols].double().cpu().numpy()
+    assert rel(got, want) < TOL_F32
