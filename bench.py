@@ -353,6 +353,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
         res.append(layer_workload(torch, ctx, tm))
+        res.append(layer_workload(torch, ctx, tm, k=440))
     if not only or only == "c5":
         res.extend(c5_workload(torch, ctx, tm))
     return res

@@ -14,6 +14,8 @@
 #include <cstring>
 #include <vector>
 
+#include <map>
+
 #include "amm_internal.hpp"
 
 namespace amm {
@@ -165,7 +167,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
       return AMM_OK;
     }
     return cd_apply_columns(ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(),
-                            d->L.as<float2>(), B, p, out, acc, s);
+                            d->L.as<float2>(), B, p, out, acc, s, d->pairs_of(false));
   }
   if (is_tsvd(d)) {
     const int k = d->K_eff;
@@ -212,7 +214,7 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
       return AMM_OK;
     }
     return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
-                         d->Ladj.as<float2>(), X, rows, out, acc, s);
+                         d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true));
   }
   if (is_tsvd(d)) {
     const int k = d->K_eff;
@@ -403,6 +405,83 @@ amm_status amm_dec_sparse_part(const amm_dec* d, int32_t* row_ptr_host, int32_t*
   return AMM_OK;
 }
 
+}  // extern "C"
+
+namespace amm {
+
+// Pair structure of a closed frequency set (see CdPairs), for the lists L
+// (shifts k_t) and for the adjoint lists Ladj_t[p] = conj(L_t[p + k_t])
+// (shifts -k_t).  Left unset (plain loop) when the set is not closed or the
+// lists are not those of a real operator to float32 rounding.
+amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
+  d->npairs = d->npairs_adj = -1;
+  d->nsingles = d->nsingles_adj = 0;
+  const int64_t n = d->n;
+  const int K = d->K_eff;
+  if (K == 0 || (int64_t)Lh.size() < (int64_t)K * n) return AMM_OK;
+  std::map<int64_t, int> idx;
+  for (int t = 0; t < K; ++t) idx[d->freqs[t]] = t;
+  for (int t = 0; t < K; ++t)
+    if (!idx.count((n - d->freqs[t]) % n)) return AMM_OK;
+  float mx = 0.f;
+  for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
+  const float tol = 1e-5f * mx + 1e-30f;
+  // adjoint lists on the host
+  std::vector<float2> La((size_t)K * n);
+  std::vector<int64_t> ka(K);
+  for (int t = 0; t < K; ++t) {
+    const int64_t k = d->freqs[t];
+    ka[t] = (n - k) % n;
+    for (int64_t p = 0; p < n; ++p) {
+      const float2 v = Lh[(size_t)t * n + (p + k) % n];
+      La[(size_t)t * n + p] = float2{v.x, -v.y};
+    }
+  }
+  // L_b[p] == conj(L_a[-p]) for every p
+  auto mirror = [&](const std::vector<float2>& Ls, int ta, int tb) {
+    for (int64_t p = 0; p < n; ++p) {
+      const float2 a = Ls[(size_t)ta * n + (n - p) % n], b = Ls[(size_t)tb * n + p];
+      if (std::fabs(b.x - a.x) > tol || std::fabs(b.y + a.y) > tol) return false;
+    }
+    return true;
+  };
+  std::vector<int2> pairs, singles, pairs_a, singles_a;
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<float2>& Ls = pass == 0 ? Lh : La;
+    auto& P = pass == 0 ? pairs : pairs_a;
+    auto& S = pass == 0 ? singles : singles_a;
+    std::map<int64_t, int> at;
+    for (int t = 0; t < K; ++t) at[pass == 0 ? (int64_t)d->freqs[t] : ka[t]] = t;
+    for (const auto& kv : at) {
+      const int64_t k = kv.first, kk = (n - k) % n;
+      const int t = kv.second, tt = at[kk];
+      if (k == kk) {
+        if (!mirror(Ls, t, t)) return AMM_OK;
+        S.push_back(int2{(int)k, t});
+      } else if (k < kk) {
+        if (!mirror(Ls, t, tt)) return AMM_OK;
+        P.push_back(int2{(int)k, t});
+      }
+    }
+  }
+  std::vector<int2> all;
+  all.insert(all.end(), pairs.begin(), pairs.end());
+  all.insert(all.end(), singles.begin(), singles.end());
+  all.insert(all.end(), pairs_a.begin(), pairs_a.end());
+  all.insert(all.end(), singles_a.begin(), singles_a.end());
+  AMM_TRY(d->pair_buf.alloc(all.size() * sizeof(int2)));
+  AMM_HIP(hipMemcpy(d->pair_buf.ptr, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice));
+  d->npairs = (int)pairs.size();
+  d->nsingles = (int)singles.size();
+  d->npairs_adj = (int)pairs_a.size();
+  d->nsingles_adj = (int)singles_a.size();
+  return AMM_OK;
+}
+
+}  // namespace amm
+
+extern "C" {
+
 amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_t* freqs,
                                     const double* eig, const float* residual, double norm_A,
                                     double norm_residual, amm_dec** out) {
@@ -448,6 +527,13 @@ amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_
   if (e == hipSuccess) e = hipMemcpy(d->Ladj.ptr, La.data(), La.size() * sizeof(float2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d->shifts.ptr, sh.data(), sh.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d->shifts_adj.ptr, sa.data(), sa.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    L.resize((size_t)K * n);
+    if ((st = cd_build_pairs(d, L)) != AMM_OK) {
+      delete d;
+      return st;
+    }
+  }
   if (e == hipSuccess && residual) {
     if ((st = d->residual.alloc(n * n * sizeof(float))) != AMM_OK) { delete d; return st; }
     e = hipMemcpy(d->residual.ptr, residual, n * n * sizeof(float), hipMemcpyDeviceToDevice);

@@ -79,6 +79,16 @@ struct TimedLaunch {
   }
 };
 
+// Optional pair structure of a real operator's closed frequency set:
+// pairs[u] = {k, t} for each pair {k, N-k} (t the list index of k), singles
+// for the self-paired 0 and N/2.  npairs < 0: use the plain K-term loop.
+struct CdPairs {
+  const int2* pairs = nullptr;
+  int npairs = -1;
+  const int2* singles = nullptr;
+  int nsingles = 0;
+};
+
 }  // namespace amm
 
 struct amm_ctx {
@@ -107,6 +117,19 @@ struct amm_dec {
   amm::DevBuf L;           // K_eff x n float2
   amm::DevBuf Ladj;        // K_eff x n float2
   amm::DevBuf energies;    // n double (decompose only)
+  // pair structure for the paired spectral MAC (npairs < 0: not available)
+  amm::DevBuf pair_buf;     // int2: pairs, singles, pairs_adj, singles_adj
+  int npairs = -1, nsingles = 0, npairs_adj = -1, nsingles_adj = 0;
+  amm::CdPairs pairs_of(bool adjoint) const {
+    const int2* b = pair_buf.as<int2>();
+    if (adjoint) {
+      if (npairs_adj < 0) return amm::CdPairs{};
+      const int2* p = b + npairs + nsingles;
+      return amm::CdPairs{p, npairs_adj, p + npairs_adj, nsingles_adj};
+    }
+    if (npairs < 0) return amm::CdPairs{};
+    return amm::CdPairs{b, npairs, b + npairs, nsingles};
+  }
   bool has_energies = false;
 
   // SVD: U m x k, V n x k, sigma k (float32), US = U diag(sigma), VS = V diag(sigma),
@@ -170,10 +193,10 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
 //               row of X (rows x n):  out_row = (op(row^T))^T.
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s);
+                            bool accumulate, hipStream_t s, CdPairs pr = CdPairs{});
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
-                         bool accumulate, hipStream_t s);
+                         bool accumulate, hipStream_t s, CdPairs pr = CdPairs{});
 
 // Forward spectra of the packed column pairs of B (n x p, p even): spec
 // (n x p floats) holds complex bin values at [p][2c], [p][2c + 1].
@@ -181,6 +204,10 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
                                hipStream_t s);
 
 // Circulant decomposition, float64 on the device.
+// Builds dec->pair_buf from host copies of the lists when the frequency set
+// is closed and the lists satisfy L_{n-k}[p] = conj(L_k[-p]).
+amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
+
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s);
 

@@ -23,10 +23,12 @@ namespace {
 
 template <int LOG2N> struct CdCfg {
   static constexpr int N = 1 << LOG2N;
-  // packed columns per workgroup: the spectra of a tile fill ~139 KiB of LDS
-  // from n = 4096 up (n = 16384 holds a single packed column pair)
-  static constexpr int C = LOG2N <= 10 ? 16 : (LOG2N >= 12 ? (1 << (14 - LOG2N)) : 8);
-  static constexpr int T = LOG2N <= 8 ? 256 : (LOG2N == 9 ? 512 : 1024);  // threads
+  // packed columns per workgroup.  n = 1024 and 2048 hold ~70 KiB of spectra
+  // (two workgroups per CU overlap their load, transform and store phases,
+  // measured faster than one 139 KiB tile); from n = 4096 up a tile fills
+  // ~139 KiB (n = 16384 holds a single packed column pair).
+  static constexpr int C = LOG2N <= 9 ? 16 : (LOG2N >= 12 ? (1 << (14 - LOG2N)) : (LOG2N == 10 ? 8 : 4));
+  static constexpr int T = LOG2N <= 8 ? 256 : (LOG2N <= 11 ? 512 : 1024);  // threads
   static constexpr int CPL = C < 4 ? C : 4;                             // cols per MAC lane
   static constexpr int G = C / CPL;
   static constexpr int BL = T / G;                                      // MAC bin lanes
@@ -108,7 +110,7 @@ template <int LOG2N, bool ROWS, bool SPEC = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const float2* __restrict__ L,
-                const float2* __restrict__ tw, int accumulate, int vec4) {
+                const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
@@ -164,43 +166,109 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   if constexpr (!SPEC) {
   // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
   constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL, NBINS = Cfg::NBINS;
-  // lanes = (bin, column group); the 4 packed columns of a group are read as 2 float4
+  // lanes = (bin, column group); the packed columns of a group are read together
   const int cg = threadIdx.x % G;
   const int bl = threadIdx.x / G;
+  auto load_x = [&](int q, float2 (&x)[CPL]) {
+    const float2* src = &lds[pad_bin(q & (N - 1)) * C + cg * CPL];
+    if constexpr (CPL == 4) {
+      const float4 x01 = reinterpret_cast<const float4*>(src)[0], x23 = reinterpret_cast<const float4*>(src)[1];
+      x[0] = float2{x01.x, x01.y};
+      x[1] = float2{x01.z, x01.w};
+      x[2] = float2{x23.x, x23.y};
+      x[3] = float2{x23.z, x23.w};
+    } else if constexpr (CPL == 2) {
+      const float4 x01 = reinterpret_cast<const float4*>(src)[0];
+      x[0] = float2{x01.x, x01.y};
+      x[1] = float2{x01.z, x01.w};
+    } else {
+      x[0] = src[0];
+    }
+  };
+  auto cmac = [](float2& a, float2 l, float2 x) {
+    a.x += l.x * x.x - l.y * x.y;
+    a.y += l.x * x.y + l.y * x.x;
+  };
   float2 acc[NBINS][CPL];
 #pragma unroll
   for (int i = 0; i < NBINS; ++i)
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[i][c] = float2{0.f, 0.f};
 
-  for (int t = 0; t < K; ++t) {
-    const int k = shifts[t];
-    const float2* __restrict__ Lt = L + (int64_t)t * N;
+  // Paired form (real operator, frequency set closed under k -> N-k): the list
+  // of N-k is L_{N-k}[p] = conj(L_k[-p]), so one read of L_k at a bin and at
+  // its mirror serves both members of the pair.  A lane then owns bin pairs
+  // (b, N-b) -- b = 0 goes with the other self-mirrored bin N/2 -- and reads
+  // half as many list entries.
+  constexpr bool CAN_PAIR = (NBINS % 2 == 0) && (N % BL == 0);
+  constexpr int NH = NBINS / 2;
+  const bool paired = CAN_PAIR && pr.npairs >= 0;
+  auto pair_bins = [&](int i, int& b1, int& b2) {
+    b1 = bl + i * BL;
+    b2 = b1 == 0 ? N / 2 : N - b1;
+  };
+  if (paired) {
+    for (int u = 0; u < pr.npairs; ++u) {
+      const int2 pk = pr.pairs[u];
+      const int k = pk.x;
+      const float2* __restrict__ Lt = L + (int64_t)pk.y * N;
 #pragma unroll
-    for (int i = 0; i < NBINS; ++i) {
-      const int p = bl + i * BL;
-      if (N % BL == 0 || p < N) {
-        const float2 l = Lt[p];
-        const int q = (p - k) & (N - 1);
-        float2 x[CPL];
-        const float2* src = &lds[pad_bin(q) * C + cg * CPL];
-        if constexpr (CPL == 4) {
-          const float4 x01 = reinterpret_cast<const float4*>(src)[0], x23 = reinterpret_cast<const float4*>(src)[1];
-          x[0] = float2{x01.x, x01.y};
-          x[1] = float2{x01.z, x01.w};
-          x[2] = float2{x23.x, x23.y};
-          x[3] = float2{x23.z, x23.w};
-        } else if constexpr (CPL == 2) {
-          const float4 x01 = reinterpret_cast<const float4*>(src)[0];
-          x[0] = float2{x01.x, x01.y};
-          x[1] = float2{x01.z, x01.w};
-        } else {
-          x[0] = src[0];
-        }
+      for (int i = 0; i < NH; ++i) {
+        int b1, b2;
+        pair_bins(i, b1, b2);
+        const float2 l1 = Lt[b1], l2 = Lt[b2];
+        const bool self = b1 == 0;                  // 0 and N/2 are their own mirrors
+        const float2 m1 = self ? l1 : l2, m2 = self ? l2 : l1;
+        const float2 c1 = float2{m1.x, -m1.y}, c2 = float2{m2.x, -m2.y};
+        float2 x[CPL], y[CPL];
+        load_x(b1 - k, x);
+        load_x(b1 + k, y);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-          acc[i][c].x += l.x * x[c].x - l.y * x[c].y;
-          acc[i][c].y += l.x * x[c].y + l.y * x[c].x;
+          cmac(acc[i][c], l1, x[c]);
+          cmac(acc[i][c], c1, y[c]);
+        }
+        load_x(b2 - k, x);
+        load_x(b2 + k, y);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          cmac(acc[NH + i][c], l2, x[c]);
+          cmac(acc[NH + i][c], c2, y[c]);
+        }
+      }
+    }
+    for (int v = 0; v < pr.nsingles; ++v) {
+      const int2 sk = pr.singles[v];
+      const int k = sk.x;
+      const float2* __restrict__ Lt = L + (int64_t)sk.y * N;
+#pragma unroll
+      for (int i = 0; i < NH; ++i) {
+        int b1, b2;
+        pair_bins(i, b1, b2);
+        float2 x[CPL];
+        load_x(b1 - k, x);
+        const float2 l1 = Lt[b1];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cmac(acc[i][c], l1, x[c]);
+        load_x(b2 - k, x);
+        const float2 l2 = Lt[b2];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cmac(acc[NH + i][c], l2, x[c]);
+      }
+    }
+  } else {
+    for (int t = 0; t < K; ++t) {
+      const int k = shifts[t];
+      const float2* __restrict__ Lt = L + (int64_t)t * N;
+#pragma unroll
+      for (int i = 0; i < NBINS; ++i) {
+        const int p = bl + i * BL;
+        if (N % BL == 0 || p < N) {
+          const float2 l = Lt[p];
+          float2 x[CPL];
+          load_x(p - k, x);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) cmac(acc[i][c], l, x[c]);
         }
       }
     }
@@ -208,7 +276,12 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NBINS; ++i) {
-    const int p = bl + i * BL;
+    int p = bl + i * BL;
+    if (paired) {
+      int b1, b2;
+      pair_bins(i < NH ? i : i - NH, b1, b2);
+      p = i < NH ? b1 : b2;
+    }
     if (N % BL == 0 || p < N) {
       float2* dst = &lds[pad_bin(p) * C + cg * CPL];
 #pragma unroll
@@ -269,7 +342,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 template <int LOG2N>
 amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
                      const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                     hipStream_t s, bool spec = false) {
+                     hipStream_t s, bool spec, CdPairs pr) {
   using Cfg = CdCfg<LOG2N>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
@@ -281,23 +354,23 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
                     ((uintptr_t)out % 16) == 0) ? 1 : 0;
   if (spec)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
-                       shifts, L, tw, 0, vec4);
+                       shifts, L, tw, 0, vec4, pr);
   else if (rows)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0, 0);
+                       shifts, L, tw, acc ? 1 : 0, 0, pr);
   else
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0, vec4);
+                       shifts, L, tw, acc ? 1 : 0, vec4, pr);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
 
 amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
                        const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                       hipStream_t s, bool spec = false) {
+                       hipStream_t s, bool spec, CdPairs pr) {
   switch (log2n) {
 #define AMM_CASE(L2) \
-  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec);
+  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
     AMM_CASE(13) AMM_CASE(14)
@@ -310,25 +383,25 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t
 
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s) {
+                            bool accumulate, hipStream_t s, CdPairs pr) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s);
+  return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
 amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t p, float* spec,
                                hipStream_t s) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  return dispatch_cd(false, log2n, B, spec, p, 0, nullptr, nullptr, tw, false, s, true);
+  return dispatch_cd(false, log2n, B, spec, p, 0, nullptr, nullptr, tw, false, s, true, CdPairs{});
 }
 
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
-                         bool accumulate, hipStream_t s) {
+                         bool accumulate, hipStream_t s, CdPairs pr) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s);
+  return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
 }  // namespace amm

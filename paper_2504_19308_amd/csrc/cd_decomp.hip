@@ -255,6 +255,10 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
     hipLaunchKernelGGL(gather_lists, dim3((unsigned)((n + 255) / 256), (unsigned)Ke), dim3(256), 0, s,
                        cur, n, dec->shifts.as<int32_t>(), dec->L.as<float2>(), dec->Ladj.as<float2>());
     AMM_HIP(hipGetLastError());
+    std::vector<float2> Lh((size_t)Ke * n);
+    AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+    AMM_TRY(cd_build_pairs(dec, Lh));
   }
 
   if (keep_residual) {
