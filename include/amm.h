@@ -116,7 +116,9 @@ const char* amm_last_error(void);
  *    lists L_t = F r_{.,k_t} (Alg. 2.3 step 4).  With keep_residual it also
  *    keeps Delta A = A - sum_{t} R_t D^{k_t}  (Alg. 2.3 step 6) in float32.
  *  kind = AMM_TSVD: rank-K randomized SVD (Alg. 2.1, with oversampling and
- *    subspace iterations), float64 on the device; K <= min(m, n).  With
+ *    subspace iterations), float64 on the device; K <= min(m, n).  A zero
+ *    operand gives K_eff = 0; an operand of rank below K keeps its extra
+ *    components with singular values at rounding level.  With
  *    keep_residual it borrows A (see amm_dec_import_tsvd) -- the caller must
  *    keep A alive and unchanged while the handle is used as a left operand.
  *  kind |= AMM_SPARSE: first splits A = S + R with S the round(frac*m*n)
@@ -186,8 +188,9 @@ void amm_dec_destroy(amm_dec* dec);
  * B is n x p on the device, dA describes an m x n operand.  dB must describe
  * B's own decomposition (n x p) and dA must hold Delta A (circulant:
  * keep_residual; SVD/sparse: borrowed A).  out is overwritten; it must not
- * alias B.  Nothing is allocated per call except the SVD and sparse
- * intermediates, which come from the context's reusable scratch. */
+ * alias B.  p == 0 is an empty product: AMM_OK, nothing is read or written
+ * (B and out may then be NULL).  Nothing is allocated per call except the SVD
+ * and sparse intermediates, which come from the context's reusable scratch. */
 amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
                              const float* B, int64_t n, int64_t p, float* out,
                              void* stream);

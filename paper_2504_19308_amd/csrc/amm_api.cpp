@@ -730,7 +730,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     amm_status st = tsvd_decompose(ctx, A, m, n, K, &o, d, s);
     if (st == AMM_OK && o.keep_residual) {
       st = d->residual.alloc(m * n * sizeof(float));
-      if (st == AMM_OK) st = tsvd_residual(A, m, n, K, d->US.as<float>(), d->V.as<float>(), d->residual.as<float>(), s);
+      if (st == AMM_OK) st = tsvd_residual(A, m, n, d->K_eff, d->US.as<float>(), d->V.as<float>(), d->residual.as<float>(), s);
       if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "residual");
     }
     if (st != AMM_OK) {
@@ -746,9 +746,11 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
 
 amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
                              int64_t n, int64_t p, float* out, void* stream) {
-  if (!ctx || !dA || !B || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");
   if (n != dA->n) return fail(AMM_ESHAPE, "B has %lld rows, A has %lld columns", (long long)n, (long long)dA->n);
-  if (p <= 0) return fail(AMM_ESHAPE, "B has no columns");
+  if (p < 0) return fail(AMM_ESHAPE, "negative column count");
+  if (p == 0) return AMM_OK;   // empty product: nothing to write
+  if (!B || !out) return fail(AMM_EINVAL, "NULL argument");
   if (dB && (dB->m != n || dB->n != p)) return fail(AMM_ESHAPE, "dB describes a %lldx%lld operand, B is %lldx%lld",
                                                     (long long)dB->m, (long long)dB->n, (long long)n, (long long)p);
   if (B == out) return fail(AMM_EINVAL, "out aliases B");

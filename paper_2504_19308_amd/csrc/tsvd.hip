@@ -185,13 +185,22 @@ amm_status orthonormalise(double* Y, double* tmp, int64_t rows, int l, DevBuf& g
     AMM_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < l; ++i)
       for (int j = 0; j < i; ++j) G[i * l + j] = G[j * l + i] = 0.5 * (G[i * l + j] + G[j * l + i]);
-    if (pass == 0) {
-      double nrm = 0.0;
-      for (int i = 0; i < l; ++i) nrm += G[i * l + i];
-      const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * nrm;
+    // the first pass is always shifted; a later pass is shifted only if its
+    // plain factorisation fails (an exactly rank-deficient operand: the extra
+    // columns then carry singular values at rounding level)
+    double nrm = 0.0;
+    for (int i = 0; i < l; ++i) nrm += G[i * l + i];
+    const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * nrm;
+    std::vector<double> G0;
+    if (pass > 0) G0 = G;
+    if (pass == 0)
       for (int i = 0; i < l; ++i) G[i * l + i] += shift;
+    if (!cholesky_upper(G, l)) {
+      if (pass == 0) return fail(AMM_EDEVICE, "CholeskyQR broke down (sketch rank-deficient)");
+      G = G0;
+      for (int i = 0; i < l; ++i) G[i * l + i] += shift;
+      if (!cholesky_upper(G, l)) return fail(AMM_EDEVICE, "CholeskyQR broke down (sketch rank-deficient)");
     }
-    if (!cholesky_upper(G, l)) return fail(AMM_EDEVICE, "CholeskyQR broke down (sketch rank-deficient)");
     std::vector<double> Ri = inv_upper(G, l);
     AMM_HIP(hipMemcpyAsync(gram.ptr, Ri.data(), l * l * sizeof(double), hipMemcpyHostToDevice, s));
     AMM_TRY(gemm_f64(rows, l, l, 1.0, Y, l, 1, gram.as<double>(), l, 1, 0.0, tmp, l, s));
@@ -232,7 +241,9 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   AMM_TRY(dec->VSt.alloc(n * kk * 4));
   AMM_TRY(dec->Vt.alloc(n * kk * 4));
   AMM_TRY(dec->sigma.alloc(kk * 4));
-  if (k == 0) {
+  if (k == 0 || dec->norm_A == 0.0) {
+    // nothing to keep (a zero operand has no nonzero singular triplet)
+    dec->K_eff = 0;
     dec->norm_residual = dec->norm_A;
     return AMM_OK;
   }
