@@ -34,7 +34,10 @@ diagonalisation by the DFT built from its definition, the shift identity
 W D^k W* = C^k, the printed n = 4 cycle-matrix example, Thm. 2.1 optimality,
 special cases (circulant input, single planted mode), and a brute-force
 comparison of the algorithm path against the dense entrywise truncated
-product for every index set at n <= 8.
+product for every index set at n <= 8.  Blocked rectangular operands: all
+components of every block reproduce A and AB exactly, a square operand is a
+single block, and the block-by-block product equals the cropped dense
+truncated matrix times B.
 """
 from __future__ import annotations
 
@@ -212,6 +215,55 @@ def apply_first_order_term(decB: CirculantDecomp, dA: np.ndarray) -> np.ndarray:
         idx = (p + k) % n
         Z += np.conj(decB.L[t][idx])[:, None] * Y[idx, :]
     return np.conj(np.fft.ifft(Z, axis=0)).T
+
+
+# ---------------------------------------------------------------------------
+# Rectangular operands in square blocks (Sec. 2.3: rectangular matrices are
+# approximated through square blocks).  Reading: s = min(m, n); the longer
+# dimension is cut into ceil(max(m, n) / s) blocks of s, the last one padded
+# with zeros; each block keeps its own K components.  Zeroth order only.
+# ---------------------------------------------------------------------------
+class BlockedCirculant:
+    """Truncated circulant decompositions of the s x s blocks of an m x n A."""
+
+    def __init__(self, A, K: int):
+        A = np.asarray(A, dtype=np.float64)
+        self.m, self.n = A.shape
+        self.s = min(self.m, self.n)
+        self.rows = self.m > self.n            # blocks stacked down the rows
+        long = max(self.m, self.n)
+        self.nb = -(-long // self.s)
+        self.blocks = []
+        for j in range(self.nb):
+            blk = np.zeros((self.s, self.s))
+            lo, hi = j * self.s, min(long, (j + 1) * self.s)
+            if self.rows:
+                blk[: hi - lo, :] = A[lo:hi, :]
+            else:
+                blk[:, : hi - lo] = A[:, lo:hi]
+            self.blocks.append(CirculantDecomp(blk, K))
+
+    def truncated_dense(self) -> np.ndarray:
+        """The m x n truncated matrix: the blocks' truncations, padding cut off."""
+        parts = [np.real(b.truncated_dense()) for b in self.blocks]
+        full = np.vstack(parts) if self.rows else np.hstack(parts)
+        return full[: self.m, : self.n]
+
+
+def apply_blocked(dec: BlockedCirculant, B: np.ndarray) -> np.ndarray:
+    """Atil B block by block (Alg. 2.3 step 5 on each block)."""
+    B = np.asarray(B, dtype=np.float64)
+    s = dec.s
+    if dec.rows:
+        out = np.vstack([np.real(apply_zeroth(b, B)) for b in dec.blocks])
+        return out[: dec.m]
+    out = np.zeros((dec.m, B.shape[1]))
+    for j, b in enumerate(dec.blocks):
+        Bj = np.zeros((s, B.shape[1]))
+        lo, hi = j * s, min(dec.n, (j + 1) * s)
+        Bj[: hi - lo] = B[lo:hi]
+        out += np.real(apply_zeroth(b, Bj))
+    return out
 
 
 def approx_product(A, B, K: int, first_order: bool, KB: int | None = None,

@@ -250,3 +250,42 @@ def test_toeplitz_one_component_first_order_soft():
     M = op.algorithm(decA, pair.B, decB)
     err = op.rel_fro(M, pair.A @ pair.B)
     assert err < 0.01
+
+
+# ---- rectangular operands in square blocks ------------------------------------
+@pytest.mark.parametrize("m,n", [(20, 8), (8, 21), (16, 16), (33, 4)])
+def test_blocked_full_expansion_is_exact(m, n):
+    """K = s keeps every component of every block: Atil = A and Atil B = AB."""
+    rng = np.random.default_rng(m * 7 + n)
+    A = rng.standard_normal((m, n))
+    B = rng.standard_normal((n, 5))
+    dec = oc.BlockedCirculant(A, min(m, n))
+    assert np.allclose(dec.truncated_dense(), A, atol=1e-12)
+    assert np.allclose(oc.apply_blocked(dec, B), A @ B, atol=1e-11)
+
+
+def test_blocked_square_is_one_block():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((16, 16))
+    B = rng.standard_normal((16, 4))
+    dec = oc.BlockedCirculant(A, 5)
+    assert dec.nb == 1
+    ref = oc.CirculantDecomp(A, 5)
+    assert list(dec.blocks[0].S) == list(ref.S)
+    assert np.allclose(oc.apply_blocked(dec, B), np.real(oc.apply_zeroth(ref, B)), atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n,K", [(24, 8, 3), (8, 27, 2), (40, 16, 5)])
+def test_blocked_product_is_cropped_dense_truncation(m, n, K):
+    """Block-by-block FFT products equal the dense truncated matrix (entrywise
+    Thm. 1.1 partial sums of each padded block, padding cut off) times B."""
+    rng = np.random.default_rng(m + n + K)
+    A = rng.standard_normal((m, n))
+    B = rng.standard_normal((n, 6))
+    dec = oc.BlockedCirculant(A, K)
+    assert np.allclose(oc.apply_blocked(dec, B), dec.truncated_dense() @ B, atol=1e-11)
+    # the padded rows/columns of a block never reach the product
+    s = min(m, n)
+    if m > n:
+        last = dec.blocks[-1]
+        assert last.A.shape == (s, s) and np.all(last.A[m - (dec.nb - 1) * s:] == 0)
