@@ -82,7 +82,9 @@ typedef struct {
   int64_t nnz;           /* sparse entries (0 if not sparse) */
   int has_residual;      /* Delta A available for first-order use */
   double norm_A;         /* ||A||_F  (float64) */
-  double norm_residual;  /* ||Delta A||_F from the dropped energy/spectrum */
+  double norm_residual;  /* ||Delta A||_F from the dropped energy/spectrum
+                            (blocked operands: over the zero-padded blocks) */
+  int blocks;            /* square circulant blocks of a rectangular operand (0: none) */
 } amm_dec_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -108,7 +110,11 @@ const char* amm_last_error(void);
 /* ---- decomposition ------------------------------------------------------ */
 
 /* Decompose the m x n float32 device matrix A.
- *  kind = AMM_CIRCULANT: m == n required.  Computes every circulant
+ *  kind = AMM_CIRCULANT: for m != n, A is cut into square blocks of side
+ *    s = min(m, n) (a power of two) along the longer dimension, the last
+ *    block zero-padded (Sec. 2.3: rectangular matrices through square
+ *    blocks), and each block is decomposed as below with its own K; such
+ *    handles serve zeroth-order products only.  For each square operand it computes every circulant
  *    coefficient (Thm. 1.1 / Alg. 2.2) in float64 on the device through the
  *    two-sided transform F A F^-1, ranks the frequencies by energy
  *    ||R_k||_F^2 (Alg. 2.3 steps 2-3) and keeps the closed set of at most K
@@ -161,6 +167,11 @@ amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n,
 
 amm_status amm_dec_query(const amm_dec* dec, amm_dec_info* info);
 
+/* Block j of a rectangular circulant decomposition (a square circulant
+ * handle of side min(m, n)), borrowed: valid while `dec` lives, never passed
+ * to amm_dec_destroy. */
+amm_status amm_dec_block(const amm_dec* dec, int j, const amm_dec** block);
+
 /* Copy the kept circulant frequencies (ascending) to `out_host` (capacity
  * `cap`); *count receives K_eff. Circulant handles (or sparse ones with a
  * circulant residue) only. */
@@ -206,7 +217,11 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
  * to the plan: later runs read and write the same buffers (the caller keeps
  * them alive and does not overlap runs of one plan).  Creation times several
  * reduction-split policies on `stream` (out_i are written while tuning),
- * keeps the fastest, and captures the two launches in a HIP graph. */
+ * keeps the fastest, and captures the two launches in a HIP graph.
+ * Circulant handles (square, or rectangular in square blocks; any mix of
+ * sizes) plan instead the fused product launch(es) of each entry, with
+ * plan-owned scratch and all twiddle tables created up front, captured in
+ * one HIP graph. */
 amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA,
                                  const float* const* B, const int64_t* p, float* const* out,
                                  void* stream, amm_batch_plan** plan);

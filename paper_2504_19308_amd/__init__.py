@@ -40,10 +40,17 @@ def _need_f32_cuda(t, name):
 class Decomposition:
     """Owns an ``amm_dec`` handle; keeps borrowed tensors alive."""
 
-    def __init__(self, ctx: "Context", handle: C.c_void_p, keep=()):
+    def __init__(self, ctx: "Context", handle: C.c_void_p, keep=(), owned: bool = True):
         self.ctx = ctx
         self.handle = handle
         self._keep = list(keep)
+        self._owned = owned
+
+    def block(self, j: int) -> "Decomposition":
+        """Square block j of a rectangular circulant decomposition (borrowed)."""
+        h = C.c_void_p()
+        _lib.check(_lib.load().amm_dec_block(self.handle, j, C.byref(h)))
+        return Decomposition(self.ctx, h, keep=(self,), owned=False)
 
     def info(self) -> dict:
         inf = _lib.AmmDecInfo()
@@ -85,9 +92,9 @@ class Decomposition:
         return rp, col[:nnz], val[:nnz]
 
     def close(self):
-        if self.handle:
+        if self.handle and self._owned:
             _lib.load().amm_dec_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def _release(self):
         """Ownership moved into another handle (sparse residue)."""

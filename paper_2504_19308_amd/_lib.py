@@ -25,7 +25,7 @@ class AmmOpts(C.Structure):
 class AmmDecInfo(C.Structure):
     _fields_ = [("kind", C.c_int), ("m", C.c_int64), ("n", C.c_int64), ("K", C.c_int),
                 ("K_eff", C.c_int), ("nnz", C.c_int64), ("has_residual", C.c_int),
-                ("norm_A", C.c_double), ("norm_residual", C.c_double)]
+                ("norm_A", C.c_double), ("norm_residual", C.c_double), ("blocks", C.c_int)]
 
 
 # name -> (restype, argtypes); every pointer is a plain void* / typed pointer
@@ -46,6 +46,7 @@ SIGNATURES = {
     "amm_dec_import_sparse": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_void_p)]),
+    "amm_dec_block": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "amm_dec_query": (C.c_int, [C.c_void_p, C.POINTER(AmmDecInfo)]),
     "amm_dec_frequencies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "amm_dec_energies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),

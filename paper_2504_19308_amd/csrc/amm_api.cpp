@@ -153,9 +153,55 @@ bool is_circ(const amm_dec* d) { return d->kind == AMM_CIRCULANT; }
 bool is_tsvd(const amm_dec* d) { return d->kind == AMM_TSVD; }
 bool is_sparse(const amm_dec* d) { return (d->kind & AMM_SPARSE) != 0; }
 
+// Rectangular circulant operand: out (m x p) = Atil B block by block.  Row
+// blocks write their s output rows (the last block's overhang goes to the
+// scratch and only the valid rows are copied); column blocks accumulate over
+// the matching row slices of B (the last slice, zero-padded, from scratch).
+// scratch: s x p floats.
+amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out, float* scratch,
+                         hipStream_t s) {
+  const int64_t sd = d->block_rows ? d->n : d->m;
+  const int l2 = log2_exact(sd);
+  const int nb = (int)d->blocks.size();
+  for (int j = 0; j < nb; ++j) {
+    const amm_dec* b = d->blocks[j];
+    const int64_t lo = (int64_t)j * sd;
+    const int64_t valid = std::min<int64_t>(sd, (d->block_rows ? d->m : d->n) - lo);
+    const bool acc = !d->block_rows && j > 0;
+    if (d->block_rows) {
+      float* dst = valid == sd ? out + lo * p : scratch;
+      if (b->K_eff == 0) AMM_TRY(fill_f32(dst, sd * p, 0.f, s));
+      else AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, dst, false, s,
+                                    b->pairs_of(false)));
+      if (valid < sd)
+        AMM_HIP(hipMemcpyAsync(out + lo * p, scratch, valid * p * sizeof(float), hipMemcpyDeviceToDevice, s));
+    } else {
+      const float* src = B + lo * p;
+      if (valid < sd) {
+        AMM_TRY(fill_f32(scratch, sd * p, 0.f, s));
+        AMM_HIP(hipMemcpyAsync(scratch, src, valid * p * sizeof(float), hipMemcpyDeviceToDevice, s));
+        src = scratch;
+      }
+      if (b->K_eff == 0) {
+        if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
+      } else {
+        AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), src, p, out, acc, s,
+                                 b->pairs_of(false)));
+      }
+    }
+  }
+  return AMM_OK;
+}
+
 // out (m x p) (+)= Atil B
 amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out,
                       bool acc, hipStream_t s) {
+  if (!d->blocks.empty()) {
+    if (acc) return fail(AMM_EUNSUPPORTED, "blocked circulant operand inside a sum");
+    const int64_t sd = d->block_rows ? d->n : d->m;
+    AMM_TRY(ctx->scratch[6].reserve((size_t)sd * p * sizeof(float)));
+    return blocked_apply(ctx, d, B, p, out, ctx->scratch[6].as<float>(), s);
+  }
   if (is_sparse(d)) {
     AMM_TRY(spmm_csr(d, B, p, out, acc, s));
     if (d->inner) AMM_TRY(left_apply(ctx, d->inner, B, p, out, true, s));
@@ -266,6 +312,7 @@ using namespace amm;
 
 amm_dec::~amm_dec() {
   if (inner) delete inner;
+  for (amm_dec* b : blocks) delete b;
 }
 
 amm_batch_plan::~amm_batch_plan() {
@@ -358,8 +405,16 @@ amm_status amm_dec_query(const amm_dec* d, amm_dec_info* info) {
   info->has_residual = (d->residual.ptr || d->A_borrowed ||
                         (d->inner && (d->inner->residual.ptr || d->inner->A_borrowed))) ? 1 : 0;
   (void)r;
+  info->blocks = (int)d->blocks.size();
   info->norm_A = d->norm_A;
   info->norm_residual = d->norm_residual;
+  return AMM_OK;
+}
+
+amm_status amm_dec_block(const amm_dec* d, int j, const amm_dec** block) {
+  if (!d || !block) return fail(AMM_EINVAL, "NULL argument");
+  if (j < 0 || j >= (int)d->blocks.size()) return fail(AMM_EINVAL, "block %d out of [0, %d)", j, (int)d->blocks.size());
+  *block = d->blocks[j];
   return AMM_OK;
 }
 
@@ -701,8 +756,60 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     *out = d;
     return AMM_OK;
   }
+  if (kind == AMM_CIRCULANT && m != n) {
+    // square blocks of side s = min(m, n) along the longer dimension
+    const int64_t sd = std::min(m, n), lg = std::max(m, n);
+    const int l2 = log2_exact(sd);
+    if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant blocks need min(m, n) a power of two in [2, 16384]");
+    if (K < 0 || K > sd) return fail(AMM_EINVAL, "K = %d out of [0, %lld]", K, (long long)sd);
+    const int nb = (int)((lg + sd - 1) / sd);
+    amm_dec* d = new amm_dec();
+    d->kind = AMM_CIRCULANT;
+    d->m = m;
+    d->n = n;
+    d->K = K;
+    d->device = ctx->device;
+    d->block_rows = m > n;
+    DevBuf blk;
+    amm_status st = blk.alloc((size_t)sd * sd * sizeof(float));
+    amm_opts ob = o;
+    ob.keep_residual = 0;
+    double a2 = 0.0, r2 = 0.0;
+    for (int j = 0; j < nb && st == AMM_OK; ++j) {
+      const int64_t lo = (int64_t)j * sd, valid = std::min(sd, lg - lo);
+      float* bp = blk.as<float>();
+      if (valid < sd) st = fill_f32(bp, sd * sd, 0.f, s);
+      if (st != AMM_OK) break;
+      hipError_t e;
+      if (d->block_rows)   // rows lo..lo+valid of A (n columns)
+        e = hipMemcpy2DAsync(bp, sd * sizeof(float), A + lo * n, n * sizeof(float), sd * sizeof(float), valid,
+                             hipMemcpyDeviceToDevice, s);
+      else                 // columns lo..lo+valid of A (m rows)
+        e = hipMemcpy2DAsync(bp, sd * sizeof(float), A + lo, n * sizeof(float), valid * sizeof(float), sd,
+                             hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy2DAsync"); break; }
+      amm_dec* b = new amm_dec();
+      b->kind = AMM_CIRCULANT;
+      b->m = b->n = sd;
+      b->K = K;
+      b->device = ctx->device;
+      st = cd_decompose(ctx, bp, l2, K, false, b, s);
+      if (st != AMM_OK) { delete b; break; }
+      d->blocks.push_back(b);
+      d->K_eff += b->K_eff;
+      a2 += b->norm_A * b->norm_A;
+      r2 += b->norm_residual * b->norm_residual;
+    }
+    if (st != AMM_OK) {
+      delete d;
+      return st;
+    }
+    d->norm_A = std::sqrt(a2);
+    d->norm_residual = std::sqrt(r2);
+    *out = d;
+    return AMM_OK;
+  }
   if (kind == AMM_CIRCULANT) {
-    if (m != n) return fail(AMM_ESHAPE, "circulant decomposition needs a square operand");
     const int l2 = log2_exact(n);
     if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384]");
     if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
@@ -756,6 +863,9 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   if (B == out) return fail(AMM_EINVAL, "out aliases B");
   hipStream_t s = (hipStream_t)stream;
   AMM_HIP(hipSetDevice(ctx->device));
+  if (dB && (!dA->blocks.empty() || !dB->blocks.empty() || (dA->inner && !dA->inner->blocks.empty()) ||
+             (dB->inner && !dB->inner->blocks.empty())))
+    return fail(AMM_EUNSUPPORTED, "first-order products of blocked circulant operands are not supported");
   if (dB) {
     // validate the residual source before any launch
     if (!(is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed)) {
@@ -847,8 +957,33 @@ amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const flo
 
 namespace {
 
-amm_status plan_build(amm_batch_plan* bp, int t) { return bp->bf16 ? batch_build_bf16(bp, t) : batch_build(bp, t); }
-amm_status plan_launch(amm_batch_plan* bp, hipStream_t s) { return bp->bf16 ? batch_launch_bf16(bp, s) : batch_launch(bp, s); }
+// circulant entries: the zeroth-order product of each entry in turn, blocked
+// operands through the plan-owned scratch (so a captured graph never points
+// into the context's growable buffers)
+amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
+  for (size_t i = 0; i < bp->items.size(); ++i) {
+    const amm_dec* d = bp->decs[i];
+    const auto& it = bp->items[i];
+    if (!d->blocks.empty()) {
+      AMM_TRY(blocked_apply(bp->ctx, d, it.B, it.p, it.out, bp->partials.as<float>(), s));
+    } else if (d->K_eff == 0) {
+      AMM_TRY(fill_f32(it.out, it.m * it.p, 0.f, s));
+    } else {
+      AMM_TRY(cd_apply_columns(bp->ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
+                               it.p, it.out, false, s, d->pairs_of(false)));
+    }
+  }
+  return AMM_OK;
+}
+
+amm_status plan_build(amm_batch_plan* bp, int t) {
+  if (bp->launches) return AMM_OK;
+  return bp->bf16 ? batch_build_bf16(bp, t) : batch_build(bp, t);
+}
+amm_status plan_launch(amm_batch_plan* bp, hipStream_t s) {
+  if (bp->launches) return circ_launches(bp, s);
+  return bp->bf16 ? batch_launch_bf16(bp, s) : batch_launch(bp, s);
+}
 
 // Autotune the reduction split policy by timing each candidate on the caller's
 // stream, then capture the two launches once on a plan-owned stream; runs
@@ -861,7 +996,16 @@ amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan)
   amm_status st = AMM_OK;
   if (hipEventCreate(&e0) != hipSuccess) st = fail(AMM_EDEVICE, "event");
   if (st == AMM_OK && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); st = fail(AMM_EDEVICE, "event"); }
-  if (st == AMM_OK) {
+  if (st == AMM_OK && bp->launches) {   // nothing to tune: time one run
+    (void)hipEventRecord(e0, s);
+    st = plan_launch(bp, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (st == AMM_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    best = 3.0 * ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  } else if (st == AMM_OK) {
     for (int t : candidates) {
       if ((st = plan_build(bp, t)) != AMM_OK) break;
       if ((st = plan_launch(bp, s)) != AMM_OK) break;  // warm-up
@@ -911,7 +1055,12 @@ amm_status plan_check(int count, const amm_dec* const* dA, const void* const* B,
   for (int i = 0; i < count; ++i) {
     const amm_dec* d = dA[i];
     if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
-    if (d->kind != AMM_TSVD) return fail(AMM_EUNSUPPORTED, "batch entries must be truncated-SVD handles");
+    if (!bf16 && d->kind == AMM_CIRCULANT && dA[0]->kind == AMM_CIRCULANT) {
+      if (p[i] <= 0) return fail(AMM_ESHAPE, "entry %d has no columns", i);
+      continue;
+    }
+    if (d->kind != AMM_TSVD || dA[0]->kind != AMM_TSVD)
+      return fail(AMM_EUNSUPPORTED, "batch entries must be all truncated-SVD or all circulant handles");
     if (k < 0) k = d->K_eff;
     if (d->K_eff != k) return fail(AMM_EUNSUPPORTED, "batch entries must share one rank");
     const bool ok = bf16 ? batch_item_ok_bf16(d->m, d->n, p[i], k) : batch_item_ok(d->m, d->n, p[i], k);
@@ -936,6 +1085,31 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
   amm_batch_plan* bp = new amm_batch_plan();
   bp->ctx = ctx;
   bp->k = k;
+  if (dA[0]->kind == AMM_CIRCULANT) {
+    // circulant entries: plan-owned scratch and every twiddle table made now,
+    // so that running (or capturing) the plan allocates nothing
+    bp->launches = true;
+    size_t scratch = 1;
+    for (int i = 0; i < count; ++i) {
+      const amm_dec* d = dA[i];
+      bp->items.push_back({d->m, d->n, p[i], nullptr, nullptr, B[i], out[i]});
+      bp->decs.push_back(d);
+      const int64_t sd = d->blocks.empty() ? d->n : std::min(d->m, d->n);
+      if (!d->blocks.empty()) scratch = std::max(scratch, (size_t)sd * p[i]);
+      const float2* tw = nullptr;
+      amm_status st = twiddles32(ctx, log2_exact(sd), &tw);
+      if (st != AMM_OK) {
+        delete bp;
+        return st;
+      }
+    }
+    amm_status st = bp->partials.alloc(scratch * sizeof(float));
+    if (st != AMM_OK) {
+      delete bp;
+      return st;
+    }
+    return plan_finish(bp, (hipStream_t)stream, plan);
+  }
   for (int i = 0; i < count; ++i)
     bp->items.push_back({dA[i]->m, dA[i]->n, p[i], dA[i]->V.as<float>(), dA[i]->US.as<float>(), B[i], out[i]});
   return plan_finish(bp, (hipStream_t)stream, plan);

@@ -143,6 +143,12 @@ struct amm_dec {
   amm::DevBuf csc_ptr, csc_row, csc_val;
   amm_dec* inner = nullptr;
 
+  // rectangular circulant operand: square blocks of side s = min(m, n) along
+  // the longer dimension (the last one zero-padded), each its own circulant
+  // decomposition; block_rows: blocks stacked down the rows (m > n)
+  std::vector<amm_dec*> blocks;
+  bool block_rows = false;
+
   // Delta A: owned (circulant) or borrowed A (SVD / sparse)
   amm::DevBuf residual;        // m x n float32, owned
   const float* A_borrowed = nullptr;
@@ -164,6 +170,8 @@ struct amm_batch_plan {
   amm_ctx* ctx = nullptr;
   int k = 0;
   bool bf16 = false;            // bfloat16 components, float32 accumulation
+  bool launches = false;        // circulant entries: one product launch sequence per entry
+  std::vector<const amm_dec*> decs;
   amm::DevBuf fac16;            // plan-owned bfloat16 factor copies
   std::vector<Item> items;
   std::vector<int> splits;

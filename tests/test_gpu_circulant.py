@@ -153,5 +153,5 @@ def test_rejects_unsupported():
     c = ctx()
     with pytest.raises(AmmError):
         c.decompose(gpu(np.zeros((6, 6))), "circulant", 2)
-    with pytest.raises(AmmError):
-        c.decompose(gpu(np.zeros((8, 4))), "circulant", 2)
+    with pytest.raises(AmmError):   # rectangular: blocks of side min(m, n) = 6, not a power of two
+        c.decompose(gpu(np.zeros((8, 6))), "circulant", 2)
