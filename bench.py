@@ -253,12 +253,13 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False):
+def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False, list_bytes=8):
     """Roofline fraction of one kernel launch of a variant (algorithmic bytes
-    and flops; the larger of the two times at peak decides the bound)."""
+    and flops; the larger of the two times at peak decides the bound).
+    list_bytes: bytes per eigenvalue-list entry (8 complex float32, 4 half)."""
     import math as _m
     if name in ("cd_apply_columns", "cd_apply_rows"):
-        byts = 2.0 * n * p * 4 + K * n * 8
+        byts = 2.0 * n * p * 4 + K * n * list_bytes
         fl = p * n * (5.0 * _m.log2(n) + 4.0 * K)
         peak_fl = VALU_F32_PEAK
     elif name == "panel":
@@ -299,6 +300,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         return d, (time.perf_counter() - a) * 1e3
 
     def measure(name, dA, dB, Bm, dec_ms, ex, K=0, k=0, nnz=0):
+        lb = 4 if dA.info().get("spectral_fp16") else 8
         first = dB is not None
         if only and only != name:
             return
@@ -309,14 +311,14 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         kt = ctx.timings()
         ctx.set_timing(False)
         err = rel_err(out, ex)
-        roofs = [r for r in (kernel_roof(kn, v[0] / v[1], n, n, K=K, k=k, nnz=nnz, first=first) for kn, v in kt.items()) if r]
+        roofs = [r for r in (kernel_roof(kn, v[0] / v[1], n, n, K=K, k=k, nnz=nnz, first=first, list_bytes=lb) for kn, v in kt.items()) if r]
         res.append({"name": name, "ms": ms, "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12,
                     "speedup_vs_dense_fp32": dense_ms / ms, "err_vs_exact": err,
                     "meets_1pct": err <= 0.01, "decompose_ms": dec_ms,
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    if not only or only not in ("batch", "layer"):
+    if not only or only not in ("batch", "layer", "c5"):
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -325,6 +327,13 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
             measure(f"circulant K={K} zeroth", dA, None, B, ta, exact, K=K_eff)
             measure(f"circulant K={K} first", dA, dB, B, ta + tb, exact, K=K_eff)
             del dA, dB
+        # float16 eigenvalue lists (half the list traffic)
+        dA, ta = dec(A, None, "circulant", 128, spectral_fp16=True)
+        dB, tb = dec(B, None, "circulant", 128, spectral_fp16=True)
+        K_eff = dA.info()["K_eff"]
+        measure("circulant K=128 zeroth fp16-lists", dA, None, B, ta, exact, K=K_eff)
+        measure("circulant K=128 first fp16-lists", dA, dB, B, ta + tb, exact, K=K_eff)
+        del dA, dB
         # truncated SVD
         for k in (32, 128):
             if ("tsvd", k) in cache:
@@ -375,33 +384,37 @@ def c5_workload(torch, ctx, tm, n=16384, K=64, ncols=256):
     exact = A.double() @ B[:, cols].double()
     torch.cuda.synchronize()
     log(f"[bench] c5 inputs {time.time() - t0:.1f}s")
-    decs = []
-    for M, seed in ((A, 1), (B, 2)):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        decs.append(ctx.decompose(M, "sparse+circulant", K, sparse_frac=0.005))
-        torch.cuda.synchronize()
-        decs[-1].ms = (time.perf_counter() - a) * 1e3
-    dA, dB = decs
     out = torch.empty((n, n), dtype=torch.float32, device="cuda")
     flops = 2.0 * n ** 3
     dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 3, 1))
     res = []
-    for name, d2 in (("zeroth", None), ("first", dB)):
-        fn = lambda: ctx.approx_matmul(dA, B, d2, out=out)
-        ms = statistics.median(tm.run(fn, 5, 2))
-        ctx.set_timing(True)
-        fn()
-        kt = ctx.timings()
-        ctx.set_timing(False)
-        err = rel_err(out[:, cols], exact)
-        res.append({"name": f"n={n} sparse0.5%+circulant K={K} {name}", "ms": ms,
-                    "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
-                    "dense_fp32_ms": dense_ms, "err_vs_exact_sampled": err, "meets_1pct": err <= 0.01,
-                    "decompose_ms": dA.ms + (dB.ms if d2 is not None else 0.0), "nnz": dA.info()["nnz"],
-                    "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
-        log(f"[bench] c5 {name}: {ms:.3f} ms (dense {dense_ms:.3f}), err {err:.3e}, kernels {res[-1]['kernels_ms']}")
-    del A, B, exact, out, dA, dB, decs
+    for half in (False, True):
+        decs = []
+        for M in (A, B):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            decs.append(ctx.decompose(M, "sparse+circulant", K, sparse_frac=0.005, spectral_fp16=half))
+            torch.cuda.synchronize()
+            decs[-1].ms = (time.perf_counter() - a) * 1e3
+        dA, dB = decs
+        tag = " fp16-lists" if half else ""
+        for name, d2 in (("zeroth", None), ("first", dB)):
+            fn = lambda: ctx.approx_matmul(dA, B, d2, out=out)
+            ms = statistics.median(tm.run(fn, 5, 2))
+            ctx.set_timing(True)
+            fn()
+            kt = ctx.timings()
+            ctx.set_timing(False)
+            err = rel_err(out[:, cols], exact)
+            res.append({"name": f"n={n} sparse0.5%+circulant K={K} {name}{tag}", "ms": ms,
+                        "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+                        "dense_fp32_ms": dense_ms, "err_vs_exact_sampled": err, "meets_1pct": err <= 0.01,
+                        "decompose_ms": dA.ms + (dB.ms if d2 is not None else 0.0), "nnz": dA.info()["nnz"],
+                        "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
+            log(f"[bench] c5 {name}{tag}: {ms:.3f} ms (dense {dense_ms:.3f}), err {err:.3e}, "
+                f"kernels {res[-1]['kernels_ms']}")
+        del dA, dB, decs
+    del A, B, exact, out
     torch.cuda.empty_cache()
     return res
 

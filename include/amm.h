@@ -68,10 +68,14 @@ typedef struct {
   uint64_t seed;       /* AMM_TSVD: counter-based sketch seed (Philox4x32-10) */
   int keep_residual;   /* keep Delta A on the device so that this handle can
                           be the left operand of a first-order product */
+  int spectral_fp16;   /* AMM_CIRCULANT with n >= 1024: store the eigenvalue
+                          lists the products use as float16 (half the list
+                          traffic; each multiplier rounded to 2^-11 relative),
+                          products and sums stay float32 (default 0) */
 } amm_opts;
 
 /* Fill `o` with the defaults (frac 0.01, nnz -1, oversample 16, power 2,
- * seed 0, keep_residual 1). */
+ * seed 0, keep_residual 1, spectral_fp16 0). */
 void amm_opts_default(amm_opts* o);
 
 typedef struct {
@@ -85,6 +89,7 @@ typedef struct {
   double norm_residual;  /* ||Delta A||_F from the dropped energy/spectrum
                             (blocked operands: over the zero-padded blocks) */
   int blocks;            /* square circulant blocks of a rectangular operand (0: none) */
+  int spectral_fp16;     /* circulant products use float16 lists */
 } amm_dec_info;
 
 /* ---- context ------------------------------------------------------------ */

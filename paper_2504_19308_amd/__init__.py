@@ -183,7 +183,7 @@ class Context:
     # -- decompositions ---------------------------------------------------------
     def decompose(self, A, kind: str, K: int, sparse_frac: float | None = None,
                   sparse_nnz: int | None = None, oversample: int = 16, power_iters: int = 2,
-                  seed: int = 0, keep_residual: bool = True) -> Decomposition:
+                  seed: int = 0, keep_residual: bool = True, spectral_fp16: bool = False) -> Decomposition:
         _need_f32_cuda(A, "A")
         lib = _lib.load()
         o = _lib.AmmOpts()
@@ -194,6 +194,7 @@ class Context:
             o.sparse_nnz = sparse_nnz
         o.oversample, o.power_iters, o.seed = oversample, power_iters, seed
         o.keep_residual = 1 if keep_residual else 0
+        o.spectral_fp16 = 1 if spectral_fp16 else 0
         h = C.c_void_p()
         m, n = A.shape
         _lib.check(lib.amm_decompose(self.handle, C.c_void_p(A.data_ptr()), m, n, KINDS[kind], K,

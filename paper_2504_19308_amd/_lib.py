@@ -19,13 +19,14 @@ AMM_SPARSE = 4
 class AmmOpts(C.Structure):
     _fields_ = [("sparse_frac", C.c_double), ("sparse_nnz", C.c_int64),
                 ("oversample", C.c_int), ("power_iters", C.c_int),
-                ("seed", C.c_uint64), ("keep_residual", C.c_int)]
+                ("seed", C.c_uint64), ("keep_residual", C.c_int), ("spectral_fp16", C.c_int)]
 
 
 class AmmDecInfo(C.Structure):
     _fields_ = [("kind", C.c_int), ("m", C.c_int64), ("n", C.c_int64), ("K", C.c_int),
                 ("K_eff", C.c_int), ("nnz", C.c_int64), ("has_residual", C.c_int),
-                ("norm_A", C.c_double), ("norm_residual", C.c_double), ("blocks", C.c_int)]
+                ("norm_A", C.c_double), ("norm_residual", C.c_double), ("blocks", C.c_int),
+                ("spectral_fp16", C.c_int)]
 
 
 # name -> (restype, argtypes); every pointer is a plain void* / typed pointer

@@ -172,7 +172,7 @@ amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t
       float* dst = valid == sd ? out + lo * p : scratch;
       if (b->K_eff == 0) AMM_TRY(fill_f32(dst, sd * p, 0.f, s));
       else AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, dst, false, s,
-                                    b->pairs_of(false)));
+                                    b->pairs_of(false), b->lists16(false)));
       if (valid < sd)
         AMM_HIP(hipMemcpyAsync(out + lo * p, scratch, valid * p * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
@@ -186,7 +186,7 @@ amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t
         if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
       } else {
         AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), src, p, out, acc, s,
-                                 b->pairs_of(false)));
+                                 b->pairs_of(false), b->lists16(false)));
       }
     }
   }
@@ -213,7 +213,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
       return AMM_OK;
     }
     return cd_apply_columns(ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(),
-                            d->L.as<float2>(), B, p, out, acc, s, d->pairs_of(false));
+                            d->L.as<float2>(), B, p, out, acc, s, d->pairs_of(false), d->lists16(false));
   }
   if (is_tsvd(d)) {
     const int k = d->K_eff;
@@ -260,7 +260,7 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
       return AMM_OK;
     }
     return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
-                         d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true));
+                         d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true), d->lists16(true));
   }
   if (is_tsvd(d)) {
     const int k = d->K_eff;
@@ -331,6 +331,7 @@ void amm_opts_default(amm_opts* o) {
   o->power_iters = 2;
   o->seed = 0;
   o->keep_residual = 1;
+  o->spectral_fp16 = 0;
 }
 
 const char* amm_last_error(void) { return g_msg; }
@@ -401,11 +402,13 @@ amm_status amm_dec_query(const amm_dec* d, amm_dec_info* info) {
   info->K = d->K;
   info->K_eff = d->K_eff;
   info->nnz = d->nnz;
-  const amm_dec* r = d;
   info->has_residual = (d->residual.ptr || d->A_borrowed ||
                         (d->inner && (d->inner->residual.ptr || d->inner->A_borrowed))) ? 1 : 0;
-  (void)r;
   info->blocks = (int)d->blocks.size();
+  {
+    const amm_dec* c = (d->inner ? d->inner : d);
+    info->spectral_fp16 = (c->fp16 || (!c->blocks.empty() && c->blocks[0]->fp16)) ? 1 : 0;
+  }
   info->norm_A = d->norm_A;
   info->norm_residual = d->norm_residual;
   return AMM_OK;
@@ -793,7 +796,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
       b->m = b->n = sd;
       b->K = K;
       b->device = ctx->device;
-      st = cd_decompose(ctx, bp, l2, K, false, b, s);
+      st = cd_decompose(ctx, bp, l2, K, false, b, s, o.spectral_fp16 != 0);
       if (st != AMM_OK) { delete b; break; }
       d->blocks.push_back(b);
       d->K_eff += b->K_eff;
@@ -818,7 +821,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     d->m = d->n = n;
     d->K = K;
     d->device = ctx->device;
-    amm_status st = cd_decompose(ctx, A, l2, K, o.keep_residual != 0, d, s);
+    amm_status st = cd_decompose(ctx, A, l2, K, o.keep_residual != 0, d, s, o.spectral_fp16 != 0);
     if (st != AMM_OK) {
       delete d;
       return st;
@@ -970,7 +973,7 @@ amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
       AMM_TRY(fill_f32(it.out, it.m * it.p, 0.f, s));
     } else {
       AMM_TRY(cd_apply_columns(bp->ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
-                               it.p, it.out, false, s, d->pairs_of(false)));
+                               it.p, it.out, false, s, d->pairs_of(false), d->lists16(false)));
     }
   }
   return AMM_OK;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include <cstdint>
 #include <map>
@@ -117,6 +118,13 @@ struct amm_dec {
   amm::DevBuf L;           // K_eff x n float2
   amm::DevBuf Ladj;        // K_eff x n float2
   amm::DevBuf energies;    // n double (decompose only)
+  // float16 copies of L and Ladj used by the products when requested (n >= 1024)
+  amm::DevBuf L16, Ladj16;
+  bool fp16 = false;
+  const __half2* lists16(bool adjoint) const {
+    if (!fp16) return nullptr;
+    return adjoint ? Ladj16.as<__half2>() : L16.as<__half2>();
+  }
   // pair structure for the paired spectral MAC (npairs < 0: not available)
   amm::DevBuf pair_buf;     // int2: pairs, singles, pairs_adj, singles_adj
   int npairs = -1, nsingles = 0, npairs_adj = -1, nsingles_adj = 0;
@@ -199,12 +207,15 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
 //  column mode: out (n x p) [+]= Atil B, B (n x p) row-major, along columns.
 //  row mode:    out (rows x n) [+]= X Btil^T-side operator applied to each
 //               row of X (rows x n):  out_row = (op(row^T))^T.
+// L16 (optional): the same lists as float16 pairs (n >= 1024), used instead of L.
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s, CdPairs pr = CdPairs{});
+                            bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
+                            const __half2* L16 = nullptr);
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
-                         bool accumulate, hipStream_t s, CdPairs pr = CdPairs{});
+                         bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
+                         const __half2* L16 = nullptr);
 
 // Forward spectra of the packed column pairs of B (n x p, p even): spec
 // (n x p floats) holds complex bin values at [p][2c], [p][2c + 1].
@@ -217,7 +228,7 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
 
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
-                        bool keep_residual, amm_dec* dec, hipStream_t s);
+                        bool keep_residual, amm_dec* dec, hipStream_t s, bool fp16 = false);
 
 // Closed-set frequency selection (host), same reading as documented in amm.h.
 std::vector<int32_t> select_closed(const std::vector<double>& E, int K);

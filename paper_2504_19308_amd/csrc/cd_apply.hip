@@ -18,8 +18,12 @@
 #include "amm_internal.hpp"
 #include "fft_core.hpp"
 
+#include <hip/hip_fp16.h>
+
 namespace amm {
 namespace {
+
+constexpr int kH16MinLog2 = 10;   // float16 lists: n >= 1024
 
 template <int LOG2N> struct CdCfg {
   static constexpr int N = 1 << LOG2N;
@@ -106,10 +110,19 @@ __device__ __forceinline__ void lds_fft(float2* lds, const float2* __restrict__ 
 // SPEC = true (column mode only): store the forward spectrum of each packed
 // column pair instead of the product, unscaled, in the same row-major slots
 // (bin p, pair c) -> out[p * extent + 2c + {re, im}].
-template <int LOG2N, bool ROWS, bool SPEC = false>
+// H16: the eigenvalue lists are stored as float16 pairs (the spectral
+// multipliers of the product in half precision); they are widened on load and
+// every product and sum stays float32.
+template <bool H16>
+__device__ __forceinline__ float2 list_at(const void* __restrict__ L, int64_t i) {
+  if constexpr (H16) return __half22float2(reinterpret_cast<const __half2*>(L)[i]);
+  else return reinterpret_cast<const float2*>(L)[i];
+}
+
+template <int LOG2N, bool ROWS, bool SPEC = false, bool H16 = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
-                int K, const int32_t* __restrict__ shifts, const float2* __restrict__ L,
+                int K, const int32_t* __restrict__ shifts, const void* __restrict__ L,
                 const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
@@ -211,12 +224,12 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
     for (int u = 0; u < pr.npairs; ++u) {
       const int2 pk = pr.pairs[u];
       const int k = pk.x;
-      const float2* __restrict__ Lt = L + (int64_t)pk.y * N;
+      const int64_t Lt = (int64_t)pk.y * N;
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
         int b1, b2;
         pair_bins(i, b1, b2);
-        const float2 l1 = Lt[b1], l2 = Lt[b2];
+        const float2 l1 = list_at<H16>(L, Lt + b1), l2 = list_at<H16>(L, Lt + b2);
         const bool self = b1 == 0;                  // 0 and N/2 are their own mirrors
         const float2 m1 = self ? l1 : l2, m2 = self ? l2 : l1;
         const float2 c1 = float2{m1.x, -m1.y}, c2 = float2{m2.x, -m2.y};
@@ -240,18 +253,18 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
     for (int v = 0; v < pr.nsingles; ++v) {
       const int2 sk = pr.singles[v];
       const int k = sk.x;
-      const float2* __restrict__ Lt = L + (int64_t)sk.y * N;
+      const int64_t Lt = (int64_t)sk.y * N;
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
         int b1, b2;
         pair_bins(i, b1, b2);
         float2 x[CPL];
         load_x(b1 - k, x);
-        const float2 l1 = Lt[b1];
+        const float2 l1 = list_at<H16>(L, Lt + b1);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) cmac(acc[i][c], l1, x[c]);
         load_x(b2 - k, x);
-        const float2 l2 = Lt[b2];
+        const float2 l2 = list_at<H16>(L, Lt + b2);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) cmac(acc[NH + i][c], l2, x[c]);
       }
@@ -259,12 +272,12 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   } else {
     for (int t = 0; t < K; ++t) {
       const int k = shifts[t];
-      const float2* __restrict__ Lt = L + (int64_t)t * N;
+      const int64_t Lt = (int64_t)t * N;
 #pragma unroll
       for (int i = 0; i < NBINS; ++i) {
         const int p = bl + i * BL;
         if (N % BL == 0 || p < N) {
-          const float2 l = Lt[p];
+          const float2 l = list_at<H16>(L, Lt + p);
           float2 x[CPL];
           load_x(p - k, x);
 #pragma unroll
@@ -341,8 +354,8 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 
 template <int LOG2N>
 amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
-                     const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                     hipStream_t s, bool spec, CdPairs pr) {
+                     const int32_t* shifts, const void* L, const float2* tw, bool acc,
+                     hipStream_t s, bool spec, CdPairs pr, bool h16) {
   using Cfg = CdCfg<LOG2N>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
@@ -355,7 +368,18 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
   if (spec)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
                        shifts, L, tw, 0, vec4, pr);
-  else if (rows)
+  else if (h16) {
+    if constexpr (LOG2N >= kH16MinLog2) {
+      if (rows)
+        hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true, false, true>), grid, block, 0, s, X, out, extent, K,
+                           shifts, L, tw, acc ? 1 : 0, 0, pr);
+      else
+        hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, false, true>), grid, block, 0, s, X, out, extent, K,
+                           shifts, L, tw, acc ? 1 : 0, vec4, pr);
+    } else {
+      return fail(AMM_EUNSUPPORTED, "float16 lists need n >= %d", 1 << kH16MinLog2);
+    }
+  } else if (rows)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
                        shifts, L, tw, acc ? 1 : 0, 0, pr);
   else
@@ -366,11 +390,11 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
 }
 
 amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
-                       const int32_t* shifts, const float2* L, const float2* tw, bool acc,
-                       hipStream_t s, bool spec, CdPairs pr) {
+                       const int32_t* shifts, const void* L, const float2* tw, bool acc,
+                       hipStream_t s, bool spec, CdPairs pr, bool h16 = false) {
   switch (log2n) {
 #define AMM_CASE(L2) \
-  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr);
+  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr, h16);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
     AMM_CASE(13) AMM_CASE(14)
@@ -383,9 +407,10 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t
 
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s, CdPairs pr) {
+                            bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
+  if (L16) return dispatch_cd(false, log2n, B, out, p, K, shifts, L16, tw, accumulate, s, false, pr, true);
   return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
@@ -398,9 +423,10 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
-                         bool accumulate, hipStream_t s, CdPairs pr) {
+                         bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
+  if (L16) return dispatch_cd(true, log2n, X, out, rows, K, shifts, L16, tw, accumulate, s, false, pr, true);
   return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s, false, pr);
 }
 

@@ -109,6 +109,11 @@ __global__ void gather_lists(const double2* __restrict__ Ahat, int n,
   Ladj[(int64_t)t * n + p] = float2{(float)b.x, (float)-b.y};
 }
 
+__global__ void lists_to_half(const float2* __restrict__ src, __half2* __restrict__ dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = __float22half2_rn(src[i]);
+}
+
 __global__ void zero_diagonals(double2* __restrict__ Ahat, int n, const int32_t* __restrict__ shifts) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -201,7 +206,7 @@ std::vector<int32_t> select_closed(const std::vector<double>& E, int K) {
 }
 
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool keep_residual,
-                        amm_dec* dec, hipStream_t s) {
+                        amm_dec* dec, hipStream_t s, bool fp16) {
   const int n = 1 << log2n;
   const int64_t nn = (int64_t)n * n;
   const double2* tw = nullptr;
@@ -259,6 +264,17 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
     AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
     AMM_HIP(hipStreamSynchronize(s));
     AMM_TRY(cd_build_pairs(dec, Lh));
+    if (fp16 && log2n >= 10) {
+      const int64_t cnt = (int64_t)Ke * n;
+      AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
+      AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));
+      hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->L.as<float2>(),
+                         dec->L16.as<__half2>(), cnt);
+      hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->Ladj.as<float2>(),
+                         dec->Ladj16.as<__half2>(), cnt);
+      AMM_HIP(hipGetLastError());
+      dec->fp16 = true;
+    }
   }
 
   if (keep_residual) {

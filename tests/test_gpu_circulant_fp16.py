@@ -1,0 +1,141 @@
+"""Circulant products with float16 eigenvalue lists (spectral_fp16, n >= 1024):
+the multipliers are stored in half precision; spectra, products and sums stay
+float32.
+
+Two kinds of check.  (1) Operands planted from eigenvalue lists that lie on a
+coarse binary grid, so every kept list is exactly representable in float16:
+storing it in half precision changes nothing and the product must meet the
+float32 bar 1e-5 against the float64 oracle.  (2) General operands: each
+stored entry carries a relative error of at most sqrt(2) u16 (u16 = 2^-11,
+real and imaginary parts rounded separately), so the product error is bounded
+by sqrt(2) u16 sum_t ||term_t||_F / ||sum_t term_t||_F (terms computed by the
+oracle) plus the float32 bar."""
+import numpy as np
+import pytest
+
+from oracle import circulant as oc
+from tests._gpu_common import TOL_F32, ctx, f32, gpu, host, note, rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+U16 = 2.0 ** -11
+
+
+class _Lists:
+    def __init__(self, n, S, L):
+        self.n, self.S, self.L = n, np.asarray(S, dtype=np.int64), np.asarray(L)
+
+
+def _grid_classes(n, modes, rng, grid=32.0):
+    """Lists for the pair classes {k, n-k}: L_k on the grid 2^-j / grid
+    (class j scaled by 2^-j so the energies are well separated), and
+    L_{n-k}[p] = conj(L_k[-p]) so the operand is real."""
+    neg = (-np.arange(n)) % n
+    out = {}
+    for j, k in enumerate(modes):
+        v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        v = (np.round(v.real * grid) + 1j * np.round(v.imag * grid)) / grid * 2.0 ** -j
+        out[k] = v
+        out[n - k] = np.conj(v[neg])
+    return out
+
+
+def _operand_from_classes(n, modes, lists):
+    """A = sum_k R_k D^k with r_k = F^-1 L_k; the class {k, n-k} contributes
+    2 Re(r_k[(p-q) mod n] w^(k q)).  Built in float64 on the device, then
+    rounded to float32."""
+    torch = torch_cuda()
+    idx = torch.arange(n, device="cuda")
+    diff = (idx[:, None] - idx[None, :]) % n
+    A = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    for k in modes:
+        r = torch.from_numpy(np.fft.ifft(lists[k])).to("cuda")
+        ph = torch.exp(2j * np.pi * ((k * idx) % n).to(torch.float64) / n)
+        A += 2.0 * (r[diff] * ph[None, :]).real
+    del diff
+    return A.float().contiguous()
+
+
+def _randn(n, p, seed):
+    torch = torch_cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.randn((n, p), generator=g, device="cuda", dtype=torch.float32)
+
+
+@pytest.mark.parametrize("n,modes,keep", [(1024, [3, 100, 400], 3), (4096, [1, 7, 900, 2000, 1500], 4),
+                                          (8192, [5, 3001], 2)])
+def test_fp16_grid_lists_exact(n, modes, keep):
+    note(f"fp16 grid lists n={n} modes={modes} keep={keep}")
+    rng = np.random.default_rng(n + len(modes))
+    lists = _grid_classes(n, modes, rng)
+    A = _operand_from_classes(n, modes, lists)
+    c = ctx()
+    K = 2 * keep
+    d = c.decompose(A, "circulant", K, spectral_fp16=True)
+    assert d.info()["spectral_fp16"] == 1
+    S = sorted(d.frequencies())
+    kept = modes[:keep]
+    assert S == sorted(kept + [n - k for k in kept])
+    B = _randn(n, 48, n + 11)
+    got = host(c.approx_matmul(d, B))
+    want = np.real(oc.apply_zeroth(_Lists(n, S, np.array([lists[k] for k in S])), host(B)))
+    assert rel(got, want) < TOL_F32
+
+
+def test_fp16_grid_first_order():
+    """A tilde B + Delta A B tilde, every kept list on the grid; Delta A holds
+    the dropped planted classes of A."""
+    n = 2048
+    rng = np.random.default_rng(77)
+    mA, mB = [2, 300, 41, 900], [9, 640, 77]
+    LA, LB = _grid_classes(n, mA, rng), _grid_classes(n, mB, rng)
+    A, B = _operand_from_classes(n, mA, LA), _operand_from_classes(n, mB, LB)
+    c = ctx()
+    dA = c.decompose(A, "circulant", 4, spectral_fp16=True)
+    dB = c.decompose(B, "circulant", 4, spectral_fp16=True)
+    SA, SB = sorted(dA.frequencies()), sorted(dB.frequencies())
+    assert SA == sorted(mA[:2] + [n - k for k in mA[:2]])
+    assert SB == sorted(mB[:2] + [n - k for k in mB[:2]])
+    got = host(c.approx_matmul(dA, B, dB))
+    Ah, Bh = host(A), host(B)
+    decA = oc.CirculantDecomp(Ah, 4, S=SA)
+    hB = _Lists(n, SB, np.array([LB[k] for k in SB]))
+    dAres = Ah - np.real(decA.truncated_dense())
+    want = np.real(oc.apply_zeroth(decA, Bh)) + np.real(oc.apply_first_order_term(hB, dAres))
+    assert rel(got, want) < TOL_F32
+
+
+@pytest.mark.parametrize("n,K", [(1024, 9), (4096, 32)])
+def test_fp16_general_operand_bound(n, K):
+    note(f"fp16 general operand n={n} K={K}")
+    from paper_2504_19308_amd import inputs
+    rng = np.random.default_rng(n + K)
+    A = f32(inputs.toeplitz_uniform(n, rng) + 0.05 * rng.standard_normal((n, n)))
+    B = f32(rng.standard_normal((n, 40)))
+    dec = oc.CirculantDecomp(A, K)
+    c = ctx()
+    d = c.decompose(gpu(A), "circulant", K, spectral_fp16=True)
+    assert d.info()["spectral_fp16"] == 1
+    assert list(d.frequencies()) == list(dec.S)
+    got = host(c.approx_matmul(d, gpu(B)))
+    want = np.real(oc.apply_zeroth(dec, B))
+    terms = sum(np.linalg.norm(np.real(oc.apply_zeroth(_Lists(n, [k], dec.L[t:t + 1]), B)))
+                for t, k in enumerate(dec.S))
+    bound = np.sqrt(2.0) * U16 * terms / np.linalg.norm(want) + TOL_F32
+    err = rel(got, want)
+    assert TOL_F32 < err < bound   # half-precision multipliers are in use, within their bound
+    d32 = c.decompose(gpu(A), "circulant", K)
+    assert rel(host(c.approx_matmul(d32, gpu(B))), want) < TOL_F32
+
+
+def test_fp16_small_n_keeps_float32():
+    n = 512
+    rng = np.random.default_rng(3)
+    from paper_2504_19308_amd import inputs
+    A = f32(inputs.toeplitz_uniform(n, rng) + 0.05 * rng.standard_normal((n, n)))
+    c = ctx()
+    d = c.decompose(gpu(A), "circulant", 5, spectral_fp16=True)
+    assert d.info()["spectral_fp16"] == 0
+    B = f32(rng.standard_normal((n, 8)))
+    assert rel(host(c.approx_matmul(d, gpu(B))), np.real(oc.apply_zeroth(oc.CirculantDecomp(A, 5), B))) < TOL_F32
