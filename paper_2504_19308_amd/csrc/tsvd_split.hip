@@ -44,11 +44,17 @@ __device__ __forceinline__ int xcd_order(int bid, int nblk) {
 }
 
 constexpr int PW = 4;    // waves per panel workgroup
-constexpr int DG = 4;    // G job: 4-row groups per load batch
-constexpr int DH = 2;    // H job: 16-column groups per load batch
+
+// Load-batch depth of a panel launch: DG 4-row groups (G job) and DH 16-column
+// groups (H job) per batch.  The deep form keeps two batches in registers and
+// issues the next batch's loads before the current batch's MFMAs (software
+// pipeline); it trades occupancy for loads in flight and is used for ranks 32.
+template <bool DEEP> struct Depth;
+template <> struct Depth<false> { static constexpr int DG = 4, DH = 2; };
+template <> struct Depth<true> { static constexpr int DG = 8, DH = 4; };
 
 // G (as Gt, p x KA) partial of split `split`: rows [split*per*PW, ...) of Y
-template <int KA>
+template <int KA, bool DEEP>
 __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* __restrict__ Y, int64_t p,
                                       int64_t n, int S, float* __restrict__ Gt, int bid, int nblk, float* red) {
   constexpr int IB = KA / 16;
@@ -64,9 +70,8 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[i][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t r = rb; r < re; r += 4 * DG) {
-    float4 y[DG];
-    float xv[DG][IB];
+  constexpr int DG = Depth<DEEP>::DG;
+  auto load = [&](int64_t r, float4(&y)[DG], float(&xv)[DG][IB]) {
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
       const int64_t row = r + 4 * d + g;
@@ -74,6 +79,8 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
 #pragma unroll
       for (int i = 0; i < IB; ++i) xv[d][i] = X[row * KA + i * 16 + t];
     }
+  };
+  auto comp = [&](const float4(&y)[DG], const float(&xv)[DG][IB]) {
 #pragma unroll
     for (int d = 0; d < DG; ++d)
 #pragma unroll
@@ -83,6 +90,30 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
         acc[i][2] = mfma_f32(xv[d][i], y[d].z, acc[i][2]);
         acc[i][3] = mfma_f32(xv[d][i], y[d].w, acc[i][3]);
       }
+  };
+  constexpr int STEP = 4 * DG;
+  if constexpr (!DEEP) {
+    for (int64_t r = rb; r < re; r += STEP) {
+      float4 y[DG];
+      float xv[DG][IB];
+      load(r, y, xv);
+      comp(y, xv);
+    }
+  } else {
+    // batches b = 0, 1, ... of STEP rows (per is a multiple of STEP); batch b + 1
+    // is in flight while batch b is multiplied
+    const int64_t nb = per / STEP;
+    float4 y0[DG], y1[DG];
+    float x0[DG][IB], x1[DG][IB];
+    load(rb, y0, x0);
+    int64_t b = 0;
+    for (; b + 1 < nb; b += 2) {
+      load(rb + (b + 1) * STEP, y1, x1);
+      comp(y0, x0);
+      if (b + 2 < nb) load(rb + (b + 2) * STEP, y0, x0);
+      comp(y1, x1);
+    }
+    if (b < nb) comp(y0, x0);
   }
   // lane: acc[i][q][rr] = G[16i + 4g + rr][j0 + 4t + q]
   if (wave > 0) {
@@ -110,7 +141,7 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
 }
 
 // H (m x KB) partial of split `split`: columns [split*per*PW, ...) of X
-template <int KB>
+template <int KB, bool DEEP>
 __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* __restrict__ X, int64_t m,
                                       int64_t n, int S, float* __restrict__ H, int bid, int nblk, float* red) {
   constexpr int CB = KB / 16;
@@ -126,9 +157,8 @@ __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* 
   for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[bb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t c0 = c0s; c0 < ce; c0 += 16 * DH) {
-    float4 a[DH][4];
-    float u[DH][4][CB];
+  constexpr int DH = Depth<DEEP>::DH;
+  auto load = [&](int64_t c0, float4(&a)[DH][4], float(&u)[DH][4][CB]) {
 #pragma unroll
     for (int d = 0; d < DH; ++d) {
       const int64_t cc = c0 + 16 * d + 4 * g;
@@ -139,6 +169,8 @@ __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* 
 #pragma unroll
         for (int c = 0; c < CB; ++c) u[d][q][c] = U[(cc + q) * KB + c * 16 + t];
     }
+  };
+  auto comp = [&](const float4(&a)[DH][4], const float(&u)[DH][4][CB]) {
 #pragma unroll
     for (int d = 0; d < DH; ++d)
 #pragma unroll
@@ -150,6 +182,28 @@ __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* 
           acc[bb][c] = mfma_f32(a[d][bb].z, u[d][2][c], acc[bb][c]);
           acc[bb][c] = mfma_f32(a[d][bb].w, u[d][3][c], acc[bb][c]);
         }
+  };
+  constexpr int STEP = 16 * DH;
+  if constexpr (!DEEP) {
+    for (int64_t c0 = c0s; c0 < ce; c0 += STEP) {
+      float4 a[DH][4];
+      float u[DH][4][CB];
+      load(c0, a, u);
+      comp(a, u);
+    }
+  } else {
+    const int64_t nb = per / STEP;
+    float4 a0[DH][4], a1[DH][4];
+    float u0[DH][4][CB], u1[DH][4][CB];
+    load(c0s, a0, u0);
+    int64_t b = 0;
+    for (; b + 1 < nb; b += 2) {
+      load(c0s + (b + 1) * STEP, a1, u1);
+      comp(a0, u0);
+      if (b + 2 < nb) load(c0s + (b + 2) * STEP, a0, u0);
+      comp(a1, u1);
+    }
+    if (b < nb) comp(a0, u0);
   }
   // lane: acc[bb][c][rr] = H[row0 + 16bb + 4g + rr][16c + t]
   if (wave > 0) {
@@ -186,13 +240,13 @@ struct PanelArgs {
   float* H;          // SH x (m x KB)
 };
 
-template <int KA, int KB>
+template <int KA, int KB, bool DEEP>
 __global__ void __launch_bounds__(256) split_panels_kernel(PanelArgs a) {
   constexpr int KM = KA > KB ? KA : KB;
   __shared__ __align__(16) float red[(PW - 1) * 64 * KM];
   const int nG = (int)(a.p / 64) * a.SG;
-  if ((int)blockIdx.x < nG) g_job<KA>(a.VA, a.Y, a.p, a.n, a.SG, a.Gt, blockIdx.x, nG, red);
-  else if constexpr (KB > 0) h_job<KB>(a.UB, a.X, a.m, a.n, a.SH, a.H, blockIdx.x - nG, gridDim.x - nG, red);
+  if ((int)blockIdx.x < nG) g_job<KA, DEEP>(a.VA, a.Y, a.p, a.n, a.SG, a.Gt, blockIdx.x, nG, red);
+  else if constexpr (KB > 0) h_job<KB, DEEP>(a.UB, a.X, a.m, a.n, a.SH, a.H, blockIdx.x - nG, gridDim.x - nG, red);
 }
 
 // sum S partial slabs of `count` floats (fixed order); two regions per launch
@@ -329,10 +383,17 @@ int pick_s(int64_t blocks1, int64_t n, int quantum, int target) {
 }
 
 template <int KA, int KB>
-amm_status launch_panels(const PanelArgs& a, hipStream_t s) {
+amm_status launch_panels(const PanelArgs& a, bool deep, hipStream_t s) {
   const int64_t blocks = (a.p / 64) * a.SG + (KB > 0 ? (a.m / 64) * a.SH : 0);
   TimedLaunch tl("panel", s);
-  hipLaunchKernelGGL((split_panels_kernel<KA, KB>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if constexpr (KA == 32 && KB <= 32) {
+    if (deep) {
+      hipLaunchKernelGGL((split_panels_kernel<KA, KB, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+      AMM_HIP(hipGetLastError());
+      return AMM_OK;
+    }
+  }
+  hipLaunchKernelGGL((split_panels_kernel<KA, KB, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -347,9 +408,9 @@ amm_status launch_out(const float* A1, const float* A2, const float* B1, const f
   return AMM_OK;
 }
 
-amm_status dispatch_panels(int ka, int kb, const PanelArgs& a, hipStream_t s) {
+amm_status dispatch_panels(int ka, int kb, const PanelArgs& a, bool deep, hipStream_t s) {
 #define AMM_P(A, B) \
-  if (ka == A && kb == B) return launch_panels<A, B>(a, s);
+  if (ka == A && kb == B) return launch_panels<A, B>(a, deep, s);
   AMM_P(32, 0) AMM_P(64, 0) AMM_P(32, 32) AMM_P(32, 64) AMM_P(64, 32) AMM_P(64, 64)
 #undef AMM_P
   return fail(AMM_EUNSUPPORTED, "split panel ranks %d, %d", ka, kb);
@@ -364,22 +425,33 @@ amm_status dispatch_out(int k1, int k2, const float* A1, const float* A2, const 
   return fail(AMM_EUNSUPPORTED, "split output ranks %d, %d", k1, k2);
 }
 
-void plan_splits(int64_t m, int64_t n, int64_t p, int kb, int* SG, int* SH) {
-  *SG = pick_s(p / 64, n, 4 * DG, 512);
-  *SH = kb > 0 ? pick_s(m / 64, n, 16 * DH, 512) : 1;
+// deep (pipelined) panels for rank-32 operands when the reduction length splits
+// into whole deep batches; they want about half as many workgroups
+bool use_deep(int64_t n, int ka, int kb) {
+  return ka == 32 && kb <= 32 && n % (PW * 16 * Depth<true>::DH) == 0 && n % (PW * 4 * Depth<true>::DG) == 0;
+}
+
+void plan_splits(int64_t m, int64_t n, int64_t p, int ka, int kb, int* SG, int* SH, bool* deep) {
+  *deep = use_deep(n, ka, kb);
+  const int target = *deep ? 128 : 512;
+  const int qg = 4 * (*deep ? Depth<true>::DG : Depth<false>::DG);
+  const int qh = 16 * (*deep ? Depth<true>::DH : Depth<false>::DH);
+  *SG = pick_s(p / 64, n, qg, target);
+  *SH = kb > 0 ? pick_s(m / 64, n, qh, target) : 1;
 }
 
 }  // namespace
 
 bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb) {
   return (ka == 32 || ka == 64) && (kb == 0 || kb == 32 || kb == 64) && m > 0 && p > 0 && m % OT == 0 &&
-         p % OT == 0 && n % (PW * 16 * DH) == 0 && n % (PW * 4 * DG) == 0 && n > 0 &&
+         p % OT == 0 && n % (PW * 16 * Depth<false>::DH) == 0 && n % (PW * 4 * Depth<false>::DG) == 0 && n > 0 &&
          (m / OT) * (p / OT) < ((int64_t)1 << 31);
 }
 
 size_t tsvd_split_scratch(int64_t m, int64_t n, int64_t p, int ka, int kb) {
   int SG, SH;
-  plan_splits(m, n, p, kb, &SG, &SH);
+  bool deep;
+  plan_splits(m, n, p, ka, kb, &SG, &SH, &deep);
   return (size_t)(SG + 1) * ka * p + (size_t)(SH + 1) * kb * m + 64;
 }
 
@@ -392,7 +464,8 @@ amm_status tsvd_split_product(int64_t m, int64_t n, int64_t p, int ka, int kb, c
   if (!tsvd_split_shapes(m, n, p, ka, kb)) return fail(AMM_EUNSUPPORTED, "split product shape");
   if (scratch_floats < tsvd_split_scratch(m, n, p, ka, kb)) return fail(AMM_EINVAL, "split product scratch too small");
   PanelArgs a{};
-  plan_splits(m, n, p, kb, &a.SG, &a.SH);
+  bool deep;
+  plan_splits(m, n, p, ka, kb, &a.SG, &a.SH, &deep);
   a.VA = V_A; a.Y = Y; a.UB = U_B; a.X = X;
   a.m = m; a.n = n; a.p = p;
   float* Gp = scratch;
@@ -401,7 +474,7 @@ amm_status tsvd_split_product(int64_t m, int64_t n, int64_t p, int ka, int kb, c
   float* H = G + (size_t)ka * p;
   a.Gt = a.SG > 1 ? Gp : G;
   a.H = a.SH > 1 ? Hp : H;
-  AMM_TRY(dispatch_panels(ka, kb, a, s));
+  AMM_TRY(dispatch_panels(ka, kb, a, deep, s));
   const int64_t gc = a.SG > 1 ? (int64_t)ka * p : 0, hc = (kb > 0 && a.SH > 1) ? (int64_t)kb * m : 0;
   if (gc + hc > 0) {
     TimedLaunch tl("reduce", s);
