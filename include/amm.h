@@ -90,6 +90,10 @@ typedef struct {
                             (blocked operands: over the zero-padded blocks) */
   int blocks;            /* square circulant blocks of a rectangular operand (0: none) */
   int spectral_fp16;     /* circulant products use float16 lists */
+  double mu;             /* circulant: spectral concentration of Delta A (see
+                            amm_estimate_error); NaN if not computed */
+  double sigma_next;     /* truncated SVD: sigma_{k+1} estimate (= ||Delta A||_2);
+                            NaN if unknown */
 } amm_dec_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -268,6 +272,68 @@ void amm_batch_plan_destroy(amm_batch_plan* plan);
 amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X,
                                       const float* dY, int64_t p, float* dX, float* dWo,
                                       void* stream);
+
+/* ---- error estimates (Sec. 2.5 and Sec. 3) ------------------------------- */
+
+/* Entry model for the a priori estimate (Thm. 3.6). */
+enum {
+  AMM_ENTRIES_SIGNED = 0,            /* mean-zero entries / Haar singular vectors */
+  AMM_ENTRIES_UNSIGNED_UNIFORM = 1   /* entries U(0, a) */
+};
+
+/* Estimates of the relative error ||AB - M||_F / ||AB||_F = ||Delta A Delta B||_F / ||AB||_F
+ * of the first-order product M = Atil B + Delta A Btil (eq. (2.1)), n the inner
+ * dimension.  Fields that cannot be formed are NaN. */
+typedef struct {
+  double norm_A, norm_B;     /* ||A||_F, ||B||_F as held by the handles */
+  double norm_dA, norm_dB;   /* ||Delta A||_F, ||Delta B||_F */
+  double norm_M;             /* ||M||_F of the given product (float64 sum) */
+  double prior;              /* Thm. 3.6 without its vanishing term: ||dA|| ||dB|| / (||A|| ||B||),
+                                times 4 / (3 sqrt(n)) for AMM_ENTRIES_UNSIGNED_UNIFORM */
+  double posterior;          /* Cor. 3.7: ||dA|| ||dB|| / (sqrt(n) ||M||) */
+  double svd_bound;          /* Thm. 3.8 over ||M||: sqrt(||dA||_2 ||dB||_2 ||dA|| ||dB||) / ||M||,
+                                both operands truncated SVDs (plain or as the residue of a sparse
+                                split) with ||dA||_2 = sigma_next.  For exact factors ||M|| <= ||AB||
+                                (proof of Cor. 3.7), so this bounds the relative error */
+  double cd_estimate;        /* circulant residual theorem of Sec. 3 over ||M||:
+                                (mu_A mu_B)^(1/4) ||dA|| ||dB|| / (sqrt(n) ||M||), both operands square
+                                circulant.  Its inequality does not hold for every input, so it is an
+                                estimate, not a bound */
+  double spec_dA, spec_dB;   /* sigma_next of the two truncated SVDs */
+  double mu_A, mu_B;         /* circulant concentration: mu = max_i X_i / (||dA||_F^2 / n),
+                                X_i = sum over dropped k of |lambda_i(R_k)|^2 */
+} amm_error_estimate;
+
+/* Fill *out from the norms and statistics the handles carry (decomposed
+ * handles, circulant imports with their norms, truncated-SVD imports with A);
+ * with M (m x p float32, device, the product of dA and dB) also ||M||_F and the
+ * estimates that divide by it.  Synchronises `stream` when M is given.
+ * Errors: AMM_ESHAPE if dA->n != dB->m or M's shape differs from the product. */
+amm_status amm_estimate_error(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* M, int64_t m,
+                              int64_t p, int entries, void* stream, amm_error_estimate* out);
+
+/* Randomized estimate of the relative error (Sec. 2.5, last item):
+ *   *est = ||A (B G) - M G||_F / ||A (B G)||_F
+ * A (m x n), B (n x p), M (m x p) and the sketch G (p x l, N(0, 1) or
+ * Rademacher entries drawn by the caller) are float32 row-major device arrays.
+ * The three products run on the matrix cores in float32, the norms in float64;
+ * the cost is 2 l (n p + m n + m p) flops.  Synchronises `stream`. */
+amm_status amm_estimate_sketch(amm_ctx* ctx, const float* A, const float* B, const float* M, const float* G,
+                               int64_t m, int64_t n, int64_t p, int64_t l, void* stream, double* est);
+
+/* The smallest truncation K (the same for A and B) whose a priori estimate
+ * (Thm. 3.6, as in amm_estimate_error) is <= tau (Sec. 2.5: add components
+ * while the estimate is not small enough).  Two square circulant handles made
+ * by amm_decompose: any K in [0, n], from their n energies and the pair-closed
+ * selection (||Delta A(K)||^2 = sum E - retained(K)); decompose again with the
+ * returned K.  Two truncated-SVD handles: K <= min(k_A, k_B) from the kept
+ * singular values (||Delta A(k)||^2 = ||A||^2 - sum_{i<k} sigma_i^2); returns
+ * that maximum when no smaller rank meets tau.  Host work only. */
+amm_status amm_choose_rank(const amm_dec* dA, const amm_dec* dB, double tau, int entries, int* K);
+
+/* Record sigma_{k+1} (>= 0) for an imported truncated SVD whose next singular
+ * value the caller knows (decomposed handles carry their sketch's estimate). */
+amm_status amm_dec_set_sigma_next(amm_dec* dec, double sigma_next);
 
 #ifdef __cplusplus
 }

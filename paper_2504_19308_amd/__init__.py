@@ -37,6 +37,9 @@ def _need_f32_cuda(t, name):
         raise ValueError(f"{name} must be a contiguous 2-D tensor")
 
 
+_ENTRIES = {"signed": _lib.AMM_ENTRIES_SIGNED, "unsigned_uniform": _lib.AMM_ENTRIES_UNSIGNED_UNIFORM}
+
+
 class Decomposition:
     """Owns an ``amm_dec`` handle; keeps borrowed tensors alive."""
 
@@ -90,6 +93,10 @@ class Decomposition:
         _lib.check(_lib.load().amm_dec_sparse_part(self.handle, rp.ctypes.data_as(C.c_void_p),
                                                    col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p)))
         return rp, col[:nnz], val[:nnz]
+
+    def set_sigma_next(self, value: float):
+        """Record sigma_{k+1} of an imported truncated SVD (for the Thm. 3.8 bound)."""
+        _lib.check(_lib.load().amm_dec_set_sigma_next(self.handle, float(value)))
 
     def close(self):
         if self.handle and self._owned:
@@ -302,6 +309,41 @@ class Context:
             C.c_void_p(dX.data_ptr()) if dX is not None else None,
             C.c_void_p(dWo.data_ptr()) if dWo is not None else None, _stream_ptr(self.torch, X.device)))
         return dX, dWo
+
+    # -- error estimates (Sec. 2.5, Sec. 3) ---------------------------------------
+    def estimate_error(self, dA: Decomposition, dB: Decomposition, M=None, entries: str = "signed") -> dict:
+        """Relative-error estimates of the first-order product (see amm_estimate_error)."""
+        est = _lib.AmmErrorEstimate()
+        if M is not None:
+            _need_f32_cuda(M, "M")
+            m, p = M.shape
+            ptr, stream = C.c_void_p(M.data_ptr()), _stream_ptr(self.torch, M.device)
+        else:
+            m = p = 0
+            ptr, stream = None, None
+        _lib.check(_lib.load().amm_estimate_error(self.handle, dA.handle, dB.handle, ptr, m, p,
+                                                  _ENTRIES[entries], stream, C.byref(est)))
+        return {f: getattr(est, f) for f, _ in _lib.AmmErrorEstimate._fields_}
+
+    def estimate_sketch(self, A, B, M, G) -> float:
+        """||A(BG) - MG||_F / ||A(BG)||_F with the caller's sketch G (p x l)."""
+        for t, nm in ((A, "A"), (B, "B"), (M, "M"), (G, "G")):
+            _need_f32_cuda(t, nm)
+        m, n = A.shape
+        p, l = G.shape
+        if tuple(B.shape) != (n, p) or tuple(M.shape) != (m, p):
+            raise ValueError("shape mismatch")
+        out = C.c_double(0.0)
+        _lib.check(_lib.load().amm_estimate_sketch(
+            self.handle, C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(M.data_ptr()),
+            C.c_void_p(G.data_ptr()), m, n, p, l, _stream_ptr(self.torch, A.device), C.byref(out)))
+        return out.value
+
+    def choose_rank(self, dA: Decomposition, dB: Decomposition, tau: float, entries: str = "signed") -> int:
+        """Smallest K whose a priori estimate meets tau (see amm_choose_rank)."""
+        K = C.c_int(0)
+        _lib.check(_lib.load().amm_choose_rank(dA.handle, dB.handle, float(tau), _ENTRIES[entries], C.byref(K)))
+        return K.value
 
     # -- product ----------------------------------------------------------------
     def approx_matmul(self, dA: Decomposition, B, dB: Decomposition | None = None, out=None):

@@ -26,7 +26,18 @@ class AmmDecInfo(C.Structure):
     _fields_ = [("kind", C.c_int), ("m", C.c_int64), ("n", C.c_int64), ("K", C.c_int),
                 ("K_eff", C.c_int), ("nnz", C.c_int64), ("has_residual", C.c_int),
                 ("norm_A", C.c_double), ("norm_residual", C.c_double), ("blocks", C.c_int),
-                ("spectral_fp16", C.c_int)]
+                ("spectral_fp16", C.c_int), ("mu", C.c_double), ("sigma_next", C.c_double)]
+
+
+AMM_ENTRIES_SIGNED = 0
+AMM_ENTRIES_UNSIGNED_UNIFORM = 1
+
+
+class AmmErrorEstimate(C.Structure):
+    _fields_ = [("norm_A", C.c_double), ("norm_B", C.c_double), ("norm_dA", C.c_double),
+                ("norm_dB", C.c_double), ("norm_M", C.c_double), ("prior", C.c_double),
+                ("posterior", C.c_double), ("svd_bound", C.c_double), ("cd_estimate", C.c_double),
+                ("spec_dA", C.c_double), ("spec_dB", C.c_double), ("mu_A", C.c_double), ("mu_B", C.c_double)]
 
 
 # name -> (restype, argtypes); every pointer is a plain void* / typed pointer
@@ -66,6 +77,12 @@ SIGNATURES = {
     "amm_batch_plan_destroy": (None, [C.c_void_p]),
     "amm_approx_matmul_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amm_estimate_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                     C.c_int, C.c_void_p, C.POINTER(AmmErrorEstimate)]),
+    "amm_estimate_sketch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
+    "amm_choose_rank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int)]),
+    "amm_dec_set_sigma_next": (C.c_int, [C.c_void_p, C.c_double]),
 }
 
 _lib = None

@@ -411,6 +411,11 @@ amm_status amm_dec_query(const amm_dec* d, amm_dec_info* info) {
   }
   info->norm_A = d->norm_A;
   info->norm_residual = d->norm_residual;
+  {
+    const amm_dec* c = (d->inner ? d->inner : d);
+    info->mu = c->mu;
+    info->sigma_next = c->sigma_next;
+  }
   return AMM_OK;
 }
 
@@ -621,6 +626,7 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
   std::vector<float> hU(m * kk, 0.f), hUS(m * kk, 0.f), hV(n * kk, 0.f), hVS(n * kk, 0.f), hs(kk, 0.f);
   double s2 = 0.0;
   for (int j = 0; j < k; ++j) { hs[j] = (float)sigma[j]; s2 += sigma[j] * sigma[j]; }
+  d->sigma64.assign(sigma, sigma + k);
   for (int64_t i = 0; i < m; ++i)
     for (int j = 0; j < k; ++j) {
       hU[i * k + j] = (float)U[i * k + j];
@@ -656,17 +662,23 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
     delete d;
     return hip_fail(e, "import tsvd");
   }
-  d->norm_A = 0.0;
-  d->norm_residual = 0.0;
+  // norms for the error estimates: known only with A
+  d->norm_A = NAN;
+  d->norm_residual = NAN;
   (void)s2;
   if (A) {
     amm_status st2 = d->residual.alloc(m * n * sizeof(float));
     if (st2 == AMM_OK) st2 = tsvd_residual(A, m, n, k, d->US.as<float>(), d->V.as<float>(), d->residual.as<float>(), 0);
     if (st2 == AMM_OK && hipDeviceSynchronize() != hipSuccess) st2 = fail(AMM_EDEVICE, "residual");
+    double a2 = 0.0, r2 = 0.0;
+    if (st2 == AMM_OK) st2 = sumsq_f32(A, m * n, 0, &a2);
+    if (st2 == AMM_OK) st2 = sumsq_f32(d->residual.as<float>(), m * n, 0, &r2);
     if (st2 != AMM_OK) {
       delete d;
       return st2;
     }
+    d->norm_A = std::sqrt(a2);
+    d->norm_residual = std::sqrt(r2);
   }
   *out = d;
   return AMM_OK;
@@ -711,6 +723,7 @@ amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n, int64_t nnz
   }
   d->inner = residue;
   if (residue) d->K = d->K_eff = residue->K_eff;
+  d->norm_A = d->norm_residual = NAN;   // not known from the parts
   *out = d;
   return AMM_OK;
 }
@@ -739,12 +752,19 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     DevBuf R;
     amm_status st = R.alloc(m * n * sizeof(float));
     if (st == AMM_OK) st = sparse_extract(ctx, A, m, n, nnz, d, R.as<float>(), s);
+    // ||A||_F, and ||Delta A||_F = ||R||_F without an inner truncation
+    double a2 = 0.0, r2 = 0.0;
+    if (st == AMM_OK) st = sumsq_f32(A, m * n, s, &a2);
+    if (st == AMM_OK && base == 0) st = sumsq_f32(R.as<float>(), m * n, s, &r2);
+    d->norm_A = std::sqrt(a2);
+    d->norm_residual = std::sqrt(r2);
     if (st == AMM_OK && base != 0) {
       amm_dec* in = nullptr;
       st = amm_decompose(ctx, R.as<float>(), m, n, base, K, &o, stream, &in);
       if (st == AMM_OK) {
         d->inner = in;
         d->K_eff = in->K_eff;
+        d->norm_residual = in->norm_residual;   // Delta A = R - trunc(R)
         // R is a temporary: the inner handle keeps its own Delta R, never R
         in->A_borrowed = nullptr;
       }
@@ -1170,6 +1190,157 @@ void amm_batch_plan_destroy(amm_batch_plan* plan) {
   if (!plan) return;
   if (plan->own) (void)hipStreamSynchronize(plan->own);
   delete plan;
+}
+
+}  // extern "C"
+
+// ---- error estimates (Sec. 2.5, Sec. 3) ------------------------------------
+namespace {
+
+const amm_dec* core_of(const amm_dec* d) { return (d->kind & AMM_SPARSE) ? d->inner : d; }
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// Thm. 3.6 without its vanishing term: the norm ratio, times 4/(3 sqrt n) for U(0, a) entries
+double prior_of(double nA, double nB, double dA, double dB, int64_t n, int entries) {
+  if (!is_finite(nA) || !is_finite(nB) || !is_finite(dA) || !is_finite(dB)) return NAN;
+  if (nA == 0.0 || nB == 0.0) return (dA * dB == 0.0) ? 0.0 : INFINITY;
+  const double ratio = dA * dB / (nA * nB);
+  return entries == AMM_ENTRIES_UNSIGNED_UNIFORM ? 4.0 / (3.0 * std::sqrt((double)n)) * ratio : ratio;
+}
+
+}  // namespace
+
+extern "C" {
+
+amm_status amm_dec_set_sigma_next(amm_dec* dec, double sigma_next) {
+  if (!dec) return fail(AMM_EINVAL, "NULL argument");
+  amm_dec* c = (dec->kind & AMM_SPARSE) ? dec->inner : dec;
+  if (!c || c->kind != AMM_TSVD) return fail(AMM_EINVAL, "not a truncated-SVD handle");
+  if (!(sigma_next >= 0.0)) return fail(AMM_EINVAL, "sigma_next must be >= 0");
+  c->sigma_next = sigma_next;
+  return AMM_OK;
+}
+
+amm_status amm_estimate_error(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* M, int64_t m,
+                              int64_t p, int entries, void* stream, amm_error_estimate* out) {
+  if (!ctx || !dA || !dB || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (entries != AMM_ENTRIES_SIGNED && entries != AMM_ENTRIES_UNSIGNED_UNIFORM)
+    return fail(AMM_EINVAL, "entries = %d", entries);
+  if (dA->n != dB->m) return fail(AMM_ESHAPE, "inner dimensions differ (%lld, %lld)", (long long)dA->n,
+                                  (long long)dB->m);
+  if (M && (m != dA->m || p != dB->n)) return fail(AMM_ESHAPE, "M is %lld x %lld, product is %lld x %lld",
+                                                   (long long)m, (long long)p, (long long)dA->m, (long long)dB->n);
+  AMM_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = dA->n;
+  amm_error_estimate e;
+  e.norm_A = dA->norm_A;
+  e.norm_B = dB->norm_A;
+  e.norm_dA = dA->norm_residual;
+  e.norm_dB = dB->norm_residual;
+  e.prior = prior_of(e.norm_A, e.norm_B, e.norm_dA, e.norm_dB, n, entries);
+  e.norm_M = NAN;
+  if (M) {
+    double t = 0.0;
+    AMM_TRY(sumsq_f32(M, m * p, s, &t));
+    e.norm_M = std::sqrt(t);
+  }
+  const double num = e.norm_dA * e.norm_dB;
+  auto over_M = [&](double v) {
+    if (!is_finite(v) || !is_finite(e.norm_M)) return (double)NAN;
+    if (e.norm_M == 0.0) return v == 0.0 ? 0.0 : (double)INFINITY;
+    return v / e.norm_M;
+  };
+  // Cor. 3.7
+  e.posterior = over_M(num / std::sqrt((double)n));
+  const amm_dec* ca = core_of(dA);
+  const amm_dec* cb = core_of(dB);
+  // Thm. 3.8 with ||Delta||_2 = sigma_{k+1}
+  e.spec_dA = (ca && ca->kind == AMM_TSVD) ? ca->sigma_next : NAN;
+  e.spec_dB = (cb && cb->kind == AMM_TSVD) ? cb->sigma_next : NAN;
+  e.svd_bound = over_M(std::sqrt(e.spec_dA * e.spec_dB * num));
+  // circulant residual theorem, used as an estimate
+  const bool cda = ca && ca->kind == AMM_CIRCULANT && ca->blocks.empty();
+  const bool cdb = cb && cb->kind == AMM_CIRCULANT && cb->blocks.empty();
+  e.mu_A = cda ? ca->mu : NAN;
+  e.mu_B = cdb ? cb->mu : NAN;
+  e.cd_estimate = over_M(std::pow(e.mu_A * e.mu_B, 0.25) / std::sqrt((double)n) * num);
+  *out = e;
+  return AMM_OK;
+}
+
+amm_status amm_estimate_sketch(amm_ctx* ctx, const float* A, const float* B, const float* M, const float* G,
+                               int64_t m, int64_t n, int64_t p, int64_t l, void* stream, double* est) {
+  if (!ctx || !A || !B || !M || !G || !est) return fail(AMM_EINVAL, "NULL argument");
+  if (m <= 0 || n <= 0 || p <= 0 || l <= 0) return fail(AMM_ESHAPE, "empty sketch shape");
+  AMM_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  DevBuf Y, N, MG;
+  AMM_TRY(Y.alloc(n * l * sizeof(float)));
+  AMM_TRY(N.alloc(m * l * sizeof(float)));
+  AMM_TRY(MG.alloc(m * l * sizeof(float)));
+  AMM_TRY(gemm_f32(n, l, p, 1.f, MatView{B, p, 1}, MatView{G, l, 1}, 0.f, Y.as<float>(), l, s, "sketch_gemm"));
+  AMM_TRY(gemm_f32(m, l, n, 1.f, MatView{A, n, 1}, MatView{Y.as<float>(), l, 1}, 0.f, N.as<float>(), l, s,
+                   "sketch_gemm"));
+  AMM_TRY(gemm_f32(m, l, p, 1.f, MatView{M, p, 1}, MatView{G, l, 1}, 0.f, MG.as<float>(), l, s, "sketch_gemm"));
+  double dd = 0.0, xx = 0.0;
+  AMM_TRY(diff_sumsq_f32(N.as<float>(), MG.as<float>(), m * l, s, &dd, &xx));
+  *est = xx > 0.0 ? std::sqrt(dd / xx) : 0.0;
+  return AMM_OK;
+}
+
+amm_status amm_choose_rank(const amm_dec* dA, const amm_dec* dB, double tau, int entries, int* K) {
+  if (!dA || !dB || !K) return fail(AMM_EINVAL, "NULL argument");
+  if (!(tau >= 0.0)) return fail(AMM_EINVAL, "tolerance must be >= 0");
+  if (entries != AMM_ENTRIES_SIGNED && entries != AMM_ENTRIES_UNSIGNED_UNIFORM)
+    return fail(AMM_EINVAL, "entries = %d", entries);
+  if (dA->n != dB->m) return fail(AMM_ESHAPE, "inner dimensions differ");
+  const int64_t n = dA->n;
+  if (dA->kind == AMM_CIRCULANT && dB->kind == AMM_CIRCULANT) {
+    if (!dA->has_energies || !dB->has_energies || !dA->blocks.empty() || !dB->blocks.empty() || dA->n != dB->n)
+      return fail(AMM_EUNSUPPORTED, "rank choice needs square circulant handles made by amm_decompose");
+    std::vector<double> EA(n), EB(n);
+    AMM_HIP(hipMemcpy(EA.data(), dA->energies.ptr, n * sizeof(double), hipMemcpyDeviceToHost));
+    AMM_HIP(hipMemcpy(EB.data(), dB->energies.ptr, n * sizeof(double), hipMemcpyDeviceToHost));
+    const std::vector<double> RA = retained_all(EA), RB = retained_all(EB);
+    double ta = 0.0, tb = 0.0;
+    for (double v : EA) ta += v;
+    for (double v : EB) tb += v;
+    for (int64_t k = 0; k <= n; ++k) {
+      const double pr = prior_of(std::sqrt(ta), std::sqrt(tb), std::sqrt(std::max(ta - RA[k], 0.0)),
+                                 std::sqrt(std::max(tb - RB[k], 0.0)), n, entries);
+      if (pr <= tau) {
+        *K = (int)k;
+        return AMM_OK;
+      }
+    }
+    *K = (int)n;
+    return AMM_OK;
+  }
+  if (dA->kind == AMM_TSVD && dB->kind == AMM_TSVD) {
+    if (!is_finite(dA->norm_A) || !is_finite(dB->norm_A))
+      return fail(AMM_ESTATE, "norms unknown (import the factors with A)");
+    const int kmax = std::min({dA->K_eff, dB->K_eff, (int)dA->sigma64.size(), (int)dB->sigma64.size()});
+    const std::vector<double>& sa = dA->sigma64;
+    const std::vector<double>& sb = dB->sigma64;
+    double ka = 0.0, kb = 0.0;
+    for (int k = 0; k <= kmax; ++k) {
+      if (k > 0) {
+        ka += sa[k - 1] * sa[k - 1];
+        kb += sb[k - 1] * sb[k - 1];
+      }
+      const double pr = prior_of(dA->norm_A, dB->norm_A, std::sqrt(std::max(dA->norm_A * dA->norm_A - ka, 0.0)),
+                                 std::sqrt(std::max(dB->norm_A * dB->norm_A - kb, 0.0)), n, entries);
+      if (pr <= tau) {
+        *K = k;
+        return AMM_OK;
+      }
+    }
+    *K = kmax;
+    return AMM_OK;
+  }
+  return fail(AMM_EUNSUPPORTED, "rank choice for two circulant or two truncated-SVD handles");
 }
 
 }  // extern "C"

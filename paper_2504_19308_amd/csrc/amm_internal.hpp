@@ -8,6 +8,7 @@
 #include <map>
 #include <string>
 #include <vector>
+#include <cmath>
 
 #include "amm.h"
 
@@ -108,6 +109,10 @@ struct amm_dec {
   int K_eff = 0;
   double norm_A = 0.0;
   double norm_residual = 0.0;
+  // residual statistics for the error estimates (NaN: not available)
+  double mu = NAN;           // circulant: max_i X_i / (||Delta A||_F^2 / n)
+  double sigma_next = NAN;   // truncated SVD: estimate of sigma_{k+1} = ||Delta A||_2
+  std::vector<double> sigma64;  // truncated SVD: the kept singular values in float64 (host)
   int device = 0;
 
   // circulant (n x n): kept frequencies, float32 eigenvalue lists and the
@@ -232,6 +237,8 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
 
 // Closed-set frequency selection (host), same reading as documented in amm.h.
 std::vector<int32_t> select_closed(const std::vector<double>& E, int K);
+// energy kept by select_closed(E, K) for every K = 0..n
+std::vector<double> retained_all(const std::vector<double>& E);
 
 // Dense float32 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C, with
 // general element strides (row-major or transposed views).
@@ -282,6 +289,10 @@ amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm
                            bool accumulate, hipStream_t s);
 
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);
+// sum of squares of count floats, accumulated in float64 (synchronises s)
+amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out);
+// ||x - y||_F^2 and ||x||_F^2 of count floats, float64 (synchronises s)
+amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStream_t s, double* dd, double* xx);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);
 amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                            float* dX, float* dW, hipStream_t s);

@@ -109,6 +109,32 @@ __global__ void gather_lists(const double2* __restrict__ Ahat, int n,
   Ladj[(int64_t)t * n + p] = float2{(float)b.x, (float)-b.y};
 }
 
+// X[p] = sum over dropped k of |L_k[p]|^2 = sum_q |Ahat[p, q]|^2 - sum_t |Ahat[p, (p - k_t) mod n]|^2:
+// the energy of Fourier mode p left in Delta A.  One workgroup of 256 per row.
+__global__ void __launch_bounds__(256) mode_energy_rows(const double2* __restrict__ Ahat, int n,
+                                                        const int32_t* __restrict__ shifts, int K,
+                                                        double* __restrict__ X) {
+  __shared__ double sh[256];
+  const int p = blockIdx.x;
+  const double2* row = Ahat + (int64_t)p * n;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += 256) {
+    const double2 v = row[q];
+    s += v.x * v.x + v.y * v.y;
+  }
+  for (int t = threadIdx.x; t < K; t += 256) {
+    const double2 v = row[(p - shifts[t]) & (n - 1)];
+    s -= v.x * v.x + v.y * v.y;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) X[p] = sh[0];
+}
+
 __global__ void lists_to_half(const float2* __restrict__ src, __half2* __restrict__ dst, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) dst[i] = __float22half2_rn(src[i]);
@@ -205,6 +231,33 @@ std::vector<int32_t> select_closed(const std::vector<double>& E, int K) {
   return best;
 }
 
+std::vector<double> retained_all(const std::vector<double>& E) {
+  // R[K] = energy kept by select_closed(E, K) for K = 0..n, from prefix sums of
+  // the sorted pair energies (the same candidate sets as select_closed)
+  const int n = (int)E.size();
+  std::vector<int> singles{0};
+  if (n % 2 == 0 && n > 1) singles.push_back(n / 2);
+  std::vector<double> pe;
+  for (int k = 1; k < (n + 1) / 2; ++k) pe.push_back(E[k] + E[n - k]);
+  std::sort(pe.begin(), pe.end(), [](double a, double b) { return a > b; });
+  std::vector<double> pre(pe.size() + 1, 0.0);
+  for (size_t i = 0; i < pe.size(); ++i) pre[i + 1] = pre[i] + pe[i];
+  std::vector<std::pair<int, double>> subsets{{0, 0.0}};
+  for (int sgl : singles) subsets.push_back({1, E[sgl]});
+  if (singles.size() == 2) subsets.push_back({2, E[singles[0]] + E[singles[1]]});
+  std::vector<double> R(n + 1, 0.0);
+  for (int K = 0; K <= n; ++K) {
+    double best = 0.0;
+    for (const auto& u : subsets) {
+      if (u.first > K) continue;
+      const size_t np = std::min<size_t>((size_t)(K - u.first) / 2, pe.size());
+      best = std::max(best, u.second + pre[np]);
+    }
+    R[K] = best;
+  }
+  return R;
+}
+
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool keep_residual,
                         amm_dec* dec, hipStream_t s, bool fp16) {
   const int n = 1 << log2n;
@@ -275,6 +328,23 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
       AMM_HIP(hipGetLastError());
       dec->fp16 = true;
     }
+  }
+
+  // spectral concentration of Delta A (circulant residual theorem of Sec. 3):
+  // mu = max_p X_p / (||Delta A||_F^2 / n)
+  {
+    DevBuf X;
+    AMM_TRY(X.alloc((size_t)n * sizeof(double)));
+    hipLaunchKernelGGL(mode_energy_rows, dim3((unsigned)n), dim3(256), 0, s, cur, n, dec->shifts.as<int32_t>(), Ke,
+                       X.as<double>());
+    AMM_HIP(hipGetLastError());
+    std::vector<double> Xh(n);
+    AMM_HIP(hipMemcpyAsync(Xh.data(), X.ptr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+    double xmax = 0.0;
+    for (double v : Xh) xmax = std::max(xmax, v);
+    const double r2 = dec->norm_residual * dec->norm_residual;
+    dec->mu = r2 > 0.0 ? xmax * n / r2 : 1.0;
   }
 
   if (keep_residual) {

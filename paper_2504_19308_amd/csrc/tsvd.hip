@@ -85,6 +85,32 @@ __global__ void sumsq_partial(const float* __restrict__ a, int64_t count, double
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+__global__ void diff_sumsq_partial(const float* __restrict__ x, const float* __restrict__ y, int64_t count,
+                                   double* __restrict__ part) {
+  __shared__ double sd[256], sx[256];
+  double d = 0.0, a = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const double u = x[i], v = u - (double)y[i];
+    a += u * u;
+    d += v * v;
+  }
+  sd[threadIdx.x] = d;
+  sx[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      sd[threadIdx.x] += sd[threadIdx.x + off];
+      sx[threadIdx.x] += sx[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sx[0];
+  }
+}
+
 // out[i*ldo + j] = (float)(src[i*lds + perm[j]] * (scale ? scale[perm[j]] : 1))
 __global__ void pick_columns(const double* __restrict__ src, int64_t rows, int64_t lds,
                              const int32_t* __restrict__ perm, const double* __restrict__ scale,
@@ -212,6 +238,41 @@ amm_status orthonormalise(double* Y, double* tmp, int64_t rows, int l, DevBuf& g
 
 }  // namespace
 
+amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out) {
+  *out = 0.0;
+  if (count <= 0) return AMM_OK;
+  const int blocks = (int)std::min<int64_t>(1024, (count + 255) / 256);
+  DevBuf part;
+  AMM_TRY(part.alloc(blocks * sizeof(double)));
+  hipLaunchKernelGGL(sumsq_partial, dim3(blocks), dim3(256), 0, s, x, count, part.as<double>());
+  AMM_HIP(hipGetLastError());
+  std::vector<double> h(blocks);
+  AMM_HIP(hipMemcpyAsync(h.data(), part.ptr, blocks * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (double v : h) t += v;
+  *out = t;
+  return AMM_OK;
+}
+
+amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStream_t s, double* dd, double* xx) {
+  *dd = *xx = 0.0;
+  if (count <= 0) return AMM_OK;
+  const int blocks = (int)std::min<int64_t>(1024, (count + 255) / 256);
+  DevBuf part;
+  AMM_TRY(part.alloc(2 * blocks * sizeof(double)));
+  hipLaunchKernelGGL(diff_sumsq_partial, dim3(blocks), dim3(256), 0, s, x, y, count, part.as<double>());
+  AMM_HIP(hipGetLastError());
+  std::vector<double> h(2 * blocks);
+  AMM_HIP(hipMemcpyAsync(h.data(), part.ptr, 2 * blocks * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < blocks; ++b) {
+    *dd += h[2 * b];
+    *xx += h[2 * b + 1];
+  }
+  return AMM_OK;
+}
+
 amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
                           const amm_opts* o, amm_dec* dec, hipStream_t s) {
   (void)ctx;
@@ -221,16 +282,8 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   dec->K_eff = k;
   // ||A||_F
   {
-    const int blocks = 1024;
-    DevBuf part;
-    AMM_TRY(part.alloc(blocks * sizeof(double)));
-    hipLaunchKernelGGL(sumsq_partial, dim3(blocks), dim3(256), 0, s, A, m * n, part.as<double>());
-    AMM_HIP(hipGetLastError());
-    std::vector<double> h(blocks);
-    AMM_HIP(hipMemcpyAsync(h.data(), part.ptr, blocks * sizeof(double), hipMemcpyDeviceToHost, s));
-    AMM_HIP(hipStreamSynchronize(s));
     double t = 0.0;
-    for (double v : h) t += v;
+    AMM_TRY(sumsq_f32(A, m * n, s, &t));
     dec->norm_A = std::sqrt(t);
   }
   const int64_t kk = std::max(k, 1);
@@ -245,6 +298,7 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
     // nothing to keep (a zero operand has no nonzero singular triplet)
     dec->K_eff = 0;
     dec->norm_residual = dec->norm_A;
+    if (dec->norm_A == 0.0) dec->sigma_next = 0.0;
     return AMM_OK;
   }
   DevBuf A64, Om, Y, Z, T1, gram, Bs;
@@ -297,6 +351,10 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
     kept += sig_k[j] * sig_k[j];
   }
   dec->norm_residual = std::sqrt(std::max(dec->norm_A * dec->norm_A - kept, 0.0));
+  dec->sigma64 = sig_k;
+  // the sketch's (k+1)-th singular value estimates ||Delta A||_2 (Thm. 3.8)
+  if (k < l) dec->sigma_next = sig[order[k]];
+  else if (k == mn) dec->sigma_next = 0.0;
   // U_full = Q W (m x l), V_full = Bs^T W diag(1/sig) (n x l)
   DevBuf Wd, Uf, Vf, perm, isg, sgk;
   AMM_TRY(Wd.alloc(l * l * sizeof(double)));
