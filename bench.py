@@ -318,7 +318,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    if not only or only not in ("batch", "layer", "c5"):
+    if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz"):
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -358,6 +358,10 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
             del dA, dB
         del As, Bs, ex_s
         torch.cuda.empty_cache()
+    if not only or only == "estimates":
+        res.append(estimate_variant(torch, ctx, A, B, exact, tm, dA_tsvd32, dB_tsvd32))
+    if not only or only == "toeplitz":
+        res.extend(toeplitz_workload(torch, ctx, tm))
     if not only or only == "batch":
         res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
@@ -365,6 +369,69 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         res.append(layer_workload(torch, ctx, tm, k=440))
     if not only or only == "c5":
         res.extend(c5_workload(torch, ctx, tm))
+    return res
+
+
+def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):
+    """Error estimates of the primary product (rank-32 first order, n = 4096):
+    the handle-based prior / posterior / Thm. 3.8 figures and the randomized
+    sketch with a Rademacher n x 32 sketch, against the measured error."""
+    from paper_2504_19308_amd import inputs
+    n = A.shape[0]
+    M = ctx.approx_matmul(dA, B, dB)
+    actual = rel_err(M, exact)
+    est = ctx.estimate_error(dA, dB, M)
+    ms_est = statistics.median(tm.run(lambda: ctx.estimate_error(dA, dB, M), 10, 2))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.seed_of(2, 8))
+    G = torch.randint(0, 2, (n, l), generator=g, device="cuda").float() * 2 - 1
+    sk = ctx.estimate_sketch(A, B, M, G)
+    ms_sk = statistics.median(tm.run(lambda: ctx.estimate_sketch(A, B, M, G), 10, 2))
+    r = {"name": "error estimates: tsvd k=32 first order, n=4096", "actual_err": actual,
+         "prior": est["prior"], "posterior": est["posterior"], "svd_bound": est["svd_bound"],
+         f"sketch_l{l}": sk, "estimate_ms": ms_est, "sketch_ms": ms_sk}
+    log(f"[bench] estimates: actual {actual:.3e} prior {est['prior']:.3e} posterior {est['posterior']:.3e} "
+        f"svd_bound {est['svd_bound']:.3e} sketch {sk:.3e}; {ms_est:.3f} ms / sketch {ms_sk:.3f} ms")
+    del M, G
+    return r
+
+
+def toeplitz_workload(torch, ctx, tm, n=4096, taus=(1e-2, 1e-3)):
+    """U(0,1) Toeplitz A and B (n = 4096), the class where the circulant
+    truncation meets 1 % (Sec. 4.2): K chosen by the a priori estimate for
+    unsigned entries (Thm. 3.6 case 2), decomposition at that K, first-order
+    product, error against AB in float64."""
+    from paper_2504_19308_amd import inputs
+    pair = inputs.workload_toeplitz(n)
+    A = torch.from_numpy(pair.A).float().cuda()
+    B = torch.from_numpy(pair.B).float().cuda()
+    exact = A.double() @ B.double()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 5, 2))
+    d0A = ctx.decompose(A, "circulant", 0)
+    d0B = ctx.decompose(B, "circulant", 0)
+    res = []
+    for tau in taus:
+        K = ctx.choose_rank(d0A, d0B, tau, "unsigned_uniform")
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        dA = ctx.decompose(A, "circulant", K)
+        dB = ctx.decompose(B, "circulant", K)
+        torch.cuda.synchronize()
+        dec_ms = (time.perf_counter() - a) * 1e3
+        fn = lambda: ctx.approx_matmul(dA, B, dB, out=out)
+        ms = statistics.median(tm.run(fn, 25, 5))
+        err = rel_err(out, exact)
+        est = ctx.estimate_error(dA, dB, out, entries="unsigned_uniform")
+        res.append({"name": f"toeplitz circulant first order, K chosen for {tau:g}", "K": K, "ms": ms,
+                    "tflop_equiv_s": 2.0 * n ** 3 / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+                    "dense_fp32_ms": dense_ms, "err_vs_exact": err, "prior": est["prior"],
+                    "posterior": est["posterior"], "cd_estimate": est["cd_estimate"], "decompose_ms": dec_ms})
+        log(f"[bench] toeplitz tau {tau:g}: K={K} {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, "
+            f"prior {est['prior']:.3e} posterior {est['posterior']:.3e} cd {est['cd_estimate']:.3e}")
+        del dA, dB
+    del A, B, exact, out, d0A, d0B
+    torch.cuda.empty_cache()
     return res
 
 

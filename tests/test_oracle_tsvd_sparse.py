@@ -176,3 +176,32 @@ def test_frozen_backward_finite_differences(kind):
         assert abs(fd - np.sum(dX * Ex)) <= 1e-7 * max(1.0, abs(fd))
     # P(W) reproduces the truncated matrix
     assert np.max(np.abs(op.project(dec, W) - np.real(dec.truncated_dense()))) < 1e-12
+
+
+def _make(kind, M, K):
+    if kind == "circulant":
+        return oc.CirculantDecomp(M, K)
+    if kind == "tsvd":
+        return ot.TSVDDecomp(M, K)
+    if kind == "sparse-tsvd":
+        return osp.SparseDecomp(M, 0.05, "tsvd", K)
+    if kind == "sparse-circ":
+        return osp.SparseDecomp(M, 0.05, "circulant", K)
+    return osp.SparseDecomp(M, 0.1)
+
+
+@pytest.mark.parametrize("ka,kb", [("circulant", "tsvd"), ("tsvd", "circulant"), ("sparse-tsvd", "circulant"),
+                                   ("circulant", "sparse-tsvd"), ("sparse", "tsvd"), ("tsvd", "sparse-circ")])
+def test_mixed_decompositions_first_order_identity(ka, kb):
+    """Different decompositions for A and B (admissible by eq. (2.1): the
+    first-order form needs only A = Atil + Delta A and B = Btil + Delta B):
+    the algorithm path equals M1 = AB - Delta A Delta B."""
+    n = 32
+    A = _spectral(n, inputs.decay_exp(n, 5.0), 21) + 0.01 * np.random.default_rng(2).standard_normal((n, n))
+    B = _spectral(n, inputs.decay_exp(n, 5.0), 22)
+    dA_, dB_ = _make(ka, A, 5), _make(kb, B, 4)
+    M1 = op.algorithm(dA_, B, dB_)
+    dA = A - np.real(dA_.truncated_dense())
+    dB = B - np.real(dB_.truncated_dense())
+    assert op.rel_fro(M1, A @ B - dA @ dB) < 1e-12
+    assert op.rel_fro(M1, op.definition(dA_, B, dB_)) < 1e-12
