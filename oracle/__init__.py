@@ -17,6 +17,7 @@ Every function is a plain, slow, float64 restatement of the paper:
 * ``sparse``     -- dominant-entry sparsification with a truncated residue,
   first-order form of eq. (2.4).
 * ``product``    -- the combination rules of eq. (2.1)-(2.3).
+* ``sfft``       -- Fourier-domain sparsification (Sec. 2.4, Alg. 2.4/2.5).
 * ``estimators`` -- relative-error estimates of the first-order product
   (Sec. 2.5, Thm. 3.6, Cor. 3.7, Thm. 3.8, the circulant residual theorem) and
   the smallest truncation meeting a tolerance.
@@ -28,4 +29,4 @@ Parity status per function is recorded in each module header; every function
 here is pinned by a ``-m "not gpu"`` test against a value that does not come
 from the oracle itself (closed forms, worked examples, brute force).
 """
-from . import circulant, tsvd, sparse, product, estimators  # noqa: F401
+from . import circulant, tsvd, sparse, product, estimators, sfft  # noqa: F401
