@@ -318,7 +318,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz"):
+    if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz", "sfft"):
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -362,6 +362,8 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         res.append(estimate_variant(torch, ctx, A, B, exact, tm, dA_tsvd32, dB_tsvd32))
     if not only or only == "toeplitz":
         res.extend(toeplitz_workload(torch, ctx, tm))
+    if not only or only == "sfft":
+        res.extend(sfft_workload(torch, ctx, tm))
     if not only or only == "batch":
         res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
@@ -431,6 +433,41 @@ def toeplitz_workload(torch, ctx, tm, n=4096, taus=(1e-2, 1e-3)):
             f"prior {est['prior']:.3e} posterior {est['posterior']:.3e} cd {est['cd_estimate']:.3e}")
         del dA, dB
     del A, B, exact, out, d0A, d0B
+    torch.cuda.empty_cache()
+    return res
+
+
+def sfft_workload(torch, ctx, tm, n=4096, k=32):
+    """Fourier-domain sparsification (Alg. 2.5) at n = 4096, k = 32 per row /
+    column, on operands whose rows (A) and columns (B) are sums of a few
+    cosines plus noise; zeroth and first order, error against AB in float64."""
+    from paper_2504_19308_amd import inputs
+    A = torch.from_numpy(inputs.sinusoid_rows(n, n, inputs.rng_of(7, 0))).float().cuda()
+    B = torch.from_numpy(inputs.sinusoid_rows(n, n, inputs.rng_of(7, 1)).T.copy()).float().cuda()
+    exact = A.double() @ B.double()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 5, 2))
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    dA = ctx.decompose(A, "sfft", k)
+    dB = ctx.decompose(B, "sfft", k)
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - a) * 1e3
+    res = []
+    for name, d2 in (("zeroth", None), ("first", dB)):
+        fn = lambda: ctx.approx_matmul(dA, B, d2, out=out)
+        ms = statistics.median(tm.run(fn, 25, 5))
+        ctx.set_timing(True)
+        fn()
+        kt = ctx.timings()
+        ctx.set_timing(False)
+        err = rel_err(out, exact)
+        res.append({"name": f"sfft k={k} {name}, n={n} cosine rows", "ms": ms,
+                    "tflop_equiv_s": 2.0 * n ** 3 / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+                    "dense_fp32_ms": dense_ms, "err_vs_exact": err, "meets_1pct": err <= 0.01,
+                    "decompose_ms": dec_ms, "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
+        log(f"[bench] sfft {name}: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, kernels {res[-1]['kernels_ms']}")
+    del A, B, exact, out, dA, dB
     torch.cuda.empty_cache()
     return res
 

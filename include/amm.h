@@ -58,7 +58,7 @@ typedef enum {
 
 /* Decomposition kinds. AMM_SPARSE may be OR-ed with AMM_CIRCULANT or
  * AMM_TSVD, which then truncates the dense residue A - S. */
-enum { AMM_CIRCULANT = 1, AMM_TSVD = 2, AMM_SPARSE = 4 };
+enum { AMM_CIRCULANT = 1, AMM_TSVD = 2, AMM_SPARSE = 4, AMM_SFFT = 8 };
 
 typedef struct {
   double sparse_frac;  /* AMM_SPARSE: keep round(frac*m*n) entries of largest |a| */
@@ -136,6 +136,18 @@ const char* amm_last_error(void);
  *    components with singular values at rounding level.  With
  *    keep_residual it borrows A (see amm_dec_import_tsvd) -- the caller must
  *    keep A alive and unchanged while the handle is used as a left operand.
+ *  kind = AMM_SFFT: Fourier-domain sparsification (Sec. 2.4, Alg. 2.4/2.5).
+ *    With W the unitary DFT of the inner dimension, AB = (A W*)(W B).  As a
+ *    left operand (n a power of two in [2, 16384]) each row of A W* keeps its
+ *    K dominant frequencies; as a right operand (m a power of two) each column
+ *    of W A keeps its K dominant frequencies.  Both are computed in float64 on
+ *    the device; the kept sets are closed under q -> n-q (the most energy in
+ *    at most K members, as for the circulant kind), which keeps products real.
+ *    Stored: the kept entries in float32 (CSR by rows, and by columns as
+ *    half-spectrum representatives), and with keep_residual the residual half
+ *    spectrum of A W* ((n/2+1) x m, float32 complex).  Products need an even
+ *    column count p; first order needs both operands of this kind.  Cannot be
+ *    combined with AMM_SPARSE.
  *  kind |= AMM_SPARSE: first splits A = S + R with S the round(frac*m*n)
  *    entries of largest |a| (ties to the smaller row-major index), stored as
  *    CSR, then truncates R with the other kind (K may be 0 for none).

@@ -105,3 +105,21 @@ def product_complex(decA: SFFTDecomp, B: np.ndarray, decB: SFFTDecomp | None = N
     if decB is not None:
         M = M + (decA.Hrow - At) @ decB.right_sparse()
     return M
+
+
+def product_entries(A: np.ndarray, B: np.ndarray, k: int, rows, cols, first_order: bool = True) -> np.ndarray:
+    """M[rows][:, cols] of Alg. 2.5 from the needed rows of F*(A) and columns of
+    F(B) only (numpy's FFT per vector: F*(A)[i] = sqrt(n) ifft(A[i]), F(B)[:, j]
+    = fft(B[:, j]) / sqrt(n)); the same selection rule as ``select_rows``."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    n = A.shape[1]
+    Ha = np.fft.ifft(A[rows], axis=1) * np.sqrt(n)
+    Hb = np.fft.fft(B[:, cols], axis=0) / np.sqrt(n)
+    ma = select_rows(Ha, k)
+    At = np.where(ma, Ha, 0.0)
+    M = At @ Hb
+    if first_order:
+        mb = select_rows(Hb.T, k).T
+        M = M + (Ha - At) @ np.where(mb, Hb, 0.0)
+    return np.real(M)

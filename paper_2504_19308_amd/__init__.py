@@ -17,10 +17,10 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import AMM_CIRCULANT, AMM_SPARSE, AMM_TSVD, AmmError  # noqa: F401
+from ._lib import AMM_CIRCULANT, AMM_SFFT, AMM_SPARSE, AMM_TSVD, AmmError  # noqa: F401
 
 KINDS = {"circulant": AMM_CIRCULANT, "tsvd": AMM_TSVD, "sparse": AMM_SPARSE,
-         "sparse+circulant": AMM_SPARSE | AMM_CIRCULANT, "sparse+tsvd": AMM_SPARSE | AMM_TSVD}
+         "sparse+circulant": AMM_SPARSE | AMM_CIRCULANT, "sparse+tsvd": AMM_SPARSE | AMM_TSVD, "sfft": AMM_SFFT}
 
 
 def _stream_ptr(torch, device):

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "AMM_OK", 1: "AMM_EINVAL", 2: "AMM_ESHAPE", 3: "AMM_EUNSUPPOR
 AMM_CIRCULANT = 1
 AMM_TSVD = 2
 AMM_SPARSE = 4
+AMM_SFFT = 8
 
 
 class AmmOpts(C.Structure):

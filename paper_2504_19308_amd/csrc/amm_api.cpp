@@ -152,6 +152,7 @@ namespace {
 bool is_circ(const amm_dec* d) { return d->kind == AMM_CIRCULANT; }
 bool is_tsvd(const amm_dec* d) { return d->kind == AMM_TSVD; }
 bool is_sparse(const amm_dec* d) { return (d->kind & AMM_SPARSE) != 0; }
+bool is_sfft(const amm_dec* d) { return d->kind == AMM_SFFT; }
 
 // Rectangular circulant operand: out (m x p) = Atil B block by block.  Row
 // blocks write their s output rows (the last block's overhang goes to the
@@ -207,6 +208,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     if (d->inner) AMM_TRY(left_apply(ctx, d->inner, B, p, out, true, s));
     return AMM_OK;
   }
+  if (is_sfft(d)) return sfft_left_apply(ctx, d, B, p, out, acc, s);
   if (is_circ(d)) {
     if (d->K_eff == 0) {
       if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
@@ -249,6 +251,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
 amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                        bool acc, hipStream_t s) {
   const int64_t n = d->m, p = d->n;  // Btil is n x p
+  if (is_sfft(d)) return fail(AMM_EUNSUPPORTED, "a Fourier-sparsified right operand pairs only with one on the left");
   if (is_sparse(d)) {
     AMM_TRY(dense_times_csr(ctx, X, rows, d, out, acc, s));
     if (d->inner) AMM_TRY(right_apply(ctx, X, rows, d->inner, out, true, s));
@@ -832,6 +835,22 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     *out = d;
     return AMM_OK;
   }
+  if (kind == AMM_SFFT) {
+    amm_dec* d = new amm_dec();
+    d->kind = AMM_SFFT;
+    d->m = m;
+    d->n = n;
+    d->K = K;
+    d->device = ctx->device;
+    amm_status st = sfft_decompose(ctx, A, m, n, K, o.keep_residual != 0, d, s);
+    if (st != AMM_OK) {
+      delete d;
+      return st;
+    }
+    d->K_eff = K;
+    *out = d;
+    return AMM_OK;
+  }
   if (kind == AMM_CIRCULANT) {
     const int l2 = log2_exact(n);
     if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384]");
@@ -889,6 +908,17 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   if (dB && (!dA->blocks.empty() || !dB->blocks.empty() || (dA->inner && !dA->inner->blocks.empty()) ||
              (dB->inner && !dB->inner->blocks.empty())))
     return fail(AMM_EUNSUPPORTED, "first-order products of blocked circulant operands are not supported");
+  if (dB && (is_sfft(dA) || is_sfft(dB))) {
+    if (!(is_sfft(dA) && is_sfft(dB)))
+      return fail(AMM_EUNSUPPORTED, "first order with Fourier sparsification needs it on both operands");
+    if (!dA->sf_left || !dA->sf_Rt.ptr)
+      return fail(AMM_ESTATE, "left operand keeps no spectral residual (n a power of two, keep_residual)");
+    if (!dB->sf_right) return fail(AMM_EUNSUPPORTED, "right operand has no column sparsification");
+    if (p % 2) return fail(AMM_EUNSUPPORTED, "Fourier-sparsified products need an even column count");
+    TimerScope ts(ctx);
+    AMM_TRY(left_apply(ctx, dA, B, p, out, false, s));
+    return sfft_first_order_term(ctx, dA, dB, out, s);
+  }
   if (dB) {
     // validate the residual source before any launch
     if (!(is_tsvd(dA) && is_tsvd(dB) && dA->A_borrowed)) {

@@ -115,6 +115,12 @@ struct amm_dec {
   std::vector<double> sigma64;  // truncated SVD: the kept singular values in float64 (host)
   int device = 0;
 
+  // Fourier-domain sparsification: left role (rows of A conj(F) / n, CSR)
+  // and its residual half spectrum ((n/2+1) x m, transposed); right role
+  // (columns of F A: half-spectrum representatives with their pair weight)
+  amm::DevBuf sf_rptr, sf_ridx, sf_rval, sf_Rt, sf_cptr, sf_cidx, sf_cval;
+  bool sf_left = false, sf_right = false;
+
   // circulant (n x n): kept frequencies, float32 eigenvalue lists and the
   // adjoint lists  Ladj_t[p] = conj(L_t[(p + k_t) mod n]) with shift -k_t.
   std::vector<int32_t> freqs;
@@ -235,6 +241,12 @@ amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s, bool fp16 = false);
 
+// Float64 Stockham FFT over `batch` vectors of length 2^log2n (element e of
+// vector b at b*bs + e*es); sign -1: exp(-2 pi i jk/n), +1: its conjugate;
+// `scale` multiplies the result, which ends in `cur` (buffers swapped).
+amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
+                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s);
+
 // Closed-set frequency selection (host), same reading as documented in amm.h.
 std::vector<int32_t> select_closed(const std::vector<double>& E, int K);
 // energy kept by select_closed(E, K) for every K = 0..n
@@ -280,6 +292,14 @@ amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const floa
 amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
                           const amm_opts* o, amm_dec* dec, hipStream_t s);
 
+// Fourier-domain sparsification (sfft.hip)
+bool sfft_left_ok(int64_t n);
+amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int K, bool keep_residual, amm_dec* d,
+                          hipStream_t s);
+amm_status sfft_left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out, bool acc,
+                           hipStream_t s);
+amm_status sfft_first_order_term(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, float* out, hipStream_t s);
+
 // Sparse path
 amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
                           amm_dec* dec, float* R_out, hipStream_t s);
@@ -289,6 +309,9 @@ amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm
                            bool accumulate, hipStream_t s);
 
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s);
+// out (cols x rows) (+)= Y^T for Y (rows x cols)
+amm_status transpose_acc_f32(const float* Y, int64_t rows, int64_t cols, float* out, bool accumulate,
+                             hipStream_t s);
 // sum of squares of count floats, accumulated in float64 (synchronises s)
 amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out);
 // ||x - y||_F^2 and ||x||_F^2 of count floats, float64 (synchronises s)

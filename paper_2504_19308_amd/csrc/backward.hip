@@ -226,7 +226,7 @@ amm_status bw_any(amm_ctx* ctx, const amm_dec* d, const float* X, const float* d
   if (d->kind & AMM_SPARSE) return bw_sparse(ctx, d, X, dY, p, dX, dW, acc_dx, s);
   if (d->kind == AMM_CIRCULANT) return bw_circulant(ctx, d, X, dY, p, dX, dW, acc_dx, s);
   if (d->kind == AMM_TSVD) return bw_tsvd(ctx, d, X, dY, p, dX, dW, acc_dx, s);
-  return fail(AMM_EINVAL, "unknown decomposition kind");
+  return fail(AMM_EUNSUPPORTED, "no backward for this decomposition kind");
 }
 
 }  // namespace

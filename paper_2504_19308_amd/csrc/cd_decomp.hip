@@ -166,24 +166,33 @@ amm_status launch_pass(int log2r, const double2* in, double2* out, int n, int Ns
   return AMM_OK;
 }
 
+}  // namespace
+
+amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
+                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s) {
+  const int n = 1 << log2n;
+  int Ns = 1;
+  const int stages = stage_count(log2n);
+  for (int st = 0; st < stages; ++st) {
+    const int lr = stage_log2r(log2n, st);
+    const double sc = (st == stages - 1) ? scale : 1.0;
+    if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
+    else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
+    std::swap(cur, tmp);
+    Ns <<= lr;
+  }
+  return AMM_OK;
+}
+
+namespace {
+
 // Transform all n vectors of the n x n array in `cur` along one axis; result
 // ends in `cur` (buffers are swapped as needed).  columns: vectors run down
 // the columns.  sign -1 forward; `scale` multiplies the final pass.
 amm_status transform_axis(double2*& cur, double2*& tmp, int log2n, bool columns, int sign,
                           double scale, const double2* tw, hipStream_t s) {
   const int n = 1 << log2n;
-  const int64_t es = columns ? n : 1, bs = columns ? 1 : n;
-  int Ns = 1;
-  const int stages = stage_count(log2n);
-  for (int st = 0; st < stages; ++st) {
-    const int lr = stage_log2r(log2n, st);
-    const double sc = (st == stages - 1) ? scale : 1.0;
-    if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, n, tw, sc, columns, s));
-    else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, n, tw, sc, columns, s));
-    std::swap(cur, tmp);
-    Ns <<= lr;
-  }
-  return AMM_OK;
+  return fft64_transform(cur, tmp, log2n, columns ? n : 1, columns ? 1 : n, n, columns, sign, scale, tw, s);
 }
 
 }  // namespace

@@ -233,6 +233,16 @@ amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* ds
   return AMM_OK;
 }
 
+amm_status transpose_acc_f32(const float* Y, int64_t rows, int64_t cols, float* out, bool accumulate,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return AMM_OK;
+  if ((rows + 31) / 32 > 65535 || (cols + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "transpose too large");
+  hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
+                     dim3(32, 8), 0, s, Y, rows, cols, out, accumulate ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   if (count <= 0) return AMM_OK;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);

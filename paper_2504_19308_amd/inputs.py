@@ -231,6 +231,18 @@ def workload_c5(n: int = 16384, rank: int = 1024, frac: float = 0.005, lap_scale
     return Pair(out[0], out[1], f"haar-pow1.5-r{rank}+sparse{frac:g}-laplace{lap_scale:g} n={n}")
 
 
+def sinusoid_rows(m: int, n: int, rng: np.random.Generator, modes: int = 11, noise: float = 0.05) -> np.ndarray:
+    """Rows that are sums of `modes` cosines (frequency f = 1..modes with
+    N(0,1)/f amplitudes and random phases) plus N(0, noise^2): a few dominant
+    frequencies per row, the structure Fourier-domain sparsification keeps."""
+    t = np.arange(n)
+    A = noise * rng.standard_normal((m, n))
+    for f in range(1, modes + 1):
+        amp = rng.standard_normal((m, 1)) / f
+        A += amp * np.cos(2 * np.pi * f * t[None, :] / n + rng.random((m, 1)) * 6)
+    return A
+
+
 def workload_toeplitz(n: int) -> Pair:
     A = toeplitz_uniform(n, rng_of(9, 0))
     B = toeplitz_uniform(n, rng_of(9, 1))

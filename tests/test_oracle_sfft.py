@@ -107,3 +107,13 @@ def test_even_k_matches_literal_topk():
             assert np.array_equal(lit[i], closed[i])
             checked += 1
     assert checked > 50
+
+
+def test_sampled_entries_match_dense_product():
+    m, n, p, k = 12, 32, 10, 5
+    A, B = _rand(m, n, 21), _rand(n, p, 22)
+    rows, cols = np.array([0, 3, 11]), np.array([1, 2, 9])
+    for first in (False, True):
+        full = osf.product(osf.SFFTDecomp(A, k), B, osf.SFFTDecomp(B, k) if first else None)
+        part = osf.product_entries(A, B, k, rows, cols, first)
+        assert np.allclose(part, full[np.ix_(rows, cols)], atol=1e-12)
