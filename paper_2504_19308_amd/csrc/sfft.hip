@@ -22,6 +22,8 @@
 //           the term is sum over representatives q of Re(R[q][.] w_q G[q, j]);
 //           computed transposed (a second SpMM with real output) and added
 //           back transposed.
+#include <type_traits>
+
 #include "amm_internal.hpp"
 
 namespace amm {
@@ -82,9 +84,11 @@ __global__ void zero_kept(const int32_t* __restrict__ ptr, const int32_t* __rest
 // CSR column ids, W complex columns, row stride ld floats).  For output row r:
 //   PACKED: out[r][2c], out[r][2c+1] = re, im of sum_e val[e] * D[idx[e]][c]
 //   REAL:   out[r][c] = re of the same sum
-// One wave per output row and 64-column slice; blocks of one XCD sweep whole
-// slices so a slice of D stays in that XCD's L2 while its rows are served.
-template <bool PACKED>
+// One wave per output row and slice of 64 * V complex columns (V = 2: a lane
+// owns two neighbouring complex columns, one 16-byte load per entry); entries
+// are taken four at a time with their loads issued together.  Blocks of one
+// XCD sweep whole slices so a slice of D stays in that XCD's L2.
+template <bool PACKED, int V>
 __global__ void __launch_bounds__(256) cspmm_slices(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                     const float2* __restrict__ val, const float* __restrict__ D,
                                                     int64_t ld, int64_t W, int64_t rows, float* __restrict__ out,
@@ -95,29 +99,64 @@ __global__ void __launch_bounds__(256) cspmm_slices(const int32_t* __restrict__ 
   if (nblk % 8 == 0) b = (b % 8) * (nblk / 8) + b / 8;
   const int slice = b / rgroups, rg = b % rgroups;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t c = (int64_t)slice * 64 + lane;
+  const int64_t c = ((int64_t)slice * 64 + lane) * V;   // first complex column of this lane
   if (c >= W) return;
+  typedef typename std::conditional<V == 2, float4, float2>::type vec_t;
   for (int k = 0; k < RPB / 4; ++k) {
     const int64_t r = (int64_t)rg * RPB + wave * (RPB / 4) + k;
     if (r >= rows) break;
-    float ar = 0.f, ai = 0.f;
-    for (int e = ptr[r]; e < ptr[r + 1]; ++e) {
-      const float2 a = val[e];
-      const float2 d = *reinterpret_cast<const float2*>(D + (int64_t)idx[e] * ld + 2 * c);
-      ar += a.x * d.x - a.y * d.y;
-      ai += a.x * d.y + a.y * d.x;
-    }
-    if (PACKED) {
-      float2* o = reinterpret_cast<float2*>(out + r * ldo + 2 * c);
-      if (accumulate) {
-        const float2 v = *o;
-        *o = float2{v.x + ar, v.y + ai};
+    float ar[V], ai[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ar[v] = ai[v] = 0.f;
+    const int e0 = ptr[r], e1 = ptr[r + 1];
+    auto mac = [&](float2 a, const vec_t& d) {
+      if constexpr (V == 2) {
+        ar[0] += a.x * d.x - a.y * d.y;
+        ai[0] += a.x * d.y + a.y * d.x;
+        ar[1] += a.x * d.z - a.y * d.w;
+        ai[1] += a.x * d.w + a.y * d.z;
       } else {
-        *o = float2{ar, ai};
+        ar[0] += a.x * d.x - a.y * d.y;
+        ai[0] += a.x * d.y + a.y * d.x;
       }
+    };
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      vec_t d[4];
+      float2 a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = val[e + u];
+        d[u] = *reinterpret_cast<const vec_t*>(D + (int64_t)idx[e + u] * ld + 2 * c);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mac(a[u], d[u]);
+    }
+    for (; e < e1; ++e) mac(val[e], *reinterpret_cast<const vec_t*>(D + (int64_t)idx[e] * ld + 2 * c));
+    if (PACKED) {
+      vec_t* o = reinterpret_cast<vec_t*>(out + r * ldo + 2 * c);
+      vec_t v;
+      if constexpr (V == 2) v = float4{ar[0], ai[0], ar[1], ai[1]};
+      else v = float2{ar[0], ai[0]};
+      if (accumulate) {
+        const vec_t w = *o;
+        if constexpr (V == 2) v = float4{v.x + w.x, v.y + w.y, v.z + w.z, v.w + w.w};
+        else v = float2{v.x + w.x, v.y + w.y};
+      }
+      *o = v;
     } else {
-      float* o = out + r * ldo + c;
-      *o = accumulate ? *o + ar : ar;
+      if constexpr (V == 2) {
+        float2* o = reinterpret_cast<float2*>(out + r * ldo + c);
+        float2 v{ar[0], ar[1]};
+        if (accumulate) {
+          const float2 w = *o;
+          v = float2{v.x + w.x, v.y + w.y};
+        }
+        *o = v;
+      } else {
+        float* o = out + r * ldo + c;
+        *o = accumulate ? *o + ar[0] : ar[0];
+      }
     }
   }
 }
@@ -125,14 +164,25 @@ __global__ void __launch_bounds__(256) cspmm_slices(const int32_t* __restrict__ 
 amm_status launch_cspmm(bool packed, const int32_t* ptr, const int32_t* idx, const float2* val, const float* D,
                         int64_t ld, int64_t W, int64_t rows, float* out, int64_t ldo, bool acc, hipStream_t s) {
   if (rows <= 0 || W <= 0) return AMM_OK;
-  const int64_t nslices = (W + 63) / 64, rgroups = (rows + 15) / 16;
+  // two complex columns per lane when every access stays 16-byte (packed) or 8-byte (real) aligned
+  const bool v2 = (W % 2 == 0) && (ld % 4 == 0) && (packed ? (ldo % 4 == 0) : (ldo % 2 == 0)) &&
+                  ((uintptr_t)D % 16 == 0) && ((uintptr_t)out % (packed ? 16 : 8) == 0);
+  const int64_t per = v2 ? 128 : 64;
+  const int64_t nslices = (W + per - 1) / per, rgroups = (rows + 15) / 16;
   if (nslices * rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
-  if (packed)
-    hipLaunchKernelGGL(cspmm_slices<true>, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, ptr, idx, val, D, ld,
-                       W, rows, out, ldo, acc ? 1 : 0, (int)nslices, (int)rgroups);
-  else
-    hipLaunchKernelGGL(cspmm_slices<false>, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, ptr, idx, val, D, ld,
-                       W, rows, out, ldo, acc ? 1 : 0, (int)nslices, (int)rgroups);
+  const dim3 grid((unsigned)(nslices * rgroups)), block(256);
+  const int a = acc ? 1 : 0;
+#define AMM_CS(P, V) \
+  hipLaunchKernelGGL((cspmm_slices<P, V>), grid, block, 0, s, ptr, idx, val, D, ld, W, rows, out, ldo, a, (int)nslices, \
+                     (int)rgroups)
+  if (packed) {
+    if (v2) AMM_CS(true, 2);
+    else AMM_CS(true, 1);
+  } else {
+    if (v2) AMM_CS(false, 2);
+    else AMM_CS(false, 1);
+  }
+#undef AMM_CS
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
