@@ -362,6 +362,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
         res.append(estimate_variant(torch, ctx, A, B, exact, tm, dA_tsvd32, dB_tsvd32))
     if not only or only == "toeplitz":
         res.extend(toeplitz_workload(torch, ctx, tm))
+        res.extend(toeplitz_workload(torch, ctx, tm, n=700, taus=(1e-2,)))
     if not only or only == "sfft":
         res.extend(sfft_workload(torch, ctx, tm))
     if not only or only == "batch":
@@ -399,8 +400,9 @@ def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):
 
 
 def toeplitz_workload(torch, ctx, tm, n=4096, taus=(1e-2, 1e-3)):
-    """U(0,1) Toeplitz A and B (n = 4096), the class where the circulant
-    truncation meets 1 % (Sec. 4.2): K chosen by the a priori estimate for
+    """U(0,1) Toeplitz A and B (n = 4096; also n = 700, the paper's size, on
+    the any-size path), the class where the circulant truncation meets 1 %
+    (Sec. 4.2): K chosen by the a priori estimate for
     unsigned entries (Thm. 3.6 case 2), decomposition at that K, first-order
     product, error against AB in float64."""
     from paper_2504_19308_amd import inputs
@@ -425,11 +427,11 @@ def toeplitz_workload(torch, ctx, tm, n=4096, taus=(1e-2, 1e-3)):
         ms = statistics.median(tm.run(fn, 25, 5))
         err = rel_err(out, exact)
         est = ctx.estimate_error(dA, dB, out, entries="unsigned_uniform")
-        res.append({"name": f"toeplitz circulant first order, K chosen for {tau:g}", "K": K, "ms": ms,
+        res.append({"name": f"toeplitz n={n} circulant first order, K chosen for {tau:g}", "K": K, "ms": ms,
                     "tflop_equiv_s": 2.0 * n ** 3 / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
                     "dense_fp32_ms": dense_ms, "err_vs_exact": err, "prior": est["prior"],
                     "posterior": est["posterior"], "cd_estimate": est["cd_estimate"], "decompose_ms": dec_ms})
-        log(f"[bench] toeplitz tau {tau:g}: K={K} {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, "
+        log(f"[bench] toeplitz n={n} tau {tau:g}: K={K} {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, "
             f"prior {est['prior']:.3e} posterior {est['posterior']:.3e} cd {est['cd_estimate']:.3e}")
         del dA, dB
     del A, B, exact, out, d0A, d0B

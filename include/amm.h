@@ -29,8 +29,10 @@
  *   - The caller owns A, B, out and the streams.  A decomposition handle owns
  *     its component buffers; it is immutable after creation and may be used
  *     from several streams, but must outlive the work enqueued with it.
- *   - Circulant decompositions need a square operand with n a power of two,
- *     2 <= n <= 16384; other n return AMM_EUNSUPPORTED.
+ *   - Circulant decompositions take square operands (or square blocks) of
+ *     side 2 <= n <= 16384.  Powers of two run the fused single-kernel
+ *     product; other sides transform through Bluestein's chirp convolution in
+ *     float64 (slower; no float16 lists, batch plans or backward for them).
  */
 #ifndef AMM_H
 #define AMM_H
@@ -120,7 +122,7 @@ const char* amm_last_error(void);
 
 /* Decompose the m x n float32 device matrix A.
  *  kind = AMM_CIRCULANT: for m != n, A is cut into square blocks of side
- *    s = min(m, n) (a power of two) along the longer dimension, the last
+ *    s = min(m, n) along the longer dimension, the last
  *    block zero-padded (Sec. 2.3: rectangular matrices through square
  *    blocks), and each block is decomposed as below with its own K; such
  *    handles serve zeroth-order products only.  For each square operand it computes every circulant

@@ -74,6 +74,24 @@ int log2_exact(int64_t n) {
   return l;
 }
 
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// circulant handles of any side n in [2, 16384]; powers of two run the fused
+// single-kernel product, other sides the float64 chirp-convolution steps
+bool circ_side_ok(int64_t n) { return n >= 2 && n <= 16384; }
+
+amm_status circ_columns(amm_ctx* ctx, const amm_dec* b, const float* B, int64_t p, float* out, bool acc,
+                        hipStream_t s) {
+  if (b->K_eff == 0) {
+    if (!acc) AMM_TRY(fill_f32(out, b->n * p, 0.f, s));
+    return AMM_OK;
+  }
+  if (is_pow2(b->n))
+    return cd_apply_columns(ctx, log2_exact(b->n), b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc,
+                            s, b->pairs_of(false), b->lists16(false));
+  return cd_apply_general(ctx, (int)b->n, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc, s);
+}
+
 // exp(-2 pi i m / n) with the angle reduced to the first octant, so every entry
 // is the correctly rounded value of an exactly representable fraction m / n.
 void twiddle_value(int64_t m, int64_t n, long double* c, long double* s) {
@@ -162,7 +180,6 @@ bool is_sfft(const amm_dec* d) { return d->kind == AMM_SFFT; }
 amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out, float* scratch,
                          hipStream_t s) {
   const int64_t sd = d->block_rows ? d->n : d->m;
-  const int l2 = log2_exact(sd);
   const int nb = (int)d->blocks.size();
   for (int j = 0; j < nb; ++j) {
     const amm_dec* b = d->blocks[j];
@@ -171,9 +188,7 @@ amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t
     const bool acc = !d->block_rows && j > 0;
     if (d->block_rows) {
       float* dst = valid == sd ? out + lo * p : scratch;
-      if (b->K_eff == 0) AMM_TRY(fill_f32(dst, sd * p, 0.f, s));
-      else AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, dst, false, s,
-                                    b->pairs_of(false), b->lists16(false)));
+      AMM_TRY(circ_columns(ctx, b, B, p, dst, false, s));
       if (valid < sd)
         AMM_HIP(hipMemcpyAsync(out + lo * p, scratch, valid * p * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
@@ -186,8 +201,7 @@ amm_status blocked_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t
       if (b->K_eff == 0) {
         if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
       } else {
-        AMM_TRY(cd_apply_columns(ctx, l2, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), src, p, out, acc, s,
-                                 b->pairs_of(false), b->lists16(false)));
+        AMM_TRY(circ_columns(ctx, b, src, p, out, acc, s));
       }
     }
   }
@@ -209,14 +223,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     return AMM_OK;
   }
   if (is_sfft(d)) return sfft_left_apply(ctx, d, B, p, out, acc, s);
-  if (is_circ(d)) {
-    if (d->K_eff == 0) {
-      if (!acc) AMM_TRY(fill_f32(out, d->m * p, 0.f, s));
-      return AMM_OK;
-    }
-    return cd_apply_columns(ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(),
-                            d->L.as<float2>(), B, p, out, acc, s, d->pairs_of(false), d->lists16(false));
-  }
+  if (is_circ(d)) return circ_columns(ctx, d, B, p, out, acc, s);
   if (is_tsvd(d)) {
     const int k = d->K_eff;
     if (k == 0) {
@@ -262,6 +269,9 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
       if (!acc) AMM_TRY(fill_f32(out, rows * p, 0.f, s));
       return AMM_OK;
     }
+    if (!is_pow2(d->n))
+      return cd_apply_rows_general(ctx, (int)d->n, d->K_eff, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), X,
+                                   rows, out, acc, s);
     return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
                          d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true), d->lists16(true));
   }
@@ -552,8 +562,7 @@ amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_
                                     const double* eig, const float* residual, double norm_A,
                                     double norm_residual, amm_dec** out) {
   if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
-  const int l2 = log2_exact(n);
-  if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384], got %lld", (long long)n);
+  if (!circ_side_ok(n)) return fail(AMM_EUNSUPPORTED, "circulant path needs n in [2, 16384], got %lld", (long long)n);
   if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
   if (K > 0 && (!freqs || !eig)) return fail(AMM_EINVAL, "NULL frequencies or eigenvalues");
   for (int t = 0; t < K; ++t)
@@ -785,8 +794,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
   if (kind == AMM_CIRCULANT && m != n) {
     // square blocks of side s = min(m, n) along the longer dimension
     const int64_t sd = std::min(m, n), lg = std::max(m, n);
-    const int l2 = log2_exact(sd);
-    if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant blocks need min(m, n) a power of two in [2, 16384]");
+    if (!circ_side_ok(sd)) return fail(AMM_EUNSUPPORTED, "circulant blocks need min(m, n) in [2, 16384]");
     if (K < 0 || K > sd) return fail(AMM_EINVAL, "K = %d out of [0, %lld]", K, (long long)sd);
     const int nb = (int)((lg + sd - 1) / sd);
     amm_dec* d = new amm_dec();
@@ -819,7 +827,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
       b->m = b->n = sd;
       b->K = K;
       b->device = ctx->device;
-      st = cd_decompose(ctx, bp, l2, K, false, b, s, o.spectral_fp16 != 0);
+      st = cd_decompose(ctx, bp, (int)sd, K, false, b, s, o.spectral_fp16 != 0);
       if (st != AMM_OK) { delete b; break; }
       d->blocks.push_back(b);
       d->K_eff += b->K_eff;
@@ -852,15 +860,14 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
     return AMM_OK;
   }
   if (kind == AMM_CIRCULANT) {
-    const int l2 = log2_exact(n);
-    if (l2 < 1 || l2 > 14) return fail(AMM_EUNSUPPORTED, "circulant path needs n a power of two in [2, 16384]");
+    if (!circ_side_ok(n)) return fail(AMM_EUNSUPPORTED, "circulant path needs n in [2, 16384]");
     if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
     amm_dec* d = new amm_dec();
     d->kind = AMM_CIRCULANT;
     d->m = d->n = n;
     d->K = K;
     d->device = ctx->device;
-    amm_status st = cd_decompose(ctx, A, l2, K, o.keep_residual != 0, d, s, o.spectral_fp16 != 0);
+    amm_status st = cd_decompose(ctx, A, (int)n, K, o.keep_residual != 0, d, s, o.spectral_fp16 != 0);
     if (st != AMM_OK) {
       delete d;
       return st;
@@ -1110,6 +1117,8 @@ amm_status plan_check(int count, const amm_dec* const* dA, const void* const* B,
     if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
     if (!bf16 && d->kind == AMM_CIRCULANT && dA[0]->kind == AMM_CIRCULANT) {
       if (p[i] <= 0) return fail(AMM_ESHAPE, "entry %d has no columns", i);
+      const int64_t side = d->blocks.empty() ? d->n : std::min(d->m, d->n);
+      if (!is_pow2(side)) return fail(AMM_EUNSUPPORTED, "entry %d: circulant plans need power-of-two sides", i);
       continue;
     }
     if (d->kind != AMM_TSVD || dA[0]->kind != AMM_TSVD)

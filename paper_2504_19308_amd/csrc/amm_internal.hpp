@@ -238,8 +238,20 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 // is closed and the lists satisfy L_{n-k}[p] = conj(L_k[-p]).
 amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
 
-amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K,
+amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s, bool fp16 = false);
+
+// Any-length float64 DFT of `batch` vectors in place (element e of vector b
+// at b*bs + e*es), sign -1: exp(-2 pi i jk/n); result times `scale`.
+// Lengths that are not powers of two go through Bluestein's chirp convolution.
+amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, int64_t batch, int sign, double scale,
+                     hipStream_t s);
+// Circulant products for sizes that are not powers of two (float64 steps):
+// out (n x p) (+)= Atil B, and out (rows x n) (+)= X Btil with the adjoint lists.
+amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
+                            int64_t p, float* out, bool acc, hipStream_t s);
+amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
+                                 const float* X, int64_t rows, float* out, bool acc, hipStream_t s);
 
 // Float64 Stockham FFT over `batch` vectors of length 2^log2n (element e of
 // vector b at b*bs + e*es); sign -1: exp(-2 pi i jk/n), +1: its conjugate;

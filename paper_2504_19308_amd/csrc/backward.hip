@@ -147,6 +147,7 @@ int ilog2(int64_t n) {
 amm_status bw_circulant(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                         float* dX, float* dW, bool acc_dx, hipStream_t s) {
   const int64_t n = d->n;
+  if (n & (n - 1)) return fail(AMM_EUNSUPPORTED, "circulant backward needs a power-of-two side");
   const int l2 = ilog2(n);
   const int K = d->K_eff;
   if (dX) {

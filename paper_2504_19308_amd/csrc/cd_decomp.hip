@@ -80,7 +80,8 @@ __global__ void energy_partial(const double2* __restrict__ Ahat, int n, int rows
   const int p1 = min(n, p0 + rows_per_chunk);
   double s = 0.0;
   for (int p = p0; p < p1; ++p) {
-    const double2 v = Ahat[(int64_t)p * n + ((p - k) & (n - 1))];
+    const int q = p - k;
+    const double2 v = Ahat[(int64_t)p * n + (q < 0 ? q + n : q)];
     s += v.x * v.x + v.y * v.y;
   }
   part[(int64_t)chunk * n + k] = s;
@@ -103,9 +104,10 @@ __global__ void gather_lists(const double2* __restrict__ Ahat, int n,
   const int t = blockIdx.y;
   if (p >= n) return;
   const int k = shifts[t];
-  const double2 a = Ahat[(int64_t)p * n + ((p - k) & (n - 1))];
+  const int q = p - k, r = p + k;
+  const double2 a = Ahat[(int64_t)p * n + (q < 0 ? q + n : q)];
   L[(int64_t)t * n + p] = float2{(float)a.x, (float)a.y};
-  const double2 b = Ahat[(int64_t)((p + k) & (n - 1)) * n + p];
+  const double2 b = Ahat[(int64_t)(r >= n ? r - n : r) * n + p];
   Ladj[(int64_t)t * n + p] = float2{(float)b.x, (float)-b.y};
 }
 
@@ -123,7 +125,8 @@ __global__ void __launch_bounds__(256) mode_energy_rows(const double2* __restric
     s += v.x * v.x + v.y * v.y;
   }
   for (int t = threadIdx.x; t < K; t += 256) {
-    const double2 v = row[(p - shifts[t]) & (n - 1)];
+    const int q = p - shifts[t];
+    const double2 v = row[q < 0 ? q + n : q];
     s -= v.x * v.x + v.y * v.y;
   }
   sh[threadIdx.x] = s;
@@ -144,7 +147,8 @@ __global__ void zero_diagonals(double2* __restrict__ Ahat, int n, const int32_t*
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   if (p >= n) return;
-  Ahat[(int64_t)p * n + ((p - shifts[t]) & (n - 1))] = double2{0.0, 0.0};
+  const int q = p - shifts[t];
+  Ahat[(int64_t)p * n + (q < 0 ? q + n : q)] = double2{0.0, 0.0};
 }
 
 template <int SIGN>
@@ -267,12 +271,19 @@ std::vector<double> retained_all(const std::vector<double>& E) {
   return R;
 }
 
-amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool keep_residual,
+amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_residual,
                         amm_dec* dec, hipStream_t s, bool fp16) {
-  const int n = 1 << log2n;
+  const bool pow2 = (n & (n - 1)) == 0;
+  int log2n = 0;
+  while ((1 << log2n) < n) ++log2n;
   const int64_t nn = (int64_t)n * n;
   const double2* tw = nullptr;
-  AMM_TRY(twiddles64(ctx, log2n, &tw));
+  if (pow2) AMM_TRY(twiddles64(ctx, log2n, &tw));
+  // transform of all n rows or columns; other sizes through the chirp convolution
+  auto xform = [&](double2*& cur, double2*& tmp, bool columns, int sign, double scale) -> amm_status {
+    if (pow2) return transform_axis(cur, tmp, log2n, columns, sign, scale, tw, s);
+    return dft64_any(ctx, cur, n, columns ? n : 1, columns ? 1 : n, n, sign, scale, s);
+  };
   DevBuf z0, z1;
   AMM_TRY(z0.alloc(nn * sizeof(double2)));
   AMM_TRY(z1.alloc(nn * sizeof(double2)));
@@ -280,8 +291,8 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
   double2* tmp = z1.as<double2>();
   hipLaunchKernelGGL(widen_real, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, cur, nn);
   AMM_HIP(hipGetLastError());
-  AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/true, -1, 1.0, tw, s));
-  AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/false, +1, 1.0 / n, tw, s));
+  AMM_TRY(xform(cur, tmp, /*columns=*/true, -1, 1.0));
+  AMM_TRY(xform(cur, tmp, /*columns=*/false, +1, 1.0 / n));
 
   // energies ||R_k||_F^2
   const int rows_per_chunk = 64;
@@ -310,7 +321,7 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
 
   const int Ke = dec->K_eff;
   std::vector<int32_t> adj(Ke);
-  for (int t = 0; t < Ke; ++t) adj[t] = (n - dec->freqs[t]) & (n - 1);
+  for (int t = 0; t < Ke; ++t) adj[t] = (n - dec->freqs[t]) % n;
   const size_t kb = (size_t)std::max(Ke, 1) * sizeof(int32_t);
   AMM_TRY(dec->shifts.alloc(kb));
   AMM_TRY(dec->shifts_adj.alloc(kb));
@@ -326,7 +337,7 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
     AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
     AMM_HIP(hipStreamSynchronize(s));
     AMM_TRY(cd_build_pairs(dec, Lh));
-    if (fp16 && log2n >= 10) {
+    if (fp16 && pow2 && log2n >= 10) {
       const int64_t cnt = (int64_t)Ke * n;
       AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
       AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));
@@ -363,8 +374,8 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int log2n, int K, bool kee
                          cur, n, dec->shifts.as<int32_t>());
       AMM_HIP(hipGetLastError());
     }
-    AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/false, -1, 1.0, tw, s));
-    AMM_TRY(transform_axis(cur, tmp, log2n, /*columns=*/true, +1, 1.0 / n, tw, s));
+    AMM_TRY(xform(cur, tmp, /*columns=*/false, -1, 1.0));
+    AMM_TRY(xform(cur, tmp, /*columns=*/true, +1, 1.0 / n));
     AMM_TRY(dec->residual.alloc(nn * sizeof(float)));
     hipLaunchKernelGGL(real_part_f32, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, cur,
                        dec->residual.as<float>(), nn);

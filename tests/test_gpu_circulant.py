@@ -151,7 +151,9 @@ def test_planted_modes_recovered():
 def test_rejects_unsupported():
     from paper_2504_19308_amd import AmmError
     c = ctx()
-    with pytest.raises(AmmError):
-        c.decompose(gpu(np.zeros((6, 6))), "circulant", 2)
-    with pytest.raises(AmmError):   # rectangular: blocks of side min(m, n) = 6, not a power of two
-        c.decompose(gpu(np.zeros((8, 6))), "circulant", 2)
+    with pytest.raises(AmmError):   # side 1 (any side in [2, 16384] is supported)
+        c.decompose(gpu(np.zeros((1, 1))), "circulant", 1)
+    with pytest.raises(AmmError):   # rectangular: blocks of side min(m, n) = 1
+        c.decompose(gpu(np.zeros((8, 1))), "circulant", 1)
+    with pytest.raises(AmmError):   # more components than the side
+        c.decompose(gpu(np.zeros((6, 6))), "circulant", 7)
