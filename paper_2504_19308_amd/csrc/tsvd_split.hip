@@ -411,7 +411,7 @@ amm_status launch_out(const float* A1, const float* A2, const float* B1, const f
 amm_status dispatch_panels(int ka, int kb, const PanelArgs& a, bool deep, hipStream_t s) {
 #define AMM_P(A, B) \
   if (ka == A && kb == B) return launch_panels<A, B>(a, deep, s);
-  AMM_P(32, 0) AMM_P(64, 0) AMM_P(32, 32) AMM_P(32, 64) AMM_P(64, 32) AMM_P(64, 64)
+  AMM_P(32, 0) AMM_P(64, 0) AMM_P(32, 32) AMM_P(32, 64) AMM_P(64, 32) AMM_P(64, 64) AMM_P(128, 0) AMM_P(128, 128)
 #undef AMM_P
   return fail(AMM_EUNSUPPORTED, "split panel ranks %d, %d", ka, kb);
 }
@@ -420,7 +420,7 @@ amm_status dispatch_out(int k1, int k2, const float* A1, const float* A2, const 
                         int64_t M, int64_t N, float* C, hipStream_t s) {
 #define AMM_O(X, Y) \
   if (k1 == X && k2 == Y) return launch_out<X, Y>(A1, A2, B1, B2, M, N, C, s);
-  AMM_O(32, 0) AMM_O(64, 0) AMM_O(32, 32) AMM_O(32, 64) AMM_O(64, 32) AMM_O(64, 64)
+  AMM_O(32, 0) AMM_O(64, 0) AMM_O(32, 32) AMM_O(32, 64) AMM_O(64, 32) AMM_O(64, 64) AMM_O(128, 0) AMM_O(128, 128)
 #undef AMM_O
   return fail(AMM_EUNSUPPORTED, "split output ranks %d, %d", k1, k2);
 }
@@ -443,7 +443,9 @@ void plan_splits(int64_t m, int64_t n, int64_t p, int ka, int kb, int* SG, int* 
 }  // namespace
 
 bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb) {
-  return (ka == 32 || ka == 64) && (kb == 0 || kb == 32 || kb == 64) && m > 0 && p > 0 && m % OT == 0 &&
+  const bool ranks = ((ka == 32 || ka == 64) && (kb == 0 || kb == 32 || kb == 64)) ||
+                     (ka == 128 && (kb == 0 || kb == 128));
+  return ranks && m > 0 && p > 0 && m % OT == 0 &&
          p % OT == 0 && n % (PW * 16 * Depth<false>::DH) == 0 && n % (PW * 4 * Depth<false>::DG) == 0 && n > 0 &&
          (m / OT) * (p / OT) < ((int64_t)1 << 31);
 }

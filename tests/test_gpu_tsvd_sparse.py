@@ -199,7 +199,7 @@ def test_sparse_decompose_end_to_end():
 
 
 @pytest.mark.parametrize("n,ka,kb", [(256, 32, 32), (512, 64, 32), (640, 32, 64), (1024, 64, 64), (384, 32, 0),
-                                      (1280, 32, 32), (2048, 32, 0)])
+                                      (1280, 32, 32), (2048, 32, 0), (512, 128, 128), (768, 128, 0)])
 def test_tsvd_split_path_first_order(n, ka, kb):
     """Shapes of the three-launch path (direct panels, reduction, output GEMM
     on split bfloat16 operands): float32 accuracy against the oracle.  Rank-32
