@@ -140,10 +140,11 @@ const char* amm_last_error(void);
  *    keep A alive and unchanged while the handle is used as a left operand.
  *  kind = AMM_SFFT: Fourier-domain sparsification (Sec. 2.4, Alg. 2.4/2.5).
  *    With W the unitary DFT of the inner dimension, AB = (A W*)(W B).  As a
- *    left operand (n a power of two in [2, 16384]) each row of A W* keeps its
- *    K dominant frequencies; as a right operand (m a power of two) each column
+ *    left operand (2 <= n <= 16384) each row of A W* keeps its
+ *    K dominant frequencies; as a right operand (2 <= m <= 16384) each column
  *    of W A keeps its K dominant frequencies.  Both are computed in float64 on
- *    the device; the kept sets are closed under q -> n-q (the most energy in
+ *    the device (sizes that are not powers of two through Bluestein's chirp
+ *    convolution); the kept sets are closed under q -> n-q (the most energy in
  *    at most K members, as for the circulant kind), which keeps products real.
  *    Stored: the kept entries in float32 (CSR by rows, and by columns as
  *    half-spectrum representatives), and with keep_residual the residual half

@@ -250,6 +250,7 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
 // out (n x p) (+)= Atil B, and out (rows x n) (+)= X Btil with the adjoint lists.
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
                             int64_t p, float* out, bool acc, hipStream_t s);
+amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s);
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
                                  const float* X, int64_t rows, float* out, bool acc, hipStream_t s);
 

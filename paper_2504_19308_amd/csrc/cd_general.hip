@@ -113,6 +113,15 @@ __global__ void unpack_pairs(const double2* __restrict__ Y, int64_t n, int64_t p
   if (2 * c + 1 < p) o[1] = accumulate ? o[1] + (float)y.y : (float)y.y;
 }
 
+// X[q][2c], X[q][2c + 1] = re, im of Z[q][c] (float32)
+__global__ void spectrum_to_f32(const double2* __restrict__ Z, int64_t count, float* __restrict__ X) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= count) return;
+  const double2 z = Z[id];
+  X[2 * id] = (float)z.x;
+  X[2 * id + 1] = (float)z.y;
+}
+
 int ceil_log2(int64_t v) {
   int l = 0;
   while ((int64_t(1) << l) < v) ++l;
@@ -184,6 +193,22 @@ amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, c
   AMM_TRY(dft64_any(ctx, y.as<double2>(), n, P2, 1, P2, +1, 1.0 / n, s));
   hipLaunchKernelGGL(unpack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, y.as<double2>(), (int64_t)n, p, P2, out,
                      acc ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  AMM_HIP(hipStreamSynchronize(s));
+  return AMM_OK;
+}
+
+// Packed forward spectra of B's column pairs for any n (p even): X (n x p
+// floats) holds F(b_2c + i b_2c+1)[q] at X[q][2c], X[q][2c + 1]
+amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s) {
+  if (p <= 0) return AMM_OK;
+  const int64_t P2 = p / 2, cnt = (int64_t)n * P2;
+  DevBuf z;
+  AMM_TRY(z.alloc(cnt * sizeof(double2)));
+  hipLaunchKernelGGL(pack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, B, (int64_t)n, p, P2, z.as<double2>());
+  AMM_HIP(hipGetLastError());
+  AMM_TRY(dft64_any(ctx, z.as<double2>(), n, P2, 1, P2, -1, 1.0, s));
+  hipLaunchKernelGGL(spectrum_to_f32, dim3(blocks_for(cnt)), dim3(256), 0, s, z.as<double2>(), cnt, X);
   AMM_HIP(hipGetLastError());
   AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;

@@ -239,16 +239,13 @@ int ilog2_exact(int64_t v) {
 
 }  // namespace
 
-bool sfft_left_ok(int64_t n) {
-  const int l = ilog2_exact(n);
-  return l >= 1 && l <= 14;
-}
+bool sfft_left_ok(int64_t n) { return n >= 2 && n <= 16384; }
 
 amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int K, bool keep_residual, amm_dec* d,
                           hipStream_t s) {
   const int ln = ilog2_exact(n), lm = ilog2_exact(m);
-  const bool left = ln >= 1 && ln <= 14, right = lm >= 1 && lm <= 14;
-  if (!left && !right) return fail(AMM_EUNSUPPORTED, "Fourier sparsification needs m or n a power of two in [2, 16384]");
+  const bool left = n >= 2 && n <= 16384, right = m >= 2 && m <= 16384;
+  if (!left && !right) return fail(AMM_EUNSUPPORTED, "Fourier sparsification needs m or n in [2, 16384]");
   if (K < 0) return fail(AMM_EINVAL, "K = %d", K);
   const int64_t mn = m * n;
   DevBuf z0, z1, E;
@@ -260,12 +257,16 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   double tot = 0.0;
   if (left) {
     // H = A conj(F) along rows
-    const double2* tw = nullptr;
-    AMM_TRY(twiddles64(ctx, ln, &tw));
     double2 *cur = z0.as<double2>(), *tmp = z1.as<double2>();
     hipLaunchKernelGGL(real_to_c64, dim3(g), dim3(256), 0, s, A, cur, mn);
     AMM_HIP(hipGetLastError());
-    AMM_TRY(fft64_transform(cur, tmp, ln, 1, n, m, false, +1, 1.0, tw, s));
+    if (ln > 0) {
+      const double2* tw = nullptr;
+      AMM_TRY(twiddles64(ctx, ln, &tw));
+      AMM_TRY(fft64_transform(cur, tmp, ln, 1, n, m, false, +1, 1.0, tw, s));
+    } else {
+      AMM_TRY(dft64_any(ctx, cur, (int)n, 1, n, m, +1, 1.0, s));
+    }
     hipLaunchKernelGGL(abs2_c64, dim3(g), dim3(256), 0, s, cur, E.as<double>(), mn);
     AMM_HIP(hipGetLastError());
     AMM_HIP(hipMemcpyAsync(Eh.data(), E.ptr, mn * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -311,12 +312,16 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   }
   if (right) {
     // G = F A along columns (A as the right operand: inner dimension m)
-    const double2* tw = nullptr;
-    AMM_TRY(twiddles64(ctx, lm, &tw));
     double2 *cur = z0.as<double2>(), *tmp = z1.as<double2>();
     hipLaunchKernelGGL(real_to_c64, dim3(g), dim3(256), 0, s, A, cur, mn);
     AMM_HIP(hipGetLastError());
-    AMM_TRY(fft64_transform(cur, tmp, lm, n, 1, n, true, -1, 1.0, tw, s));
+    if (lm > 0) {
+      const double2* tw = nullptr;
+      AMM_TRY(twiddles64(ctx, lm, &tw));
+      AMM_TRY(fft64_transform(cur, tmp, lm, n, 1, n, true, -1, 1.0, tw, s));
+    } else {
+      AMM_TRY(dft64_any(ctx, cur, (int)m, n, 1, n, -1, 1.0, s));
+    }
     hipLaunchKernelGGL(abs2_c64, dim3(g), dim3(256), 0, s, cur, E.as<double>(), mn);
     AMM_HIP(hipGetLastError());
     AMM_HIP(hipMemcpyAsync(Eh.data(), E.ptr, mn * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -367,11 +372,13 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
 amm_status sfft_left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p, float* out, bool acc,
                            hipStream_t s) {
   const int64_t m = d->m, n = d->n;
-  if (!d->sf_left) return fail(AMM_EUNSUPPORTED, "handle has no row sparsification (n not a power of two)");
+  if (!d->sf_left) return fail(AMM_EUNSUPPORTED, "handle has no row sparsification (n out of range)");
   if (p % 2) return fail(AMM_EUNSUPPORTED, "Fourier-sparsified products need an even column count");
   AMM_TRY(ctx->scratch[6].reserve((size_t)n * p * sizeof(float)));
   float* X = ctx->scratch[6].as<float>();
-  AMM_TRY(cd_spectrum_columns(ctx, ilog2_exact(n), B, p, X, s));
+  const int ln = ilog2_exact(n);
+  if (ln > 0) AMM_TRY(cd_spectrum_columns(ctx, ln, B, p, X, s));
+  else AMM_TRY(spectrum_columns_general(ctx, (int)n, B, p, X, s));
   TimedLaunch tl("sfft_spmm", s);
   return launch_cspmm(true, d->sf_rptr.as<int32_t>(), d->sf_ridx.as<int32_t>(), d->sf_rval.as<float2>(), X, p, p / 2,
                       m, out, p, acc, s);
@@ -381,7 +388,7 @@ amm_status sfft_left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64
 amm_status sfft_first_order_term(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, float* out, hipStream_t s) {
   const int64_t m = dA->m, n = dA->n, p = dB->n;
   if (!dA->sf_Rt.ptr) return fail(AMM_ESTATE, "left operand keeps no spectral residual (decompose with keep_residual)");
-  if (!dB->sf_right) return fail(AMM_EUNSUPPORTED, "right operand has no column sparsification (m not a power of two)");
+  if (!dB->sf_right) return fail(AMM_EUNSUPPORTED, "right operand has no column sparsification (m out of range)");
   if (dB->m != n) return fail(AMM_ESHAPE, "inner dimensions differ");
   AMM_TRY(ctx->scratch[7].reserve((size_t)p * m * sizeof(float)));
   float* Y = ctx->scratch[7].as<float>();   // p x m: row j = column j of the term

@@ -16,7 +16,8 @@ def _smooth(m, n, seed):
     return f32(inputs.sinusoid_rows(m, n, np.random.default_rng(seed)))
 
 
-@pytest.mark.parametrize("m,n,p,k", [(64, 64, 40, 6), (96, 128, 50, 9), (256, 256, 256, 16), (200, 512, 64, 33)])
+@pytest.mark.parametrize("m,n,p,k", [(64, 64, 40, 6), (96, 128, 50, 9), (256, 256, 256, 16), (200, 512, 64, 33),
+                                     (50, 300, 40, 7), (70, 700, 64, 12)])
 def test_sfft_zeroth_parity(m, n, p, k):
     note(f"sfft zeroth m={m} n={n} p={p} k={k}")
     A = _smooth(m, n, m + n)
@@ -29,7 +30,7 @@ def test_sfft_zeroth_parity(m, n, p, k):
     assert rel(got, osf.product(dec, B)) < TOL_F32
 
 
-@pytest.mark.parametrize("m,n,p,k", [(64, 64, 64, 6), (128, 256, 96, 12), (256, 128, 256, 7)])
+@pytest.mark.parametrize("m,n,p,k", [(64, 64, 64, 6), (128, 256, 96, 12), (256, 128, 256, 7), (60, 300, 70, 9)])
 def test_sfft_first_order_parity(m, n, p, k):
     note(f"sfft first order m={m} n={n} p={p} k={k}")
     A = _smooth(m, n, 3 * m + n)
@@ -71,7 +72,7 @@ def test_sfft_rejected_cases():
     with pytest.raises(AmmError):
         c.approx_matmul(d, gpu(A), dt)                       # mixed with another kind
     with pytest.raises(AmmError):
-        c.decompose(gpu(np.ones((48, 40))), "sfft", 4)       # neither side a power of two
+        c.decompose(gpu(np.ones((1, 1))), "sfft", 1)         # neither side in [2, 16384]
 
 
 def test_sfft_first_order_full_size_sampled():
