@@ -32,7 +32,7 @@
  *   - Circulant decompositions take square operands (or square blocks) of
  *     side 2 <= n <= 16384.  Powers of two run the fused single-kernel
  *     product; other sides transform through Bluestein's chirp convolution in
- *     float64 (slower; no float16 lists, batch plans or backward for them).
+ *     float64 (slower; no float16 lists or batch plans for them).
  */
 #ifndef AMM_H
 #define AMM_H

@@ -37,13 +37,14 @@ spectral_sddmm(const float2* __restrict__ Zy, const float2* __restrict__ Zx, int
                int K, const int32_t* __restrict__ shifts, float2* __restrict__ Lg) {
   __shared__ float2 red[256];
   const int p = blockIdx.x;
-  const int pm = (n - p) & (n - 1);
+  const int pm = p == 0 ? 0 : n - p;
   const float2* yp = Zy + (int64_t)p * pairs;
   const float2* ym = Zy + (int64_t)pm * pairs;
   const float sc = 0.5f / (float)n;
   for (int t = 0; t < K; ++t) {
-    const int q = (p - shifts[t]) & (n - 1);
-    const int qm = (n - q) & (n - 1);
+    int q = p - shifts[t];
+    if (q < 0) q += n;
+    const int qm = q == 0 ? 0 : n - q;
     const float2* xq = Zx + (int64_t)q * pairs;
     const float2* xm = Zx + (int64_t)qm * pairs;
     float ar = 0.f, ai = 0.f;
@@ -147,15 +148,18 @@ int ilog2(int64_t n) {
 amm_status bw_circulant(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                         float* dX, float* dW, bool acc_dx, hipStream_t s) {
   const int64_t n = d->n;
-  if (n & (n - 1)) return fail(AMM_EUNSUPPORTED, "circulant backward needs a power-of-two side");
+  const bool pow2 = (n & (n - 1)) == 0;   // other sides: the chirp-convolution path
   const int l2 = ilog2(n);
   const int K = d->K_eff;
   if (dX) {
     if (K == 0) {
       if (!acc_dx) AMM_TRY(fill_f32(dX, n * p, 0.f, s));
-    } else {
+    } else if (pow2) {
       AMM_TRY(cd_apply_columns(ctx, l2, K, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), dY, p, dX, acc_dx, s,
                                d->pairs_of(true), d->lists16(true)));
+    } else {
+      AMM_TRY(cd_apply_general(ctx, (int)n, K, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), dY, p, dX, acc_dx,
+                               s));
     }
   }
   if (dW) {
@@ -169,8 +173,13 @@ amm_status bw_circulant(amm_ctx* ctx, const amm_dec* d, const float* X, const fl
     float* Zx = ctx->scratch[1].as<float>();
     float* I = ctx->scratch[2].as<float>();
     float2* Lg = ctx->scratch[3].as<float2>();
-    AMM_TRY(cd_spectrum_columns(ctx, l2, dY, p, Zy, s));
-    AMM_TRY(cd_spectrum_columns(ctx, l2, X, p, Zx, s));
+    if (pow2) {
+      AMM_TRY(cd_spectrum_columns(ctx, l2, dY, p, Zy, s));
+      AMM_TRY(cd_spectrum_columns(ctx, l2, X, p, Zx, s));
+    } else {
+      AMM_TRY(spectrum_columns_general(ctx, (int)n, dY, p, Zy, s));
+      AMM_TRY(spectrum_columns_general(ctx, (int)n, X, p, Zx, s));
+    }
     {
       TimedLaunch tl("spectral_sddmm", s);
       hipLaunchKernelGGL(spectral_sddmm, dim3((unsigned)n), dim3(256), 0, s, (const float2*)Zy, (const float2*)Zx,
@@ -179,7 +188,8 @@ amm_status bw_circulant(amm_ctx* ctx, const amm_dec* d, const float* X, const fl
     }
     hipLaunchKernelGGL(set_identity, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, I, n);
     AMM_HIP(hipGetLastError());
-    AMM_TRY(cd_apply_columns(ctx, l2, K, d->shifts.as<int32_t>(), Lg, I, n, dW, false, s));
+    if (pow2) AMM_TRY(cd_apply_columns(ctx, l2, K, d->shifts.as<int32_t>(), Lg, I, n, dW, false, s));
+    else AMM_TRY(cd_apply_general(ctx, (int)n, K, d->shifts.as<int32_t>(), Lg, I, n, dW, false, s));
   }
   return AMM_OK;
 }

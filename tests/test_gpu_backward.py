@@ -34,7 +34,7 @@ def test_backward_tsvd(n, p, k):
     assert rel(host(dW), want_dw) < TOL_F32
 
 
-@pytest.mark.parametrize("n,p,K", [(16, 8, 3), (64, 64, 9), (256, 100, 16), (1024, 256, 33)])
+@pytest.mark.parametrize("n,p,K", [(16, 8, 3), (64, 64, 9), (256, 100, 16), (1024, 256, 33), (300, 64, 11), (700, 20, 5)])
 def test_backward_circulant(n, p, K):
     note(f"backward circulant n={n} p={p} K={K}")
     rng = np.random.default_rng(n + K)

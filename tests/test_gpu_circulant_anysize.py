@@ -66,7 +66,7 @@ def test_anysize_full_expansion_and_blocks():
     assert rel(host(c.approx_matmul(db, gpu(Bb))), oc.apply_blocked(dec, Bb)) < TOL_F32
 
 
-def test_anysize_mu_and_rejections():
+def test_anysize_mu_and_plan_rejection():
     from paper_2504_19308_amd import AmmError
     from oracle import estimators as oe
     n = 300
@@ -78,5 +78,3 @@ def test_anysize_mu_and_rejections():
     B = gpu(np.ones((n, 8)))
     with pytest.raises(AmmError):
         c.batch_plan([d], [B])
-    with pytest.raises(AmmError):
-        c.approx_matmul_backward(d, B, gpu(np.ones((n, 8))))
