@@ -46,12 +46,12 @@ __device__ __forceinline__ int xcd_order(int bid, int nblk) {
 constexpr int PW = 4;    // waves per panel workgroup
 
 // Load-batch depth of a panel launch: DG 4-row groups (G job) and DH 16-column
-// groups (H job) per batch.  The deep form keeps two batches in registers and
-// issues the next batch's loads before the current batch's MFMAs (software
-// pipeline); it trades occupancy for loads in flight and is used for ranks 32.
+// groups (H job) per batch.  The deep form keeps three batches in registers and
+// issues a batch's loads two batches before its MFMAs (software pipeline); it
+// trades occupancy for loads in flight and is used for ranks 32.
 template <bool DEEP> struct Depth;
 template <> struct Depth<false> { static constexpr int DG = 4, DH = 2; };
-template <> struct Depth<true> { static constexpr int DG = 8, DH = 4; };
+template <> struct Depth<true> { static constexpr int DG = 4, DH = 2; };
 
 // G (as Gt, p x KA) partial of split `split`: rows [split*per*PW, ...) of Y
 template <int KA, bool DEEP>
@@ -100,20 +100,22 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
       comp(y, xv);
     }
   } else {
-    // batches b = 0, 1, ... of STEP rows (per is a multiple of STEP); batch b + 1
-    // is in flight while batch b is multiplied
+    // batches b = 0, 1, ... of STEP rows (per is a multiple of STEP) rotate
+    // through three register sets; batches b + 1 and b + 2 are in flight
+    // while batch b is multiplied
     const int64_t nb = per / STEP;
-    float4 y0[DG], y1[DG];
-    float x0[DG][IB], x1[DG][IB];
+    float4 y0[DG], y1[DG], y2[DG];
+    float x0[DG][IB], x1[DG][IB], x2[DG][IB];
     load(rb, y0, x0);
-    int64_t b = 0;
-    for (; b + 1 < nb; b += 2) {
-      load(rb + (b + 1) * STEP, y1, x1);
+    if (nb > 1) load(rb + STEP, y1, x1);
+    for (int64_t b = 0; b < nb; b += 3) {
+      if (b + 2 < nb) load(rb + (b + 2) * STEP, y2, x2);
       comp(y0, x0);
-      if (b + 2 < nb) load(rb + (b + 2) * STEP, y0, x0);
-      comp(y1, x1);
+      if (b + 3 < nb) load(rb + (b + 3) * STEP, y0, x0);
+      if (b + 1 < nb) comp(y1, x1);
+      if (b + 4 < nb) load(rb + (b + 4) * STEP, y1, x1);
+      if (b + 2 < nb) comp(y2, x2);
     }
-    if (b < nb) comp(y0, x0);
   }
   // lane: acc[i][q][rr] = G[16i + 4g + rr][j0 + 4t + q]
   if (wave > 0) {
@@ -193,17 +195,18 @@ __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* 
     }
   } else {
     const int64_t nb = per / STEP;
-    float4 a0[DH][4], a1[DH][4];
-    float u0[DH][4][CB], u1[DH][4][CB];
+    float4 a0[DH][4], a1[DH][4], a2[DH][4];
+    float u0[DH][4][CB], u1[DH][4][CB], u2[DH][4][CB];
     load(c0s, a0, u0);
-    int64_t b = 0;
-    for (; b + 1 < nb; b += 2) {
-      load(c0s + (b + 1) * STEP, a1, u1);
+    if (nb > 1) load(c0s + STEP, a1, u1);
+    for (int64_t b = 0; b < nb; b += 3) {
+      if (b + 2 < nb) load(c0s + (b + 2) * STEP, a2, u2);
       comp(a0, u0);
-      if (b + 2 < nb) load(c0s + (b + 2) * STEP, a0, u0);
-      comp(a1, u1);
+      if (b + 3 < nb) load(c0s + (b + 3) * STEP, a0, u0);
+      if (b + 1 < nb) comp(a1, u1);
+      if (b + 4 < nb) load(c0s + (b + 4) * STEP, a1, u1);
+      if (b + 2 < nb) comp(a2, u2);
     }
-    if (b < nb) comp(a0, u0);
   }
   // lane: acc[bb][c][rr] = H[row0 + 16bb + 4g + rr][16c + t]
   if (wave > 0) {
@@ -426,14 +429,18 @@ amm_status dispatch_out(int k1, int k2, const float* A1, const float* A2, const 
 }
 
 // deep (pipelined) panels for rank-32 operands when the reduction length splits
-// into whole deep batches; they want about half as many workgroups
+// into whole deep batches; they want fewer, longer workgroups
 bool use_deep(int64_t n, int ka, int kb) {
   return ka == 32 && kb <= 32 && n % (PW * 16 * Depth<true>::DH) == 0 && n % (PW * 4 * Depth<true>::DG) == 0;
 }
 
 void plan_splits(int64_t m, int64_t n, int64_t p, int ka, int kb, int* SG, int* SH, bool* deep) {
   *deep = use_deep(n, ka, kb);
-  const int target = *deep ? 128 : 512;
+  // deep panels: about one workgroup per CU in total (the G and H jobs of a
+  // first-order product side by side), each wave with three batches of loads
+  // in flight; doubling the splits measured slower (more partial traffic,
+  // shorter pipelines)
+  const int target = *deep ? (kb > 0 ? 64 : 128) : 512;
   const int qg = 4 * (*deep ? Depth<true>::DG : Depth<false>::DG);
   const int qh = 16 * (*deep ? Depth<true>::DH : Depth<false>::DH);
   *SG = pick_s(p / 64, n, qg, target);
