@@ -18,6 +18,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // vector types keep staging in registers
 
 __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -63,11 +64,6 @@ __device__ __forceinline__ int find_job16(const int* start, int count, int b) {
   return lo;
 }
 
-union U4 {
-  uint4 v;
-  unsigned short h[8];
-};
-
 template <int K>
 __global__ void __launch_bounds__(256)
 panel_bf16_kernel(const PanelJobB* __restrict__ jobs, const int* __restrict__ start, int count) {
@@ -93,26 +89,29 @@ panel_bf16_kernel(const PanelJobB* __restrict__ jobs, const int* __restrict__ st
 #pragma unroll
   for (int f = 0; f < FB; ++f) acc[f][0] = acc[f][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  U4 x0, x1;
-  uint4 vr[VQ];
+  u32x4 x0, x1;   // eight bf16 of rows 2rp and 2rp + 1, element u in half (u & 1) of word u / 2
+  u32x4 vr[VQ];
   auto fetch = [&](int64_t r0) {
-    x0.v = *reinterpret_cast<const uint4*>(jb.B + (r0 + 2 * rp) * jb.p + j0 + 8 * cc);
-    x1.v = *reinterpret_cast<const uint4*>(jb.B + (r0 + 2 * rp + 1) * jb.p + j0 + 8 * cc);
+    x0 = *reinterpret_cast<const u32x4*>(jb.B + (r0 + 2 * rp) * jb.p + j0 + 8 * cc);
+    x1 = *reinterpret_cast<const u32x4*>(jb.B + (r0 + 2 * rp + 1) * jb.p + j0 + 8 * cc);
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
       const int e = t + 256 * q;
-      if (e < K * 4) vr[q] = *reinterpret_cast<const uint4*>(jb.Vt + (int64_t)(e >> 2) * jb.n + r0 + 8 * (e & 3));
+      if (e < K * 4) vr[q] = *reinterpret_cast<const u32x4*>(jb.Vt + (int64_t)(e >> 2) * jb.n + r0 + 8 * (e & 3));
     }
   };
   auto stash = [&]() {
     unsigned int* bw = reinterpret_cast<unsigned int*>(Bs);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      bw[((8 * cc + u) * LS + 2 * rp) >> 1] = (unsigned int)x0.h[u] | ((unsigned int)x1.h[u] << 16);
+    for (int u = 0; u < 8; ++u) {
+      const unsigned int h0 = (x0[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+      const unsigned int h1 = (x1[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+      bw[((8 * cc + u) * LS + 2 * rp) >> 1] = h0 | (h1 << 16);
+    }
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
       const int e = t + 256 * q;
-      if (e < K * 4) *reinterpret_cast<uint4*>(Vs + (e >> 2) * LS + 8 * (e & 3)) = vr[q];
+      if (e < K * 4) *reinterpret_cast<u32x4*>(Vs + (e >> 2) * LS + 8 * (e & 3)) = vr[q];
     }
   };
 
@@ -169,23 +168,20 @@ out_bf16_kernel(const OutJobB* __restrict__ jobs, const int* __restrict__ start,
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ur[2];
-  float4 gr[4];
+  u32x4 ur[2];
+  f32x4 gr[4];
   auto fetch = [&](int f0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = t + 256 * q;
-      ur[q] = *reinterpret_cast<const uint4*>(jb.US + (m0 + (e >> 2)) * K + f0 + 8 * (e & 3));
+      ur[q] = *reinterpret_cast<const u32x4*>(jb.US + (m0 + (e >> 2)) * K + f0 + 8 * (e & 3));
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + 256 * q;
       const float* src = jb.Gt + (n0 + (e >> 3)) * K + f0 + 4 * (e & 7);
-      float4 v = *reinterpret_cast<const float4*>(src);
-      for (int s = 1; s < jb.splits; ++s) {
-        const float4 w = *reinterpret_cast<const float4*>(src + s * jb.split_stride);
-        v = float4{v.x + w.x, v.y + w.y, v.z + w.z, v.w + w.w};
-      }
+      f32x4 v = *reinterpret_cast<const f32x4*>(src);
+      for (int s = 1; s < jb.splits; ++s) v += *reinterpret_cast<const f32x4*>(src + s * jb.split_stride);
       gr[q] = v;
     }
   };
@@ -193,12 +189,12 @@ out_bf16_kernel(const OutJobB* __restrict__ jobs, const int* __restrict__ start,
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = t + 256 * q;
-      *reinterpret_cast<uint4*>(Us + (e >> 2) * LS + 8 * (e & 3)) = ur[q];
+      *reinterpret_cast<u32x4*>(Us + (e >> 2) * LS + 8 * (e & 3)) = ur[q];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + 256 * q;
-      const float g[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
+      const f32x4 g = gr[q];
       __bf16* dh = Gh + (e >> 3) * LS + 4 * (e & 7);
       __bf16* dl = Gl + (e >> 3) * LS + 4 * (e & 7);
 #pragma unroll
