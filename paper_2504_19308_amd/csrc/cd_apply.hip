@@ -38,6 +38,11 @@ template <int LOG2N> struct CdCfg {
   static constexpr int BL = T / G;                                      // MAC bin lanes
   static constexpr int NBINS = (N + BL - 1) / BL;
   static constexpr int LDS_SLOTS = (N + N / 16 + 1) * C;
+  // stage twiddles W^e, e < N, as W^(e_hi 2^TWB) W^(e_lo): two LDS tables of
+  // TWL and TWH entries copied from the float32 table (one product, no global
+  // loads inside the transform); n <= 256 keeps the whole table
+  static constexpr int TWB = LOG2N <= 8 ? LOG2N : (LOG2N + 1) / 2;
+  static constexpr int TWL = 1 << TWB, TWH = N >> TWB;
 };
 
 __device__ __forceinline__ int pad_bin(int bin) { return bin + (bin >> 4); }
@@ -51,7 +56,7 @@ __device__ __forceinline__ int slot(int bin, int col) {
 }
 
 template <int R, int SIGN, int LOG2N, int Ns, bool ROWS>
-__device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict__ tw) {
+__device__ __forceinline__ void lds_stage(float2* lds, const float2* twl, const float2* twh) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
   constexpr int NBF = (N / R) * C;
@@ -73,7 +78,9 @@ __device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict_
         const unsigned k = (unsigned)j & (Ns - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[(unsigned)r * k * (unsigned)twstep];
+          const unsigned e = (unsigned)r * k * (unsigned)twstep;   // < N
+          float2 w = twl[e & (Cfg::TWL - 1)];
+          if constexpr (Cfg::TWH > 1) w = cmul(twh[e >> Cfg::TWB], w);
           if (SIGN > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -97,11 +104,11 @@ __device__ __forceinline__ void lds_stage(float2* lds, const float2* __restrict_
 }
 
 template <int SIGN, int LOG2N, bool ROWS, int ST = 0, int Ns = 1>
-__device__ __forceinline__ void lds_fft(float2* lds, const float2* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(float2* lds, const float2* twl, const float2* twh) {
   if constexpr (ST < stage_count(LOG2N)) {
     constexpr int lr = stage_log2r(LOG2N, ST);
-    lds_stage<(1 << lr), SIGN, LOG2N, Ns, ROWS>(lds, tw);
-    lds_fft<SIGN, LOG2N, ROWS, ST + 1, (Ns << lr)>(lds, tw);
+    lds_stage<(1 << lr), SIGN, LOG2N, Ns, ROWS>(lds, twl, twh);
+    lds_fft<SIGN, LOG2N, ROWS, ST + 1, (Ns << lr)>(lds, twl, twh);
   }
 }
 
@@ -127,7 +134,12 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
+  __shared__ float2 twl[Cfg::TWL], twh[Cfg::TWH];
   float* ldsf = reinterpret_cast<float*>(lds);
+  for (int i = threadIdx.x; i < Cfg::TWL + Cfg::TWH; i += T) {
+    if (i < Cfg::TWL) twl[i] = tw[i];
+    else twh[i - Cfg::TWL] = tw[(i - Cfg::TWL) << Cfg::TWB];
+  }
 
   // XCD-aware tile order: consecutive tiles land on the same XCD so that the
   // row segments they share stay in one L2.
@@ -174,7 +186,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   }
   __syncthreads();
 
-  lds_fft<-1, LOG2N, ROWS>(lds, tw);
+  lds_fft<-1, LOG2N, ROWS>(lds, twl, twh);
 
   if constexpr (!SPEC) {
   // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
@@ -303,7 +315,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   }
   __syncthreads();
 
-  lds_fft<+1, LOG2N, ROWS>(lds, tw);
+  lds_fft<+1, LOG2N, ROWS>(lds, twl, twh);
   }
 
   // ---- store ----------------------------------------------------------------
