@@ -160,6 +160,10 @@ struct amm_dec {
   int64_t nnz = 0;
   amm::DevBuf row_ptr, col, val;
   amm::DevBuf csc_ptr, csc_row, csc_val;
+  // entry ranges of each CSR row (CSC column) per block of 4096 inner indices,
+  // (blocks + 1) offsets per row; blocks = 1 keeps row_ptr (csc_ptr) alone
+  amm::DevBuf csr_blk, csc_blk;
+  int csr_blocks = 1, csc_blocks = 1;
   amm_dec* inner = nullptr;
 
   // rectangular circulant operand: square blocks of side s = min(m, n) along
@@ -296,8 +300,11 @@ bool panel_full_ok(int a, int64_t ncols);
 amm_status gemm_short(int64_t M, int64_t N, int K, const float* A, const float* B, float* C, hipStream_t s);
 bool gemm_short_ok(int64_t M, int64_t N, int K);
 // Raw CSR x dense: out (rows x p) (+)= S B
+// rows of S from row_ptr, or per block of 4096 inner indices from blk_ptr
+// ((blocks + 1) offsets per row) when blocks > 1
 amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
-                    const float* B, int64_t p, float* out, bool accumulate, hipStream_t s);
+                    const float* B, int64_t p, float* out, bool accumulate, hipStream_t s,
+                    const int32_t* blk_ptr = nullptr, int blocks = 1);
 
 // Delta A = A - (U S) V^T into dst (m x n)
 amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const float* US, const float* V,

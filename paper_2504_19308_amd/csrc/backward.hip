@@ -203,7 +203,7 @@ amm_status bw_sparse(amm_ctx* ctx, const amm_dec* d, const float* X, const float
   if (dX) {
     // S^T dY: the CSC arrays are the CSR of S^T (n rows)
     AMM_TRY(spmm_raw(d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), n, dY, p, dX,
-                     acc_dx, s));
+                     acc_dx, s, d->csc_blk.as<int32_t>(), d->csc_blocks));
   }
   if (dW) {
     if (d->inner) {

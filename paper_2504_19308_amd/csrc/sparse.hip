@@ -123,12 +123,16 @@ fill_rows(const float* __restrict__ A, int64_t n, uint32_t T, const int32_t* __r
 // slice rows of B (4 gathers in flight, summed in entry order).  Blocks are
 // dealt so that every XCD sweeps whole slices: all rows of a slice run on one
 // XCD, whose L2 then holds that slice of B (n x 256 bytes) while it is reused
-// by every stored entry.
+// by every stored entry.  A row's entries are taken from rng[row * stride +
+// blk] to rng[row * stride + blk + 1]: the whole row (rng = row_ptr, stride 1)
+// or, for long inner dimensions, the part of the row in one block of inner
+// indices, launched block after block with the later blocks accumulating, so
+// that the slice of B an XCD holds is 4096 x 256 bytes.
 constexpr int SW = 64;    // columns per slice
 constexpr int RPB = 16;   // rows per block
 
 __global__ void __launch_bounds__(256)
-spmm_slices(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t* __restrict__ col,
             const float* __restrict__ val, const float* __restrict__ B, int64_t rows, int64_t p,
             float* __restrict__ out, int accumulate, int nslices, int rgroups, int vec) {
   const int bid = blockIdx.x;
@@ -144,7 +148,7 @@ spmm_slices(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col
   const int64_t row = (int64_t)rg * RPB + (threadIdx.x >> 4);
   const int64_t c0 = (int64_t)slice * SW + (threadIdx.x & 15) * 4;
   if (row >= rows || c0 >= p) return;
-  const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
+  const int e0 = rng[row * stride + blk], e1 = rng[row * stride + blk + 1];
   float* o = out + row * p + c0;
   if (vec) {  // p % 4 == 0 and 16-byte aligned B / out: c0 + 3 < p
     float4 acc{0.f, 0.f, 0.f, 0.f};
@@ -250,6 +254,39 @@ amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   return AMM_OK;
 }
 
+namespace {
+
+constexpr int64_t kSpBlock = 4096;   // inner indices per block of a blocked SpMM
+
+// Entry ranges per block of kSpBlock inner indices for rows whose indices are
+// sorted: (blocks + 1) offsets per row, or blocks = 1 when the inner dimension
+// is short (up to 8192, where the whole slice of B stays in an XCD's L2) or a
+// row is unsorted.
+amm_status block_ranges(const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx, int64_t rows,
+                        int64_t inner, amm::DevBuf* out, int* blocks) {
+  *blocks = 1;
+  if (inner <= 2 * kSpBlock) return AMM_OK;
+  for (int64_t i = 0; i < rows; ++i)
+    for (int32_t e = ptr[i] + 1; e < ptr[i + 1]; ++e)
+      if (idx[e] < idx[e - 1]) return AMM_OK;
+  const int nb = (int)((inner + kSpBlock - 1) / kSpBlock);
+  std::vector<int32_t> h((size_t)rows * (nb + 1));
+  for (int64_t i = 0; i < rows; ++i) {
+    int32_t e = ptr[i];
+    for (int b = 0; b < nb; ++b) {
+      while (e < ptr[i + 1] && idx[e] < (int64_t)b * kSpBlock) ++e;
+      h[(size_t)i * (nb + 1) + b] = e;
+    }
+    h[(size_t)i * (nb + 1) + nb] = ptr[i + 1];
+  }
+  AMM_TRY(out->alloc(h.size() * 4));
+  AMM_HIP(hipMemcpy(out->ptr, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  *blocks = nb;
+  return AMM_OK;
+}
+
+}  // namespace
+
 amm_status build_csc(amm_dec* d) {
   const int64_t m = d->m, n = d->n, nnz = d->nnz;
   std::vector<int32_t> rp(m + 1), cl(std::max<int64_t>(nnz, 1));
@@ -276,6 +313,8 @@ amm_status build_csc(amm_dec* d) {
   AMM_HIP(hipMemcpy(d->csc_ptr.ptr, cp.data(), (n + 1) * 4, hipMemcpyHostToDevice));
   AMM_HIP(hipMemcpy(d->csc_row.ptr, rr.data(), rr.size() * 4, hipMemcpyHostToDevice));
   AMM_HIP(hipMemcpy(d->csc_val.ptr, cv.data(), cv.size() * 4, hipMemcpyHostToDevice));
+  AMM_TRY(block_ranges(rp, cl, m, n, &d->csr_blk, &d->csr_blocks));
+  AMM_TRY(block_ranges(cp, rr, n, m, &d->csc_blk, &d->csc_blocks));
   return AMM_OK;
 }
 
@@ -350,21 +389,42 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   return AMM_OK;
 }
 
-amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
-                    const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
+namespace {
+
+amm_status spmm_launch(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
+                       const float* B, int64_t p, float* out, bool acc, hipStream_t s, const int32_t* blk_ptr,
+                       int blocks) {
   if (rows <= 0 || p <= 0) return AMM_OK;
   const int64_t nslices = (p + SW - 1) / SW, rgroups = (rows + RPB - 1) / RPB;
   if (nslices * rgroups > 0x7fffffff || rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
+  if (blocks > 1 && !blk_ptr) return fail(AMM_EINVAL, "blocked SpMM without block ranges");
   const int vec = (p % 4 == 0 && ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
-  TimedLaunch tl("spmm_csr", s);
-  hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, row_ptr, col, val, B, rows,
-                     p, out, acc ? 1 : 0, (int)nslices, (int)rgroups, vec);
-  AMM_HIP(hipGetLastError());
+  if (blocks <= 1) {
+    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, row_ptr, 1, 0, col, val, B,
+                       rows, p, out, acc ? 1 : 0, (int)nslices, (int)rgroups, vec);
+    AMM_HIP(hipGetLastError());
+    return AMM_OK;
+  }
+  for (int b = 0; b < blocks; ++b) {
+    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, blk_ptr, blocks + 1, b, col,
+                       val, B, rows, p, out, (acc || b > 0) ? 1 : 0, (int)nslices, (int)rgroups, vec);
+    AMM_HIP(hipGetLastError());
+  }
   return AMM_OK;
 }
 
+}  // namespace
+
+amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
+                    const float* B, int64_t p, float* out, bool acc, hipStream_t s, const int32_t* blk_ptr,
+                    int blocks) {
+  TimedLaunch tl("spmm_csr", s);
+  return spmm_launch(row_ptr, col, val, rows, B, p, out, acc, s, blk_ptr, blocks);
+}
+
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
-  return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s);
+  return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s,
+                  d->csr_blk.as<int32_t>(), d->csr_blocks);
 }
 
 // out (rows x p) (+)= X S for X rows x n and S n x p sparse:
@@ -381,15 +441,8 @@ amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm
   float* Y = ctx->scratch[7].as<float>();
   TimedLaunch tl("dense_times_csr", s);
   AMM_TRY(transpose_f32(X, rows, n, Xt, s));
-  {
-    const int64_t nslices = (rows + SW - 1) / SW, rgroups = (p + RPB - 1) / RPB;
-    if (nslices * rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
-    const int vec = (rows % 4 == 0) ? 1 : 0;   // scratch buffers are 256-byte aligned
-    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, d->csc_ptr.as<int32_t>(),
-                       d->csc_row.as<int32_t>(), d->csc_val.as<float>(), Xt, p, rows, Y, 0, (int)nslices,
-                       (int)rgroups, vec);
-    AMM_HIP(hipGetLastError());
-  }
+  AMM_TRY(spmm_launch(d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, Xt, rows, Y,
+                      false, s, d->csc_blk.as<int32_t>(), d->csc_blocks));
   hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((rows + 31) / 32), (unsigned)((p + 31) / 32)),
                      dim3(32, 8), 0, s, Y, p, rows, out, acc ? 1 : 0);
   AMM_HIP(hipGetLastError());

@@ -174,3 +174,63 @@ def test_c5_first_order_identity_sampled():
     want = A64 @ B[:, cols].double() - (A64 @ dBc - AhatdB)
     got = M1[:, cols].double()
     assert float((got - want).norm() / want.norm()) < TOL_F32
+
+
+@pytest.mark.parametrize("m,n,p,nnz", [(700, 9000, 67, 20000), (333, 12289, 128, 9000)])
+def test_spmm_blocked_inner(m, n, p, nnz):
+    """Inner dimension above 8192: each row's entries are taken per block of
+    4096 inner indices (the last block partial), later blocks accumulating."""
+    torch = torch_cuda()
+    note(f"sparse blocked S B m={m} n={n} p={p} nnz={nnz}")
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n)).astype(np.float32).astype(np.float64)
+    S = osp.extract_dominant(A, nnz)
+    B = rng.standard_normal((n, p)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    d = c.import_sparse(m, n, S.row_ptr, S.col, S.val)
+    got = c.approx_matmul(d, torch.from_numpy(B.astype(np.float32)).cuda())
+    assert rel(got.double().cpu().numpy(), osp.spmm(S, B)) < TOL_F32
+
+
+def test_spmm_unsorted_rows_long_inner():
+    """Rows stored with descending column indices keep the one-pass gather."""
+    torch = torch_cuda()
+    m, n, p, nnz = 200, 9000, 64, 6000
+    note(f"sparse unsorted rows m={m} n={n}")
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((m, n)).astype(np.float32).astype(np.float64)
+    S = osp.extract_dominant(A, nnz)
+    col, val = S.col.copy(), S.val.copy()
+    for i in range(m):
+        a, b = S.row_ptr[i], S.row_ptr[i + 1]
+        col[a:b] = col[a:b][::-1]
+        val[a:b] = val[a:b][::-1]
+    R = osp.CSR(m, n, S.row_ptr, col, val)
+    B = rng.standard_normal((n, p)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    d = c.import_sparse(m, n, R.row_ptr, R.col, R.val)
+    got = c.approx_matmul(d, torch.from_numpy(B.astype(np.float32)).cuda())
+    assert rel(got.double().cpu().numpy(), osp.spmm(R, B)) < TOL_F32
+
+
+def test_dense_times_sparse_blocked_inner():
+    """X S_B with 9000 inner indices (CSC columns taken per block of 4096 rows)
+    through the first-order term of an empty circulant truncation whose
+    residual is X; sampled rows against the oracle."""
+    torch = torch_cuda()
+    n, p, nnz = 9000, 96, 5000
+    note(f"sparse blocked X S n={n} p={p}")
+    rng = np.random.default_rng(23)
+    Sd = rng.standard_normal((n, p)).astype(np.float32).astype(np.float64)
+    S = osp.extract_dominant(Sd, nnz)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.seed_of(5, 6))
+    X = torch.randn((n, n), generator=g, device="cuda", dtype=torch.float32)
+    c = ctx()
+    dA = c.import_circulant(n, [], np.zeros((0, n)), residual=X)
+    dB = c.import_sparse(n, p, S.row_ptr, S.col, S.val)
+    out = c.approx_matmul(dA, torch.zeros((n, p), device="cuda", dtype=torch.float32), dB)
+    torch.cuda.synchronize()
+    rows = np.sort(rng.choice(n, 12, replace=False))
+    want = osp.dense_times_sparse(X[rows].double().cpu().numpy(), S)
+    assert rel(out[rows].double().cpu().numpy(), want) < TOL_F32
