@@ -201,10 +201,14 @@ struct amm_batch_plan {
   int target_blocks = 0;
   int panel_blocks = 0, out_blocks = 0;
   amm::DevBuf partials, tables;
+  amm::DevBuf gsplit;           // bfloat16 plans: hi and lo parts of every G^T
   void* pjobs = nullptr;
   void* ojobs = nullptr;
+  void* rjobs = nullptr;
   int* pstart = nullptr;
   int* ostart = nullptr;
+  int* rstart = nullptr;
+  int red_blocks = 0;
   hipStream_t own = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

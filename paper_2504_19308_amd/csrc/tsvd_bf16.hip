@@ -2,11 +2,12 @@
 // paper, one zeroth-order product U_i S_i (V_i^T B_i) per pair): the factors
 // and the activations B_i are bfloat16, every product accumulates in float32.
 //
-// Two launches cover all pairs, like the float32 batch:
+// Three launches cover all pairs:
 //   panel:  G_i = V_i^T B_i      (k x p, float32; split reductions as partials)
-//   output: out_i = (U_i S_i) G_i with G_i carried as hi + lo bfloat16 pairs
-//           (hi = bf16(g), lo = bf16(g - hi)), so the second product sees G_i to
-//           ~2^-17 relative and only the stored components are bfloat16.
+//   split:  the partials summed in split order and G_i carried as hi + lo
+//           bfloat16 pairs (hi = bf16(g), lo = bf16(g - hi)), once per pair
+//   output: out_i = (U_i S_i) G_i, so the second product sees G_i to ~2^-17
+//           relative and only the stored components are bfloat16.
 // Matrix cores: v_mfma_f32_16x16x32_bf16, lane l holding a[j] = A[l%16][8(l/16)+j],
 // b[j] = B[8(l/16)+j][l%16] and d[r] = D[4(l/16)+r][l%16].  Both operands are
 // staged k-contiguous in LDS (row stride 40 bf16: 16-byte aligned rows whose
@@ -40,12 +41,20 @@ struct PanelJobB {
   int64_t split_stride;
 };
 
-struct OutJobB {
-  int64_t m, p;
-  const __bf16* US;   // m x k
+struct RedJobB {
   const float* Gt;    // splits x (p x k)
   int splits;
   int64_t split_stride;
+  int64_t count;      // p x k
+  __bf16* Gh;         // p x k
+  __bf16* Gl;
+};
+
+struct OutJobB {
+  int64_t m, p;
+  const __bf16* US;   // m x k
+  const __bf16* Gh;   // p x k, hi and lo parts of G^T
+  const __bf16* Gl;
   float* out;         // m x p
 };
 
@@ -144,6 +153,29 @@ panel_bf16_kernel(const PanelJobB* __restrict__ jobs, const int* __restrict__ st
     }
 }
 
+// G^T of every pair: split partials summed in split order, then hi + lo bf16
+__global__ void __launch_bounds__(256)
+g_split_kernel(const RedJobB* __restrict__ jobs, const int* __restrict__ start, int count) {
+  __shared__ int st[MAXB + 1];
+  for (int i = threadIdx.x; i <= count; i += blockDim.x) st[i] = start[i];
+  __syncthreads();
+  const int bid = blockIdx.x;
+  const int jx = find_job16(st, count, bid);
+  const RedJobB jb = jobs[jx];
+  const int64_t i = ((int64_t)(bid - st[jx]) * 256 + threadIdx.x) * 4;
+  if (i >= jb.count) return;
+  f32x4 v = *reinterpret_cast<const f32x4*>(jb.Gt + i);
+  for (int s = 1; s < jb.splits; ++s) v += *reinterpret_cast<const f32x4*>(jb.Gt + s * jb.split_stride + i);
+  __bf16 h[4], l[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    h[r] = (__bf16)v[r];
+    l[r] = (__bf16)(v[r] - (float)h[r]);
+  }
+  *reinterpret_cast<uint2*>(jb.Gh + i) = *reinterpret_cast<const uint2*>(h);
+  *reinterpret_cast<uint2*>(jb.Gl + i) = *reinterpret_cast<const uint2*>(l);
+}
+
 template <int K>
 __global__ void __launch_bounds__(256)
 out_bf16_kernel(const OutJobB* __restrict__ jobs, const int* __restrict__ start, int count) {
@@ -168,41 +200,24 @@ out_bf16_kernel(const OutJobB* __restrict__ jobs, const int* __restrict__ start,
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 ur[2];
-  f32x4 gr[4];
+  // 128 rows (columns of G) x 32 bf16 per chunk and operand: 8 bf16 per load
+  u32x4 ur[2], hr[2], lr[2];
   auto fetch = [&](int f0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = t + 256 * q;
       ur[q] = *reinterpret_cast<const u32x4*>(jb.US + (m0 + (e >> 2)) * K + f0 + 8 * (e & 3));
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q;
-      const float* src = jb.Gt + (n0 + (e >> 3)) * K + f0 + 4 * (e & 7);
-      f32x4 v = *reinterpret_cast<const f32x4*>(src);
-      for (int s = 1; s < jb.splits; ++s) v += *reinterpret_cast<const f32x4*>(src + s * jb.split_stride);
-      gr[q] = v;
+      hr[q] = *reinterpret_cast<const u32x4*>(jb.Gh + (n0 + (e >> 2)) * K + f0 + 8 * (e & 3));
+      lr[q] = *reinterpret_cast<const u32x4*>(jb.Gl + (n0 + (e >> 2)) * K + f0 + 8 * (e & 3));
     }
   };
   auto stash = [&]() {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int e = t + 256 * q;
-      *reinterpret_cast<u32x4*>(Us + (e >> 2) * LS + 8 * (e & 3)) = ur[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q;
-      const f32x4 g = gr[q];
-      __bf16* dh = Gh + (e >> 3) * LS + 4 * (e & 7);
-      __bf16* dl = Gl + (e >> 3) * LS + 4 * (e & 7);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const __bf16 hi = (__bf16)g[i];
-        dh[i] = hi;
-        dl[i] = (__bf16)(g[i] - (float)hi);
-      }
+      const int e = t + 256 * q, off = (e >> 2) * LS + 8 * (e & 3);
+      *reinterpret_cast<u32x4*>(Us + off) = ur[q];
+      *reinterpret_cast<u32x4*>(Gh + off) = hr[q];
+      *reinterpret_cast<u32x4*>(Gl + off) = lr[q];
     }
   };
 
@@ -265,6 +280,12 @@ amm_status launch_bf16(const amm_batch_plan* bp, hipStream_t s) {
                        reinterpret_cast<const PanelJobB*>(bp->pjobs), (const int*)bp->pstart, count);
     AMM_HIP(hipGetLastError());
   }
+  {
+    TimedLaunch tl("batch_split_bf16", s);
+    hipLaunchKernelGGL(g_split_kernel, dim3((unsigned)bp->red_blocks), dim3(256), 0, s,
+                       reinterpret_cast<const RedJobB*>(bp->rjobs), (const int*)bp->rstart, count);
+    AMM_HIP(hipGetLastError());
+  }
   TimedLaunch tl("batch_out_bf16", s);
   hipLaunchKernelGGL((out_bf16_kernel<K>), dim3((unsigned)bp->out_blocks), dim3(256), 0, s,
                      reinterpret_cast<const OutJobB*>(bp->ojobs), (const int*)bp->ostart, count);
@@ -313,7 +334,8 @@ amm_status batch_build_bf16(amm_batch_plan* bp, int target_blocks) {
   const int k = bp->k;
   std::vector<PanelJobB> pj(count);
   std::vector<OutJobB> oj(count);
-  std::vector<int> ps(count + 1, 0), os(count + 1, 0), splits(count);
+  std::vector<RedJobB> rj(count);
+  std::vector<int> ps(count + 1, 0), os(count + 1, 0), rs(count + 1, 0), splits(count);
   int64_t total_tiles = 0;
   for (auto& it : bp->items) total_tiles += it.p / PT;
   size_t part_floats = 0;
@@ -326,29 +348,43 @@ amm_status batch_build_bf16(amm_batch_plan* bp, int target_blocks) {
     part_floats += (size_t)sp * k * it.p;
     ps[i + 1] = ps[i] + (int)(it.p / PT) * sp;
     os[i + 1] = os[i] + (int)((it.m / OT16) * (it.p / OT16));
+    rs[i + 1] = rs[i] + (int)(((int64_t)k * it.p / 4 + 255) / 256);
   }
+  size_t g_elems = 0;
+  for (const auto& it : bp->items) g_elems += (size_t)k * it.p;
   AMM_TRY(bp->partials.reserve(part_floats * sizeof(float)));
-  size_t off = 0;
+  AMM_TRY(bp->gsplit.reserve(std::max<size_t>(g_elems, 1) * 2 * sizeof(__bf16)));
+  size_t off = 0, goff = 0;
   for (int i = 0; i < count; ++i) {
     const auto& it = bp->items[i];
     float* G = bp->partials.as<float>() + off;
     off += (size_t)splits[i] * k * it.p;
+    __bf16* gh = bp->gsplit.as<__bf16>() + goff;
+    __bf16* gl = gh + g_elems;
+    goff += (size_t)k * it.p;
     pj[i] = PanelJobB{static_cast<const __bf16*>(it.Vt16), static_cast<const __bf16*>(it.B16), it.n, it.p,
                       (int)(it.p / PT), splits[i], G, (int64_t)k * it.p};
-    oj[i] = OutJobB{it.m, it.p, static_cast<const __bf16*>(it.US16), G, splits[i], (int64_t)k * it.p, it.out};
+    rj[i] = RedJobB{G, splits[i], (int64_t)k * it.p, (int64_t)k * it.p, gh, gl};
+    oj[i] = OutJobB{it.m, it.p, static_cast<const __bf16*>(it.US16), gh, gl, it.out};
   }
-  AMM_TRY(bp->tables.reserve(count * (sizeof(PanelJobB) + sizeof(OutJobB)) + 2 * (count + 1) * sizeof(int) + 64));
+  const size_t tbytes = count * (sizeof(PanelJobB) + sizeof(OutJobB) + sizeof(RedJobB)) + 3 * (count + 1) * sizeof(int);
+  AMM_TRY(bp->tables.reserve(tbytes + 64));
   char* base = bp->tables.as<char>();
   bp->pjobs = base;
   bp->ojobs = base + count * sizeof(PanelJobB);
-  bp->pstart = reinterpret_cast<int*>(base + count * (sizeof(PanelJobB) + sizeof(OutJobB)));
+  bp->rjobs = base + count * (sizeof(PanelJobB) + sizeof(OutJobB));
+  bp->pstart = reinterpret_cast<int*>(base + count * (sizeof(PanelJobB) + sizeof(OutJobB) + sizeof(RedJobB)));
   bp->ostart = bp->pstart + count + 1;
+  bp->rstart = bp->ostart + count + 1;
   AMM_HIP(hipMemcpy(bp->pjobs, pj.data(), count * sizeof(PanelJobB), hipMemcpyHostToDevice));
   AMM_HIP(hipMemcpy(bp->ojobs, oj.data(), count * sizeof(OutJobB), hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(bp->rjobs, rj.data(), count * sizeof(RedJobB), hipMemcpyHostToDevice));
   AMM_HIP(hipMemcpy(bp->pstart, ps.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
   AMM_HIP(hipMemcpy(bp->ostart, os.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
+  AMM_HIP(hipMemcpy(bp->rstart, rs.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
   bp->panel_blocks = ps[count];
   bp->out_blocks = os[count];
+  bp->red_blocks = rs[count];
   bp->splits = splits;
   bp->target_blocks = target_blocks;
   return AMM_OK;
