@@ -97,7 +97,8 @@ struct amm_ctx {
   int device = 0;
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[8];              // grow-only work areas for products
+  amm::DevBuf scratch[14];             // grow-only work areas for products (8-13: chirp-convolution path)
+  std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   amm::KernelTimer timer;
   bool timing = false;
 };
@@ -252,8 +253,10 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K,
 // Any-length float64 DFT of `batch` vectors in place (element e of vector b
 // at b*bs + e*es), sign -1: exp(-2 pi i jk/n); result times `scale`.
 // Lengths that are not powers of two go through Bluestein's chirp convolution.
+// sync = false leaves the work queued on s (the chirp-convolution products,
+// whose results only kernels on s read)
 amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, int64_t batch, int sign, double scale,
-                     hipStream_t s);
+                     hipStream_t s, bool sync = true);
 // Circulant products for sizes that are not powers of two (float64 steps):
 // out (n x p) (+)= Atil B, and out (rows x n) (+)= X Btil with the adjoint lists.
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,

@@ -133,30 +133,36 @@ unsigned blocks_for(int64_t count) { return (unsigned)((count + 255) / 256); }
 }  // namespace
 
 amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, int64_t batch, int sign, double scale,
-                     hipStream_t s) {
+                     hipStream_t s, bool sync) {
   if (n < 1 || batch <= 0) return AMM_OK;
   const int lN = ceil_log2(2 * (int64_t)n - 1);
   if (lN > 15) return fail(AMM_EUNSUPPORTED, "DFT length %d too large", n);
   const int N = 1 << std::max(lN, 1);
   const double2* tw = nullptr;
   AMM_TRY(twiddles64(ctx, std::max(lN, 1), &tw));
-  // kernel spectrum Bh = FFT_N(b)
-  DevBuf bk, bt;
-  AMM_TRY(bk.alloc((size_t)N * sizeof(double2)));
-  AMM_TRY(bt.alloc((size_t)N * sizeof(double2)));
-  hipLaunchKernelGGL(chirp_kernel_vec, dim3(blocks_for(N)), dim3(256), 0, s, bk.as<double2>(), n, N, sign);
-  AMM_HIP(hipGetLastError());
-  double2 *kc = bk.as<double2>(), *kt = bt.as<double2>();
-  AMM_TRY(fft64_transform(kc, kt, std::max(lN, 1), 1, N, 1, false, -1, 1.0, tw, s));
-  const double2* Bh = kc;
-  // vectors in chunks of at most ~512 MiB of padded data
+  // kernel spectrum Bh = FFT_N(b), computed once per (n, sign) and kept by the context
+  const int64_t key = 2 * (int64_t)n + (sign > 0 ? 1 : 0);
+  auto it = ctx->chirp64.find(key);
+  if (it == ctx->chirp64.end()) {
+    DevBuf bk, bt;
+    AMM_TRY(bk.alloc((size_t)N * sizeof(double2)));
+    AMM_TRY(bt.alloc((size_t)N * sizeof(double2)));
+    hipLaunchKernelGGL(chirp_kernel_vec, dim3(blocks_for(N)), dim3(256), 0, s, bk.as<double2>(), n, N, sign);
+    AMM_HIP(hipGetLastError());
+    double2 *kc = bk.as<double2>(), *kt = bt.as<double2>();
+    AMM_TRY(fft64_transform(kc, kt, std::max(lN, 1), 1, N, 1, false, -1, 1.0, tw, s));
+    AMM_HIP(hipStreamSynchronize(s));   // the other buffer is released on return
+    // the passes ping-pong: keep whichever buffer holds the spectrum
+    it = ctx->chirp64.emplace(key, std::move(kc == bk.as<double2>() ? bk : bt)).first;
+  }
+  const double2* Bh = it->second.as<double2>();
+  // vectors in chunks of at most ~512 MiB of padded data, in the context's work areas
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(batch, ((int64_t)512 << 20) / ((int64_t)N * 16)));
-  DevBuf p0, p1;
-  AMM_TRY(p0.alloc((size_t)chunk * N * sizeof(double2)));
-  AMM_TRY(p1.alloc((size_t)chunk * N * sizeof(double2)));
+  AMM_TRY(ctx->scratch[10].reserve((size_t)chunk * N * sizeof(double2)));
+  AMM_TRY(ctx->scratch[11].reserve((size_t)chunk * N * sizeof(double2)));
   for (int64_t v0 = 0; v0 < batch; v0 += chunk) {
     const int64_t nv = std::min(chunk, batch - v0);
-    double2 *cur = p0.as<double2>(), *tmp = p1.as<double2>();
+    double2 *cur = ctx->scratch[10].as<double2>(), *tmp = ctx->scratch[11].as<double2>();
     hipLaunchKernelGGL(bluestein_pad, dim3(blocks_for(nv * N)), dim3(256), 0, s, x, n, es, bs, v0, nv, N, sign, cur);
     AMM_HIP(hipGetLastError());
     AMM_TRY(fft64_transform(cur, tmp, std::max(lN, 1), 1, N, nv, false, -1, 1.0, tw, s));
@@ -167,8 +173,7 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
                        nv, x);
     AMM_HIP(hipGetLastError());
   }
-  // the chunk buffers and the kernel spectrum are released on return
-  AMM_HIP(hipStreamSynchronize(s));
+  if (sync) AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;
 }
 
@@ -180,21 +185,18 @@ amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, c
     return AMM_OK;
   }
   const int64_t P2 = (p + 1) / 2, cnt = (int64_t)n * P2;
-  DevBuf z, y;
-  AMM_TRY(z.alloc(cnt * sizeof(double2)));
-  AMM_TRY(y.alloc(cnt * sizeof(double2)));
+  AMM_TRY(ctx->scratch[8].reserve(cnt * sizeof(double2)));
+  AMM_TRY(ctx->scratch[9].reserve(cnt * sizeof(double2)));
+  double2 *z = ctx->scratch[8].as<double2>(), *y = ctx->scratch[9].as<double2>();
   TimedLaunch tl("cd_apply_general", s);
-  hipLaunchKernelGGL(pack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, B, (int64_t)n, p, P2, z.as<double2>());
+  hipLaunchKernelGGL(pack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, B, (int64_t)n, p, P2, z);
   AMM_HIP(hipGetLastError());
-  AMM_TRY(dft64_any(ctx, z.as<double2>(), n, P2, 1, P2, -1, 1.0, s));
-  hipLaunchKernelGGL(spectral_mac, dim3(blocks_for(cnt)), dim3(256), 0, s, z.as<double2>(), n, P2, K, shifts, L,
-                     y.as<double2>());
+  AMM_TRY(dft64_any(ctx, z, n, P2, 1, P2, -1, 1.0, s, false));
+  hipLaunchKernelGGL(spectral_mac, dim3(blocks_for(cnt)), dim3(256), 0, s, z, n, P2, K, shifts, L, y);
   AMM_HIP(hipGetLastError());
-  AMM_TRY(dft64_any(ctx, y.as<double2>(), n, P2, 1, P2, +1, 1.0 / n, s));
-  hipLaunchKernelGGL(unpack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, y.as<double2>(), (int64_t)n, p, P2, out,
-                     acc ? 1 : 0);
+  AMM_TRY(dft64_any(ctx, y, n, P2, 1, P2, +1, 1.0 / n, s, false));
+  hipLaunchKernelGGL(unpack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, y, (int64_t)n, p, P2, out, acc ? 1 : 0);
   AMM_HIP(hipGetLastError());
-  AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;
 }
 
@@ -203,14 +205,13 @@ amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, c
 amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s) {
   if (p <= 0) return AMM_OK;
   const int64_t P2 = p / 2, cnt = (int64_t)n * P2;
-  DevBuf z;
-  AMM_TRY(z.alloc(cnt * sizeof(double2)));
-  hipLaunchKernelGGL(pack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, B, (int64_t)n, p, P2, z.as<double2>());
+  AMM_TRY(ctx->scratch[8].reserve(cnt * sizeof(double2)));
+  double2* z = ctx->scratch[8].as<double2>();
+  hipLaunchKernelGGL(pack_pairs, dim3(blocks_for(cnt)), dim3(256), 0, s, B, (int64_t)n, p, P2, z);
   AMM_HIP(hipGetLastError());
-  AMM_TRY(dft64_any(ctx, z.as<double2>(), n, P2, 1, P2, -1, 1.0, s));
-  hipLaunchKernelGGL(spectrum_to_f32, dim3(blocks_for(cnt)), dim3(256), 0, s, z.as<double2>(), cnt, X);
+  AMM_TRY(dft64_any(ctx, z, n, P2, 1, P2, -1, 1.0, s, false));
+  hipLaunchKernelGGL(spectrum_to_f32, dim3(blocks_for(cnt)), dim3(256), 0, s, z, cnt, X);
   AMM_HIP(hipGetLastError());
-  AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;
 }
 
@@ -219,13 +220,12 @@ amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
                                  const float* X, int64_t rows, float* out, bool acc, hipStream_t s) {
   if (rows <= 0) return AMM_OK;
-  DevBuf xt, yt;
-  AMM_TRY(xt.alloc((size_t)n * rows * sizeof(float)));
-  AMM_TRY(yt.alloc((size_t)n * rows * sizeof(float)));
-  AMM_TRY(transpose_f32(X, rows, n, xt.as<float>(), s));
-  AMM_TRY(cd_apply_general(ctx, n, K, shifts_adj, Ladj, xt.as<float>(), rows, yt.as<float>(), false, s));
-  AMM_TRY(transpose_acc_f32(yt.as<float>(), n, rows, out, acc, s));
-  AMM_HIP(hipStreamSynchronize(s));
+  AMM_TRY(ctx->scratch[12].reserve((size_t)n * rows * sizeof(float)));
+  AMM_TRY(ctx->scratch[13].reserve((size_t)n * rows * sizeof(float)));
+  float *xt = ctx->scratch[12].as<float>(), *yt = ctx->scratch[13].as<float>();
+  AMM_TRY(transpose_f32(X, rows, n, xt, s));
+  AMM_TRY(cd_apply_general(ctx, n, K, shifts_adj, Ladj, xt, rows, yt, false, s));
+  AMM_TRY(transpose_acc_f32(yt, n, rows, out, acc, s));
   return AMM_OK;
 }
 
