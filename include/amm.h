@@ -182,7 +182,11 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k,
 
 /* Import a sparse part (CSR on the host: row_ptr m+1, col nnz ascending per
  * row, val nnz) plus an optional truncated residue handle, whose ownership
- * passes to the new handle.  A (device, borrowed) as in amm_dec_import_tsvd. */
+ * passes to the new handle.  A (device, borrowed) as in amm_dec_import_tsvd.
+ * Rows whose columns are not ascending are accepted (index range and row_ptr
+ * are checked, AMM_EINVAL otherwise); products with them keep the one-pass
+ * gather instead of the blocked one used when n > 8192, and sum a row's
+ * entries in stored order. */
 amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n,
                                  int64_t nnz, const int32_t* row_ptr_host,
                                  const int32_t* col_host, const float* val_host,
