@@ -198,13 +198,14 @@ def test_sparse_decompose_end_to_end():
     assert rel(got, want) < 1e-4
 
 
-@pytest.mark.parametrize("n,ka,kb", [(256, 32, 32), (512, 64, 32), (640, 32, 64), (1024, 64, 64), (384, 32, 0),
+@pytest.mark.parametrize("n,ka,kb", [(128, 32, 32), (256, 32, 32), (512, 64, 32), (640, 32, 64), (1024, 64, 64), (384, 32, 0),
                                       (1280, 32, 32), (2048, 32, 0), (512, 128, 128), (768, 128, 0)])
 def test_tsvd_split_path_first_order(n, ka, kb):
     """Shapes of the three-launch path (direct panels, reduction, output GEMM
     on split bfloat16 operands): float32 accuracy against the oracle.  Rank-32
-    panels with n a multiple of 256 take the pipelined form; n = 256, 1280 and
-    2048 give it one, five and two load batches per wave."""
+    panels with n a multiple of 128 take the pipelined form (three load batches
+    rotating per wave); n = 128 gives the H job a single batch, n = 1280 batch
+    counts that are not multiples of three."""
     note(f"tsvd split path n={n} ka={ka} kb={kb}")
     sig = inputs.decay_power(n, 1.5)
     A = _spectral(n, n, sig, 21 + n)
