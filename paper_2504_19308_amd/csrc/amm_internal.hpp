@@ -99,6 +99,7 @@ struct amm_ctx {
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
   amm::DevBuf scratch[14];             // grow-only work areas for products (8-13: chirp-convolution path)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
+  std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
   amm::KernelTimer timer;
   bool timing = false;
 };
@@ -259,6 +260,13 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
                      hipStream_t s, bool sync = true);
 // Circulant products for sizes that are not powers of two (float64 steps):
 // out (n x p) (+)= Atil B, and out (rows x n) (+)= X Btil with the adjoint lists.
+// Circulant products for sides that are not powers of two: fused float32
+// chirp-convolution kernel up to kChirpFusedMax, float64 steps above.
+constexpr int kChirpFusedMax = 2048;
+// [ch (n) | H_fwd / M (M) | H_inv / M (M)] in float32, M = 2^ceil(log2(2n - 1)), cached per n
+amm_status chirp_tables32(amm_ctx* ctx, int n, hipStream_t s, const float2** tab);
+amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
+                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s);
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
                             int64_t p, float* out, bool acc, hipStream_t s);
 amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s);

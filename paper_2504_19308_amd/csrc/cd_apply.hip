@@ -364,6 +364,161 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   }
 }
 
+// ---- sides that are not powers of two (n <= 2048), fused ---------------------
+// The length-n DFT of sign s is Bluestein's chirp convolution,
+//   X[k] = ch_k sum_j (x_j ch_j) conj(ch_{k-j}),   ch_t = exp(s pi i t^2 / n),
+// done as a cyclic convolution of length M = 2^LOG2M >= 2n - 1 in LDS:
+// chirp, forward FFT, times H (the FFT of the wrapped conj(ch), over M), inverse
+// FFT, chirp.  The forward DFT, the shifted spectral MAC over n bins (indices
+// mod n) and the inverse DFT (conjugate chirp, its own H, 1/n) run in one
+// kernel per tile of 2C real columns (or rows), as cd_apply_kernel does for
+// powers of two.  tab = [ch (n) | H_fwd / M (M) | H_inv / M (M)].
+template <int LOG2M, bool ROWS>
+__global__ void __launch_bounds__(CdCfg<LOG2M>::T)
+cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent, int n, int K,
+                const int32_t* __restrict__ shifts, const float2* __restrict__ L, const float2* __restrict__ tab,
+                const float2* __restrict__ tw, int accumulate) {
+  using Cfg = CdCfg<LOG2M>;
+  constexpr int M = Cfg::N, C = Cfg::C, T = Cfg::T;
+  __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
+  __shared__ float2 twl[Cfg::TWL], twh[Cfg::TWH];
+  float* ldsf = reinterpret_cast<float*>(lds);
+  for (int i = threadIdx.x; i < Cfg::TWL + Cfg::TWH; i += T) {
+    if (i < Cfg::TWL) twl[i] = tw[i];
+    else twh[i - Cfg::TWL] = tw[(i - Cfg::TWL) << Cfg::TWB];
+  }
+  const float2* ch = tab;
+  const float2* Hf = tab + n;
+  const float2* Hb = tab + n + M;
+  const int nblk = gridDim.x;
+  const int xcd = blockIdx.x % 8, slot_ = blockIdx.x / 8;
+  int tile = xcd * ((nblk + 7) / 8) + slot_;
+  if ((nblk & 7) != 0) tile = blockIdx.x;
+  const int64_t first = (int64_t)tile * 2 * C;
+
+  // load (bins >= n are the zero padding)
+  if (!ROWS) {
+    for (int e = threadIdx.x; e < M * 2 * C; e += T) {
+      const int rc = e % (2 * C), row = e / (2 * C);
+      const int64_t c = first + rc;
+      ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = (row < n && c < extent) ? X[(int64_t)row * extent + c] : 0.f;
+    }
+  } else {
+    for (int e = threadIdx.x; e < M * 2 * C; e += T) {
+      const int q = e % M, rl = e / M;
+      const int64_t r = first + rl;
+      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = (q < n && r < extent) ? X[r * n + q] : 0.f;
+    }
+  }
+  __syncthreads();
+  // a (bins < n) times w (tw_conj: use conj(w))
+  auto scale_bins = [&](int count, const float2* w, bool conj_w) {
+    for (int e = threadIdx.x; e < count * C; e += T) {
+      const int bin = e / C, col = e % C;
+      float2 f = w[bin];
+      if (conj_w) f.y = -f.y;
+      float2& v = lds[pad_bin(bin) * C + col];
+      v = cmul(v, f);
+    }
+    __syncthreads();
+  };
+  // forward DFT of length n
+  scale_bins(n, ch, false);
+  lds_fft<-1, LOG2M, ROWS>(lds, twl, twh);
+  scale_bins(M, Hf, false);
+  lds_fft<+1, LOG2M, ROWS>(lds, twl, twh);
+  scale_bins(n, ch, false);
+
+  // shifted spectral MAC over n bins: Y[p] = sum_t L_t[p] X[(p - k_t) mod n]
+  constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL;
+  constexpr int NB = (M / 2 + BL - 1) / BL;    // n <= M / 2
+  const int cg = threadIdx.x % G, bl = threadIdx.x / G;
+  float2 acc[NB][CPL];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[i][c] = float2{0.f, 0.f};
+  for (int t = 0; t < K; ++t) {
+    const int k = shifts[t];
+    const int64_t Lt = (int64_t)t * n;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int p = bl + i * BL;
+      if (p < n) {
+        const float2 l = L[Lt + p];
+        int q = p - k;
+        if (q < 0) q += n;
+        const float2* src = &lds[pad_bin(q) * C + cg * CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const float2 x = src[c];
+          acc[i][c].x += l.x * x.x - l.y * x.y;
+          acc[i][c].y += l.x * x.y + l.y * x.x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // inverse DFT of length n (conjugate chirp), padding re-zeroed
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int p = bl + i * BL;
+    if (p < n) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) lds[pad_bin(p) * C + cg * CPL + c] = acc[i][c];
+    }
+  }
+  for (int e = threadIdx.x; e < (M - n) * C; e += T) lds[pad_bin(n + e / C) * C + e % C] = float2{0.f, 0.f};
+  __syncthreads();
+  scale_bins(n, ch, true);
+  lds_fft<-1, LOG2M, ROWS>(lds, twl, twh);
+  scale_bins(M, Hb, false);
+  lds_fft<+1, LOG2M, ROWS>(lds, twl, twh);
+  scale_bins(n, ch, true);
+
+  // store y / n
+  const float sc = 1.0f / (float)n;
+  if (!ROWS) {
+    for (int e = threadIdx.x; e < n * 2 * C; e += T) {
+      const int rc = e % (2 * C), row = e / (2 * C);
+      const int64_t c = first + rc;
+      if (c < extent) {
+        const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * sc;
+        float* o = out + (int64_t)row * extent + c;
+        *o = accumulate ? *o + v : v;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * 2 * C; e += T) {
+      const int q = e % n, rl = e / n;
+      const int64_t r = first + rl;
+      if (r < extent) {
+        const float v = ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] * sc;
+        float* o = out + r * n + q;
+        *o = accumulate ? *o + v : v;
+      }
+    }
+  }
+}
+
+template <int LOG2M>
+amm_status launch_chirp(bool rows, const float* X, float* out, int64_t extent, int n, int K, const int32_t* shifts,
+                        const float2* L, const float2* tab, const float2* tw, bool acc, hipStream_t s) {
+  using Cfg = CdCfg<LOG2M>;
+  const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
+  if (tiles == 0) return AMM_OK;
+  if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
+  TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
+  if (rows)
+    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true>), dim3((unsigned)tiles), dim3(Cfg::T), 0, s, X, out, extent, n, K,
+                       shifts, L, tab, tw, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false>), dim3((unsigned)tiles), dim3(Cfg::T), 0, s, X, out, extent, n,
+                       K, shifts, L, tab, tw, acc ? 1 : 0);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
 template <int LOG2N>
 amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
                      const int32_t* shifts, const void* L, const float2* tw, bool acc,
@@ -431,6 +586,28 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
   return dispatch_cd(false, log2n, B, spec, p, 0, nullptr, nullptr, tw, false, s, true, CdPairs{});
+}
+
+// Fused chirp-convolution product for 3 <= n <= 2048, n not a power of two:
+// rows = false: out (n x extent) (+)= Atil X for X n x extent; rows = true:
+// out (extent x n) (+)= the operator applied to each row of X (extent x n).
+amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
+                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s) {
+  if (n < 3 || n > kChirpFusedMax) return fail(AMM_EUNSUPPORTED, "fused chirp product needs 3 <= n <= %d", kChirpFusedMax);
+  int lM = 0;
+  while ((1 << lM) < 2 * n - 1) ++lM;
+  const float2* tab = nullptr;
+  AMM_TRY(chirp_tables32(ctx, n, s, &tab));
+  const float2* tw = nullptr;
+  AMM_TRY(twiddles32(ctx, lM, &tw));
+  switch (lM) {
+#define AMM_CASE(L2) \
+  case L2: return launch_chirp<L2>(rows, X, out, extent, n, K, shifts, L, tab, tw, accumulate, s);
+    AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6) AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10)
+    AMM_CASE(11) AMM_CASE(12)
+#undef AMM_CASE
+    default: return fail(AMM_EUNSUPPORTED, "fused chirp product length %d", n);
+  }
 }
 
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,

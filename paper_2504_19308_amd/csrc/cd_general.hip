@@ -130,7 +130,62 @@ int ceil_log2(int64_t v) {
 
 unsigned blocks_for(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+// float32 tables of the fused product: tab[t] = ch_t (sign -1), then the two
+// kernel spectra scaled by 1/N
+__global__ void chirp_tables_f32(const double2* __restrict__ Bf, const double2* __restrict__ Bb, int n, int N,
+                                 float2* __restrict__ tab) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n + 2 * N) return;
+  double2 v;
+  if (id < n) v = chirp(id, n, -1);
+  else if (id < n + N) v = double2{Bf[id - n].x / N, Bf[id - n].y / N};
+  else v = double2{Bb[id - n - N].x / N, Bb[id - n - N].y / N};
+  tab[id] = float2{(float)v.x, (float)v.y};
+}
+
+// FFT_N of the wrapped conj(ch) for (n, sign), computed once per context
+amm_status chirp_spectrum64(amm_ctx* ctx, int n, int sign, hipStream_t s, const double2** out) {
+  const int lN = std::max(ceil_log2(2 * (int64_t)n - 1), 1);
+  const int N = 1 << lN;
+  const int64_t key = 2 * (int64_t)n + (sign > 0 ? 1 : 0);
+  auto it = ctx->chirp64.find(key);
+  if (it == ctx->chirp64.end()) {
+    const double2* tw = nullptr;
+    AMM_TRY(twiddles64(ctx, lN, &tw));
+    DevBuf bk, bt;
+    AMM_TRY(bk.alloc((size_t)N * sizeof(double2)));
+    AMM_TRY(bt.alloc((size_t)N * sizeof(double2)));
+    hipLaunchKernelGGL(chirp_kernel_vec, dim3(blocks_for(N)), dim3(256), 0, s, bk.as<double2>(), n, N, sign);
+    AMM_HIP(hipGetLastError());
+    double2 *kc = bk.as<double2>(), *kt = bt.as<double2>();
+    AMM_TRY(fft64_transform(kc, kt, lN, 1, N, 1, false, -1, 1.0, tw, s));
+    AMM_HIP(hipStreamSynchronize(s));   // the other buffer is released on return
+    // the passes ping-pong: keep whichever buffer holds the spectrum
+    it = ctx->chirp64.emplace(key, std::move(kc == bk.as<double2>() ? bk : bt)).first;
+  }
+  *out = it->second.as<double2>();
+  return AMM_OK;
+}
+
 }  // namespace
+
+amm_status chirp_tables32(amm_ctx* ctx, int n, hipStream_t s, const float2** tab) {
+  auto it = ctx->chirp32.find(n);
+  if (it == ctx->chirp32.end()) {
+    const int N = 1 << std::max(ceil_log2(2 * (int64_t)n - 1), 1);
+    const double2 *Bf = nullptr, *Bb = nullptr;
+    AMM_TRY(chirp_spectrum64(ctx, n, -1, s, &Bf));
+    AMM_TRY(chirp_spectrum64(ctx, n, +1, s, &Bb));
+    DevBuf t;
+    AMM_TRY(t.alloc((size_t)(n + 2 * N) * sizeof(float2)));
+    hipLaunchKernelGGL(chirp_tables_f32, dim3(blocks_for(n + 2 * N)), dim3(256), 0, s, Bf, Bb, n, N, t.as<float2>());
+    AMM_HIP(hipGetLastError());
+    AMM_HIP(hipStreamSynchronize(s));
+    it = ctx->chirp32.emplace(n, std::move(t)).first;
+  }
+  *tab = it->second.as<float2>();
+  return AMM_OK;
+}
 
 amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, int64_t batch, int sign, double scale,
                      hipStream_t s, bool sync) {
@@ -141,21 +196,8 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
   const double2* tw = nullptr;
   AMM_TRY(twiddles64(ctx, std::max(lN, 1), &tw));
   // kernel spectrum Bh = FFT_N(b), computed once per (n, sign) and kept by the context
-  const int64_t key = 2 * (int64_t)n + (sign > 0 ? 1 : 0);
-  auto it = ctx->chirp64.find(key);
-  if (it == ctx->chirp64.end()) {
-    DevBuf bk, bt;
-    AMM_TRY(bk.alloc((size_t)N * sizeof(double2)));
-    AMM_TRY(bt.alloc((size_t)N * sizeof(double2)));
-    hipLaunchKernelGGL(chirp_kernel_vec, dim3(blocks_for(N)), dim3(256), 0, s, bk.as<double2>(), n, N, sign);
-    AMM_HIP(hipGetLastError());
-    double2 *kc = bk.as<double2>(), *kt = bt.as<double2>();
-    AMM_TRY(fft64_transform(kc, kt, std::max(lN, 1), 1, N, 1, false, -1, 1.0, tw, s));
-    AMM_HIP(hipStreamSynchronize(s));   // the other buffer is released on return
-    // the passes ping-pong: keep whichever buffer holds the spectrum
-    it = ctx->chirp64.emplace(key, std::move(kc == bk.as<double2>() ? bk : bt)).first;
-  }
-  const double2* Bh = it->second.as<double2>();
+  const double2* Bh = nullptr;
+  AMM_TRY(chirp_spectrum64(ctx, n, sign, s, &Bh));
   // vectors in chunks of at most ~512 MiB of padded data, in the context's work areas
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(batch, ((int64_t)512 << 20) / ((int64_t)N * 16)));
   AMM_TRY(ctx->scratch[10].reserve((size_t)chunk * N * sizeof(double2)));
@@ -184,6 +226,7 @@ amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, c
     if (!acc) return fill_f32(out, (int64_t)n * p, 0.f, s);
     return AMM_OK;
   }
+  if (n >= 3 && n <= kChirpFusedMax) return cd_chirp_apply(ctx, false, n, K, shifts, L, B, p, out, acc, s);
   const int64_t P2 = (p + 1) / 2, cnt = (int64_t)n * P2;
   AMM_TRY(ctx->scratch[8].reserve(cnt * sizeof(double2)));
   AMM_TRY(ctx->scratch[9].reserve(cnt * sizeof(double2)));
@@ -220,6 +263,10 @@ amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
                                  const float* X, int64_t rows, float* out, bool acc, hipStream_t s) {
   if (rows <= 0) return AMM_OK;
+  if (n >= 3 && n <= kChirpFusedMax) {
+    if (K == 0) return acc ? AMM_OK : fill_f32(out, (int64_t)n * rows, 0.f, s);
+    return cd_chirp_apply(ctx, true, n, K, shifts_adj, Ladj, X, rows, out, acc, s);
+  }
   AMM_TRY(ctx->scratch[12].reserve((size_t)n * rows * sizeof(float)));
   AMM_TRY(ctx->scratch[13].reserve((size_t)n * rows * sizeof(float)));
   float *xt = ctx->scratch[12].as<float>(), *yt = ctx->scratch[13].as<float>();

@@ -1,6 +1,7 @@
 """Circulant decomposition and products for sides that are not powers of two
-(the paper's own examples use n = 700): Bluestein's chirp convolution in
-float64 on the device, against the float64 oracle (which handles any n)."""
+(the paper's own examples use n = 700): Bluestein's chirp convolution on the
+device (float64 decomposition; products in one fused float32 kernel up to
+n = 2048, float64 steps above), against the float64 oracle (any n)."""
 import numpy as np
 import pytest
 
@@ -17,7 +18,8 @@ def _toeplitz(n, seed, noise=0.05):
     return f32(inputs.toeplitz_uniform(n, rng) + noise * rng.standard_normal((n, n)))
 
 
-@pytest.mark.parametrize("n,K,p", [(3, 1, 5), (12, 5, 7), (100, 9, 31), (700, 11, 64), (1000, 32, 100)])
+@pytest.mark.parametrize("n,K,p", [(3, 1, 5), (12, 5, 7), (100, 9, 31), (700, 11, 64), (1000, 32, 100),
+                                   (2047, 20, 3), (2049, 6, 9)])
 def test_anysize_decompose_and_zeroth(n, K, p):
     note(f"circulant any size n={n} K={K} p={p}")
     A = _toeplitz(n, n + K)
@@ -33,7 +35,7 @@ def test_anysize_decompose_and_zeroth(n, K, p):
     assert rel(got, np.real(oc.apply_zeroth(dec, B))) < TOL_F32
 
 
-@pytest.mark.parametrize("n,KA,KB", [(700, 7, 5), (384 + 3, 6, 10)])
+@pytest.mark.parametrize("n,KA,KB", [(700, 7, 5), (384 + 3, 6, 10), (1531, 9, 4)])
 def test_anysize_first_order(n, KA, KB):
     note(f"circulant any size first order n={n}")
     A, B = _toeplitz(n, 1), _toeplitz(n, 2)
