@@ -12,8 +12,10 @@
 // columns of B, two real columns packed into one complex column (the
 // truncated operator is real, hence complex-linear): forward DFT, the
 // spectral multiply-accumulate of the kept shifted spectra, inverse DFT.
-// These sizes are outside the fused single-kernel path; the float64 steps
-// keep the float32 parity bar with room to spare.
+// Up to n = 2048 the product runs instead as one fused float32 kernel (the
+// chirp convolutions in LDS, cd_chirp_kernel) fed by the float32 tables built
+// here; larger sides take the float64 steps, which keep the float32 parity
+// bar with room to spare.
 #include "amm_internal.hpp"
 
 namespace amm {
