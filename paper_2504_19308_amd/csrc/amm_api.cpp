@@ -386,10 +386,9 @@ amm_status amm_ctx_timings(amm_ctx* ctx, char* names, int name_len, double* tota
     auto& acc = t.totals[p.name];
     acc.first += ms;
     acc.second += 1;
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
   }
   t.pending.clear();
+  t.used = 0;   // every pooled event is resolved: reuse them
   *count = (int)t.totals.size();
   if (names || total_ms || launches) {
     if (cap < (int)t.totals.size()) return fail(AMM_EINVAL, "capacity %d < %d", cap, (int)t.totals.size());

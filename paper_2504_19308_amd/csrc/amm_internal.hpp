@@ -61,6 +61,21 @@ struct KernelTimer {
   struct Pending { const char* name; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, long>> totals;  // ms, launches
+  // events are created once and reused, so a timed launch adds two records
+  // and no event creation to the host's launch path
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~KernelTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 extern thread_local KernelTimer* g_timer;
 
@@ -70,9 +85,9 @@ struct TimedLaunch {
   const char* name_;
   TimedLaunch(const char* name, hipStream_t s) : s_(s), name_(name) {
     if (!g_timer) return;
-    hipEvent_t a;
-    if (hipEventCreate(&a) != hipSuccess) return;
-    if (hipEventCreate(&b_) != hipSuccess) { (void)hipEventDestroy(a); b_ = nullptr; return; }
+    hipEvent_t a = g_timer->take();
+    b_ = a ? g_timer->take() : nullptr;
+    if (!b_) return;
     (void)hipEventRecord(a, s_);
     g_timer->pending.push_back({name_, a, b_});
   }
