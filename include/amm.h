@@ -31,8 +31,9 @@
  *     from several streams, but must outlive the work enqueued with it.
  *   - Circulant decompositions take square operands (or square blocks) of
  *     side 2 <= n <= 16384.  Powers of two run the fused single-kernel
- *     product; other sides transform through Bluestein's chirp convolution in
- *     float64 (slower; no float16 lists or batch plans for them).
+ *     product; other sides transform through Bluestein's chirp convolution:
+ *     one fused float32 kernel up to n = 2048, float64 steps above (no
+ *     float16 lists or batch plans for them).
  */
 #ifndef AMM_H
 #define AMM_H
