@@ -45,13 +45,12 @@ __device__ __forceinline__ int xcd_order(int bid, int nblk) {
 
 constexpr int PW = 4;    // waves per panel workgroup
 
-// Load-batch depth of a panel launch: DG 4-row groups (G job) and DH 16-column
-// groups (H job) per batch.  The deep form keeps three batches in registers and
-// issues a batch's loads two batches before its MFMAs (software pipeline); it
-// trades occupancy for loads in flight and is used for ranks 32.
-template <bool DEEP> struct Depth;
-template <> struct Depth<false> { static constexpr int DG = 4, DH = 2; };
-template <> struct Depth<true> { static constexpr int DG = 4, DH = 2; };
+// Load batch of a panel wave: DG 4-row groups (G job) or DH 16-column groups
+// (H job).  The plain form loads a batch and multiplies it; the deep form
+// keeps three batches in registers and issues a batch's loads two batches
+// before its MFMAs (software pipeline), trading occupancy for loads in flight;
+// it is used for ranks 32.
+constexpr int DG = 4, DH = 2;
 
 // G (as Gt, p x KA) partial of split `split`: rows [split*per*PW, ...) of Y
 template <int KA, bool DEEP>
@@ -70,7 +69,6 @@ __device__ __forceinline__ void g_job(const float* __restrict__ X, const float* 
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[i][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  constexpr int DG = Depth<DEEP>::DG;
   auto load = [&](int64_t r, float4(&y)[DG], float(&xv)[DG][IB]) {
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
@@ -159,7 +157,6 @@ __device__ __forceinline__ void h_job(const float* __restrict__ U, const float* 
   for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[bb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  constexpr int DH = Depth<DEEP>::DH;
   auto load = [&](int64_t c0, float4(&a)[DH][4], float(&u)[DH][4][CB]) {
 #pragma unroll
     for (int d = 0; d < DH; ++d) {
@@ -431,7 +428,7 @@ amm_status dispatch_out(int k1, int k2, const float* A1, const float* A2, const 
 // deep (pipelined) panels for rank-32 operands when the reduction length splits
 // into whole deep batches; they want fewer, longer workgroups
 bool use_deep(int64_t n, int ka, int kb) {
-  return ka == 32 && kb <= 32 && n % (PW * 16 * Depth<true>::DH) == 0 && n % (PW * 4 * Depth<true>::DG) == 0;
+  return ka == 32 && kb <= 32 && n % (PW * 16 * DH) == 0 && n % (PW * 4 * DG) == 0;
 }
 
 void plan_splits(int64_t m, int64_t n, int64_t p, int ka, int kb, int* SG, int* SH, bool* deep) {
@@ -441,8 +438,7 @@ void plan_splits(int64_t m, int64_t n, int64_t p, int ka, int kb, int* SG, int* 
   // in flight; doubling the splits measured slower (more partial traffic,
   // shorter pipelines)
   const int target = *deep ? (kb > 0 ? 64 : 128) : 512;
-  const int qg = 4 * (*deep ? Depth<true>::DG : Depth<false>::DG);
-  const int qh = 16 * (*deep ? Depth<true>::DH : Depth<false>::DH);
+  const int qg = 4 * DG, qh = 16 * DH;
   *SG = pick_s(p / 64, n, qg, target);
   *SH = kb > 0 ? pick_s(m / 64, n, qh, target) : 1;
 }
@@ -453,7 +449,7 @@ bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb) {
   const bool ranks = ((ka == 32 || ka == 64) && (kb == 0 || kb == 32 || kb == 64)) ||
                      (ka == 128 && (kb == 0 || kb == 128));
   return ranks && m > 0 && p > 0 && m % OT == 0 &&
-         p % OT == 0 && n % (PW * 16 * Depth<false>::DH) == 0 && n % (PW * 4 * Depth<false>::DG) == 0 && n > 0 &&
+         p % OT == 0 && n % (PW * 16 * DH) == 0 && n % (PW * 4 * DG) == 0 && n > 0 &&
          (m / OT) * (p / OT) < ((int64_t)1 << 31);
 }
 
