@@ -318,6 +318,9 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
+    if only == "tables":
+        res.extend(tables_workload(torch, ctx))
+        return res
     if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz", "sfft"):
         # circulant
         for K in (8, 32, 128):
@@ -373,6 +376,120 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
     if not only or only == "c5":
         res.extend(c5_workload(torch, ctx, tm))
     return res
+
+
+# Components needed for 5 % and 1 % relative error at n = 700, as the paper's
+# Tables 4.1 (truncated SVD) and 4.2 (circulant) report them: s with
+# ceil(s log2 n) components, None where the paper reports none within range.
+# Zeroth order there multiplies the truncations of both operands.
+PAPER_S = {
+    ("Type-1 & Type-1", "svd0"): (5, 7), ("Type-1 & Type-1", "svd1"): (3, 4),
+    ("Type-1 & Toeplitz", "svd0"): (73, None), ("Type-1 & Toeplitz", "svd1"): (4, 6),
+    ("Toeplitz & Toeplitz", "svd0"): (1, 31), ("Toeplitz & Toeplitz", "svd1"): (1, 9),
+    ("Type-2 & Type-2", "svd0"): (27, 67), ("Type-2 & Type-2", "svd1"): (2, 16),
+    ("Kappa & Kappa", "svd0"): (68, 76), ("Kappa & Kappa", "svd1"): (40, 60),
+    ("Kappa & Toeplitz", "svd0"): (69, None), ("Kappa & Toeplitz", "svd1"): (39, 61),
+    ("Type-3 & Toeplitz", "svd0"): (74, None), ("Type-3 & Toeplitz", "svd1"): (56, 69),
+    ("Type-3 & Type-3", "svd0"): (76, None), ("Type-3 & Type-3", "svd1"): (62, 71),
+    ("Toeplitz & Toeplitz", "cd0"): (1, 1), ("Toeplitz & Toeplitz", "cd1"): (1, 1),
+    ("Kappa & Toeplitz", "cd0"): (22, 54), ("Kappa & Toeplitz", "cd1"): (1, 10),
+    ("Kappa & Kappa", "cd0"): (35, 66), ("Kappa & Kappa", "cd1"): (11, 34),
+    ("Type-3 & Toeplitz", "cd0"): (None, None), ("Type-3 & Toeplitz", "cd1"): (5, 41),
+    ("Type-1 & Toeplitz", "cd0"): (None, None), ("Type-1 & Toeplitz", "cd1"): (5, 42),
+    ("Type-2 & Type-2", "cd0"): (76, None), ("Type-2 & Type-2", "cd1"): (59, 74),
+    ("Type-1 & Type-1", "cd0"): (None, None), ("Type-1 & Type-1", "cd1"): (74, 77),
+    ("Type-3 & Type-3", "cd0"): (None, None), ("Type-3 & Type-3", "cd1"): (74, 77),
+}
+
+
+def table_pairs(n, seed=11):
+    """The synthetic operand pairs of the tables, seeded (one instance each)."""
+    from paper_2504_19308_amd import inputs
+    g = lambda j: inputs.rng_of(11, j, seed)
+    T1, T1b = inputs.type1_matrix(n, g(0)), inputs.type1_matrix(n, g(1))
+    T2, T2b = inputs.type2_matrix(n, g(2)), inputs.type2_matrix(n, g(3))
+    T3, T3b = inputs.type3_matrix(n, g(4)), inputs.type3_matrix(n, g(5))
+    To, Tob = inputs.toeplitz_uniform(n, g(6)), inputs.toeplitz_uniform(n, g(7))
+    Ka = inputs.kappa_matrix(n)
+    return {"Type-1 & Type-1": (T1, T1b), "Type-1 & Toeplitz": (T1, To), "Toeplitz & Toeplitz": (To, Tob),
+            "Type-2 & Type-2": (T2, T2b), "Kappa & Kappa": (Ka, Ka), "Kappa & Toeplitz": (Ka, To),
+            "Type-3 & Toeplitz": (T3, To), "Type-3 & Type-3": (T3, T3b)}
+
+
+def components_needed(err, n, tol):
+    """Smallest s with error <= tol when ceil(s log2 n) components of each
+    operand are kept (the tables' unit), by bisection over s (the error falls
+    with the number of components); None if even all n components miss."""
+    l2 = math.log2(n)
+    smax = int(math.ceil(n / l2))
+    K = lambda s_: min(n, int(math.ceil(s_ * l2)))
+    lo, hi = 1, smax
+    if err(K(hi)) > tol:
+        return None
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if err(K(mid)) <= tol:
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo
+
+
+def tables_workload(torch, ctx, n=700):
+    """Tables 4.1 / 4.2 cross-check at n = 700: for each synthetic pair and
+    method, the s needed for 5 % and 1 % error next to the paper's s.  The
+    products run on the device; the circulant decompositions too, the SVD
+    factors come from one host LAPACK SVD per operand, imported and truncated."""
+    rows = []
+    for name, (Ah, Bh) in table_pairs(n).items():
+        A = torch.from_numpy(Ah.astype(np.float32)).cuda()
+        B = torch.from_numpy(Bh.astype(np.float32)).cuda()
+        A64, B64 = Ah.astype(np.float32).astype(np.float64), Bh.astype(np.float32).astype(np.float64)
+        exact = A.double() @ B.double()
+        eye = torch.eye(n, device="cuda", dtype=torch.float32)
+        svd = {}
+        for key, M in (("A", A64), ("B", B64)):
+            U, sv, Vt = np.linalg.svd(M)
+            svd[key] = (U, sv, Vt.T)
+        decs = {}
+
+        def make(kind, K):
+            if (kind, K) not in decs:
+                if kind == "tsvd":
+                    (Ua, sa, Va), (Ub, sb, Vb) = svd["A"], svd["B"]
+                    dA = ctx.import_tsvd(Ua[:, :K], sa[:K], Va[:, :K], A=A)
+                    dB = ctx.import_tsvd(Ub[:, :K], sb[:K], Vb[:, :K], A=B)
+                else:
+                    dA = ctx.decompose(A, "circulant", K)
+                    dB = dA if Ah is Bh else ctx.decompose(B, "circulant", K)
+                decs.clear()
+                decs[(kind, K)] = (dA, dB)
+            return decs[(kind, K)]
+
+        for method in ("svd0", "svd1", "cd0", "cd1"):
+            paper = PAPER_S.get((name, method))
+            if paper is None:
+                continue
+            kind = "tsvd" if method.startswith("svd") else "circulant"
+            cache = {}
+
+            def err(K):
+                if K not in cache:
+                    dA, dB = make(kind, K)
+                    if method.endswith("1"):
+                        M = ctx.approx_matmul(dA, B, dB)
+                    else:
+                        M = ctx.approx_matmul(dA, ctx.approx_matmul(dB, eye))   # truncated A times truncated B
+                    cache[K] = rel_err(M, exact)
+                return cache[K]
+
+            got = [components_needed(err, n, tol) for tol in (0.05, 0.01)]
+            rows.append({"pair": name, "method": method, "s_5pct": got[0], "s_1pct": got[1],
+                         "paper_s_5pct": paper[0], "paper_s_1pct": paper[1]})
+            log(f"[bench] table n={n} {name:20s} {method}: s {got} paper s {list(paper)}")
+        del decs
+        torch.cuda.empty_cache()
+    return [{"name": f"tables 4.1/4.2 cross-check, n = {n}", "rows": rows}]
 
 
 def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):

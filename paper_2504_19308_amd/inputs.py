@@ -243,6 +243,35 @@ def sinusoid_rows(m: int, n: int, rng: np.random.Generator, modes: int = 11, noi
     return A
 
 
+# ---------------------------------------------------------------------------
+# Synthetic classes of the paper's result tables (App. "randomly generated
+# matrices with a given distribution of singular values", Sec. 4.1)
+# ---------------------------------------------------------------------------
+def type1_matrix(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar Q1 diag(exp(-i/10)) Q2^T, i = 0..n-1."""
+    return spectral_matrix(n, n, decay_exp(n, 10.0), rng)
+
+
+def type3_matrix(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar Q1 diag((n - i)/n) Q2^T, i = 0..n-1 (linear decay)."""
+    return spectral_matrix(n, n, (n - np.arange(n, dtype=np.float64)) / n, rng)
+
+
+def type2_matrix(n: int, rng: np.random.Generator) -> np.ndarray:
+    """A Type-1 matrix T plus full-rank noise 0.5 ||T||_F / ||U||_F U, U ~ U(0,1)."""
+    T = type1_matrix(n, rng)
+    U = rng.random((n, n))
+    return T + (0.5 * np.linalg.norm(T) / np.linalg.norm(U)) * U
+
+
+def kappa_matrix(n: int) -> np.ndarray:
+    """Symmetric sign-oscillating matrix exp(-|i - j|/2) sin(i + 1), the sine
+    taken at the larger of the two indices (the lower triangle's row)."""
+    i = np.arange(n)
+    big = np.maximum(i[:, None], i[None, :])
+    return np.exp(-0.5 * np.abs(i[:, None] - i[None, :])) * np.sin(big + 1.0)
+
+
 def workload_toeplitz(n: int) -> Pair:
     A = toeplitz_uniform(n, rng_of(9, 0))
     B = toeplitz_uniform(n, rng_of(9, 1))
