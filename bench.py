@@ -379,7 +379,8 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
 
 
 # Components needed for 5 % and 1 % relative error at n = 700, as the paper's
-# Tables 4.1 (truncated SVD) and 4.2 (circulant) report them: s with
+# Tables 4.1 (truncated SVD), 4.2 (circulant) and 4.3 (S-FFT, first order,
+# ceil(s log2 n) kept entries per row / column) report them: s with
 # ceil(s log2 n) components, None where the paper reports none within range.
 # Zeroth order there multiplies the truncations of both operands.
 PAPER_S = {
@@ -399,6 +400,10 @@ PAPER_S = {
     ("Type-2 & Type-2", "cd0"): (76, None), ("Type-2 & Type-2", "cd1"): (59, 74),
     ("Type-1 & Type-1", "cd0"): (None, None), ("Type-1 & Type-1", "cd1"): (74, 77),
     ("Type-3 & Type-3", "cd0"): (None, None), ("Type-3 & Type-3", "cd1"): (74, 77),
+    ("Toeplitz & Toeplitz", "sfft1"): (1, 5), ("Kappa & Kappa", "sfft1"): (35, 50),
+    ("Type-2 & Type-2", "sfft1"): (29, 52), ("Type-1 & Type-1", "sfft1"): (52, 63),
+    ("Type-3 & Type-3", "sfft1"): (52, 64), ("Kappa & Toeplitz", "sfft1"): (43, 67),
+    ("Type-3 & Toeplitz", "sfft1"): (62, 71), ("Type-1 & Toeplitz", "sfft1"): (63, 71),
 }
 
 
@@ -460,17 +465,17 @@ def tables_workload(torch, ctx, n=700):
                     dA = ctx.import_tsvd(Ua[:, :K], sa[:K], Va[:, :K], A=A)
                     dB = ctx.import_tsvd(Ub[:, :K], sb[:K], Vb[:, :K], A=B)
                 else:
-                    dA = ctx.decompose(A, "circulant", K)
-                    dB = dA if Ah is Bh else ctx.decompose(B, "circulant", K)
+                    dA = ctx.decompose(A, kind, K)
+                    dB = dA if Ah is Bh else ctx.decompose(B, kind, K)
                 decs.clear()
                 decs[(kind, K)] = (dA, dB)
             return decs[(kind, K)]
 
-        for method in ("svd0", "svd1", "cd0", "cd1"):
+        for method in ("svd0", "svd1", "cd0", "cd1", "sfft1"):
             paper = PAPER_S.get((name, method))
             if paper is None:
                 continue
-            kind = "tsvd" if method.startswith("svd") else "circulant"
+            kind = {"svd": "tsvd", "cd": "circulant", "sfft": "sfft"}[method.rstrip("01")]
             cache = {}
 
             def err(K):

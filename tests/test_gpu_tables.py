@@ -1,10 +1,10 @@
-"""Soft cross-check of the circulant rows of Table 4.2 at n = 700 on the
-device: the number of components (as s with ceil(s log2 n) kept frequencies
-per operand) that first-order and zeroth-order circulant products need for
-5 % and 1 % relative error, against the values the paper reports for the
-synthetic pairs whose generators it fully specifies.  One seeded instance per
-pair, where the paper averages several, so agreement is asked within
-max(1, 15 %) of the paper's s."""
+"""Soft cross-check of Tables 4.2 (circulant) and 4.3 (S-FFT) at n = 700 on
+the device: the number of components (as s with ceil(s log2 n) kept
+frequencies per operand, or kept entries per row / column for S-FFT) that the
+products need for 5 % and 1 % relative error, against the values the paper
+reports for synthetic pairs whose generators it fully specifies.  One seeded
+instance per pair, where the paper averages several, so agreement is asked
+within max(1, 15 %) of the paper's s."""
 import math
 
 import numpy as np
@@ -17,12 +17,14 @@ pytestmark = pytest.mark.gpu
 
 N = 700
 
-# (pair, order): (s for 5 %, s for 1 %), Table 4.2
+# (pair, kind, order): (s for 5 %, s for 1 %), Tables 4.2 and 4.3
 PAPER = {
-    ("Toeplitz & Toeplitz", 0): (1, 1), ("Toeplitz & Toeplitz", 1): (1, 1),
-    ("Kappa & Toeplitz", 0): (22, 54), ("Kappa & Toeplitz", 1): (1, 10),
-    ("Kappa & Kappa", 1): (11, 34),
-    ("Type-3 & Toeplitz", 1): (5, 41),
+    ("Toeplitz & Toeplitz", "circulant", 0): (1, 1), ("Toeplitz & Toeplitz", "circulant", 1): (1, 1),
+    ("Kappa & Toeplitz", "circulant", 0): (22, 54), ("Kappa & Toeplitz", "circulant", 1): (1, 10),
+    ("Kappa & Kappa", "circulant", 1): (11, 34),
+    ("Type-3 & Toeplitz", "circulant", 1): (5, 41),
+    ("Toeplitz & Toeplitz", "sfft", 1): (1, 5), ("Type-1 & Type-1", "sfft", 1): (52, 63),
+    ("Type-2 & Type-2", "sfft", 1): (29, 52), ("Type-3 & Type-3", "sfft", 1): (52, 64),
 }
 
 
@@ -36,6 +38,12 @@ def _pair(name):
     if name == "Kappa & Kappa":
         K = inputs.kappa_matrix(N)
         return K, K
+    if name == "Type-1 & Type-1":
+        return inputs.type1_matrix(N, g(0)), inputs.type1_matrix(N, g(1))
+    if name == "Type-2 & Type-2":
+        return inputs.type2_matrix(N, g(2)), inputs.type2_matrix(N, g(3))
+    if name == "Type-3 & Type-3":
+        return inputs.type3_matrix(N, g(4)), inputs.type3_matrix(N, g(5))
     return inputs.type3_matrix(N, g(4)), To
 
 
@@ -53,10 +61,10 @@ def _s_needed(err, tol):
     return lo
 
 
-@pytest.mark.parametrize("name,order", sorted(PAPER))
-def test_table_4_2_components(name, order):
+@pytest.mark.parametrize("name,kind,order", sorted(PAPER))
+def test_table_components(name, kind, order):
     torch = torch_cuda()
-    note(f"table 4.2 n={N} {name} order {order}")
+    note(f"tables n={N} {name} {kind} order {order}")
     Ah, Bh = _pair(name)
     A = torch.from_numpy(Ah.astype(np.float32)).cuda()
     B = torch.from_numpy(Bh.astype(np.float32)).cuda()
@@ -67,14 +75,14 @@ def test_table_4_2_components(name, order):
 
     def err(K):
         if K not in cache:
-            dA = c.decompose(A, "circulant", K)
-            dB = c.decompose(B, "circulant", K)
+            dA = c.decompose(A, kind, K)
+            dB = c.decompose(B, kind, K)
             M = c.approx_matmul(dA, B, dB) if order == 1 else c.approx_matmul(dA, c.approx_matmul(dB, eye))
             cache[K] = float((M.double() - exact).norm() / exact.norm())
         return cache[K]
 
     got = [_s_needed(err, tol) for tol in (0.05, 0.01)]
-    want = PAPER[(name, order)]
+    want = PAPER[(name, kind, order)]
     note(f"  s {got} paper {list(want)}")
     for g_, w in zip(got, want):
         assert abs(g_ - w) <= max(1, math.ceil(0.15 * w))
