@@ -320,6 +320,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
 
     if only == "tables":
         res.extend(tables_workload(torch, ctx))
+        res.append(figures_workload(torch, ctx))
         return res
     if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz", "sfft"):
         # circulant
@@ -495,6 +496,32 @@ def tables_workload(torch, ctx, n=700):
         del decs
         torch.cuda.empty_cache()
     return [{"name": f"tables 4.1/4.2 cross-check, n = {n}", "rows": rows}]
+
+
+def figures_workload(torch, ctx, sizes=(128, 256, 512, 1024, 2048)):
+    """Figs. 4.1 / 4.2 on the device: relative error of the first-order SVD
+    product of two independent Type-1 (then Type-2) matrices with
+    5 ceil(log2 n) components, decomposed on the device, next to the a priori
+    (Thm. 3.6) and posterior (Cor. 3.7) estimates, over n."""
+    from paper_2504_19308_amd import inputs
+    rows = []
+    for cls, gen in (("Type-1", inputs.type1_matrix), ("Type-2", inputs.type2_matrix)):
+        for n in sizes:
+            g = lambda j: inputs.rng_of(12, j, n)
+            Ah, Bh = gen(n, g(0)), gen(n, g(1))
+            A = torch.from_numpy(Ah.astype(np.float32)).cuda()
+            B = torch.from_numpy(Bh.astype(np.float32)).cuda()
+            K = 5 * int(math.ceil(math.log2(n)))
+            dA = ctx.decompose(A, "tsvd", K)
+            dB = ctx.decompose(B, "tsvd", K)
+            M = ctx.approx_matmul(dA, B, dB)
+            actual = rel_err(M, A.double() @ B.double())
+            est = ctx.estimate_error(dA, dB, M)
+            rows.append({"class": cls, "n": n, "K": K, "actual": actual, "prior": est["prior"],
+                         "posterior": est["posterior"]})
+            log(f"[bench] figure {cls} n={n} K={K}: actual {actual:.3e} prior {est['prior']:.3e} "
+                f"posterior {est['posterior']:.3e}")
+    return {"name": "figures 4.1/4.2: first-order SVD error and estimates over n", "rows": rows}
 
 
 def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):
