@@ -405,6 +405,9 @@ PAPER_S = {
     ("Type-2 & Type-2", "sfft1"): (29, 52), ("Type-1 & Type-1", "sfft1"): (52, 63),
     ("Type-3 & Type-3", "sfft1"): (52, 64), ("Kappa & Toeplitz", "sfft1"): (43, 67),
     ("Type-3 & Toeplitz", "sfft1"): (62, 71), ("Type-1 & Toeplitz", "sfft1"): (63, 71),
+    ("General & Toeplitz", "cd0"): (1, 66), ("General & Toeplitz", "cd1"): (1, 1),
+    ("General & General", "cd0"): (1, 71), ("General & General", "cd1"): (1, 16),
+    ("General & Toeplitz", "sfft1"): (1, 6), ("General & General", "sfft1"): (1, 5),
 }
 
 
@@ -417,7 +420,8 @@ def table_pairs(n, seed=11):
     T3, T3b = inputs.type3_matrix(n, g(4)), inputs.type3_matrix(n, g(5))
     To, Tob = inputs.toeplitz_uniform(n, g(6)), inputs.toeplitz_uniform(n, g(7))
     Ka = inputs.kappa_matrix(n)
-    return {"Type-1 & Type-1": (T1, T1b), "Type-1 & Toeplitz": (T1, To), "Toeplitz & Toeplitz": (To, Tob),
+    Ge, Geb = inputs.general_uniform(n, g(8)), inputs.general_uniform(n, g(9))
+    return {"General & Toeplitz": (Ge, To), "General & General": (Ge, Geb),"Type-1 & Type-1": (T1, T1b), "Type-1 & Toeplitz": (T1, To), "Toeplitz & Toeplitz": (To, Tob),
             "Type-2 & Type-2": (T2, T2b), "Kappa & Kappa": (Ka, Ka), "Kappa & Toeplitz": (Ka, To),
             "Type-3 & Toeplitz": (T3, To), "Type-3 & Type-3": (T3, T3b)}
 
@@ -499,10 +503,12 @@ def tables_workload(torch, ctx, n=700):
 
 
 def figures_workload(torch, ctx, sizes=(128, 256, 512, 1024, 2048)):
-    """Figs. 4.1 / 4.2 on the device: relative error of the first-order SVD
-    product of two independent Type-1 (then Type-2) matrices with
-    5 ceil(log2 n) components, decomposed on the device, next to the a priori
-    (Thm. 3.6) and posterior (Cor. 3.7) estimates, over n."""
+    """Figs. 4.1-4.6 on the device: relative error over n of first-order
+    products with 5 ceil(log2 n) components, decomposed on the device: SVD for
+    two independent Type-1 (then Type-2) matrices, circulant and S-FFT for a
+    U(0,1) general matrix times a U(0,1) Toeplitz one (then two general
+    ones), with the a priori (Thm. 3.6) and posterior (Cor. 3.7) estimates
+    for the SVD and circulant products."""
     from paper_2504_19308_amd import inputs
     rows = []
     for cls, gen in (("Type-1", inputs.type1_matrix), ("Type-2", inputs.type2_matrix)):
@@ -521,7 +527,30 @@ def figures_workload(torch, ctx, sizes=(128, 256, 512, 1024, 2048)):
                          "posterior": est["posterior"]})
             log(f"[bench] figure {cls} n={n} K={K}: actual {actual:.3e} prior {est['prior']:.3e} "
                 f"posterior {est['posterior']:.3e}")
-    return {"name": "figures 4.1/4.2: first-order SVD error and estimates over n", "rows": rows}
+    # Figs. 4.3-4.6: U(0,1) general times U(0,1) Toeplitz, and two U(0,1)
+    # general matrices, 5 ceil(log2 n) circulant components / S-FFT entries
+    for pair in ("General & Toeplitz", "General & General"):
+        for n in sizes:
+            g = lambda j: inputs.rng_of(13, j, n)
+            Ah = inputs.general_uniform(n, g(0))
+            Bh = inputs.toeplitz_uniform(n, g(1)) if pair.endswith("Toeplitz") else inputs.general_uniform(n, g(1))
+            A = torch.from_numpy(Ah.astype(np.float32)).cuda()
+            B = torch.from_numpy(Bh.astype(np.float32)).cuda()
+            exact = A.double() @ B.double()
+            K = 5 * int(math.ceil(math.log2(n)))
+            for kind in ("circulant", "sfft"):
+                dA = ctx.decompose(A, kind, K)
+                dB = ctx.decompose(B, kind, K)
+                M = ctx.approx_matmul(dA, B, dB)
+                row = {"class": pair, "kind": kind, "n": n, "K": K, "actual": rel_err(M, exact)}
+                msg = f"[bench] figure {pair} {kind} n={n} K={K}: actual {row['actual']:.3e}"
+                if kind == "circulant":
+                    est = ctx.estimate_error(dA, dB, M, entries="unsigned_uniform")
+                    row.update(prior=est["prior"], posterior=est["posterior"])
+                    msg += f" prior {est['prior']:.3e} posterior {est['posterior']:.3e}"
+                rows.append(row)
+                log(msg)
+    return {"name": "figures 4.1-4.6: first-order error and estimates over n", "rows": rows}
 
 
 def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):

@@ -264,6 +264,11 @@ def type2_matrix(n: int, rng: np.random.Generator) -> np.ndarray:
     return T + (0.5 * np.linalg.norm(T) / np.linalg.norm(U)) * U
 
 
+def general_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
+    """'General' matrix of the result figures: i.i.d. U(0,1) entries."""
+    return rng.random((n, n))
+
+
 def kappa_matrix(n: int) -> np.ndarray:
     """Symmetric sign-oscillating matrix exp(-|i - j|/2) sin(i + 1), the sine
     taken at the larger of the two indices (the lower triangle's row)."""

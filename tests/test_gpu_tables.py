@@ -25,6 +25,7 @@ PAPER = {
     ("Type-3 & Toeplitz", "circulant", 1): (5, 41),
     ("Toeplitz & Toeplitz", "sfft", 1): (1, 5), ("Type-1 & Type-1", "sfft", 1): (52, 63),
     ("Type-2 & Type-2", "sfft", 1): (29, 52), ("Type-3 & Type-3", "sfft", 1): (52, 64),
+    ("General & General", "circulant", 1): (1, 16), ("General & Toeplitz", "sfft", 1): (1, 6),
 }
 
 
@@ -33,6 +34,10 @@ def _pair(name):
     To, Tob = inputs.toeplitz_uniform(N, g(6)), inputs.toeplitz_uniform(N, g(7))
     if name == "Toeplitz & Toeplitz":
         return To, Tob
+    if name == "General & General":
+        return inputs.general_uniform(N, g(8)), inputs.general_uniform(N, g(9))
+    if name == "General & Toeplitz":
+        return inputs.general_uniform(N, g(8)), To
     if name == "Kappa & Toeplitz":
         return inputs.kappa_matrix(N), To
     if name == "Kappa & Kappa":
