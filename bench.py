@@ -408,6 +408,19 @@ PAPER_S = {
     ("General & Toeplitz", "cd0"): (1, 66), ("General & Toeplitz", "cd1"): (1, 1),
     ("General & General", "cd0"): (1, 71), ("General & General", "cd1"): (1, 16),
     ("General & Toeplitz", "sfft1"): (1, 6), ("General & General", "sfft1"): (1, 5),
+    ("Symmetric & Toeplitz", "svd0"): (1, 1), ("Symmetric & Toeplitz", "svd1"): (1, 1),
+    ("Symmetric & Symmetric", "svd0"): (1, 1), ("Symmetric & Symmetric", "svd1"): (1, 1),
+    ("Symmetric & Hankel", "svd0"): (1, 1), ("Symmetric & Hankel", "svd1"): (1, 1),
+    ("General & Symmetric", "svd0"): (1, 1), ("General & Symmetric", "svd1"): (1, 1),
+    ("Symmetric & Toeplitz", "cd0"): (1, 53), ("Symmetric & Toeplitz", "cd1"): (1, 1),
+    ("Symmetric & Symmetric", "cd0"): (1, 63), ("Symmetric & Symmetric", "cd1"): (1, 1),
+    ("Symmetric & Hankel", "cd0"): (1, 59), ("Symmetric & Hankel", "cd1"): (1, 1),
+    ("General & Symmetric", "cd0"): (1, 68), ("General & Symmetric", "cd1"): (1, 1),
+    ("Hankel & Hankel", "svd0"): (1, 31), ("Hankel & Hankel", "svd1"): (1, 9),
+    ("Hankel & Hankel", "cd0"): (1, 54), ("Hankel & Hankel", "cd1"): (1, 5),
+    ("Symmetric & Toeplitz", "sfft1"): (1, 1), ("Symmetric & Symmetric", "sfft1"): (1, 1),
+    ("Symmetric & Hankel", "sfft1"): (1, 1), ("General & Symmetric", "sfft1"): (1, 1),
+    ("Hankel & Hankel", "sfft1"): (1, 6),
 }
 
 
@@ -421,7 +434,11 @@ def table_pairs(n, seed=11):
     To, Tob = inputs.toeplitz_uniform(n, g(6)), inputs.toeplitz_uniform(n, g(7))
     Ka = inputs.kappa_matrix(n)
     Ge, Geb = inputs.general_uniform(n, g(8)), inputs.general_uniform(n, g(9))
-    return {"General & Toeplitz": (Ge, To), "General & General": (Ge, Geb),"Type-1 & Type-1": (T1, T1b), "Type-1 & Toeplitz": (T1, To), "Toeplitz & Toeplitz": (To, Tob),
+    Sy, Syb = inputs.symmetric_uniform(n, g(10)), inputs.symmetric_uniform(n, g(11))
+    Ha, Hab = inputs.hankel_uniform(n, g(12)), inputs.hankel_uniform(n, g(13))
+    return {"Symmetric & Toeplitz": (Sy, To), "Symmetric & Symmetric": (Sy, Syb), "Symmetric & Hankel": (Sy, Ha),
+            "General & Symmetric": (Ge, Sy), "Hankel & Hankel": (Ha, Hab),
+            "General & Toeplitz": (Ge, To), "General & General": (Ge, Geb),"Type-1 & Type-1": (T1, T1b), "Type-1 & Toeplitz": (T1, To), "Toeplitz & Toeplitz": (To, Tob),
             "Type-2 & Type-2": (T2, T2b), "Kappa & Kappa": (Ka, Ka), "Kappa & Toeplitz": (Ka, To),
             "Type-3 & Toeplitz": (T3, To), "Type-3 & Type-3": (T3, T3b)}
 

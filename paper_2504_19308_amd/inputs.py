@@ -269,6 +269,19 @@ def general_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
     return rng.random((n, n))
 
 
+def symmetric_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Random symmetric matrix (U + U^T) / 2, U with i.i.d. U(0,1) entries."""
+    U = rng.random((n, n))
+    return 0.5 * (U + U.T)
+
+
+def hankel_uniform(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Hankel matrix from 2n-1 U(0,1) values: H[i,j] = v[i+j]."""
+    v = rng.random(2 * n - 1)
+    i = np.arange(n)
+    return v[i[:, None] + i[None, :]]
+
+
 def kappa_matrix(n: int) -> np.ndarray:
     """Symmetric sign-oscillating matrix exp(-|i - j|/2) sin(i + 1), the sine
     taken at the larger of the two indices (the lower triangle's row)."""

@@ -26,6 +26,8 @@ PAPER = {
     ("Toeplitz & Toeplitz", "sfft", 1): (1, 5), ("Type-1 & Type-1", "sfft", 1): (52, 63),
     ("Type-2 & Type-2", "sfft", 1): (29, 52), ("Type-3 & Type-3", "sfft", 1): (52, 64),
     ("General & General", "circulant", 1): (1, 16), ("General & Toeplitz", "sfft", 1): (1, 6),
+    ("Symmetric & Toeplitz", "circulant", 0): (1, 53), ("Symmetric & Symmetric", "circulant", 0): (1, 63),
+    ("General & Symmetric", "sfft", 1): (1, 1),
 }
 
 
@@ -38,6 +40,12 @@ def _pair(name):
         return inputs.general_uniform(N, g(8)), inputs.general_uniform(N, g(9))
     if name == "General & Toeplitz":
         return inputs.general_uniform(N, g(8)), To
+    if name == "Symmetric & Toeplitz":
+        return inputs.symmetric_uniform(N, g(10)), To
+    if name == "Symmetric & Symmetric":
+        return inputs.symmetric_uniform(N, g(10)), inputs.symmetric_uniform(N, g(11))
+    if name == "General & Symmetric":
+        return inputs.general_uniform(N, g(8)), inputs.symmetric_uniform(N, g(10))
     if name == "Kappa & Toeplitz":
         return inputs.kappa_matrix(N), To
     if name == "Kappa & Kappa":

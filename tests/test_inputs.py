@@ -39,3 +39,10 @@ def test_toeplitz_structure_and_seeding():
     a = inputs.type1_matrix(16, inputs.rng_of(11, 0, 11))
     b = inputs.type1_matrix(16, inputs.rng_of(11, 0, 11))
     assert np.array_equal(a, b)
+
+
+def test_symmetric_and_hankel():
+    S = inputs.symmetric_uniform(8, np.random.default_rng(5))
+    assert np.array_equal(S, S.T) and S.min() >= 0 and S.max() < 1
+    H = inputs.hankel_uniform(8, np.random.default_rng(6))
+    assert np.allclose(H[1:, :-1], H[:-1, 1:])
