@@ -33,7 +33,7 @@
  *     side 2 <= n <= 16384.  Powers of two run the fused single-kernel
  *     product; other sides transform through Bluestein's chirp convolution:
  *     one fused float32 kernel up to n = 2048, float64 steps above (no
- *     float16 lists or batch plans for them).
+ *     float16 lists for them; batch plans up to 2048).
  */
 #ifndef AMM_H
 #define AMM_H
@@ -249,8 +249,9 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
  * keeps the fastest, and captures the two launches in a HIP graph.
  * Circulant handles (square, or rectangular in square blocks; any mix of
  * sizes) plan instead the fused product launch(es) of each entry, with
- * plan-owned scratch and all twiddle tables created up front, captured in
- * one HIP graph. */
+ * plan-owned scratch and all twiddle (and chirp) tables created up front,
+ * captured in one HIP graph; their sides are powers of two or at most 2048
+ * (AMM_EUNSUPPORTED otherwise). */
 amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA,
                                  const float* const* B, const int64_t* p, float* const* out,
                                  void* stream, amm_batch_plan** plan);

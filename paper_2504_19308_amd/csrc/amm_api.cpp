@@ -1027,6 +1027,9 @@ amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
       AMM_TRY(blocked_apply(bp->ctx, d, it.B, it.p, it.out, bp->partials.as<float>(), s));
     } else if (d->K_eff == 0) {
       AMM_TRY(fill_f32(it.out, it.m * it.p, 0.f, s));
+    } else if (!is_pow2(d->n)) {
+      AMM_TRY(cd_chirp_apply(bp->ctx, false, (int)d->n, d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
+                             it.p, it.out, false, s));
     } else {
       AMM_TRY(cd_apply_columns(bp->ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
                                it.p, it.out, false, s, d->pairs_of(false), d->lists16(false)));
@@ -1117,7 +1120,9 @@ amm_status plan_check(int count, const amm_dec* const* dA, const void* const* B,
     if (!bf16 && d->kind == AMM_CIRCULANT && dA[0]->kind == AMM_CIRCULANT) {
       if (p[i] <= 0) return fail(AMM_ESHAPE, "entry %d has no columns", i);
       const int64_t side = d->blocks.empty() ? d->n : std::min(d->m, d->n);
-      if (!is_pow2(side)) return fail(AMM_EUNSUPPORTED, "entry %d: circulant plans need power-of-two sides", i);
+      if (!is_pow2(side) && !(side >= 3 && side <= kChirpFusedMax))
+        return fail(AMM_EUNSUPPORTED, "entry %d: circulant plans need power-of-two sides or sides up to %d", i,
+                    kChirpFusedMax);
       continue;
     }
     if (d->kind != AMM_TSVD || dA[0]->kind != AMM_TSVD)
@@ -1158,7 +1163,16 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
       const int64_t sd = d->blocks.empty() ? d->n : std::min(d->m, d->n);
       if (!d->blocks.empty()) scratch = std::max(scratch, (size_t)sd * p[i]);
       const float2* tw = nullptr;
-      amm_status st = twiddles32(ctx, log2_exact(sd), &tw);
+      amm_status st;
+      if (is_pow2(sd)) {
+        st = twiddles32(ctx, log2_exact(sd), &tw);
+      } else {   // the fused chirp-convolution kernel: its twiddles and chirp tables
+        int lM = 0;
+        while ((int64_t(1) << lM) < 2 * sd - 1) ++lM;
+        const float2* tab = nullptr;
+        st = twiddles32(ctx, lM, &tw);
+        if (st == AMM_OK) st = chirp_tables32(ctx, (int)sd, (hipStream_t)stream, &tab);
+      }
       if (st != AMM_OK) {
         delete bp;
         return st;

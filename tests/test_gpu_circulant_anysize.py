@@ -8,7 +8,7 @@ import pytest
 from oracle import circulant as oc
 from oracle import product as op
 from paper_2504_19308_amd import inputs
-from tests._gpu_common import TOL_F32, ctx, f32, gpu, host, note, rel
+from tests._gpu_common import TOL_F32, ctx, f32, gpu, host, note, rel, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -68,8 +68,7 @@ def test_anysize_full_expansion_and_blocks():
     assert rel(host(c.approx_matmul(db, gpu(Bb))), oc.apply_blocked(dec, Bb)) < TOL_F32
 
 
-def test_anysize_mu_and_plan_rejection():
-    from paper_2504_19308_amd import AmmError
+def test_anysize_mu():
     from oracle import estimators as oe
     n = 300
     A = _toeplitz(n, 9)
@@ -77,6 +76,41 @@ def test_anysize_mu_and_plan_rejection():
     c = ctx()
     d = c.decompose(gpu(A), "circulant", 5)
     assert abs(d.info()["mu"] - oe.cd_mu(dec)) <= 1e-9 * oe.cd_mu(dec)
-    B = gpu(np.ones((n, 8)))
+
+
+def test_anysize_batch_plan():
+    """Plans take sides up to 2048 that are not powers of two (the fused
+    kernel; square and blocked entries mixed with a power of two); graph
+    replays equal the eager run and the oracle; a side of 2049 is rejected."""
+    from paper_2504_19308_amd import AmmError
+    torch = torch_cuda()
+    c = ctx()
+    cases = [(300, 300, 5, 24), (700, 300, 4, 9), (256, 256, 6, 16), (1000, 1000, 9, 31)]
+    decs, Bs, wants = [], [], []
+    for i, (m, n, K, p) in enumerate(cases):
+        rng = np.random.default_rng(80 + i)
+        A = f32(inputs.toeplitz_uniform(max(m, n), rng)[:m, :n] + 0.05 * rng.standard_normal((m, n)))
+        B = f32(rng.standard_normal((n, p)))
+        decs.append(c.decompose(gpu(A), "circulant", K))
+        Bs.append(gpu(B))
+        if m == n:
+            wants.append(np.real(oc.apply_zeroth(oc.CirculantDecomp(A, K), B)))
+        else:
+            wants.append(oc.apply_blocked(oc.BlockedCirculant(A, K), B))
+    plan = c.batch_plan(decs, Bs)
+    eager = [o.clone() for o in plan.run(use_graph=False)]
+    torch.cuda.synchronize()
+    for o, w in zip(eager, wants):
+        assert rel(host(o), w) < TOL_F32
+    for rep in range(3):
+        for o in plan.outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run(use_graph=True)
+        torch.cuda.synchronize()
+        for o, e in zip(plan.outs, eager):
+            assert torch.equal(o, e), f"replay {rep} differs"
+    n = 2049
+    d = c.decompose(gpu(_toeplitz(n, 3)), "circulant", 3)
     with pytest.raises(AmmError):
-        c.batch_plan([d], [B])
+        c.batch_plan([d], [gpu(np.ones((n, 4)))])
