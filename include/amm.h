@@ -32,8 +32,8 @@
  *   - Circulant decompositions take square operands (or square blocks) of
  *     side 2 <= n <= 16384.  Powers of two run the fused single-kernel
  *     product; other sides transform through Bluestein's chirp convolution:
- *     one fused float32 kernel up to n = 2048, float64 steps above (no
- *     float16 lists for them; batch plans up to 2048).
+ *     one fused float32 kernel up to n = 2048 (float16 lists and batch
+ *     plans included), float64 steps above.
  */
 #ifndef AMM_H
 #define AMM_H
@@ -71,10 +71,11 @@ typedef struct {
   uint64_t seed;       /* AMM_TSVD: counter-based sketch seed (Philox4x32-10) */
   int keep_residual;   /* keep Delta A on the device so that this handle can
                           be the left operand of a first-order product */
-  int spectral_fp16;   /* AMM_CIRCULANT with n >= 1024: store the eigenvalue
-                          lists the products use as float16 (half the list
-                          traffic; each multiplier rounded to 2^-11 relative),
-                          products and sums stay float32 (default 0) */
+  int spectral_fp16;   /* AMM_CIRCULANT with n >= 1024 (a power of two, or at
+                          most 2048): store the eigenvalue lists the products
+                          use as float16 (half the list traffic; each
+                          multiplier rounded to 2^-11 relative), products and
+                          sums stay float32 (default 0) */
 } amm_opts;
 
 /* Fill `o` with the defaults (frac 0.01, nnz -1, oversample 16, power 2,

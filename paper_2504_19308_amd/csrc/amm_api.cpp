@@ -89,7 +89,8 @@ amm_status circ_columns(amm_ctx* ctx, const amm_dec* b, const float* B, int64_t 
   if (is_pow2(b->n))
     return cd_apply_columns(ctx, log2_exact(b->n), b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc,
                             s, b->pairs_of(false), b->lists16(false));
-  return cd_apply_general(ctx, (int)b->n, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc, s);
+  return cd_apply_general(ctx, (int)b->n, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc, s,
+                          b->lists16(false));
 }
 
 // exp(-2 pi i m / n) with the angle reduced to the first octant, so every entry
@@ -271,7 +272,7 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
     }
     if (!is_pow2(d->n))
       return cd_apply_rows_general(ctx, (int)d->n, d->K_eff, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), X,
-                                   rows, out, acc, s);
+                                   rows, out, acc, s, d->lists16(true));
     return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
                          d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true), d->lists16(true));
   }
@@ -1029,7 +1030,7 @@ amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
       AMM_TRY(fill_f32(it.out, it.m * it.p, 0.f, s));
     } else if (!is_pow2(d->n)) {
       AMM_TRY(cd_chirp_apply(bp->ctx, false, (int)d->n, d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
-                             it.p, it.out, false, s));
+                             it.p, it.out, false, s, d->lists16(false)));
     } else {
       AMM_TRY(cd_apply_columns(bp->ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
                                it.p, it.out, false, s, d->pairs_of(false), d->lists16(false)));

@@ -280,13 +280,16 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
 constexpr int kChirpFusedMax = 2048;
 // [ch (n) | H_fwd / M (M) | H_inv / M (M)] in float32, M = 2^ceil(log2(2n - 1)), cached per n
 amm_status chirp_tables32(amm_ctx* ctx, int n, hipStream_t s, const float2** tab);
+// L16 (optional, n >= 1024): the lists as float16 pairs, used instead of L
 amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
-                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s);
+                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s,
+                          const __half2* L16 = nullptr);
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
-                            int64_t p, float* out, bool acc, hipStream_t s);
+                            int64_t p, float* out, bool acc, hipStream_t s, const __half2* L16 = nullptr);
 amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s);
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
-                                 const float* X, int64_t rows, float* out, bool acc, hipStream_t s);
+                                 const float* X, int64_t rows, float* out, bool acc, hipStream_t s,
+                                 const __half2* Ladj16 = nullptr);
 
 // Float64 Stockham FFT over `batch` vectors of length 2^log2n (element e of
 // vector b at b*bs + e*es); sign -1: exp(-2 pi i jk/n), +1: its conjugate;

@@ -373,10 +373,10 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 // mod n) and the inverse DFT (conjugate chirp, its own H, 1/n) run in one
 // kernel per tile of 2C real columns (or rows), as cd_apply_kernel does for
 // powers of two.  tab = [ch (n) | H_fwd / M (M) | H_inv / M (M)].
-template <int LOG2M, bool ROWS>
+template <int LOG2M, bool ROWS, bool H16>
 __global__ void __launch_bounds__(CdCfg<LOG2M>::T)
 cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent, int n, int K,
-                const int32_t* __restrict__ shifts, const float2* __restrict__ L, const float2* __restrict__ tab,
+                const int32_t* __restrict__ shifts, const void* __restrict__ L, const float2* __restrict__ tab,
                 const float2* __restrict__ tw, int accumulate) {
   using Cfg = CdCfg<LOG2M>;
   constexpr int M = Cfg::N, C = Cfg::C, T = Cfg::T;
@@ -445,7 +445,7 @@ cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
     for (int i = 0; i < NB; ++i) {
       const int p = bl + i * BL;
       if (p < n) {
-        const float2 l = L[Lt + p];
+        const float2 l = list_at<H16>(L, Lt + p);
         int q = p - k;
         if (q < 0) q += n;
         const float2* src = &lds[pad_bin(q) * C + cg * CPL];
@@ -503,18 +503,30 @@ cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 
 template <int LOG2M>
 amm_status launch_chirp(bool rows, const float* X, float* out, int64_t extent, int n, int K, const int32_t* shifts,
-                        const float2* L, const float2* tab, const float2* tw, bool acc, hipStream_t s) {
+                        const void* L, bool h16, const float2* tab, const float2* tw, bool acc, hipStream_t s) {
   using Cfg = CdCfg<LOG2M>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
   if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
   TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
-  if (rows)
-    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true>), dim3((unsigned)tiles), dim3(Cfg::T), 0, s, X, out, extent, n, K,
-                       shifts, L, tab, tw, acc ? 1 : 0);
+  const dim3 grid((unsigned)tiles), block(Cfg::T);
+  if (h16) {
+    if constexpr (LOG2M >= 12) {   // float16 lists: n > 1024
+      if (rows)
+        hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true, true>), grid, block, 0, s, X, out, extent, n, K, shifts, L,
+                           tab, tw, acc ? 1 : 0);
+      else
+        hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false, true>), grid, block, 0, s, X, out, extent, n, K, shifts, L,
+                           tab, tw, acc ? 1 : 0);
+    } else {
+      return fail(AMM_EUNSUPPORTED, "float16 lists need n >= 1024");
+    }
+  } else if (rows)
+    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true, false>), grid, block, 0, s, X, out, extent, n, K, shifts, L, tab,
+                       tw, acc ? 1 : 0);
   else
-    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false>), dim3((unsigned)tiles), dim3(Cfg::T), 0, s, X, out, extent, n,
-                       K, shifts, L, tab, tw, acc ? 1 : 0);
+    hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false, false>), grid, block, 0, s, X, out, extent, n, K, shifts, L, tab,
+                       tw, acc ? 1 : 0);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -592,7 +604,8 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 // rows = false: out (n x extent) (+)= Atil X for X n x extent; rows = true:
 // out (extent x n) (+)= the operator applied to each row of X (extent x n).
 amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
-                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s) {
+                          const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s,
+                          const __half2* L16) {
   if (n < 3 || n > kChirpFusedMax) return fail(AMM_EUNSUPPORTED, "fused chirp product needs 3 <= n <= %d", kChirpFusedMax);
   int lM = 0;
   while ((1 << lM) < 2 * n - 1) ++lM;
@@ -602,7 +615,8 @@ amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* 
   AMM_TRY(twiddles32(ctx, lM, &tw));
   switch (lM) {
 #define AMM_CASE(L2) \
-  case L2: return launch_chirp<L2>(rows, X, out, extent, n, K, shifts, L, tab, tw, accumulate, s);
+  case L2: return launch_chirp<L2>(rows, X, out, extent, n, K, shifts, L16 ? (const void*)L16 : (const void*)L, \
+                                   L16 != nullptr, tab, tw, accumulate, s);
     AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6) AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10)
     AMM_CASE(11) AMM_CASE(12)
 #undef AMM_CASE

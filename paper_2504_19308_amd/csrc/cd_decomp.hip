@@ -337,7 +337,7 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_re
     AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
     AMM_HIP(hipStreamSynchronize(s));
     AMM_TRY(cd_build_pairs(dec, Lh));
-    if (fp16 && pow2 && log2n >= 10) {
+    if (fp16 && n >= 1024 && (pow2 || n <= kChirpFusedMax)) {
       const int64_t cnt = (int64_t)Ke * n;
       AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
       AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));

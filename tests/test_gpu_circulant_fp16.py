@@ -106,7 +106,7 @@ def test_fp16_grid_first_order():
     assert rel(got, want) < TOL_F32
 
 
-@pytest.mark.parametrize("n,K", [(1024, 9), (4096, 32)])
+@pytest.mark.parametrize("n,K", [(1024, 9), (4096, 32), (1500, 12)])
 def test_fp16_general_operand_bound(n, K):
     note(f"fp16 general operand n={n} K={K}")
     from paper_2504_19308_amd import inputs
