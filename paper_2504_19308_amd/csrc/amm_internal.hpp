@@ -115,6 +115,7 @@ struct amm_ctx {
   amm::DevBuf scratch[14];             // grow-only work areas for products (8-13: chirp-convolution path)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
+  amm::DevBuf rsvd[10];                     // grow-only float64 work areas of the randomized SVD
   amm::KernelTimer timer;
   bool timing = false;
 };

@@ -275,7 +275,6 @@ amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStre
 
 amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
                           const amm_opts* o, amm_dec* dec, hipStream_t s) {
-  (void)ctx;
   const int64_t mn = std::min(m, n);
   const int l = (int)std::min<int64_t>(mn, (int64_t)k + std::max(o->oversample, 0));
   const int q = std::max(o->power_iters, 0);
@@ -301,14 +300,17 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
     if (dec->norm_A == 0.0) dec->sigma_next = 0.0;
     return AMM_OK;
   }
-  DevBuf A64, Om, Y, Z, T1, gram, Bs;
-  AMM_TRY(A64.alloc(m * n * sizeof(double)));
-  AMM_TRY(Om.alloc(n * l * sizeof(double)));
-  AMM_TRY(Y.alloc(m * l * sizeof(double)));
-  AMM_TRY(Z.alloc(n * l * sizeof(double)));
-  AMM_TRY(T1.alloc(std::max(m, n) * l * sizeof(double)));
-  AMM_TRY(gram.alloc(l * l * sizeof(double)));
-  AMM_TRY(Bs.alloc(l * n * sizeof(double)));
+  // work buffers come from the context's grow-only areas: repeated decompositions
+  // allocate (and free) nothing once the areas have grown
+  DevBuf* ws = ctx->rsvd;
+  DevBuf &A64 = ws[0], &Om = ws[1], &Y = ws[2], &Z = ws[3], &T1 = ws[4], &gram = ws[5], &Bs = ws[6];
+  AMM_TRY(A64.reserve(m * n * sizeof(double)));
+  AMM_TRY(Om.reserve(n * l * sizeof(double)));
+  AMM_TRY(Y.reserve(m * l * sizeof(double)));
+  AMM_TRY(Z.reserve(n * l * sizeof(double)));
+  AMM_TRY(T1.reserve(std::max(m, n) * l * sizeof(double)));
+  AMM_TRY(gram.reserve(l * l * sizeof(double)));
+  AMM_TRY(Bs.reserve(l * n * sizeof(double)));
   hipLaunchKernelGGL(widen_f32, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, A, A64.as<double>(), m * n);
   const int64_t cnt = n * l;
   hipLaunchKernelGGL(gaussian_sketch, dim3((unsigned)((cnt / 2 + 256) / 256)), dim3(256), 0, s, Om.as<double>(), cnt, o->seed);
@@ -356,10 +358,11 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   if (k < l) dec->sigma_next = sig[order[k]];
   else if (k == mn) dec->sigma_next = 0.0;
   // U_full = Q W (m x l), V_full = Bs^T W diag(1/sig) (n x l)
-  DevBuf Wd, Uf, Vf, perm, isg, sgk;
-  AMM_TRY(Wd.alloc(l * l * sizeof(double)));
-  AMM_TRY(Uf.alloc(m * l * sizeof(double)));
-  AMM_TRY(Vf.alloc(n * l * sizeof(double)));
+  DevBuf &Wd = ws[7], &Uf = ws[8], &Vf = ws[9];
+  DevBuf perm, isg, sgk;
+  AMM_TRY(Wd.reserve(l * l * sizeof(double)));
+  AMM_TRY(Uf.reserve(m * l * sizeof(double)));
+  AMM_TRY(Vf.reserve(n * l * sizeof(double)));
   AMM_TRY(perm.alloc(l * 4));
   AMM_TRY(isg.alloc(l * sizeof(double)));
   AMM_TRY(sgk.alloc(k * sizeof(double)));
