@@ -2,7 +2,7 @@
 
 Products are compared on identical decompositions (oracle factors / CSR
 imported through the C ABI) to the float32 bar 1e-5 relative Frobenius.  The
-device randomized SVD is judged on what the mathematics fixes (singular
+device randomized SVD is checked against what the mathematics fixes (singular
 values of the generator, the Eckart-Young tail); the device extraction must
 give the oracle's CSR exactly.
 """
