@@ -76,7 +76,8 @@ def spmm(S: CSR, B: np.ndarray) -> np.ndarray:
 
 def dense_times_sparse(D: np.ndarray, S: CSR) -> np.ndarray:
     """D S, looping over the stored entries of S (row j of S feeds column c)."""
-    D = np.asarray(D, dtype=np.float64)
+    # a complex D (a circulant residual) keeps its real part: S is real
+    D = np.real(np.asarray(D)).astype(np.float64)
     out = np.zeros((D.shape[0], S.n))
     for j in range(S.m):
         for e in range(S.row_ptr[j], S.row_ptr[j + 1]):

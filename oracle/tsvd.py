@@ -57,8 +57,13 @@ def apply_zeroth(dec: TSVDDecomp, B: np.ndarray) -> np.ndarray:
 
 
 def apply_first_order_term(decB: TSVDDecomp, dA: np.ndarray) -> np.ndarray:
-    """sum_i sigma_i^B Delta A w_i y_i^T = (Delta A W) S_B Y^T."""
-    return ((np.asarray(dA, dtype=np.float64) @ decB.U) * decB.s[None, :]) @ decB.V.T
+    """sum_i sigma_i^B Delta A w_i y_i^T = (Delta A W) S_B Y^T.
+
+    A circulant residual arrives complex (its imaginary part is rounding for a
+    real A); the factors here are real, so the real part of the product is the
+    product of the real part and only that is kept.
+    """
+    return ((np.real(np.asarray(dA)).astype(np.float64) @ decB.U) * decB.s[None, :]) @ decB.V.T
 
 
 def approx_product(A, B, k: int, first_order: bool, kB: int | None = None):
