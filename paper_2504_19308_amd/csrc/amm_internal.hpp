@@ -62,13 +62,16 @@ struct KernelTimer {
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, long>> totals;  // ms, launches
   // events are created once and reused, so a timed launch adds two records
-  // and no event creation to the host's launch path
+  // and no event creation to the host's launch path.  They only carry
+  // timestamps (the host waits on the stream, not on them), so they are made
+  // without the system-scope fence, which would write back the caches at
+  // every marker and bill that to the kernel between them.
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   hipEvent_t take() {
     if (used == pool.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       pool.push_back(e);
     }
     return pool[used++];
