@@ -176,7 +176,8 @@ def test_c5_first_order_identity_sampled():
     assert float((got - want).norm() / want.norm()) < TOL_F32
 
 
-@pytest.mark.parametrize("m,n,p,nnz", [(700, 9000, 67, 20000), (333, 12289, 128, 9000)])
+@pytest.mark.parametrize("m,n,p,nnz", [(700, 9000, 67, 20000), (333, 12289, 128, 9000), (100, 20000, 64, 8000),
+                                       (129, 16385, 36, 4000)])
 def test_spmm_blocked_inner(m, n, p, nnz):
     """Inner dimension above 8192: each row's entries are taken per block of
     4096 inner indices (the last block partial), later blocks accumulating."""
