@@ -9,7 +9,7 @@ offline step).  Every other variant of the workload (circulant K = 8/32/128,
 SVD rank 32/128, zeroth and first order, sparsified operands) is measured too
 and listed under "variants" with its error against the exact product.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark measures one GPU (the sharding plan is described, not run).
 """
 from __future__ import annotations
 
@@ -110,7 +110,7 @@ def rel_err(M, exact64):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2504_19308_amd import Context, inputs
