@@ -34,7 +34,9 @@ diagonalisation by the DFT built from its definition, the shift identity
 W D^k W* = C^k, the printed n = 4 cycle-matrix example, Thm. 2.1 optimality,
 special cases (circulant input, single planted mode), and a brute-force
 comparison of the algorithm path against the dense entrywise truncated
-product for every index set at n <= 8.  Blocked rectangular operands: all
+product for every index set at n <= 8.  The magnitudes T[k] are checked
+against components found by orthogonal projection onto span{C^j D^k}, and the
+literal top-K against an exhaustive search over K-subsets.  Blocked rectangular operands: all
 components of every block reproduce A and AB exactly, a square operand is a
 single block, and the block-by-block product equals the cropped dense
 truncated matrix times B.

@@ -30,13 +30,18 @@ the norms the decompositions carry (Sec. 2.5 and Sec. 3):
   estimate is not small enough); one K for both operands, as Alg. 2.3 uses a
   single k.
 
-Pins (tests/test_oracle_estimators.py): Thm. 3.8 and the circulant theorem hold
-as inequalities on random and structured instances; the flat cases reduce to
-their closed forms (identical residual singular values: Cor. 3.9; flat Fourier
-energy: mu = 1); sum_i X_i = ||dA||_F^2 and mu <= mu_upper; ||M|| <= ||AB||
-for the truncated SVD (proof of Cor. 3.7); the sketch with G = I is the exact
-ratio and its Rademacher form is unbiased in ||.||^2; the prior estimate
-matches Monte-Carlo relative errors for Haar operands and the U(0,1) constant
+Pins (tests/test_oracle_estimators.py): Thm. 3.8 holds as an inequality on
+random and structured instances; the flat cases reduce to their closed forms
+(identical residual singular values: Cor. 3.9; flat Fourier energy: mu = 1);
+the circulant theorem is an equality for single-component residues with
+eigenvalues of one modulus on a support T (mu = n / |T|), and fails on some
+other inputs (an estimate, not a bound); sum_i X_i = ||dA||_F^2 and
+mu <= mu_upper; ||M|| <= ||AB|| for the truncated SVD (proof of Cor. 3.7);
+the posterior matches err / sqrt(1 - err^2) on Haar operands truncated half
+way (Lemma 3.1 with ||AB||^2 = ||M||^2 + ||dA dB||^2) and tracks the observed
+error where it is small; the sketch with G = I is the exact ratio and its
+Rademacher form is unbiased in ||.||^2; the prior estimate matches
+Monte-Carlo relative errors for Haar operands and the U(0,1) constant
 matches the finite-n expectation of Thm. 3.5's proof; the rank choices agree
 with a search over every K.
 """

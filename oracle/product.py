@@ -83,7 +83,7 @@ def project(dec, G: np.ndarray) -> np.ndarray:
     if isinstance(dec, _tsvd.TSVDDecomp):
         return dec.U @ (dec.U.T @ G @ dec.V) @ dec.V.T
     if isinstance(dec, _sp.SparseDecomp):
-        mask = dec.S.dense() != 0
+        mask = dec.S.pattern()
         out = np.where(mask, G, 0.0)
         if dec.inner is not None:
             rest = np.where(mask, 0.0, G)
@@ -98,7 +98,7 @@ def project_adjoint(dec, G: np.ndarray) -> np.ndarray:
     adjoint G o Omega + P_in(G) o Omega^c."""
     G = np.asarray(G, dtype=np.float64)
     if isinstance(dec, _sp.SparseDecomp):
-        mask = dec.S.dense() != 0
+        mask = dec.S.pattern()
         out = np.where(mask, G, 0.0)
         if dec.inner is not None:
             out = out + np.where(mask, 0.0, project_adjoint(dec.inner, G))

@@ -13,10 +13,12 @@ A - (S + trunc(R)); with no truncation this is exactly eq. (2.4).
 Sparse storage is CSR with column indices ascending inside each row.  The
 products are plain per-row loops.
 
-Parity pins (tests/test_oracle_sparse.py): S B equals the dense (A o Omega) B,
-f = 1 gives the exact product, f = 0 reduces to the pure truncation, the
-selected set is checked against a brute-force sort of tiny inputs, and the
-first-order identity M = AB - Delta A Delta B.
+Parity pins (tests/test_oracle_tsvd_sparse.py): S B equals the dense
+(A o Omega) B, f = 1 gives the exact product, f = 0 reduces to the pure
+truncation, the selected set is checked against a brute-force sort of tiny
+inputs, and the first-order identity M = AB - Delta A Delta B.  Omega is the
+set of stored positions (``CSR.pattern``), which keeps a selected entry whose
+value is exactly zero.
 """
 from __future__ import annotations
 
@@ -43,6 +45,15 @@ class CSR:
             a, b = self.row_ptr[i], self.row_ptr[i + 1]
             D[i, self.col[a:b]] = self.val[a:b]
         return D
+
+    def pattern(self) -> np.ndarray:
+        """Boolean m x n mask of the stored positions (the kept index set
+        Omega), including stored entries whose value is exactly zero."""
+        P = np.zeros((self.m, self.n), dtype=bool)
+        for i in range(self.m):
+            a, b = self.row_ptr[i], self.row_ptr[i + 1]
+            P[i, self.col[a:b]] = True
+        return P
 
 
 def dominant_count(m: int, n: int, frac: float) -> int:

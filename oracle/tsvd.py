@@ -17,7 +17,9 @@ Q2), which pins this module together with the Eckart-Young identity
 ||A - A_k||_F = sqrt(sum_{i>k} sigma_i^2) (Sec. 2.2, relative-error formula).
 
 The error bound of Thm. 3.8, ||dA dB||_F^2 <= ||dA||_F ||dB||_F ||dA||_2
-||dB||_2, is exposed for the invariant tests.
+||dB||_2, is exposed for the invariant tests; it is pinned by its flat-tail
+closed form (c_A c_B)^2 (n - k) and by its equality case (rank-one residues
+sharing a singular vector).
 """
 from __future__ import annotations
 

@@ -289,3 +289,50 @@ def test_blocked_product_is_cropped_dense_truncation(m, n, K):
     if m > n:
         last = dec.blocks[-1]
         assert last.A.shape == (s, s) and np.all(last.A[m - (dec.nb - 1) * s:] == 0)
+
+
+@pytest.mark.parametrize("n", [5, 8, 12])
+def test_magnitudes_by_projection(n):
+    """T[k] = ||R_k e_0||_2 (Alg. 2.3 step 2) with R_k found without the
+    oracle's transforms: the components R_k D^k are Frobenius-orthogonal and
+    span{C^j D^k : j} has the orthogonal basis C^j D^k of norm sqrt(n)
+    (Rem. 1.2), so R_k = sum_j <A, C^j D^k> / n C^j, and its first column holds
+    the coefficients of C^j (C^j e_0 = e_j)."""
+    A = _rand(n, 50 + n) + 0.5 * _rand(n, 60 + n) @ _rand(n, 70 + n)
+    T = oc.magnitudes(oc.circulant_coefficients(A))
+    C = oc.permutation_C(n)
+    for k in range(n):
+        Dk = oc.phase_D(n, k)
+        coef = np.zeros(n, dtype=complex)
+        P = np.eye(n)
+        for j in range(n):
+            basis = P @ Dk
+            coef[j] = np.sum(np.conj(basis) * A) / n
+            P = C @ P
+        assert np.isclose(T[k], np.linalg.norm(coef), rtol=1e-12, atol=1e-14)
+
+
+def test_select_literal_bruteforce():
+    """Literal top-K (Alg. 2.3 step 3, ties to the smaller frequency): among
+    all K-subsets with the largest sum of T, the lexicographically smallest;
+    checked on values with many ties."""
+    rng = np.random.default_rng(7)
+    for n in (6, 9):
+        T = rng.integers(0, 4, size=n).astype(float)
+        for K in range(n + 1):
+            best = max(sum(T[list(c)]) for c in itertools.combinations(range(n), K))
+            want = min(c for c in itertools.combinations(range(n), K) if sum(T[list(c)]) == best)
+            assert sorted(oc.select_literal(T, K).tolist()) == list(want)
+
+
+def test_literal_decomposition_first_order_identity():
+    """The literal selection (which may split a conjugate pair, making the
+    truncation complex) still satisfies M1 = AB - Delta A Delta B entrywise."""
+    n = 12
+    A, B = _rand(n, 81), _rand(n, 82)
+    dA_ = oc.CirculantDecomp(A, 3, literal=True)
+    dB_ = oc.CirculantDecomp(B, 5, literal=True)
+    assert len(dA_.S) == 3
+    M1 = oc.apply_zeroth(dA_, B) + oc.apply_first_order_term(dB_, dA_.residual_dense())
+    dA, dB = dA_.residual_dense(), dB_.residual_dense()
+    assert np.max(np.abs(M1 - (A @ B - dA @ dB))) < 1e-10

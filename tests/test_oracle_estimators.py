@@ -221,3 +221,94 @@ def test_choose_k_svd_exhaustive():
                 want = k
                 break
         assert oe.choose_k_svd(sA, sB, np.linalg.norm(A), np.linalg.norm(B), n, tau) == want
+
+
+def test_posterior_haar_monte_carlo_large_error():
+    """Cor. 3.7 on Haar operands with flat spectra, truncated half way, where
+    M and AB differ by about 13 %.  Two facts fix the expected posterior
+    without using its formula: the expansion of ||M||^2 in the corollary's
+    proof gives ||AB||^2 = ||M||^2 + ||dA dB||^2 for the truncated SVD, and
+    Lemma 3.1 gives ||dA dB||^2 ~ ||dA||^2 ||dB||^2 / n for independent Haar
+    singular vectors.  Hence posterior = ||dA|| ||dB|| / (sqrt(n) ||M||)
+    ~ err / sqrt(1 - err^2), err the observed relative error; a posterior
+    divided by ||AB|| would give err itself (0.50 against 0.58 here), one
+    without the 1/sqrt(n) a value sqrt(n) = 8 times larger."""
+    n, k = 64, 32
+    rng = np.random.default_rng(31)
+    post, target, err = [], [], []
+    for _ in range(40):
+        A = inputs.spectral_matrix(n, n, np.ones(n), rng)
+        B = inputs.spectral_matrix(n, n, 2.0 * np.ones(n), rng)
+        M, dA_, dB_ = ot.approx_product(A, B, k, first_order=True)
+        AB = A @ B
+        dA, dB = dA_.residual_dense(), dB_.residual_dense()
+        nab, nm, ndd = np.linalg.norm(AB), np.linalg.norm(M), np.linalg.norm(dA @ dB)
+        assert abs(nab ** 2 - nm ** 2 - ndd ** 2) <= 1e-10 * nab ** 2
+        e = np.linalg.norm(AB - M) / nab
+        err.append(e)
+        target.append(e / np.sqrt(1.0 - e * e))
+        post.append(oe.posterior(np.linalg.norm(dA), np.linalg.norm(dB), nm, n))
+    assert 0.45 < np.mean(err) < 0.55
+    assert abs(np.mean(post) / np.mean(target) - 1) < 0.01
+    # the bound direction of Cor. 3.7 for exact truncated-SVD factors
+    assert np.mean(err) <= np.mean(post)
+
+
+def test_posterior_small_error_tracks_actual():
+    """Fast decay, rank 8 of 96: M ~ AB and the posterior tracks the observed
+    relative error of each draw (Lemma 3.1 concentrates for Haar factors)."""
+    n, k = 96, 8
+    rng = np.random.default_rng(32)
+    ratios = []
+    for _ in range(30):
+        A = inputs.spectral_matrix(n, n, inputs.decay_power(n, 0.9), rng)
+        B = inputs.spectral_matrix(n, n, inputs.decay_exp(n, 25.0), rng)
+        M, dA_, dB_ = ot.approx_product(A, B, k, first_order=True)
+        e = np.linalg.norm(A @ B - M) / np.linalg.norm(A @ B)
+        p = oe.posterior(np.linalg.norm(dA_.residual_dense()), np.linalg.norm(dB_.residual_dense()),
+                         np.linalg.norm(M), n)
+        ratios.append(e / p)
+    assert abs(np.mean(ratios) - 1) < 0.05
+    assert np.std(ratios) < 0.2
+
+
+def _real_flat_lists(n, support, level, rng):
+    """Eigenvalues of a real circulant: modulus sqrt(level) on a support closed
+    under i -> n - i, zero elsewhere, conjugate-symmetric phases."""
+    lam = np.zeros(n, dtype=np.complex128)
+    for i in support:
+        if i == 0 or 2 * i == n:
+            lam[i] = np.sqrt(level) * rng.choice([-1.0, 1.0])
+        elif i < n - i:
+            ph = np.exp(2j * np.pi * rng.random())
+            lam[i] = np.sqrt(level) * ph
+            lam[n - i] = np.conj(lam[i])
+    return lam
+
+
+@pytest.mark.parametrize("n,support", [(16, [0, 1, 15, 4, 12]), (32, [2, 30, 5, 27, 16]), (24, list(range(24)))])
+def test_cd_bound_equality_case(n, support):
+    """The circulant residual theorem is an equality when each residual is a
+    single real component, Delta A = R (frequency 0) and Delta B = R' D^(n/2),
+    whose eigenvalues have one common modulus on one support T (closed under
+    i -> n - i) and vanish off it: then the convolution step holds with
+    equality (one term per mode), the mode energies are flat on T so the
+    Cauchy-Schwarz and max steps are tight, and mu = n / |T|, which is 1 only
+    for a full support.  The dense product gives ||dA dB||_F independently.
+    Kept components (a strong pair at frequency 3) do not change this."""
+    rng = np.random.default_rng(n + len(support))
+    ca, cb = 2.0, 0.5
+    big = np.fft.fft(rng.standard_normal(n)) * 20.0
+    neg = (-np.arange(n)) % n
+    A = _dense_from_lists(n, {0: _real_flat_lists(n, support, ca, rng), 3: big, n - 3: np.conj(big[neg])})
+    B = _dense_from_lists(n, {n // 2: _real_flat_lists(n, support, cb, rng)})
+    assert np.max(np.abs(A.imag)) < 1e-10 and np.max(np.abs(B.imag)) < 1e-10
+    decA, decB = oc.CirculantDecomp(A.real, 2), oc.CirculantDecomp(B.real, 0)
+    assert sorted(decA.S.tolist()) == [3, n - 3]
+    dA, dB = np.real(decA.residual_dense()), np.real(decB.residual_dense())
+    muA, muB = oe.cd_mu(decA), oe.cd_mu(decB)
+    assert np.isclose(muA, n / len(support), rtol=1e-10) and np.isclose(muB, n / len(support), rtol=1e-10)
+    b = oe.cd_bound(muA, muB, np.linalg.norm(dA), np.linalg.norm(dB), n)
+    assert np.isclose(np.linalg.norm(dA @ dB), b, rtol=1e-10)
+    # closed form: ||dA dB||^2 = |T| ca cb
+    assert np.isclose(b, np.sqrt(len(support) * ca * cb), rtol=1e-10)

@@ -205,3 +205,58 @@ def test_mixed_decompositions_first_order_identity(ka, kb):
     dB = B - np.real(dB_.truncated_dense())
     assert op.rel_fro(M1, A @ B - dA @ dB) < 1e-12
     assert op.rel_fro(M1, op.definition(dA_, B, dB_)) < 1e-12
+
+
+def test_thm38_flat_tail_closed_form():
+    """Flat residual spectra (Cor. 3.9's setting): the residual singular values
+    are c_A and c_B (n - k of each), so ||dA||_F = c sqrt(n - k) and
+    ||dA||_2 = c, and the right-hand side of Thm. 3.8 (squared form) is
+    (c_A c_B)^2 (n - k), from the generator's singular values alone."""
+    n, k, cA, cB = 40, 7, 0.3, 1.7
+    head = np.linspace(9.0, 4.0, k)
+    A = _spectral(n, np.concatenate([head, np.full(n - k, cA)]), 41)
+    B = _spectral(n, np.concatenate([head * 2.0, np.full(n - k, cB)]), 42)
+    dA, dB = ot.TSVDDecomp(A, k).residual_dense(), ot.TSVDDecomp(B, k).residual_dense()
+    assert np.isclose(ot.thm38_bound_sq(dA, dB), (cA * cB) ** 2 * (n - k), rtol=1e-10)
+
+
+def test_thm38_equality_aligned_rank_one_residues():
+    """Thm. 3.8 is tight when both residues have rank one and A's dropped right
+    singular vector is B's dropped left singular vector: dA = a u v^T,
+    dB = b v w^T, so ||dA dB||_F^2 = (ab)^2 = ||dA||_F ||dB||_F ||dA||_2 ||dB||_2."""
+    n, k, a, b = 24, 4, 0.8, 1.9
+    rng = np.random.default_rng(43)
+    Q1, Q2, Q3 = (inputs.haar_columns(n, n, rng) for _ in range(3))
+    sA = np.zeros(n)
+    sA[:k + 1] = [9.0, 7.0, 5.0, 3.0, a]
+    sB = np.zeros(n)
+    sB[:k + 1] = [8.0, 6.0, 4.0, 2.5, b]
+    A = (Q1 * sA) @ Q2.T
+    B = (Q2 * sB) @ Q3.T          # B's left singular vectors are A's right ones
+    dA, dB = ot.TSVDDecomp(A, k).residual_dense(), ot.TSVDDecomp(B, k).residual_dense()
+    lhs = np.linalg.norm(dA @ dB) ** 2
+    assert np.isclose(lhs, (a * b) ** 2, rtol=1e-9)
+    assert np.isclose(ot.thm38_bound_sq(dA, dB), lhs, rtol=1e-9)
+
+
+def test_frozen_pattern_keeps_zero_valued_entries():
+    """Reading G25: the frozen sparse structure is the kept index set Omega, so
+    a kept entry whose value is exactly 0 stays in Omega and the projection
+    P(G) = G o Omega keeps G there.  A has 5 nonzeros and 9 entries are kept,
+    four of them zeros (ties at |a| = 0 go to the smallest row-major index)."""
+    A = np.zeros((4, 5))
+    A[0, 3], A[1, 1], A[2, 4], A[3, 0], A[3, 2] = 5.0, -4.0, 3.0, -2.0, 1.0
+    dec = osp.SparseDecomp(A, 0.0, nnz=9)
+    kept = sorted(r * 5 + c for r in range(4) for c in dec.S.col[dec.S.row_ptr[r]:dec.S.row_ptr[r + 1]])
+    assert kept == sorted([3, 6, 14, 15, 17, 0, 1, 2, 4])
+    G = np.arange(1.0, 21.0).reshape(4, 5)
+    P = op.project(dec, G)
+    want = np.zeros(20)
+    want[kept] = G.reshape(-1)[kept]
+    assert np.array_equal(P.reshape(-1), want)
+    assert np.array_equal(op.project_adjoint(dec, G), P)
+    # the frozen-structure gradient of <P(W) X, Y> puts dY X^T on every kept position
+    rng = np.random.default_rng(44)
+    X, Y = rng.standard_normal((5, 3)), rng.standard_normal((4, 3))
+    _, dW = op.backward(dec, X, Y)
+    assert np.count_nonzero(dW.reshape(-1)[kept]) == 9
