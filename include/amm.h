@@ -72,10 +72,19 @@ typedef struct {
   int keep_residual;   /* keep Delta A on the device so that this handle can
                           be the left operand of a first-order product */
   int spectral_fp16;   /* AMM_CIRCULANT with n >= 1024 (a power of two, or at
-                          most 2048): store the eigenvalue lists the products
-                          use as float16 (half the list traffic; each
-                          multiplier rounded to 2^-11 relative), products and
-                          sums stay float32 (default 0) */
+                          most 2048): float16 spectral products (Alg. 2.3
+                          step 5 with half-precision multiplicands).  The
+                          eigenvalue lists are stored as float16 pairs scaled
+                          by a power of two; powers of two also round each
+                          tile's forward spectrum to float16 (scaled by a
+                          power of two per tile) and form every list-times-
+                          spectrum product in half precision with float32
+                          sums; both FFTs and the output stay float32.
+                          Other sides widen the float16 lists and multiply in
+                          float32.  Each multiplicand carries a relative
+                          rounding of 2^-11, so the circulant term differs
+                          from its float32 value by about 1e-3 relative
+                          (default 0) */
 } amm_opts;
 
 /* Fill `o` with the defaults (frac 0.01, nnz -1, oversample 16, power 2,
@@ -93,7 +102,7 @@ typedef struct {
   double norm_residual;  /* ||Delta A||_F from the dropped energy/spectrum
                             (blocked operands: over the zero-padded blocks) */
   int blocks;            /* square circulant blocks of a rectangular operand (0: none) */
-  int spectral_fp16;     /* circulant products use float16 lists */
+  int spectral_fp16;     /* circulant products use float16 spectral products */
   double mu;             /* circulant: spectral concentration of Delta A (see
                             amm_estimate_error); NaN if not computed */
   double sigma_next;     /* truncated SVD: sigma_{k+1} estimate (= ||Delta A||_2);
@@ -352,6 +361,14 @@ amm_status amm_estimate_sketch(amm_ctx* ctx, const float* A, const float* B, con
  * singular values (||Delta A(k)||^2 = ||A||^2 - sum_{i<k} sigma_i^2); returns
  * that maximum when no smaller rank meets tau.  Host work only. */
 amm_status amm_choose_rank(const amm_dec* dA, const amm_dec* dB, double tau, int entries, int* K);
+
+/* Switch float16 spectral products (see amm_opts.spectral_fp16) on or off
+ * for a circulant handle (or the circulant residue of a sparse handle; every
+ * block of a rectangular one), e.g. after amm_dec_import_circulant.  Builds
+ * the scaled float16 lists from the float32 ones on the handle's device
+ * (synchronous); call it before the handle is used in enqueued work.
+ * AMM_EUNSUPPORTED for sides below 1024 or, not powers of two, above 2048. */
+amm_status amm_dec_set_spectral_fp16(amm_dec* dec, int enable);
 
 /* Record sigma_{k+1} (>= 0) for an imported truncated SVD whose next singular
  * value the caller knows (decomposed handles carry their sketch's estimate). */

@@ -98,6 +98,11 @@ class Decomposition:
         """Record sigma_{k+1} of an imported truncated SVD (for the Thm. 3.8 bound)."""
         _lib.check(_lib.load().amm_dec_set_sigma_next(self.handle, float(value)))
 
+    def set_spectral_fp16(self, enable: bool = True):
+        """Switch float16 spectral products on or off (circulant handles)."""
+        _lib.check(_lib.load().amm_dec_set_spectral_fp16(self.handle, 1 if enable else 0))
+        return self
+
     def close(self):
         if self.handle and self._owned:
             _lib.load().amm_dec_destroy(self.handle)

@@ -84,6 +84,7 @@ SIGNATURES = {
                                       C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
     "amm_choose_rank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "amm_dec_set_sigma_next": (C.c_int, [C.c_void_p, C.c_double]),
+    "amm_dec_set_spectral_fp16": (C.c_int, [C.c_void_p, C.c_int]),
 }
 
 _lib = None

@@ -88,9 +88,9 @@ amm_status circ_columns(amm_ctx* ctx, const amm_dec* b, const float* B, int64_t 
   }
   if (is_pow2(b->n))
     return cd_apply_columns(ctx, log2_exact(b->n), b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc,
-                            s, b->pairs_of(false), b->lists16(false));
+                            s, b->pairs_of(false), b->lists16(false), b->l16_inv);
   return cd_apply_general(ctx, (int)b->n, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc, s,
-                          b->lists16(false));
+                          b->lists16(false), b->l16_inv);
 }
 
 // exp(-2 pi i m / n) with the angle reduced to the first octant, so every entry
@@ -272,9 +272,9 @@ amm_status right_apply(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec
     }
     if (!is_pow2(d->n))
       return cd_apply_rows_general(ctx, (int)d->n, d->K_eff, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), X,
-                                   rows, out, acc, s, d->lists16(true));
+                                   rows, out, acc, s, d->lists16(true), d->l16_inv);
     return cd_apply_rows(ctx, log2_exact(d->n), d->K_eff, d->shifts_adj.as<int32_t>(),
-                         d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true), d->lists16(true));
+                         d->Ladj.as<float2>(), X, rows, out, acc, s, d->pairs_of(true), d->lists16(true), d->l16_inv);
   }
   if (is_tsvd(d)) {
     const int k = d->K_eff;
@@ -1030,10 +1030,10 @@ amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
       AMM_TRY(fill_f32(it.out, it.m * it.p, 0.f, s));
     } else if (!is_pow2(d->n)) {
       AMM_TRY(cd_chirp_apply(bp->ctx, false, (int)d->n, d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
-                             it.p, it.out, false, s, d->lists16(false)));
+                             it.p, it.out, false, s, d->lists16(false), d->l16_inv));
     } else {
       AMM_TRY(cd_apply_columns(bp->ctx, log2_exact(d->n), d->K_eff, d->shifts.as<int32_t>(), d->L.as<float2>(), it.B,
-                               it.p, it.out, false, s, d->pairs_of(false), d->lists16(false)));
+                               it.p, it.out, false, s, d->pairs_of(false), d->lists16(false), d->l16_inv));
     }
   }
   return AMM_OK;
@@ -1265,6 +1265,34 @@ double prior_of(double nA, double nB, double dA, double dB, int64_t n, int entri
 }  // namespace
 
 extern "C" {
+
+amm_status amm_dec_set_spectral_fp16(amm_dec* dec, int enable) {
+  if (!dec) return fail(AMM_EINVAL, "NULL handle");
+  amm_dec* c = is_sparse(dec) ? dec->inner : dec;
+  if (!c || c->kind != AMM_CIRCULANT) return fail(AMM_EINVAL, "not a circulant handle (or sparse with a circulant residue)");
+  std::vector<amm_dec*> parts;
+  if (c->blocks.empty()) parts.push_back(c);
+  else parts.assign(c->blocks.begin(), c->blocks.end());
+  for (amm_dec* b : parts) {
+    const bool pow2 = is_pow2(b->n);
+    if (enable && (b->n < 1024 || (!pow2 && b->n > kChirpFusedMax)))
+      return fail(AMM_EUNSUPPORTED, "float16 spectral products need n >= 1024 (a power of two, or at most %d)",
+                  kChirpFusedMax);
+  }
+  AMM_HIP(hipSetDevice(c->device));
+  for (amm_dec* b : parts) {
+    if (!enable) {
+      b->fp16 = false;
+      continue;
+    }
+    if (b->fp16 || b->K_eff == 0) continue;
+    std::vector<float2> Lh((size_t)b->K_eff * b->n);
+    AMM_HIP(hipMemcpy(Lh.data(), b->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost));
+    AMM_TRY(cd_make_half_lists(b, Lh, nullptr));
+    AMM_HIP(hipStreamSynchronize(nullptr));
+  }
+  return AMM_OK;
+}
 
 amm_status amm_dec_set_sigma_next(amm_dec* dec, double sigma_next) {
   if (!dec) return fail(AMM_EINVAL, "NULL argument");

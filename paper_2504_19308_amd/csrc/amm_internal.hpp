@@ -153,6 +153,7 @@ struct amm_dec {
   // float16 copies of L and Ladj used by the products when requested (n >= 1024)
   amm::DevBuf L16, Ladj16;
   bool fp16 = false;
+  float l16_inv = 1.0f;   // the float16 lists hold L / l16_inv (a power of two)
   const __half2* lists16(bool adjoint) const {
     if (!fp16) return nullptr;
     return adjoint ? Ladj16.as<__half2>() : L16.as<__half2>();
@@ -247,15 +248,17 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
 //  column mode: out (n x p) [+]= Atil B, B (n x p) row-major, along columns.
 //  row mode:    out (rows x n) [+]= X Btil^T-side operator applied to each
 //               row of X (rows x n):  out_row = (op(row^T))^T.
-// L16 (optional): the same lists as float16 pairs (n >= 1024), used instead of L.
+// L16 (optional, n >= 1024): the lists as float16 pairs scaled by a power of
+// two (l16_inv = its inverse); the spectral products then run in float16 with
+// float32 sums (see cd_apply_kernel).
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
                             bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
-                            const __half2* L16 = nullptr);
+                            const __half2* L16 = nullptr, float l16_inv = 1.0f);
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
                          bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
-                         const __half2* L16 = nullptr);
+                         const __half2* L16 = nullptr, float l16_inv = 1.0f);
 
 // Forward spectra of the packed column pairs of B (n x p, p even): spec
 // (n x p floats) holds complex bin values at [p][2c], [p][2c + 1].
@@ -266,6 +269,10 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 // Builds dec->pair_buf from host copies of the lists when the frequency set
 // is closed and the lists satisfy L_{n-k}[p] = conj(L_k[-p]).
 amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
+
+// float16 copies of dec->L and dec->Ladj (host copy of L given) with a
+// power-of-two scale; sets dec->fp16 and dec->l16_inv.
+amm_status cd_make_half_lists(amm_dec* dec, const std::vector<float2>& L_host, hipStream_t s);
 
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s, bool fp16 = false);
@@ -284,16 +291,18 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
 constexpr int kChirpFusedMax = 2048;
 // [ch (n) | H_fwd / M (M) | H_inv / M (M)] in float32, M = 2^ceil(log2(2n - 1)), cached per n
 amm_status chirp_tables32(amm_ctx* ctx, int n, hipStream_t s, const float2** tab);
-// L16 (optional, n >= 1024): the lists as float16 pairs, used instead of L
+// L16 (optional, n >= 1024): the lists as float16 pairs scaled by 1 / l16_inv,
+// widened on load (float32 products)
 amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
                           const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s,
-                          const __half2* L16 = nullptr);
+                          const __half2* L16 = nullptr, float l16_inv = 1.0f);
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
-                            int64_t p, float* out, bool acc, hipStream_t s, const __half2* L16 = nullptr);
+                            int64_t p, float* out, bool acc, hipStream_t s, const __half2* L16 = nullptr,
+                            float l16_inv = 1.0f);
 amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t p, float* X, hipStream_t s);
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
                                  const float* X, int64_t rows, float* out, bool acc, hipStream_t s,
-                                 const __half2* Ladj16 = nullptr);
+                                 const __half2* Ladj16 = nullptr, float l16_inv = 1.0f);
 
 // Float64 Stockham FFT over `batch` vectors of length 2^log2n (element e of
 // vector b at b*bs + e*es); sign -1: exp(-2 pi i jk/n), +1: its conjugate;

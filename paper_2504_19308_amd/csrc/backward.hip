@@ -156,7 +156,7 @@ amm_status bw_circulant(amm_ctx* ctx, const amm_dec* d, const float* X, const fl
       if (!acc_dx) AMM_TRY(fill_f32(dX, n * p, 0.f, s));
     } else if (pow2) {
       AMM_TRY(cd_apply_columns(ctx, l2, K, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), dY, p, dX, acc_dx, s,
-                               d->pairs_of(true), d->lists16(true)));
+                               d->pairs_of(true), d->lists16(true), d->l16_inv));
     } else {
       AMM_TRY(cd_apply_general(ctx, (int)n, K, d->shifts_adj.as<int32_t>(), d->Ladj.as<float2>(), dY, p, dX, acc_dx,
                                s));

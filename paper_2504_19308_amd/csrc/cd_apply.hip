@@ -117,24 +117,98 @@ __device__ __forceinline__ void lds_fft(float2* lds, const float2* twl, const fl
 // SPEC = true (column mode only): store the forward spectrum of each packed
 // column pair instead of the product, unscaled, in the same row-major slots
 // (bin p, pair c) -> out[p * extent + 2c + {re, im}].
-// H16: the eigenvalue lists are stored as float16 pairs (the spectral
-// multipliers of the product in half precision); they are widened on load and
-// every product and sum stays float32.
+// H16 = true: float16 spectral products.  The lists are float16 pairs scaled
+// by a power of two (l16_inv undoes it).  After the forward transform the
+// tile's spectrum is scaled by the power of two that puts its largest
+// component in [2^14, 2^15), rounded to float16 pairs and laid out without
+// padding, twice in a row (bins 0 .. 2N-1, bin q + N a copy of bin q): every
+// shifted read (p - k or p + k) then lands inside the doubled range without a
+// modulo, and a lane's reads for one shift are one base plus constant offsets.
+// Each complex product is two v_dot2_f32_f16 (two float16 products summed
+// into a float32 accumulator); both transforms, the sums and the output stay
+// float32.
 template <bool H16>
 __device__ __forceinline__ float2 list_at(const void* __restrict__ L, int64_t i) {
   if constexpr (H16) return __half22float2(reinterpret_cast<const __half2*>(L)[i]);
   else return reinterpret_cast<const float2*>(L)[i];
 }
 
+// float32 multipliers: a list value times a spectrum value, complex.
+struct MulF { float2 v; };
+__device__ __forceinline__ MulF mul_plain(float2 l) { return MulF{l}; }
+__device__ __forceinline__ MulF mul_conj(float2 l) { return MulF{float2{l.x, -l.y}}; }
+__device__ __forceinline__ void mac(float2& a, const MulF& m, float2 x) {
+  a.x += m.v.x * x.x - m.v.y * x.y;
+  a.y += m.v.x * x.y + m.v.y * x.x;
+}
+
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// float16 multipliers.  A value is (re, im) in the two halves of a 32-bit word
+// (re low).  m x = (mr xr - mi xi) + i (mi xr + mr xi): the real part dots x
+// with m, the high product negated, the imaginary part with m's halves swapped;
+// conj(m) x = (mr xr + mi xi) + i (mr xi - mi xr): m itself, and the swapped
+// word with the low product negated.  The negations are operand modifiers of
+// v_dot2_f32_f16 (two float16 products summed into a float32 accumulator), so
+// a list value costs one swap; the compiler does not fold sign flips of
+// float16 pairs into these modifiers, hence the instruction is written out.
+struct MulH { uint32_t m, sw; };    // value and its swapped halves
+struct MulHc { uint32_t m, sw; };   // the same, applied conjugated
+__device__ __forceinline__ uint32_t swap_halves(uint32_t u) { return (u >> 16) | (u << 16); }
+__device__ __forceinline__ MulH mul_plain(uint32_t l) { return MulH{l, swap_halves(l)}; }
+__device__ __forceinline__ MulHc mul_conj(uint32_t l) { return MulHc{l, swap_halves(l)}; }
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(half2v, a), __builtin_bit_cast(half2v, b), c, false);
+}
+__device__ __forceinline__ float dot2_neg_hi(uint32_t a, uint32_t b, float c) {
+  asm("v_dot2_f32_f16 %0, %1, %2, %0 neg_hi:[1,0,0]" : "+v"(c) : "v"(a), "v"(b));
+  return c;
+}
+__device__ __forceinline__ float dot2_neg_lo(uint32_t a, uint32_t b, float c) {
+  asm("v_dot2_f32_f16 %0, %1, %2, %0 neg_lo:[1,0,0]" : "+v"(c) : "v"(a), "v"(b));
+  return c;
+}
+__device__ __forceinline__ void mac(float2& a, const MulH& m, uint32_t x) {
+  a.x = dot2_neg_hi(m.m, x, a.x);
+  a.y = dot2(m.sw, x, a.y);
+}
+__device__ __forceinline__ void mac(float2& a, const MulHc& m, uint32_t x) {
+  a.x = dot2(m.m, x, a.x);
+  a.y = dot2_neg_lo(m.sw, x, a.y);
+}
+
+template <bool H16> struct ListVal { using type = float2; };
+template <> struct ListVal<true> { using type = uint32_t; };
+template <bool H16>
+__device__ __forceinline__ typename ListVal<H16>::type list_val(const void* __restrict__ L, int64_t i) {
+  if constexpr (H16) return reinterpret_cast<const uint32_t*>(L)[i];
+  else return reinterpret_cast<const float2*>(L)[i];
+}
+
+// CPL float16 spectrum values of one bin (consecutive words from word w)
+template <int CPL>
+__device__ __forceinline__ void read_h(const uint32_t* hs, int w, uint32_t (&x)[CPL]) {
+  if constexpr (CPL == 4) {
+    const uint4 v = *reinterpret_cast<const uint4*>(hs + w);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else if constexpr (CPL == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(hs + w);
+    x[0] = v.x; x[1] = v.y;
+  } else {
+    x[0] = hs[w];
+  }
+}
+
 template <int LOG2N, bool ROWS, bool SPEC = false, bool H16 = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const void* __restrict__ L,
-                const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr) {
+                const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr, float l16_inv) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
   __shared__ float2 twl[Cfg::TWL], twh[Cfg::TWH];
+  __shared__ float red[(T + 63) / 64];
   float* ldsf = reinterpret_cast<float*>(lds);
   for (int i = threadIdx.x; i < Cfg::TWL + Cfg::TWH; i += T) {
     if (i < Cfg::TWL) twl[i] = tw[i];
@@ -188,12 +262,51 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 
   lds_fft<-1, LOG2N, ROWS>(lds, twl, twh);
 
+  float scale = SPEC ? 1.0f : 1.0f / (float)N;
   if constexpr (!SPEC) {
   // ---- shifted spectral MAC: Y[p] = sum_t L_t[p] X[(p - k_t) mod N] ---------
   constexpr int CPL = Cfg::CPL, G = Cfg::G, BL = Cfg::BL, NBINS = Cfg::NBINS;
+  using LV = typename ListVal<H16>::type;
   // lanes = (bin, column group); the packed columns of a group are read together
   const int cg = threadIdx.x % G;
   const int bl = threadIdx.x / G;
+  uint32_t* hs = reinterpret_cast<uint32_t*>(lds);
+
+  if constexpr (H16) {
+    // scale, round and double the spectrum (see above)
+    constexpr int NV = (N * C + T - 1) / T;
+    float2 v[NV];
+    float mx = 0.f;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + q * T;   // bin * C + column
+      if ((N * C) % T == 0 || e < N * C) {
+        v[q] = lds[pad_bin(e / C) * C + e % C];
+        mx = fmaxf(mx, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();    // also: every thread has read its values
+    mx = red[0];
+    for (int w = 1; w < (T + 63) / 64; ++w) mx = fmaxf(mx, red[w]);
+    int ex = 0;
+    (void)frexpf(mx, &ex);                        // mx < 2^ex
+    const int sh = min(max(15 - ex, -100), 100);  // mx 2^sh < 2^15
+    const float sx = ldexpf(1.0f, sh);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + q * T;
+      if ((N * C) % T == 0 || e < N * C) {
+        const uint32_t u = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[q].x * sx, v[q].y * sx));
+        hs[e] = u;
+        hs[e + N * C] = u;
+      }
+    }
+    __syncthreads();
+    scale = ldexpf(l16_inv / (float)N, -sh);
+  }
+
   auto load_x = [&](int q, float2 (&x)[CPL]) {
     const float2* src = &lds[pad_bin(q & (N - 1)) * C + cg * CPL];
     if constexpr (CPL == 4) {
@@ -210,10 +323,8 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       x[0] = src[0];
     }
   };
-  auto cmac = [](float2& a, float2 l, float2 x) {
-    a.x += l.x * x.x - l.y * x.y;
-    a.y += l.x * x.y + l.y * x.x;
-  };
+  // word offset of bin q (0 <= q < 2N) in the doubled float16 spectrum
+  auto hw = [&](int q) { return q * C + cg * CPL; };
   float2 acc[NBINS][CPL];
 #pragma unroll
   for (int i = 0; i < NBINS; ++i)
@@ -233,34 +344,81 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
     b2 = b1 == 0 ? N / 2 : N - b1;
   };
   if (paired) {
-    for (int u = 0; u < pr.npairs; ++u) {
-      const int2 pk = pr.pairs[u];
-      const int k = pk.x;
-      const int64_t Lt = (int64_t)pk.y * N;
+    constexpr int NHA = NH > 0 ? NH : 1;
+    auto fetch = [&](int u, LV (&v1)[NHA], LV (&v2)[NHA]) {
+      const int64_t Lt = (int64_t)pr.pairs[u].y * N;
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
         int b1, b2;
         pair_bins(i, b1, b2);
-        const float2 l1 = list_at<H16>(L, Lt + b1), l2 = list_at<H16>(L, Lt + b2);
+        v1[i] = list_val<H16>(L, Lt + b1);
+        v2[i] = list_val<H16>(L, Lt + b2);
+      }
+    };
+    // both members of the pair (k, N - k) at the lane's bins, lists v1 = L_k[b1], v2 = L_k[b2]
+    auto apply = [&](int k, const LV (&v1)[NHA], const LV (&v2)[NHA]) {
+      // float16 reads: b1 -+ k step +BL with i; b2 -+ k step -BL (bases at
+      // i = NH-1); lane 0's partner of bin 0 is N/2
+      const int wx1 = hw(bl - k + N), wy1 = hw(bl + k);
+      const int wx2 = hw(2 * N - bl - (NH - 1) * BL - k), wy2 = hw(N - bl - (NH - 1) * BL + k);
+      const int sx2 = hw(N / 2 - k + N), sy2 = hw(N / 2 + k);
+#pragma unroll
+      for (int i = 0; i < NH; ++i) {
+        int b1, b2;
+        pair_bins(i, b1, b2);
         const bool self = b1 == 0;                  // 0 and N/2 are their own mirrors
-        const float2 m1 = self ? l1 : l2, m2 = self ? l2 : l1;
-        const float2 c1 = float2{m1.x, -m1.y}, c2 = float2{m2.x, -m2.y};
-        float2 x[CPL], y[CPL];
-        load_x(b1 - k, x);
-        load_x(b1 + k, y);
+        const LV l1 = v1[i], l2 = v2[i];
+        const LV m1 = self ? l1 : l2, m2 = self ? l2 : l1;
+        if constexpr (H16) {
+          // swap each list value once; the conjugated uses are m1 = l2 and m2 = l1
+          // except at the self-mirrored bins
+          const uint32_t s1 = swap_halves(l1), s2 = swap_halves(l2);
+          const MulH p1{l1, s1}, p2{l2, s2};
+          const MulHc q1{m1, self ? s1 : s2}, q2{m2, self ? s2 : s1};
+          uint32_t x[CPL], y[CPL];
+          read_h<CPL>(hs, wx1 + i * BL * C, x);
+          read_h<CPL>(hs, wy1 + i * BL * C, y);
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          cmac(acc[i][c], l1, x[c]);
-          cmac(acc[i][c], c1, y[c]);
-        }
-        load_x(b2 - k, x);
-        load_x(b2 + k, y);
+          for (int c = 0; c < CPL; ++c) {
+            mac(acc[i][c], p1, x[c]);
+            mac(acc[i][c], q1, y[c]);
+          }
+          int ax = wx2 + (NH - 1 - i) * BL * C, ay = wy2 + (NH - 1 - i) * BL * C;
+          if (i == 0 && bl == 0) {
+            ax = sx2;
+            ay = sy2;
+          }
+          read_h<CPL>(hs, ax, x);
+          read_h<CPL>(hs, ay, y);
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          cmac(acc[NH + i][c], l2, x[c]);
-          cmac(acc[NH + i][c], c2, y[c]);
+          for (int c = 0; c < CPL; ++c) {
+            mac(acc[NH + i][c], p2, x[c]);
+            mac(acc[NH + i][c], q2, y[c]);
+          }
+        } else {
+          const auto p1 = mul_plain(l1), q1 = mul_conj(m1), p2 = mul_plain(l2), q2 = mul_conj(m2);
+          float2 x[CPL], y[CPL];
+          load_x(b1 - k, x);
+          load_x(b1 + k, y);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            mac(acc[i][c], p1, x[c]);
+            mac(acc[i][c], q1, y[c]);
+          }
+          load_x(b2 - k, x);
+          load_x(b2 + k, y);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            mac(acc[NH + i][c], p2, x[c]);
+            mac(acc[NH + i][c], q2, y[c]);
+          }
         }
       }
+    };
+    LV c1[NHA], c2[NHA];
+    for (int u = 0; u < pr.npairs; ++u) {
+      fetch(u, c1, c2);
+      apply(pr.pairs[u].x, c1, c2);
     }
     for (int v = 0; v < pr.nsingles; ++v) {
       const int2 sk = pr.singles[v];
@@ -270,15 +428,24 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       for (int i = 0; i < NH; ++i) {
         int b1, b2;
         pair_bins(i, b1, b2);
-        float2 x[CPL];
-        load_x(b1 - k, x);
-        const float2 l1 = list_at<H16>(L, Lt + b1);
+        const auto p1 = mul_plain(list_val<H16>(L, Lt + b1)), p2 = mul_plain(list_val<H16>(L, Lt + b2));
+        if constexpr (H16) {
+          uint32_t x[CPL];
+          read_h<CPL>(hs, hw(b1 - k + N), x);
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) cmac(acc[i][c], l1, x[c]);
-        load_x(b2 - k, x);
-        const float2 l2 = list_at<H16>(L, Lt + b2);
+          for (int c = 0; c < CPL; ++c) mac(acc[i][c], p1, x[c]);
+          read_h<CPL>(hs, hw(b2 - k + N), x);
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) cmac(acc[NH + i][c], l2, x[c]);
+          for (int c = 0; c < CPL; ++c) mac(acc[NH + i][c], p2, x[c]);
+        } else {
+          float2 x[CPL];
+          load_x(b1 - k, x);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) mac(acc[i][c], p1, x[c]);
+          load_x(b2 - k, x);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) mac(acc[NH + i][c], p2, x[c]);
+        }
       }
     }
   } else {
@@ -289,11 +456,18 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       for (int i = 0; i < NBINS; ++i) {
         const int p = bl + i * BL;
         if (N % BL == 0 || p < N) {
-          const float2 l = list_at<H16>(L, Lt + p);
-          float2 x[CPL];
-          load_x(p - k, x);
+          const auto m = mul_plain(list_val<H16>(L, Lt + p));
+          if constexpr (H16) {
+            uint32_t x[CPL];
+            read_h<CPL>(hs, hw(p - k + N), x);
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) cmac(acc[i][c], l, x[c]);
+            for (int c = 0; c < CPL; ++c) mac(acc[i][c], m, x[c]);
+          } else {
+            float2 x[CPL];
+            load_x(p - k, x);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) mac(acc[i][c], m, x[c]);
+          }
         }
       }
     }
@@ -319,7 +493,6 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   }
 
   // ---- store ----------------------------------------------------------------
-  const float scale = SPEC ? 1.0f : 1.0f / (float)N;
   if (!ROWS) {
     if (2 * C >= 4 && vec4) {
       constexpr int V = 2 * C >= 4 ? 2 * C / 4 : 1;
@@ -377,7 +550,7 @@ template <int LOG2M, bool ROWS, bool H16>
 __global__ void __launch_bounds__(CdCfg<LOG2M>::T)
 cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent, int n, int K,
                 const int32_t* __restrict__ shifts, const void* __restrict__ L, const float2* __restrict__ tab,
-                const float2* __restrict__ tw, int accumulate) {
+                const float2* __restrict__ tw, int accumulate, float l16_inv) {
   using Cfg = CdCfg<LOG2M>;
   constexpr int M = Cfg::N, C = Cfg::C, T = Cfg::T;
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
@@ -476,8 +649,8 @@ cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
   lds_fft<+1, LOG2M, ROWS>(lds, twl, twh);
   scale_bins(n, ch, true);
 
-  // store y / n
-  const float sc = 1.0f / (float)n;
+  // store y / n (float16 lists: also undo their power-of-two scale)
+  const float sc = (H16 ? l16_inv : 1.0f) / (float)n;
   if (!ROWS) {
     for (int e = threadIdx.x; e < n * 2 * C; e += T) {
       const int rc = e % (2 * C), row = e / (2 * C);
@@ -503,38 +676,48 @@ cd_chirp_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
 
 template <int LOG2M>
 amm_status launch_chirp(bool rows, const float* X, float* out, int64_t extent, int n, int K, const int32_t* shifts,
-                        const void* L, bool h16, const float2* tab, const float2* tw, bool acc, hipStream_t s) {
+                        const void* L, bool h16, float l16_inv, const float2* tab, const float2* tw, bool acc,
+                        hipStream_t s) {
   using Cfg = CdCfg<LOG2M>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
   if (tiles > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "too many column tiles");
   TimedLaunch tl(rows ? "cd_apply_rows" : "cd_apply_columns", s);
   const dim3 grid((unsigned)tiles), block(Cfg::T);
+  const int a = acc ? 1 : 0;
   if (h16) {
     if constexpr (LOG2M >= 12) {   // float16 lists: n > 1024
       if (rows)
         hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true, true>), grid, block, 0, s, X, out, extent, n, K, shifts, L,
-                           tab, tw, acc ? 1 : 0);
+                           tab, tw, a, l16_inv);
       else
         hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false, true>), grid, block, 0, s, X, out, extent, n, K, shifts, L,
-                           tab, tw, acc ? 1 : 0);
+                           tab, tw, a, l16_inv);
     } else {
       return fail(AMM_EUNSUPPORTED, "float16 lists need n >= 1024");
     }
   } else if (rows)
     hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, true, false>), grid, block, 0, s, X, out, extent, n, K, shifts, L, tab,
-                       tw, acc ? 1 : 0);
+                       tw, a, 1.0f);
   else
     hipLaunchKernelGGL((cd_chirp_kernel<LOG2M, false, false>), grid, block, 0, s, X, out, extent, n, K, shifts, L, tab,
-                       tw, acc ? 1 : 0);
+                       tw, a, 1.0f);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
+}
+
+template <int LOG2N, bool ROWS, bool H16>
+void launch_cd_kernel(dim3 grid, dim3 block, hipStream_t s, const float* X, float* out, int64_t extent, int K,
+                      const int32_t* shifts, const void* L, const float2* tw, int acc, int vec4, CdPairs pr,
+                      float l16_inv) {
+  hipLaunchKernelGGL((cd_apply_kernel<LOG2N, ROWS, false, H16>), grid, block, 0, s, X, out,
+                     extent, K, shifts, L, tw, acc, vec4, pr, l16_inv);
 }
 
 template <int LOG2N>
 amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
                      const int32_t* shifts, const void* L, const float2* tw, bool acc,
-                     hipStream_t s, bool spec, CdPairs pr, bool h16) {
+                     hipStream_t s, bool spec, CdPairs pr, bool h16, float l16_inv) {
   using Cfg = CdCfg<LOG2N>;
   const int64_t tiles = (extent + 2 * Cfg::C - 1) / (2 * Cfg::C);
   if (tiles == 0) return AMM_OK;
@@ -544,36 +727,31 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
   // float4 path: whole float4 groups inside a row and 16-byte aligned rows
   const int vec4 = (!rows && 2 * Cfg::C >= 4 && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 &&
                     ((uintptr_t)out % 16) == 0) ? 1 : 0;
+  const int a = acc ? 1 : 0;
   if (spec)
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
-                       shifts, L, tw, 0, vec4, pr);
+                       shifts, L, tw, 0, vec4, pr, 1.0f);
   else if (h16) {
     if constexpr (LOG2N >= kH16MinLog2) {
-      if (rows)
-        hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true, false, true>), grid, block, 0, s, X, out, extent, K,
-                           shifts, L, tw, acc ? 1 : 0, 0, pr);
-      else
-        hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, false, true>), grid, block, 0, s, X, out, extent, K,
-                           shifts, L, tw, acc ? 1 : 0, vec4, pr);
+      if (rows) launch_cd_kernel<LOG2N, true, true>(grid, block, s, X, out, extent, K, shifts, L, tw, a, 0, pr, l16_inv);
+      else launch_cd_kernel<LOG2N, false, true>(grid, block, s, X, out, extent, K, shifts, L, tw, a, vec4, pr, l16_inv);
     } else {
-      return fail(AMM_EUNSUPPORTED, "float16 lists need n >= %d", 1 << kH16MinLog2);
+      return fail(AMM_EUNSUPPORTED, "float16 spectral products need n >= %d", 1 << kH16MinLog2);
     }
   } else if (rows)
-    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, true>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0, 0, pr);
+    launch_cd_kernel<LOG2N, true, false>(grid, block, s, X, out, extent, K, shifts, L, tw, a, 0, pr, 1.0f);
   else
-    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false>), grid, block, 0, s, X, out, extent, K,
-                       shifts, L, tw, acc ? 1 : 0, vec4, pr);
+    launch_cd_kernel<LOG2N, false, false>(grid, block, s, X, out, extent, K, shifts, L, tw, a, vec4, pr, 1.0f);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
 
 amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
                        const int32_t* shifts, const void* L, const float2* tw, bool acc,
-                       hipStream_t s, bool spec, CdPairs pr, bool h16 = false) {
+                       hipStream_t s, bool spec, CdPairs pr, bool h16 = false, float l16_inv = 1.0f) {
   switch (log2n) {
 #define AMM_CASE(L2) \
-  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr, h16);
+  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr, h16, l16_inv);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
     AMM_CASE(13) AMM_CASE(14)
@@ -586,10 +764,10 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t
 
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16) {
+                            bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  if (L16) return dispatch_cd(false, log2n, B, out, p, K, shifts, L16, tw, accumulate, s, false, pr, true);
+  if (L16) return dispatch_cd(false, log2n, B, out, p, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
   return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
@@ -605,7 +783,7 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 // out (extent x n) (+)= the operator applied to each row of X (extent x n).
 amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* shifts, const float2* L,
                           const float* X, int64_t extent, float* out, bool accumulate, hipStream_t s,
-                          const __half2* L16) {
+                          const __half2* L16, float l16_inv) {
   if (n < 3 || n > kChirpFusedMax) return fail(AMM_EUNSUPPORTED, "fused chirp product needs 3 <= n <= %d", kChirpFusedMax);
   int lM = 0;
   while ((1 << lM) < 2 * n - 1) ++lM;
@@ -616,7 +794,7 @@ amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* 
   switch (lM) {
 #define AMM_CASE(L2) \
   case L2: return launch_chirp<L2>(rows, X, out, extent, n, K, shifts, L16 ? (const void*)L16 : (const void*)L, \
-                                   L16 != nullptr, tab, tw, accumulate, s);
+                                   L16 != nullptr, l16_inv, tab, tw, accumulate, s);
     AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6) AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10)
     AMM_CASE(11) AMM_CASE(12)
 #undef AMM_CASE
@@ -626,10 +804,10 @@ amm_status cd_chirp_apply(amm_ctx* ctx, bool rows, int n, int K, const int32_t* 
 
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
-                         bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16) {
+                         bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  if (L16) return dispatch_cd(true, log2n, X, out, rows, K, shifts, L16, tw, accumulate, s, false, pr, true);
+  if (L16) return dispatch_cd(true, log2n, X, out, rows, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
   return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s, false, pr);
 }
 

@@ -138,9 +138,10 @@ __global__ void __launch_bounds__(256) mode_energy_rows(const double2* __restric
   if (threadIdx.x == 0) X[p] = sh[0];
 }
 
-__global__ void lists_to_half(const float2* __restrict__ src, __half2* __restrict__ dst, int64_t count) {
+__global__ void lists_to_half(const float2* __restrict__ src, __half2* __restrict__ dst, int64_t count,
+                              float scale) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = __float22half2_rn(src[i]);
+  if (i < count) dst[i] = __floats2half2_rn(src[i].x * scale, src[i].y * scale);
 }
 
 __global__ void zero_diagonals(double2* __restrict__ Ahat, int n, const int32_t* __restrict__ shifts) {
@@ -271,6 +272,29 @@ std::vector<double> retained_all(const std::vector<double>& E) {
   return R;
 }
 
+// float16 copies of L and Ladj, scaled by the power of two that puts the
+// largest list component in [2^13, 2^14) (the lists of a small residue would
+// otherwise sit among the float16 subnormals); l16_inv undoes the scale.
+amm_status cd_make_half_lists(amm_dec* dec, const std::vector<float2>& Lh, hipStream_t s) {
+  float mx = 0.f;
+  for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
+  int ex = 0;
+  (void)std::frexp(mx, &ex);                         // mx < 2^ex
+  const int sh = std::min(std::max(14 - ex, -100), 100);
+  const int64_t cnt = (int64_t)Lh.size();
+  AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
+  AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));
+  const float sc = std::ldexp(1.0f, sh);
+  hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->L.as<float2>(),
+                     dec->L16.as<__half2>(), cnt, sc);
+  hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->Ladj.as<float2>(),
+                     dec->Ladj16.as<__half2>(), cnt, sc);
+  AMM_HIP(hipGetLastError());
+  dec->l16_inv = std::ldexp(1.0f, -sh);
+  dec->fp16 = true;
+  return AMM_OK;
+}
+
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_residual,
                         amm_dec* dec, hipStream_t s, bool fp16) {
   const bool pow2 = (n & (n - 1)) == 0;
@@ -337,17 +361,7 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_re
     AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
     AMM_HIP(hipStreamSynchronize(s));
     AMM_TRY(cd_build_pairs(dec, Lh));
-    if (fp16 && n >= 1024 && (pow2 || n <= kChirpFusedMax)) {
-      const int64_t cnt = (int64_t)Ke * n;
-      AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
-      AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));
-      hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->L.as<float2>(),
-                         dec->L16.as<__half2>(), cnt);
-      hipLaunchKernelGGL(lists_to_half, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dec->Ladj.as<float2>(),
-                         dec->Ladj16.as<__half2>(), cnt);
-      AMM_HIP(hipGetLastError());
-      dec->fp16 = true;
-    }
+    if (fp16 && n >= 1024 && (pow2 || n <= kChirpFusedMax)) AMM_TRY(cd_make_half_lists(dec, Lh, s));
   }
 
   // spectral concentration of Delta A (circulant residual theorem of Sec. 3):

@@ -222,13 +222,14 @@ amm_status dft64_any(amm_ctx* ctx, double2* x, int n, int64_t es, int64_t bs, in
 }
 
 amm_status cd_apply_general(amm_ctx* ctx, int n, int K, const int32_t* shifts, const float2* L, const float* B,
-                            int64_t p, float* out, bool acc, hipStream_t s, const __half2* L16) {
+                            int64_t p, float* out, bool acc, hipStream_t s, const __half2* L16,
+                            float l16_inv) {
   if (p <= 0) return AMM_OK;
   if (K == 0) {
     if (!acc) return fill_f32(out, (int64_t)n * p, 0.f, s);
     return AMM_OK;
   }
-  if (n >= 3 && n <= kChirpFusedMax) return cd_chirp_apply(ctx, false, n, K, shifts, L, B, p, out, acc, s, L16);
+  if (n >= 3 && n <= kChirpFusedMax) return cd_chirp_apply(ctx, false, n, K, shifts, L, B, p, out, acc, s, L16, l16_inv);
   const int64_t P2 = (p + 1) / 2, cnt = (int64_t)n * P2;
   AMM_TRY(ctx->scratch[8].reserve(cnt * sizeof(double2)));
   AMM_TRY(ctx->scratch[9].reserve(cnt * sizeof(double2)));
@@ -264,11 +265,11 @@ amm_status spectrum_columns_general(amm_ctx* ctx, int n, const float* B, int64_t
 // adjoint lists, transposed back
 amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shifts_adj, const float2* Ladj,
                                  const float* X, int64_t rows, float* out, bool acc, hipStream_t s,
-                                 const __half2* Ladj16) {
+                                 const __half2* Ladj16, float l16_inv) {
   if (rows <= 0) return AMM_OK;
   if (n >= 3 && n <= kChirpFusedMax) {
     if (K == 0) return acc ? AMM_OK : fill_f32(out, (int64_t)n * rows, 0.f, s);
-    return cd_chirp_apply(ctx, true, n, K, shifts_adj, Ladj, X, rows, out, acc, s, Ladj16);
+    return cd_chirp_apply(ctx, true, n, K, shifts_adj, Ladj, X, rows, out, acc, s, Ladj16, l16_inv);
   }
   AMM_TRY(ctx->scratch[12].reserve((size_t)n * rows * sizeof(float)));
   AMM_TRY(ctx->scratch[13].reserve((size_t)n * rows * sizeof(float)));
