@@ -1,15 +1,20 @@
-"""Benchmark: approximate product at n = 4096 (square float32 operands with
-Haar singular vectors and sigma_i = i^-1.5), against dense float32 GEMM.
+"""Benchmark: approximate product of two n = 16384 float32 operands, each a
+sparse part (0.5 % of the entries, Laplace(0, 20), at uniform positions) over a
+rank-1024 residue with Haar singular vectors and sigma_i = i^-1.5, against
+dense float32 GEMM on the same GPU.
 
-One step = one first-order approximate product M = Atil B + Delta A Btil of
-the primary variant (truncated SVD, rank 32 for both operands), with both
-decompositions made beforehand on the device and timed separately
-(decompose_ms; the paper treats the decomposition of a static operand as an
-offline step).  Every other variant of the workload (circulant K = 8/32/128,
-SVD rank 32/128, zeroth and first order, sparsified operands) is measured too
-and listed under "variants" with its error against the exact product.
+Both operands are decomposed on the device as S + trunc_K(R): the dominant
+0.5 % of the entries as CSR and a circulant truncation with K = 64 of the
+residue (eq. (2.4) with a truncated residue; Alg. 2.2/2.3).  One step = one
+zeroth-order product M0 = Atil B with float16 spectral products (float32
+sums), the decompositions made beforehand and timed separately
+(decompose_ms).  The error against AB is measured in float64 on 256 seeded
+output columns.  Every other workload (float32 spectral products, first
+order, the n = 4096 variants, the n = 256 parity configuration, batches,
+the differentiable layer, Toeplitz, S-FFT) is listed under "variants".
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark measures one GPU (the sharding plan is described, not run).
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark measures
+one GPU (the sharding plan is described, not run).
 """
 from __future__ import annotations
 
@@ -31,11 +36,11 @@ MFMA_F32_PEAK = 157.3e12     # flop/s, dense FP32 matrix cores
 VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz; no packed-FP32 forms
 
 
-# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised
-# in profiles/ (KiB per dispatch, n = 4096, rank 32),
-# with the scale factors a 256 MiB elementwise copy gave (FETCH x2.0, WRITE x1.0).
-# A figure is reported only while the kernel source still has the hash it had
-# when the counters were taken.
+# HBM bytes per dispatch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# summarised in profiles/ (KiB per dispatch), with the scale factors a 256 MiB
+# elementwise copy gave (FETCH x2.0, WRITE x1.0).  A figure is reported only
+# while the kernel source still has the hash it had when the counters were
+# taken.
 TRAFFIC = {
     # kernel tag: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch and the source they were taken on
     "panel": {"fetch_kib": 67709.3, "write_kib": 2048.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
@@ -72,10 +77,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default="", help="run just one variant name (profiling)")
+    ap.add_argument("--only", default="", help="run just one group of variants (profiling): c5, c2, c1, "
+                                               "estimates, toeplitz, sfft, batch, layer, tables")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (reference for byte counters)")
     return ap.parse_args()
@@ -107,116 +113,149 @@ def rel_err(M, exact64):
     return float(d.norm() / exact64.norm())
 
 
+# kernel-name tag of a TimedLaunch -> (name of the kernel in a rocprofv3 trace,
+# dispatches per tag launch) for the headline step
+HEADLINE_KERNELS = {
+    "spmm_csr": ("spmm_bcast", 4),                                 # one dispatch per block of 4096 inner indices
+    "cd_apply_columns": ("cd_apply_kernel<14, false, false, true>", 1),
+    "repitch": ("repitch_kernel", 1),
+}
+
+
+def headline_roofline(kt, steps, n, nnz, K, list_bytes=4):
+    """Roofline of the kernel with the largest time in the timed steps.
+
+    Algorithmic work per step (SURVEY 8(d) per-unit figures for the fused
+    steps): SpMM 2 nnz p flops, 8 nnz + 4 (n p + m p) bytes; circulant product
+    p n (5 log2 n + 4 K) flops, 2 * 4 n p + K n list_bytes bytes; the spread
+    pitch copy 2 * 4 n p bytes.  Per dispatch: the step's figure over the
+    dispatches per step."""
+    p = m = n
+    per_step = {
+        "spmm_csr": (8.0 * nnz + 4.0 * (n * p + m * p), 2.0 * nnz * p, VALU_F32_PEAK),
+        "cd_apply_columns": (2.0 * 4 * n * p + K * n * list_bytes, p * n * (5.0 * math.log2(n) + 4.0 * K),
+                             VALU_F32_PEAK),
+        "repitch": (2.0 * 4 * n * p, 0.0, VALU_F32_PEAK),
+    }
+    rows = {}
+    for tag, (ms, launches) in kt.items():
+        if tag not in per_step:
+            continue
+        byts, fl, peak = per_step[tag]
+        kname, disp = HEADLINE_KERNELS[tag]
+        nd = launches * disp / steps                  # dispatches per step
+        t = ms / steps / nd * 1e-3                    # seconds per dispatch
+        b1, f1 = byts / disp, fl / disp               # per dispatch
+        if f1 / peak > b1 / HBM_PEAK:
+            r = {"bound": "alu", "achieved": f1 / t / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+        else:
+            r = {"bound": "hbm", "achieved": b1 / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        r.update(kernel=kname, tag=tag, dispatches_per_step=nd, avg_us=t * 1e6, ms_per_step=ms / steps,
+                 algorithmic_bytes=b1, algorithmic_flops=f1)
+        rows[tag] = r
+    top = max(rows.values(), key=lambda r: r["ms_per_step"])
+    out = dict(top)
+    out["traffic"] = traffic_bytes(top["tag"])
+    out["per_kernel"] = rows
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
-    from paper_2504_19308_amd import Context, inputs
+    from paper_2504_19308_amd import Context
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.backends.cuda.matmul.allow_tf32 = False
-    dev = "cuda"
-    n = args.n
-    t0 = time.time()
-    log(f"[bench] generating n={n} operands")
-    pair = inputs.workload_c2(n, device=dev)
-    A = pair.A.float().contiguous()
-    B = pair.B.float().contiguous()
-    exact = A.double() @ B.double()
-    torch.cuda.synchronize()
-    log(f"[bench] inputs ready {time.time() - t0:.1f}s")
-    tm = Timer(torch)
-    flops_equiv = 2.0 * n * n * n
-
-    # dense baselines on the same GPU
-    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B), 25, 5))
-    Ab, Bb = A.bfloat16(), B.bfloat16()
-    dense_bf16_ms = statistics.median(tm.run(lambda: torch.matmul(Ab, Bb), 25, 5))
-    log(f"[bench] dense fp32 {dense_ms:.3f} ms, bf16 {dense_bf16_ms:.3f} ms")
-
     ctx = Context(0)
-
-    def decompose_timed(M, kind, K, **kw):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        d = ctx.decompose(M, kind, K, **kw)
-        torch.cuda.synchronize()
-        return d, (time.perf_counter() - a) * 1e3
-
-    out = torch.empty((n, n), dtype=torch.float32, device=dev)
-
-    # ---- primary variant: SVD rank 32, first order ---------------------------
-    kp = 32
-    dA, tA = decompose_timed(A, "tsvd", kp, seed=1)
-    dB, tB = decompose_timed(B, "tsvd", kp, seed=2)
-    step = lambda: ctx.approx_matmul(dA, B, dB, out=out)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    kt = ctx.timings()
-    ctx.set_timing(False)
-    # the event brackets add a little; time the same steps without them too
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_step = total_ms / args.steps
-    err_primary = rel_err(out, exact)
-    value = flops_equiv / (ms_step * 1e-3) / 1e12
-    log(f"[bench] primary tsvd k={kp} first order: {ms_step:.4f} ms/step, err {err_primary:.3e}")
-
-    # roofline of the dominant kernel (largest total time in the timed steps)
-    name, (kms, launches) = max(kt.items(), key=lambda kv: kv[1][0])
-    avg_s = kms / launches * 1e-3
-    kc = 2 * kp
-    shapes = {
-        # name: (algorithmic bytes per launch, flops per launch)
-        # panel: streams A and Delta B once, reads the factors, writes G and H
-        "panel": (4.0 * (2 * n * n + 2 * n * kp + kp * n + n * kp), 2.0 * kp * n * n * 2),
-        # gemm_out: reads [U_A S_A | H] and [G ; S_B V_B^T], writes the n x n result
-        "gemm_out": (4.0 * (n * kc + kc * n + n * n), 2.0 * n * n * kc),
-    }
-    byts, fl = shapes.get(name, (float("nan"), float("nan")))
-    if fl / MFMA_F32_PEAK > byts / HBM_PEAK:
-        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_bytes(name)
-    roof["kernel"] = name
-    roof["avg_us"] = avg_s * 1e6
-    roof["algorithmic_bytes"] = byts
-    roof["algorithmic_flops"] = fl
-    roof["per_kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in kt.items()}
-    roof["per_kernel_launches_per_step"] = {k: v[1] / args.steps for k, v in kt.items()}
+    tm = Timer(torch)
+    rec, state = c5_headline(torch, ctx, tm, args)
 
     if args.calib_copy:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).normal_()
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").normal_()
         dst = torch.empty_like(src)
         for _ in range(5):
             torch.neg(src, out=dst)    # one elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
         del src, dst
 
-    variants = []
+    variants = list(state.pop("variants"))
+    cpu = None if args.no_cpu else cpu_baseline_c5(state)
+    state.clear()
+    torch.cuda.empty_cache()
     if not args.no_variants:
-        variants = run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, args.only, dA, dB)
+        variants += run_variants(torch, ctx, tm, args.only)
+    rec["cpu_baseline"] = cpu
+    rec["variants"] = variants
+    print(json.dumps(rec), flush=True)
 
-    cpu = None if args.no_cpu else cpu_baseline(pair, A, B, kp, flops_equiv)
+
+def c5_headline(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
+    """The headline step and the other n = 16384 variants (float32 spectral
+    products, first order)."""
+    from paper_2504_19308_amd import inputs
+    n = args.n
+    t0 = time.time()
+    log(f"[bench] generating n={n} operands (sparse {frac:g} + rank-1024 decay)")
+    pair = inputs.workload_c5(n, device="cuda")
+    A = pair.A.float().contiguous()
+    B = pair.B.float().contiguous()
+    del pair
+    torch.cuda.empty_cache()
+    cols = np.sort(np.random.default_rng(inputs.seed_of(5, 9)).choice(n, ncols, replace=False))
+    cols_t = torch.from_numpy(cols).cuda()
+    exact = A.double() @ B[:, cols_t].double()
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready {time.time() - t0:.1f}s")
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    flops_equiv = 2.0 * n ** 3
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 3, 1))
+    Ab, Bb = A.bfloat16(), B.bfloat16()
+    dense_bf16_ms = statistics.median(tm.run(lambda: torch.matmul(Ab, Bb), 3, 1))
+    del Ab, Bb
+    torch.cuda.empty_cache()
+    log(f"[bench] dense fp32 {dense_ms:.3f} ms, bf16 {dense_bf16_ms:.3f} ms")
+
+    def decompose_timed(M, half):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        d = ctx.decompose(M, "sparse+circulant", K, sparse_frac=frac, spectral_fp16=half)
+        torch.cuda.synchronize()
+        return d, (time.perf_counter() - a) * 1e3
+
+    # ---- headline: zeroth order, float16 spectral products -------------------
+    dA, tA = decompose_timed(A, True)
+    dB, tB = decompose_timed(B, True)
+    info = dA.info()
+    step = lambda: ctx.approx_matmul(dA, B, out=out)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kt = ctx.timings()
+    ctx.set_timing(False)
+    # the timing events add a little; time the same steps without them
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    err = rel_err(out[:, cols_t], exact)
+    value = flops_equiv / (ms_step * 1e-3) / 1e12
+    log(f"[bench] headline: {ms_step:.3f} ms/step, err {err:.3e} (sampled), kernels "
+        f"{ {k: round(v[0] / args.steps, 3) for k, v in kt.items()} }")
+    roof = headline_roofline(kt, args.steps, n, info["nnz"], info["K_eff"])
 
     rec = {
         "metric": "approx-matmul TFLOP-equiv/s and speedup vs dense GEMM at <=1% rel. Frobenius error",
@@ -229,28 +268,164 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f16",
         "data": "synthetic",
         "config": {
-            "workload": f"square n={n} float32 A,B = Q1 diag(i^-1.5) Q2^T (Haar Q, seeded); "
-                        f"first-order truncated-SVD product, rank {kp} for A and B",
-            "n": n, "variant": f"tsvd k={kp} first order",
+            "workload": f"square n={n} float32 A, B = S + R: S {frac * 100:g}% Laplace(0,20) entries at uniform "
+                        f"positions, R = Q1 diag(i^-1.5, i=1..1024) Q2^T (Haar, seeded); zeroth-order product "
+                        f"(S_A + circulant_K{K}(R_A)) B with float16 spectral products and float32 sums",
+            "n": n, "K": K, "sparse_frac": frac, "nnz": info["nnz"], "K_eff": info["K_eff"],
+            "order": "zeroth", "spectral_products": "float16 x float16 -> float32",
+            "sparse_products": "float32",
         },
-        "err_vs_exact": err_primary,
+        "err_vs_exact": err,
+        "err_sample": f"{ncols} seeded output columns against AB in float64",
         "dense_fp32_ms": dense_ms,
         "dense_bf16_ms": dense_bf16_ms,
         "speedup_vs_dense_fp32": dense_ms / ms_step,
         "decompose_ms": {"A": tA, "B": tB},
         "end_to_end": {
-            "ms": ms_step + tA + tB,
-            "tflop_equiv_s": flops_equiv / ((ms_step + tA + tB) * 1e-3) / 1e12,
-            "speedup_vs_dense_fp32": dense_ms / (ms_step + tA + tB),
+            "ms": ms_step + tA,
+            "tflop_equiv_s": flops_equiv / ((ms_step + tA) * 1e-3) / 1e12,
+            "speedup_vs_dense_fp32": dense_ms / (ms_step + tA),
+            "note": "decomposition of A plus one product (the zeroth-order product needs A's decomposition only)",
         },
         "roofline": roof,
-        "cpu_baseline": cpu,
-        "variants": variants,
     }
-    print(json.dumps(rec), flush=True)
+
+    # ---- other n = 16384 variants ---------------------------------------------
+    variants = []
+
+    def variant(name, d1, d2):
+        fn = lambda: ctx.approx_matmul(d1, B, d2, out=out)
+        ms = statistics.median(tm.run(fn, 5, 2))
+        ctx.set_timing(True)
+        fn()
+        kt2 = ctx.timings()
+        ctx.set_timing(False)
+        e = rel_err(out[:, cols_t], exact)
+        variants.append({"name": name, "ms": ms, "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12,
+                         "speedup_vs_dense_fp32": dense_ms / ms, "dense_fp32_ms": dense_ms,
+                         "err_vs_exact_sampled": e, "meets_1pct": e <= 0.01,
+                         "kernels_ms": {kn: v[0] for kn, v in kt2.items()}})
+        log(f"[bench] c5 {name}: {ms:.3f} ms, err {e:.3e}, kernels {variants[-1]['kernels_ms']}")
+
+    if not args.only or args.only == "c5":
+        variant(f"n={n} sparse0.5%+circulant K={K} first, float16 spectral products", dA, dB)
+        dA32, tA32 = decompose_timed(A, False)
+        dB32, tB32 = decompose_timed(B, False)
+        variant(f"n={n} sparse0.5%+circulant K={K} zeroth, float32 spectral products", dA32, None)
+        variant(f"n={n} sparse0.5%+circulant K={K} first, float32 spectral products", dA32, dB32)
+        # float16 against float32 spectral products: the circulant term alone
+        o16 = ctx.approx_matmul(dA, B)
+        o32 = ctx.approx_matmul(dA32, B)
+        variants[-1]["fp16_vs_fp32_products_rel_diff"] = rel_err(o16, o32.double())
+        del dA32, dB32, o16, o32
+    state = {"dA": dA, "B_cols": B[:, cols_t].double().cpu().numpy(), "cols": cols, "n": n,
+             "variants": variants}
+    del dB, A, B, exact, out
+    torch.cuda.empty_cache()
+    return rec, state
+
+
+def cpu_baseline_c5(state):
+    """The float64 oracle's zeroth-order product (sparse rows, then the
+    circulant spectral product) on the sampled output columns, with the
+    device decomposition's kept entries and eigenvalue lists read back; the
+    oracle as it stands (numpy, its FFT single-threaded).  Value scaled by the
+    sampled columns' dense-equivalent flops (2 n^2 per column)."""
+    import threadpoolctl
+    from oracle import circulant as oc
+    from oracle import sparse as osp
+
+    class _Lists:   # the three fields the oracle's circulant product reads
+        def __init__(self, n, S, L):
+            self.n, self.S, self.L = n, np.asarray(S, dtype=np.int64), L
+
+    d = state["dA"]
+    n = state["n"]
+    rp, col, val = d.sparse_part()
+    S = osp.CSR(n, n, rp, col, val)
+    lists = _Lists(n, d.frequencies(), d.lists())
+    Bc = state["B_cols"]
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    reps = 0
+    t = time.perf_counter()
+    while True:
+        M = osp.spmm(S, Bc) + np.real(oc.apply_zeroth(lists, Bc))
+        reps += 1
+        if time.perf_counter() - t > 10.0:
+            break
+    dt = (time.perf_counter() - t) / reps
+    del M
+    ncols = Bc.shape[1]
+    return {"value": 2.0 * n * n * ncols / dt / 1e12, "unit": "TFLOP-equiv/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle zeroth-order product (float64, numpy; Python row loop for the sparse part, numpy FFT "
+                      f"for the circulant part) on {ncols} of {n} output columns, {reps} repetition(s) over ~10 s; "
+                      f"value = 2 n^2 x {ncols} dense-equivalent flops / time; cores = the BLAS thread count "
+                      f"(this product uses no BLAS call: the FFT and the row loop run on one core)"}
+
+
+def c2_workload(torch, ctx, tm, only=""):
+    """n = 4096 square float32 operands Q1 diag(i^-1.5) Q2^T (Haar): the
+    first-order truncated-SVD product of rank 32 (previously the headline),
+    and the circulant / SVD / sparsified variants and error estimates."""
+    from paper_2504_19308_amd import inputs
+    n = 4096
+    pair = inputs.workload_c2(n, device="cuda")
+    A = pair.A.float().contiguous()
+    B = pair.B.float().contiguous()
+    exact = A.double() @ B.double()
+    del pair
+    flops_equiv = 2.0 * n ** 3
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B), 25, 5))
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    kp = 32
+    t0 = time.perf_counter()
+    dA = ctx.decompose(A, "tsvd", kp, seed=1)
+    torch.cuda.synchronize()
+    tA = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    dB = ctx.decompose(B, "tsvd", kp, seed=2)
+    torch.cuda.synchronize()
+    tB = (time.perf_counter() - t0) * 1e3
+    step = lambda: ctx.approx_matmul(dA, B, dB, out=out)
+    ms = statistics.median(tm.run(step, 25, 5))
+    ctx.set_timing(True)
+    for _ in range(20):
+        step()
+    kt = ctx.timings()
+    ctx.set_timing(False)
+    err = rel_err(out, exact)
+    # roofline of the dominant kernel of this product
+    name, (kms, launches) = max(kt.items(), key=lambda kv: kv[1][0])
+    avg_s = kms / launches * 1e-3
+    kc = 2 * kp
+    shapes = {
+        "panel": (4.0 * (2 * n * n + 2 * n * kp + kp * n + n * kp), 2.0 * kp * n * n * 2),
+        "gemm_out": (4.0 * (n * kc + kc * n + n * n), 2.0 * n * n * kc),
+    }
+    byts, fl = shapes.get(name, (float("nan"), float("nan")))
+    if fl / MFMA_F32_PEAK > byts / HBM_PEAK:
+        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof.update(frac=roof["achieved"] / roof["peak"], traffic=traffic_bytes(name), kernel=name,
+                avg_us=avg_s * 1e6, algorithmic_bytes=byts, algorithmic_flops=fl)
+    res = [{"name": f"n={n} tsvd k={kp} first (both operands rank {kp})", "ms": ms,
+            "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
+            "dense_fp32_ms": dense_ms, "err_vs_exact": err, "meets_1pct": err <= 0.01,
+            "decompose_ms": {"A": tA, "B": tB},
+            "end_to_end": {"ms": ms + tA + tB, "speedup_vs_dense_fp32": dense_ms / (ms + tA + tB)},
+            "kernels_ms": {k: v[0] / 20 for k, v in kt.items()}, "roofline": roof}]
+    log(f"[bench] c2 tsvd k={kp} first: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, roofline "
+        f"{roof['kernel']} {roof['frac']:.2f}")
+    res += c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA, dB)
+    del A, B, exact, out, dA, dB
+    torch.cuda.empty_cache()
+    return res
 
 
 def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False, list_bytes=8):
@@ -286,7 +461,7 @@ def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False, list_by
             "frac": byts / t / HBM_PEAK}
 
 
-def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
+def c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
     n = A.shape[0]
     res = []
     out = torch.empty_like(A)
@@ -302,8 +477,6 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
     def measure(name, dA, dB, Bm, dec_ms, ex, K=0, k=0, nnz=0):
         lb = 4 if dA.info().get("spectral_fp16") else 8
         first = dB is not None
-        if only and only != name:
-            return
         fn = lambda: ctx.approx_matmul(dA, Bm, dB, out=out)
         ms = statistics.median(tm.run(fn, 25, 5))
         ctx.set_timing(True)
@@ -318,11 +491,7 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    if only == "tables":
-        res.extend(tables_workload(torch, ctx))
-        res.append(figures_workload(torch, ctx))
-        return res
-    if not only or only not in ("batch", "layer", "c5", "estimates", "toeplitz", "sfft"):
+    if not only or only == "c2":
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -331,12 +500,12 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
             measure(f"circulant K={K} zeroth", dA, None, B, ta, exact, K=K_eff)
             measure(f"circulant K={K} first", dA, dB, B, ta + tb, exact, K=K_eff)
             del dA, dB
-        # float16 eigenvalue lists (half the list traffic)
+        # float16 spectral products
         dA, ta = dec(A, None, "circulant", 128, spectral_fp16=True)
         dB, tb = dec(B, None, "circulant", 128, spectral_fp16=True)
         K_eff = dA.info()["K_eff"]
-        measure("circulant K=128 zeroth fp16-lists", dA, None, B, ta, exact, K=K_eff)
-        measure("circulant K=128 first fp16-lists", dA, dB, B, ta + tb, exact, K=K_eff)
+        measure("circulant K=128 zeroth fp16 products", dA, None, B, ta, exact, K=K_eff)
+        measure("circulant K=128 first fp16 products", dA, dB, B, ta + tb, exact, K=K_eff)
         del dA, dB
         # truncated SVD
         for k in (32, 128):
@@ -362,8 +531,21 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
             del dA, dB
         del As, Bs, ex_s
         torch.cuda.empty_cache()
-    if not only or only == "estimates":
+    if not only or only in ("c2", "estimates"):
         res.append(estimate_variant(torch, ctx, A, B, exact, tm, dA_tsvd32, dB_tsvd32))
+    return res
+
+
+def run_variants(torch, ctx, tm, only):
+    res = []
+    if only == "tables":
+        res.extend(tables_workload(torch, ctx))
+        res.append(figures_workload(torch, ctx))
+        return res
+    if not only or only in ("c2", "estimates"):
+        res.extend(c2_workload(torch, ctx, tm, only))
+    if not only or only == "c1":
+        res.extend(c1_workload(torch, ctx, tm))
     if not only or only == "toeplitz":
         res.extend(toeplitz_workload(torch, ctx, tm))
         res.extend(toeplitz_workload(torch, ctx, tm, n=700, taus=(1e-2,)))
@@ -374,8 +556,6 @@ def run_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_ts
     if not only or only == "layer":
         res.append(layer_workload(torch, ctx, tm))
         res.append(layer_workload(torch, ctx, tm, k=440))
-    if not only or only == "c5":
-        res.extend(c5_workload(torch, ctx, tm))
     return res
 
 
@@ -594,6 +774,55 @@ def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):
     return r
 
 
+def c1_workload(torch, ctx, tm, n=256, K=16):
+    """n = 256: A, B = Q1 diag(exp(-i/20)) Q2^T + 1e-3 N(0, 1) (Haar Q, seeded,
+    float64, rounded to float32 for the device); circulant K = 16 and
+    truncated SVD k = 16, zeroth and first order.  Each product against the
+    float64 oracle on the same decomposition (the circulant handles made on
+    the device, whose kept frequencies the oracle's selection must equal; the
+    SVD factors from the oracle's exact SVD, imported) and against AB."""
+    from oracle import circulant as oc
+    from oracle import product as op
+    from oracle import tsvd as ot
+    from paper_2504_19308_amd import inputs
+    pair = inputs.workload_c1(n)
+    Ah = pair.A.astype(np.float32).astype(np.float64)
+    Bh = pair.B.astype(np.float32).astype(np.float64)
+    A = torch.from_numpy(Ah).float().cuda()
+    B = torch.from_numpy(Bh).float().cuda()
+    exact = Ah @ Bh
+    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B), 25, 5))
+    res = []
+    cA, cB = ctx.decompose(A, "circulant", K), ctx.decompose(B, "circulant", K)
+    oA, oB = oc.CirculantDecomp(Ah, K), oc.CirculantDecomp(Bh, K)
+    same_sets = list(cA.frequencies()) == list(oA.S) and list(cB.frequencies()) == list(oB.S)
+    tA, tB = ot.TSVDDecomp(Ah, K), ot.TSVDDecomp(Bh, K)
+    sA = ctx.import_tsvd(tA.U, tA.s, tA.V, A=A)
+    sB = ctx.import_tsvd(tB.U, tB.s, tB.V)
+    rA, rB = ctx.decompose(A, "tsvd", K, seed=5), ctx.decompose(B, "tsvd", K, seed=6)
+    for kind, (gA, gB), (hA, hB) in (("circulant", (cA, cB), (oA, oB)), ("tsvd", (sA, sB), (tA, tB)),
+                                     ("tsvd (device rSVD)", (rA, rB), (None, None))):
+        for order in ("zeroth", "first"):
+            d2 = gB if order == "first" else None
+            fn = lambda: ctx.approx_matmul(gA, B, d2)
+            ms = statistics.median(tm.run(fn, 25, 5))
+            got = fn().double().cpu().numpy()
+            row = {"name": f"n={n} {kind} K={K} {order}", "ms": ms, "dense_fp32_ms": dense_ms,
+                   "speedup_vs_dense_fp32": dense_ms / ms,
+                   "err_vs_exact": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+            if hA is not None:
+                want = np.real(op.algorithm(hA, Bh, hB if order == "first" else None))
+                row["err_vs_oracle"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+                row["parity_1e-5"] = row["err_vs_oracle"] <= 1e-5
+            if kind == "circulant":
+                row["same_frequencies_as_oracle"] = same_sets
+            res.append(row)
+            log(f"[bench] c1 {row['name']}: {ms:.4f} ms, err vs exact {row['err_vs_exact']:.3e}"
+                + (f", vs oracle {row['err_vs_oracle']:.2e}" if "err_vs_oracle" in row else ""))
+    del A, B
+    return res
+
+
 def toeplitz_workload(torch, ctx, tm, n=4096, taus=(1e-2, 1e-3)):
     """U(0,1) Toeplitz A and B (n = 4096; also n = 700, the paper's size, on
     the any-size path), the class where the circulant truncation meets 1 %
@@ -665,57 +894,6 @@ def sfft_workload(torch, ctx, tm, n=4096, k=32):
                     "decompose_ms": dec_ms, "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
         log(f"[bench] sfft {name}: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, kernels {res[-1]['kernels_ms']}")
     del A, B, exact, out, dA, dB
-    torch.cuda.empty_cache()
-    return res
-
-
-def c5_workload(torch, ctx, tm, n=16384, K=64, ncols=256):
-    """n = 16384 operands S + R (0.5 % Laplace(20) entries over a rank-1024
-    decay), A and B decomposed as S + circulant_64(R); zeroth- and first-order
-    products over all 16384 columns; the error against AB in float64 on 256
-    sampled columns."""
-    from paper_2504_19308_amd import inputs
-    t0 = time.time()
-    pair = inputs.workload_c5(n, device="cuda")
-    A = pair.A.float().contiguous()
-    B = pair.B.float().contiguous()
-    del pair
-    torch.cuda.empty_cache()
-    cols = torch.from_numpy(np.sort(np.random.default_rng(inputs.seed_of(5, 9)).choice(n, ncols, replace=False))).cuda()
-    exact = A.double() @ B[:, cols].double()
-    torch.cuda.synchronize()
-    log(f"[bench] c5 inputs {time.time() - t0:.1f}s")
-    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    flops = 2.0 * n ** 3
-    dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B, out=out), 3, 1))
-    res = []
-    for half in (False, True):
-        decs = []
-        for M in (A, B):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            decs.append(ctx.decompose(M, "sparse+circulant", K, sparse_frac=0.005, spectral_fp16=half))
-            torch.cuda.synchronize()
-            decs[-1].ms = (time.perf_counter() - a) * 1e3
-        dA, dB = decs
-        tag = " fp16-lists" if half else ""
-        for name, d2 in (("zeroth", None), ("first", dB)):
-            fn = lambda: ctx.approx_matmul(dA, B, d2, out=out)
-            ms = statistics.median(tm.run(fn, 5, 2))
-            ctx.set_timing(True)
-            fn()
-            kt = ctx.timings()
-            ctx.set_timing(False)
-            err = rel_err(out[:, cols], exact)
-            res.append({"name": f"n={n} sparse0.5%+circulant K={K} {name}{tag}", "ms": ms,
-                        "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
-                        "dense_fp32_ms": dense_ms, "err_vs_exact_sampled": err, "meets_1pct": err <= 0.01,
-                        "decompose_ms": dA.ms + (dB.ms if d2 is not None else 0.0), "nnz": dA.info()["nnz"],
-                        "kernels_ms": {kn: v[0] for kn, v in kt.items()}})
-            log(f"[bench] c5 {name}{tag}: {ms:.3f} ms (dense {dense_ms:.3f}), err {err:.3e}, "
-                f"kernels {res[-1]['kernels_ms']}")
-        del dA, dB, decs
-    del A, B, exact, out
     torch.cuda.empty_cache()
     return res
 
@@ -897,50 +1075,6 @@ def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
     del W, X, dY, Y, exact
     torch.cuda.empty_cache()
     return rec
-
-
-def cpu_baseline(pair, A, B, k, flops_equiv):
-    """The float64 oracle's first-order SVD product on 128 sampled output
-    columns (factors from the oracle's own exact float64 SVD of the operands
-    would cost minutes; the device factors are reused instead, so this times
-    the oracle's product step only)."""
-    import threadpoolctl
-    from oracle import tsvd as ot
-    Ah = A.double().cpu().numpy()
-    Bh = B.double().cpu().numpy()
-    n = Ah.shape[0]
-    cols = np.sort(np.random.default_rng(0).choice(n, 128, replace=False))
-    # rank-k factors for the timed product (setup, not timed): numpy SVD of a
-    # power-iterated sketch
-    def factors(M):
-        rng = np.random.default_rng(1)
-        Q, _ = np.linalg.qr(M @ rng.standard_normal((n, k + 16)))
-        for _ in range(2):
-            Q, _ = np.linalg.qr(M @ (M.T @ Q))
-        U, s, Vt = np.linalg.svd(Q.T @ M, full_matrices=False)
-        return (Q @ U)[:, :k], s[:k], Vt[:k].T
-    UA, sA, VA = factors(Ah)
-    UB, sB, VB = factors(Bh)
-    decA = ot.TSVDDecomp(Ah, k, UA, sA, VA)
-    decB_cols = ot.TSVDDecomp(Bh[:, cols], k, UB, sB, VB[cols])
-    Bc = Bh[:, cols]
-    info = threadpoolctl.threadpool_info()
-    cores = max([i.get("num_threads", 1) for i in info] + [1])
-    reps = 0
-    t = time.perf_counter()
-    while True:
-        M0 = ot.apply_zeroth(decA, Bc)
-        M1 = M0 + ot.apply_first_order_term(decB_cols, decA.residual_dense())
-        reps += 1
-        if time.perf_counter() - t > 10.0:
-            break
-    dt = (time.perf_counter() - t) / reps
-    sample_flops = 2.0 * n * n * len(cols)
-    return {"value": sample_flops / dt / 1e12, "unit": "TFLOP-equiv/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"oracle first-order SVD product (float64, numpy) on {len(cols)} of {n} output "
-                      f"columns, rank {k}, {reps} repetitions over ~10 s; value scaled by the sampled "
-                      f"columns' dense-equivalent flops"}
 
 
 if __name__ == "__main__":

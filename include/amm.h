@@ -217,6 +217,14 @@ amm_status amm_dec_block(const amm_dec* dec, int j, const amm_dec** block);
 amm_status amm_dec_frequencies(const amm_dec* dec, int32_t* out_host, int cap,
                                int* count);
 
+/* Copy the eigenvalue lists L_t = F r_{.,k_t} of a square circulant handle
+ * (or the circulant residue of a sparse one) to the host: K_eff x n complex
+ * values, interleaved (re, im), row t for the t-th frequency that
+ * amm_dec_frequencies reports (Alg. 2.3 step 4).  The lists the products use
+ * are float32; they are widened exactly, so amm_dec_import_circulant of these
+ * values rebuilds the same float32 lists.  cap counts complex values. */
+amm_status amm_dec_circulant_lists(const amm_dec* dec, double* eig_host, int64_t cap);
+
 /* Copy the float64 per-frequency energies ||R_k||_F^2 (n values) of a
  * circulant decomposition made by amm_decompose to the host. */
 amm_status amm_dec_energies(const amm_dec* dec, double* out_host, int64_t cap);

@@ -68,6 +68,14 @@ class Decomposition:
         _lib.check(lib.amm_dec_frequencies(self.handle, out.ctypes.data_as(C.c_void_p), len(out), C.byref(cnt)))
         return out[: cnt.value].copy()
 
+    def lists(self) -> np.ndarray:
+        """K_eff x n complex eigenvalue lists (float32 values, widened)."""
+        inf = self.info()
+        n, K = inf["n"], len(self.frequencies())
+        out = np.zeros((max(K, 1), n), dtype=np.complex128)
+        _lib.check(_lib.load().amm_dec_circulant_lists(self.handle, out.ctypes.data_as(C.c_void_p), K * n))
+        return out[:K].copy()
+
     def energies(self) -> np.ndarray:
         n = self.info()["n"]
         out = np.zeros(n, dtype=np.float64)

@@ -63,6 +63,7 @@ SIGNATURES = {
     "amm_dec_query": (C.c_int, [C.c_void_p, C.POINTER(AmmDecInfo)]),
     "amm_dec_frequencies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "amm_dec_energies": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "amm_dec_circulant_lists": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "amm_dec_tsvd_factors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amm_dec_sparse_part": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amm_dec_destroy": (None, [C.c_void_p]),

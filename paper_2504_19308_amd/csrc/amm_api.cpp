@@ -219,9 +219,29 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     return blocked_apply(ctx, d, B, p, out, ctx->scratch[6].as<float>(), s);
   }
   if (is_sparse(d)) {
-    AMM_TRY(spmm_csr(d, B, p, out, acc, s));
-    if (d->inner) AMM_TRY(left_apply(ctx, d->inner, B, p, out, true, s));
-    return AMM_OK;
+    // The row gathers of the sparse part (and the column reads of a circulant
+    // residue) at a row pitch that is a large power of two all land on one L2
+    // channel: both read a copy of B at a spread pitch instead.  The residue
+    // goes first (it writes out), the sparse part then adds its rows.
+    const float* Bs = B;
+    int64_t ldb = p;
+    const int64_t sp = spread_pitch(p);
+    if (sp != p && d->nnz > 0 && ((uintptr_t)B % 16) == 0) {
+      AMM_TRY(ctx->scratch[14].reserve((size_t)d->n * sp * sizeof(float)));
+      AMM_TRY(repitch_f32(B, d->n, p, ctx->scratch[14].as<float>(), sp, s));
+      Bs = ctx->scratch[14].as<float>();
+      ldb = sp;
+    }
+    if (d->inner) {
+      if (is_circ(d->inner) && d->inner->blocks.empty() && is_pow2(d->inner->n) && d->inner->K_eff > 0)
+        AMM_TRY(cd_apply_columns(ctx, log2_exact(d->inner->n), d->inner->K_eff, d->inner->shifts.as<int32_t>(),
+                                 d->inner->L.as<float2>(), Bs, p, out, acc, s, d->inner->pairs_of(false),
+                                 d->inner->lists16(false), d->inner->l16_inv, ldb));
+      else
+        AMM_TRY(left_apply(ctx, d->inner, B, p, out, acc, s));
+      acc = true;
+    }
+    return spmm_csr(d, Bs, ldb, p, out, acc, s);
   }
   if (is_sfft(d)) return sfft_left_apply(ctx, d, B, p, out, acc, s);
   if (is_circ(d)) return circ_columns(ctx, d, B, p, out, acc, s);
@@ -447,6 +467,23 @@ amm_status amm_dec_frequencies(const amm_dec* d, int32_t* out_host, int cap, int
   if (out_host) {
     if (cap < (int)c->freqs.size()) return fail(AMM_EINVAL, "capacity %d < %d", cap, (int)c->freqs.size());
     std::memcpy(out_host, c->freqs.data(), c->freqs.size() * sizeof(int32_t));
+  }
+  return AMM_OK;
+}
+
+amm_status amm_dec_circulant_lists(const amm_dec* d, double* eig_host, int64_t cap) {
+  if (!d || !eig_host) return fail(AMM_EINVAL, "NULL argument");
+  const amm_dec* c = is_sparse(d) ? d->inner : d;
+  if (!c || !is_circ(c)) return fail(AMM_ESTATE, "not a circulant decomposition");
+  if (!c->blocks.empty()) return fail(AMM_EINVAL, "blocked circulant handle: read the lists of each block");
+  const int64_t cnt = (int64_t)c->K_eff * c->n;
+  if (cap < cnt) return fail(AMM_EINVAL, "capacity %lld < %lld", (long long)cap, (long long)cnt);
+  if (cnt == 0) return AMM_OK;
+  std::vector<float2> L((size_t)cnt);
+  AMM_HIP(hipMemcpy(L.data(), c->L.ptr, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < cnt; ++i) {
+    eig_host[2 * i] = L[i].x;
+    eig_host[2 * i + 1] = L[i].y;
   }
   return AMM_OK;
 }

@@ -115,7 +115,8 @@ struct amm_ctx {
   int device = 0;
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[14];             // grow-only work areas for products (8-13: chirp-convolution path)
+  amm::DevBuf scratch[15];             // grow-only work areas for products (8-13: chirp-convolution path,
+                                       // 14: B at a spread row pitch for sparse products)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
   amm::DevBuf rsvd[10];                     // grow-only float64 work areas of the randomized SVD
@@ -251,10 +252,11 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
 // L16 (optional, n >= 1024): the lists as float16 pairs scaled by a power of
 // two (l16_inv = its inverse); the spectral products then run in float16 with
 // float32 sums (see cd_apply_kernel).
+// ldb: row pitch of B in floats (0 = p); out is contiguous.
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
                             bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
-                            const __half2* L16 = nullptr, float l16_inv = 1.0f);
+                            const __half2* L16 = nullptr, float l16_inv = 1.0f, int64_t ldb = 0);
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
                          bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
@@ -348,9 +350,10 @@ bool gemm_short_ok(int64_t M, int64_t N, int K);
 // Raw CSR x dense: out (rows x p) (+)= S B
 // rows of S from row_ptr, or per block of 4096 inner indices from blk_ptr
 // ((blocks + 1) offsets per row) when blocks > 1
+// (ldb, ldo: row pitches of B and out in floats; 0 = p)
 amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
                     const float* B, int64_t p, float* out, bool accumulate, hipStream_t s,
-                    const int32_t* blk_ptr = nullptr, int blocks = 1);
+                    const int32_t* blk_ptr = nullptr, int blocks = 1, int64_t ldb = 0, int64_t ldo = 0);
 
 // Delta A = A - (U S) V^T into dst (m x n)
 amm_status tsvd_residual(const float* A, int64_t m, int64_t n, int k, const float* US, const float* V,
@@ -369,7 +372,8 @@ amm_status sfft_first_order_term(amm_ctx* ctx, const amm_dec* dA, const amm_dec*
 // Sparse path
 amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
                           amm_dec* dec, float* R_out, hipStream_t s);
-amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool accumulate,
+// out (m x p, contiguous) (+)= S B, B with row pitch ldb (floats)
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool accumulate,
                     hipStream_t s);
 amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                            bool accumulate, hipStream_t s);
@@ -383,6 +387,16 @@ amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out);
 // ||x - y||_F^2 and ||x||_F^2 of count floats, float64 (synchronises s)
 amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStream_t s, double* dd, double* xx);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);
+// the same with row pitches (floats) on both sides
+amm_status transpose_ld_f32(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst,
+                            int64_t ld_dst, hipStream_t s);
+amm_status transpose_acc_ld_f32(const float* Y, int64_t ldy, int64_t rows, int64_t cols, float* out, int64_t ldo,
+                                bool accumulate, hipStream_t s);
+// Row pitch for a scratch copy of a matrix with `cols` columns that spreads a
+// column slice's rows over the L2 channels (cols + 64 for multiples of 2048).
+int64_t spread_pitch(int64_t cols);
+// dst (rows x cols, row pitch ld_dst) = src (rows x cols, contiguous); float4 aligned
+amm_status repitch_f32(const float* src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst, hipStream_t s);
 amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                            float* dX, float* dW, hipStream_t s);
 // Batched truncated-SVD products (tsvd_apply.hip)

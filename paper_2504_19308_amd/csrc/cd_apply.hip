@@ -201,7 +201,7 @@ __device__ __forceinline__ void read_h(const uint32_t* hs, int w, uint32_t (&x)[
 
 template <int LOG2N, bool ROWS, bool SPEC = false, bool H16 = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
-cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t extent,
+cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ out, int64_t ldo, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const void* __restrict__ L,
                 const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr, float l16_inv) {
   using Cfg = CdCfg<LOG2N>;
@@ -236,7 +236,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
         const int e = threadIdx.x + q * T;
         const int row = e / V, v = e % V;
         const int64_t c = first + 4 * v;
-        r[q] = (e < TOT && c < extent) ? *reinterpret_cast<const float4*>(X + (int64_t)row * extent + c)
+        r[q] = (e < TOT && c < extent) ? *reinterpret_cast<const float4*>(X + (int64_t)row * ldx + c)
                                        : float4{0.f, 0.f, 0.f, 0.f};
       }
 #pragma unroll
@@ -248,14 +248,14 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       for (int e = threadIdx.x; e < N * 2 * C; e += T) {
         const int rc = e % (2 * C), row = e / (2 * C);
         const int64_t c = first + rc;
-        ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * extent + c] : 0.f;
+        ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * ldx + c] : 0.f;
       }
     }
   } else {
     for (int e = threadIdx.x; e < N * 2 * C; e += T) {
       const int q = e % N, rl = e / N;
       const int64_t r = first + rl;
-      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = r < extent ? X[r * N + q] : 0.f;
+      ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] = r < extent ? X[r * ldx + q] : 0.f;
     }
   }
   __syncthreads();
@@ -505,7 +505,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
         if (e < TOT && c < extent) {
           float4 y = *reinterpret_cast<const float4*>(&lds[pad_bin(row) * C + 2 * v]);
           y = float4{y.x * scale, y.y * scale, y.z * scale, y.w * scale};
-          float4* o = reinterpret_cast<float4*>(out + (int64_t)row * extent + c);
+          float4* o = reinterpret_cast<float4*>(out + (int64_t)row * ldo + c);
           if (accumulate) {
             const float4 z = *o;
             y = float4{y.x + z.x, y.y + z.y, y.z + z.z, y.w + z.w};
@@ -519,7 +519,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
         const int64_t c = first + rc;
         if (c < extent) {
           const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * scale;
-          float* o = out + (int64_t)row * extent + c;
+          float* o = out + (int64_t)row * ldo + c;
           *o = accumulate ? *o + v : v;
         }
       }
@@ -530,7 +530,7 @@ cd_apply_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t ex
       const int64_t r = first + rl;
       if (r < extent) {
         const float v = ldsf[(pad_bin(q) * C + (rl >> 1)) * 2 + (rl & 1)] * scale;
-        float* o = out + r * N + q;
+        float* o = out + r * ldo + q;
         *o = accumulate ? *o + v : v;
       }
     }
@@ -707,15 +707,15 @@ amm_status launch_chirp(bool rows, const float* X, float* out, int64_t extent, i
 }
 
 template <int LOG2N, bool ROWS, bool H16>
-void launch_cd_kernel(dim3 grid, dim3 block, hipStream_t s, const float* X, float* out, int64_t extent, int K,
-                      const int32_t* shifts, const void* L, const float2* tw, int acc, int vec4, CdPairs pr,
-                      float l16_inv) {
-  hipLaunchKernelGGL((cd_apply_kernel<LOG2N, ROWS, false, H16>), grid, block, 0, s, X, out,
+void launch_cd_kernel(dim3 grid, dim3 block, hipStream_t s, const float* X, int64_t ldx, float* out, int64_t ldo,
+                      int64_t extent, int K, const int32_t* shifts, const void* L, const float2* tw, int acc, int vec4,
+                      CdPairs pr, float l16_inv) {
+  hipLaunchKernelGGL((cd_apply_kernel<LOG2N, ROWS, false, H16>), grid, block, 0, s, X, ldx, out, ldo,
                      extent, K, shifts, L, tw, acc, vec4, pr, l16_inv);
 }
 
 template <int LOG2N>
-amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int K,
+amm_status launch_cd(bool rows, const float* X, int64_t ldx, float* out, int64_t ldo, int64_t extent, int K,
                      const int32_t* shifts, const void* L, const float2* tw, bool acc,
                      hipStream_t s, bool spec, CdPairs pr, bool h16, float l16_inv) {
   using Cfg = CdCfg<LOG2N>;
@@ -725,33 +725,38 @@ amm_status launch_cd(bool rows, const float* X, float* out, int64_t extent, int 
   dim3 grid((unsigned)tiles), block(Cfg::T);
   TimedLaunch tl(spec ? "cd_spectrum" : (rows ? "cd_apply_rows" : "cd_apply_columns"), s);
   // float4 path: whole float4 groups inside a row and 16-byte aligned rows
-  const int vec4 = (!rows && 2 * Cfg::C >= 4 && extent % 4 == 0 && ((uintptr_t)X % 16) == 0 &&
-                    ((uintptr_t)out % 16) == 0) ? 1 : 0;
+  const int vec4 = (!rows && 2 * Cfg::C >= 4 && extent % 4 == 0 && ldx % 4 == 0 && ldo % 4 == 0 &&
+                    ((uintptr_t)X % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
   const int a = acc ? 1 : 0;
   if (spec)
-    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, out, extent, 0,
+    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, ldx, out, ldo, extent, 0,
                        shifts, L, tw, 0, vec4, pr, 1.0f);
   else if (h16) {
     if constexpr (LOG2N >= kH16MinLog2) {
-      if (rows) launch_cd_kernel<LOG2N, true, true>(grid, block, s, X, out, extent, K, shifts, L, tw, a, 0, pr, l16_inv);
-      else launch_cd_kernel<LOG2N, false, true>(grid, block, s, X, out, extent, K, shifts, L, tw, a, vec4, pr, l16_inv);
+      if (rows)
+        launch_cd_kernel<LOG2N, true, true>(grid, block, s, X, ldx, out, ldo, extent, K, shifts, L, tw, a, 0, pr,
+                                            l16_inv);
+      else
+        launch_cd_kernel<LOG2N, false, true>(grid, block, s, X, ldx, out, ldo, extent, K, shifts, L, tw, a, vec4, pr,
+                                             l16_inv);
     } else {
       return fail(AMM_EUNSUPPORTED, "float16 spectral products need n >= %d", 1 << kH16MinLog2);
     }
   } else if (rows)
-    launch_cd_kernel<LOG2N, true, false>(grid, block, s, X, out, extent, K, shifts, L, tw, a, 0, pr, 1.0f);
+    launch_cd_kernel<LOG2N, true, false>(grid, block, s, X, ldx, out, ldo, extent, K, shifts, L, tw, a, 0, pr, 1.0f);
   else
-    launch_cd_kernel<LOG2N, false, false>(grid, block, s, X, out, extent, K, shifts, L, tw, a, vec4, pr, 1.0f);
+    launch_cd_kernel<LOG2N, false, false>(grid, block, s, X, ldx, out, ldo, extent, K, shifts, L, tw, a, vec4, pr,
+                                          1.0f);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
 
-amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t extent, int K,
-                       const int32_t* shifts, const void* L, const float2* tw, bool acc,
+amm_status dispatch_cd(bool rows, int log2n, const float* X, int64_t ldx, float* out, int64_t ldo, int64_t extent,
+                       int K, const int32_t* shifts, const void* L, const float2* tw, bool acc,
                        hipStream_t s, bool spec, CdPairs pr, bool h16 = false, float l16_inv = 1.0f) {
   switch (log2n) {
 #define AMM_CASE(L2) \
-  case L2: return launch_cd<L2>(rows, X, out, extent, K, shifts, L, tw, acc, s, spec, pr, h16, l16_inv);
+  case L2: return launch_cd<L2>(rows, X, ldx, out, ldo, extent, K, shifts, L, tw, acc, s, spec, pr, h16, l16_inv);
     AMM_CASE(1) AMM_CASE(2) AMM_CASE(3) AMM_CASE(4) AMM_CASE(5) AMM_CASE(6)
     AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12)
     AMM_CASE(13) AMM_CASE(14)
@@ -764,18 +769,21 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, float* out, int64_t
 
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
-                            bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv) {
+                            bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv,
+                            int64_t ldb) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  if (L16) return dispatch_cd(false, log2n, B, out, p, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
-  return dispatch_cd(false, log2n, B, out, p, K, shifts, L, tw, accumulate, s, false, pr);
+  const int64_t ldx = ldb > 0 ? ldb : p;
+  if (L16)
+    return dispatch_cd(false, log2n, B, ldx, out, p, p, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
+  return dispatch_cd(false, log2n, B, ldx, out, p, p, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
 amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t p, float* spec,
                                hipStream_t s) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  return dispatch_cd(false, log2n, B, spec, p, 0, nullptr, nullptr, tw, false, s, true, CdPairs{});
+  return dispatch_cd(false, log2n, B, p, spec, p, p, 0, nullptr, nullptr, tw, false, s, true, CdPairs{});
 }
 
 // Fused chirp-convolution product for 3 <= n <= 2048, n not a power of two:
@@ -807,8 +815,10 @@ amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  if (L16) return dispatch_cd(true, log2n, X, out, rows, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
-  return dispatch_cd(true, log2n, X, out, rows, K, shifts, L, tw, accumulate, s, false, pr);
+  const int64_t n = int64_t{1} << log2n;
+  if (L16)
+    return dispatch_cd(true, log2n, X, n, out, n, rows, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
+  return dispatch_cd(true, log2n, X, n, out, n, rows, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
 }  // namespace amm

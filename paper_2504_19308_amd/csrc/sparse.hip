@@ -12,6 +12,7 @@
 // the entries with key == T are then taken in row-major order until nnz is
 // reached.  A per-row pass writes CSR rows (column order) and R.
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "amm_internal.hpp"
@@ -133,8 +134,8 @@ constexpr int RPB = 16;   // rows per block
 
 __global__ void __launch_bounds__(256)
 spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t* __restrict__ col,
-            const float* __restrict__ val, const float* __restrict__ B, int64_t rows, int64_t p,
-            float* __restrict__ out, int accumulate, int nslices, int rgroups, int vec) {
+            const float* __restrict__ val, const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p,
+            float* __restrict__ out, int64_t ldo, int accumulate, int nslices, int rgroups, int vec) {
   const int bid = blockIdx.x;
   int slice, rg;
   if ((nslices & 7) == 0) {
@@ -149,8 +150,8 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
   const int64_t c0 = (int64_t)slice * SW + (threadIdx.x & 15) * 4;
   if (row >= rows || c0 >= p) return;
   const int e0 = rng[row * stride + blk], e1 = rng[row * stride + blk + 1];
-  float* o = out + row * p + c0;
-  if (vec) {  // p % 4 == 0 and 16-byte aligned B / out: c0 + 3 < p
+  float* o = out + row * ldo + c0;
+  if (vec) {  // p, ldb, ldo % 4 == 0 and 16-byte aligned B / out: c0 + 3 < p
     float4 acc{0.f, 0.f, 0.f, 0.f};
     int e = e0;
     for (; e + 4 <= e1; e += 4) {
@@ -159,7 +160,7 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         v[u] = val[e + u];
-        x[u] = *reinterpret_cast<const float4*>(B + (int64_t)col[e + u] * p + c0);
+        x[u] = *reinterpret_cast<const float4*>(B + (int64_t)col[e + u] * ldb + c0);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -168,7 +169,7 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
     }
     for (; e < e1; ++e) {
       const float v = val[e];
-      const float4 x = *reinterpret_cast<const float4*>(B + (int64_t)col[e] * p + c0);
+      const float4 x = *reinterpret_cast<const float4*>(B + (int64_t)col[e] * ldb + c0);
       acc.x += v * x.x; acc.y += v * x.y; acc.z += v * x.z; acc.w += v * x.w;
     }
     if (accumulate) {
@@ -180,27 +181,100 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     for (int e = e0; e < e1; ++e) {
       const float v = val[e];
-      const float* b = B + (int64_t)col[e] * p + c0;
+      const float* b = B + (int64_t)col[e] * ldb + c0;
       for (int q = 0; q < 4 && c0 + q < p; ++q) acc[q] += v * b[q];
     }
     for (int q = 0; q < 4 && c0 + q < p; ++q) o[q] = accumulate ? o[q] + acc[q] : acc[q];
   }
 }
 
-// out (cols x rows) (+)= Y^T for Y rows x cols, through 32 x 33 LDS tiles
-__global__ void transpose_acc_kernel(const float* __restrict__ Y, int64_t rows, int64_t cols,
-                                     float* __restrict__ out, int accumulate) {
+// The same product with the row's stored entries fetched sixteen at a time:
+// lane l of a row's 16 lanes loads entry base + l (one coalesced read of the
+// column indices and one of the values per row), and each entry is then
+// broadcast to the row's 16 lanes with ds_swizzle, so the index reads no
+// longer sit in front of every gather; eight gathers of B are in flight per
+// lane.  Needs the float4 path (p % 4 == 0, 16-byte aligned B and out).
+// A row's 16 lanes are one half of a 32-lane swizzle group; a row's lanes are
+// all active or all inactive together (they share the entry range), so a
+// broadcast never reads an inactive lane.
+template <int J>
+__device__ __forceinline__ int bcast16(int v) {
+  // bit mode: source lane = (lane & 0x10) | J within each group of 32
+  return __builtin_amdgcn_ds_swizzle(v, 0x10 | (J << 5));
+}
+
+template <int H, int... J>
+__device__ __forceinline__ void spmm_round(std::integer_sequence<int, J...>, int my_c, int my_v, int cnt,
+                                           const float* __restrict__ B, int64_t ldb, int64_t c0, bool ok,
+                                           float4& acc) {
+  // broadcasts first, by every lane of the row (each reads its own group's
+  // lanes), and only then the guarded gathers
+  int c[sizeof...(J)];
+  float v[sizeof...(J)];
+  float4 x[sizeof...(J)];
+  ((c[J] = bcast16<H * 8 + J>(my_c), v[J] = __int_as_float(bcast16<H * 8 + J>(my_v))), ...);
+  ((x[J] = (H * 8 + J < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)c[J] * ldb + c0)
+                                   : float4{0.f, 0.f, 0.f, 0.f}),
+   ...);
+  ((acc.x += v[J] * x[J].x, acc.y += v[J] * x[J].y, acc.z += v[J] * x[J].z, acc.w += v[J] * x[J].w), ...);
+}
+
+__global__ void __launch_bounds__(256)
+spmm_bcast(const int32_t* __restrict__ rng, int stride, int blk, const int32_t* __restrict__ col,
+           const float* __restrict__ val, const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p,
+           float* __restrict__ out, int64_t ldo, int accumulate, int nslices, int rgroups) {
+  const int bid = blockIdx.x;
+  int slice, rg;
+  if ((nslices & 7) == 0) {
+    const int xcd = bid & 7, local = bid >> 3;
+    slice = xcd * (nslices >> 3) + local / rgroups;
+    rg = local % rgroups;
+  } else {
+    slice = bid / rgroups;
+    rg = bid % rgroups;
+  }
+  const int lane16 = threadIdx.x & 15;
+  const int64_t row = (int64_t)rg * RPB + (threadIdx.x >> 4);
+  const int64_t c0 = (int64_t)slice * SW + lane16 * 4;
+  if (row >= rows) return;            // the whole row's 16 lanes leave together
+  const bool ok = c0 < p;             // lanes past the last column still serve the broadcasts
+  const int e0 = rng[row * stride + blk], e1 = rng[row * stride + blk + 1];
+  float4 acc{0.f, 0.f, 0.f, 0.f};
+  for (int base = e0; base < e1; base += 16) {
+    const int e = base + lane16;
+    int my_c = 0, my_v = 0;           // entries past the row's end add 0 x 0
+    if (e < e1) {
+      my_c = col[e];
+      my_v = __float_as_int(val[e]);
+    }
+    const int cnt = min(16, e1 - base);
+    spmm_round<0>(std::make_integer_sequence<int, 8>{}, my_c, my_v, cnt, B, ldb, c0, ok, acc);
+    if (cnt > 8) spmm_round<1>(std::make_integer_sequence<int, 8>{}, my_c, my_v, cnt, B, ldb, c0, ok, acc);
+  }
+  if (!ok) return;
+  float4* o = reinterpret_cast<float4*>(out + row * ldo + c0);
+  if (accumulate) {
+    const float4 z = *o;
+    acc = float4{acc.x + z.x, acc.y + z.y, acc.z + z.z, acc.w + z.w};
+  }
+  *o = acc;
+}
+
+// out (cols x rows, row pitch ldo) (+)= Y^T for Y rows x cols (row pitch ldy),
+// through 32 x 33 LDS tiles
+__global__ void transpose_acc_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int64_t cols,
+                                     float* __restrict__ out, int64_t ldo, int accumulate) {
   __shared__ float tile[32][33];
   const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
   for (int i = threadIdx.y; i < 32; i += 8) {
     const int64_t r = r0 + i, c = c0 + threadIdx.x;
-    if (r < rows && c < cols) tile[i][threadIdx.x] = Y[r * cols + c];
+    if (r < rows && c < cols) tile[i][threadIdx.x] = Y[r * ldy + c];
   }
   __syncthreads();
   for (int i = threadIdx.y; i < 32; i += 8) {
     const int64_t c = c0 + i, r = r0 + threadIdx.x;
     if (r < rows && c < cols) {
-      float* o = out + c * rows + r;
+      float* o = out + c * ldo + r;
       *o = accumulate ? *o + tile[threadIdx.x][i] : tile[threadIdx.x][i];
     }
   }
@@ -213,36 +287,76 @@ __global__ void fill_kernel(float* __restrict__ p, int64_t count, float v) {
 
 }  // namespace
 
-__global__ void transpose_kernel(const float* __restrict__ src, int64_t rows, int64_t cols,
-                                 float* __restrict__ dst) {
+__global__ void transpose_kernel(const float* __restrict__ src, int64_t lds_, int64_t rows, int64_t cols,
+                                 float* __restrict__ dst, int64_t ldd) {
   __shared__ float tile[32][33];
   const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
   for (int i = threadIdx.y; i < 32; i += 8) {
     const int64_t r = r0 + i, c = c0 + threadIdx.x;
-    if (r < rows && c < cols) tile[i][threadIdx.x] = src[r * cols + c];
+    if (r < rows && c < cols) tile[i][threadIdx.x] = src[r * lds_ + c];
   }
   __syncthreads();
   for (int i = threadIdx.y; i < 32; i += 8) {
     const int64_t c = c0 + i, r = r0 + threadIdx.x;
-    if (r < rows && c < cols) dst[c * rows + r] = tile[threadIdx.x][i];
+    if (r < rows && c < cols) dst[c * ldd + r] = tile[threadIdx.x][i];
   }
 }
 
-amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s) {
+amm_status transpose_ld_f32(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst,
+                            int64_t ld_dst, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return AMM_OK;
   if ((rows + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "transpose too tall");
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
-                     dim3(32, 8), 0, s, src, rows, cols, dst);
+                     dim3(32, 8), 0, s, src, ld_src, rows, cols, dst, ld_dst);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s) {
+  return transpose_ld_f32(src, cols, rows, cols, dst, rows, s);
+}
+
+amm_status transpose_acc_ld_f32(const float* Y, int64_t ldy, int64_t rows, int64_t cols, float* out, int64_t ldo,
+                                bool accumulate, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return AMM_OK;
+  if ((rows + 31) / 32 > 65535 || (cols + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "transpose too large");
+  hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
+                     dim3(32, 8), 0, s, Y, ldy, rows, cols, out, ldo, accumulate ? 1 : 0);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
 
 amm_status transpose_acc_f32(const float* Y, int64_t rows, int64_t cols, float* out, bool accumulate,
                              hipStream_t s) {
+  return transpose_acc_ld_f32(Y, cols, rows, cols, out, rows, accumulate, s);
+}
+
+// Row pitch (in floats) for a scratch copy of a matrix with `cols` columns
+// whose gathers or column reads would otherwise all fall on one L2 channel:
+// pitches that are large multiples of a power of two (16384 floats = 64 KiB,
+// say) put every row of a column slice at the same address bits; 64 extra
+// floats shift consecutive rows by 256 bytes.
+int64_t spread_pitch(int64_t cols) { return (cols >= 2048 && cols % 2048 == 0) ? cols + 64 : cols; }
+
+// dst (rows x cols, row pitch ld_dst) = src (rows x cols, contiguous)
+__global__ void repitch_kernel(const float4* __restrict__ src, int64_t rows, int64_t cols4, float4* __restrict__ dst,
+                               int64_t ld4) {
+  const int64_t total = rows * cols4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols4, c = i - r * cols4;
+    dst[r * ld4 + c] = src[i];
+  }
+}
+
+amm_status repitch_f32(const float* src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return AMM_OK;
-  if ((rows + 31) / 32 > 65535 || (cols + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "transpose too large");
-  hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
-                     dim3(32, 8), 0, s, Y, rows, cols, out, accumulate ? 1 : 0);
+  if (cols % 4 || ld_dst % 4 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+    return fail(AMM_EINVAL, "repitch needs float4-aligned rows");
+  TimedLaunch tl("repitch", s);
+  const int64_t cols4 = cols / 4, total = rows * cols4;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(repitch_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float4*>(src), rows, cols4,
+                     reinterpret_cast<float4*>(dst), ld_dst / 4);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -391,23 +505,26 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
 
 namespace {
 
+
 amm_status spmm_launch(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
-                       const float* B, int64_t p, float* out, bool acc, hipStream_t s, const int32_t* blk_ptr,
-                       int blocks) {
+                       const float* B, int64_t ldb, int64_t p, float* out, int64_t ldo, bool acc, hipStream_t s,
+                       const int32_t* blk_ptr, int blocks) {
   if (rows <= 0 || p <= 0) return AMM_OK;
   const int64_t nslices = (p + SW - 1) / SW, rgroups = (rows + RPB - 1) / RPB;
   if (nslices * rgroups > 0x7fffffff || rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
   if (blocks > 1 && !blk_ptr) return fail(AMM_EINVAL, "blocked SpMM without block ranges");
-  const int vec = (p % 4 == 0 && ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0) ? 1 : 0;
-  if (blocks <= 1) {
-    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, row_ptr, 1, 0, col, val, B,
-                       rows, p, out, acc ? 1 : 0, (int)nslices, (int)rgroups, vec);
-    AMM_HIP(hipGetLastError());
-    return AMM_OK;
-  }
-  for (int b = 0; b < blocks; ++b) {
-    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, blk_ptr, blocks + 1, b, col,
-                       val, B, rows, p, out, (acc || b > 0) ? 1 : 0, (int)nslices, (int)rgroups, vec);
+  const int vec = (p % 4 == 0 && ldb % 4 == 0 && ldo % 4 == 0 && ((uintptr_t)B % 16) == 0 &&
+                   ((uintptr_t)out % 16) == 0) ? 1 : 0;
+  const int32_t* rng = blocks <= 1 ? row_ptr : blk_ptr;
+  const int stride = blocks <= 1 ? 1 : blocks + 1;
+  for (int b = 0; b < std::max(blocks, 1); ++b) {
+    const int a = (acc || b > 0) ? 1 : 0;
+    if (vec)
+      hipLaunchKernelGGL(spmm_bcast, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, rng, stride, b, col, val,
+                         B, ldb, rows, p, out, ldo, a, (int)nslices, (int)rgroups);
+    else
+      hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, rng, stride, b, col,
+                         val, B, ldb, rows, p, out, ldo, a, (int)nslices, (int)rgroups, vec);
     AMM_HIP(hipGetLastError());
   }
   return AMM_OK;
@@ -417,36 +534,36 @@ amm_status spmm_launch(const int32_t* row_ptr, const int32_t* col, const float* 
 
 amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
                     const float* B, int64_t p, float* out, bool acc, hipStream_t s, const int32_t* blk_ptr,
-                    int blocks) {
+                    int blocks, int64_t ldb, int64_t ldo) {
   TimedLaunch tl("spmm_csr", s);
-  return spmm_launch(row_ptr, col, val, rows, B, p, out, acc, s, blk_ptr, blocks);
+  return spmm_launch(row_ptr, col, val, rows, B, ldb > 0 ? ldb : p, p, out, ldo > 0 ? ldo : p, acc, s, blk_ptr,
+                     blocks);
 }
 
-amm_status spmm_csr(const amm_dec* d, const float* B, int64_t p, float* out, bool acc, hipStream_t s) {
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool acc, hipStream_t s) {
   return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s,
-                  d->csr_blk.as<int32_t>(), d->csr_blocks);
+                  d->csr_blk.as<int32_t>(), d->csr_blocks, ldb, p);
 }
 
 // out (rows x p) (+)= X S for X rows x n and S n x p sparse:
 //   (X S)^T = S^T X^T, and S^T in CSR is S in CSC, so the product is the row
-//   gather above on X^T, transposed back into out.
+//   gather above on X^T, transposed back into out.  The transposed scratch
+//   copies get a pitch that spreads their rows over the L2 channels.
 amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                            bool acc, hipStream_t s) {
   const int64_t n = d->m, p = d->n;
   if (rows <= 0 || p <= 0) return AMM_OK;
   if ((rows + 31) / 32 > 65535 || (p + 31) / 32 > 65535) return fail(AMM_EUNSUPPORTED, "sparse operand too large");
-  AMM_TRY(ctx->scratch[6].reserve((size_t)n * rows * sizeof(float)));
-  AMM_TRY(ctx->scratch[7].reserve((size_t)p * rows * sizeof(float)));
+  const int64_t ld = spread_pitch(rows);
+  AMM_TRY(ctx->scratch[6].reserve((size_t)n * ld * sizeof(float)));
+  AMM_TRY(ctx->scratch[7].reserve((size_t)p * ld * sizeof(float)));
   float* Xt = ctx->scratch[6].as<float>();
   float* Y = ctx->scratch[7].as<float>();
   TimedLaunch tl("dense_times_csr", s);
-  AMM_TRY(transpose_f32(X, rows, n, Xt, s));
-  AMM_TRY(spmm_launch(d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, Xt, rows, Y,
-                      false, s, d->csc_blk.as<int32_t>(), d->csc_blocks));
-  hipLaunchKernelGGL(transpose_acc_kernel, dim3((unsigned)((rows + 31) / 32), (unsigned)((p + 31) / 32)),
-                     dim3(32, 8), 0, s, Y, p, rows, out, acc ? 1 : 0);
-  AMM_HIP(hipGetLastError());
-  return AMM_OK;
+  AMM_TRY(transpose_ld_f32(X, n, rows, n, Xt, ld, s));
+  AMM_TRY(spmm_launch(d->csc_ptr.as<int32_t>(), d->csc_row.as<int32_t>(), d->csc_val.as<float>(), p, Xt, ld, rows, Y,
+                      ld, false, s, d->csc_blk.as<int32_t>(), d->csc_blocks));
+  return transpose_acc_ld_f32(Y, ld, p, rows, out, p, acc, s);
 }
 
 }  // namespace amm

@@ -34,12 +34,7 @@ def rng_of(config: int, operand: int, stream: int = 0) -> np.random.Generator:
 # ---------------------------------------------------------------------------
 def _sign_fixed_q(M, qr):
     Q, R = qr(M)
-    d = np.sign(np.diag(R)) if isinstance(R, np.ndarray) else None
-    if d is None:  # torch path
-        import torch
-        d = torch.sign(torch.diagonal(R))
-        d = torch.where(d == 0, torch.ones_like(d), d)
-        return Q * d.unsqueeze(0)
+    d = np.sign(np.diag(R))
     d[d == 0] = 1.0
     return Q * d[None, :]
 
@@ -47,16 +42,18 @@ def _sign_fixed_q(M, qr):
 def haar_columns(rows: int, cols: int, rng: np.random.Generator, device=None):
     """rows x cols matrix with orthonormal, Haar-distributed columns (cols <= rows).
 
-    With ``device`` set (a torch device string) the Gaussian draw still comes
-    from ``rng`` on the host; only the QR runs on that device in float64.  The
-    sign fix makes Q unique, so host and device results agree to rounding.
+    The Gaussian draw and the QR run on the host in float64 (the sign fix
+    makes Q unique); with ``device`` set (a torch device string) the factor is
+    then copied there as a float64 tensor.  No device linear-algebra library
+    runs in the generator, so profiled processes see only the library's own
+    kernels and plain copies and products.
     """
     M = rng.standard_normal((rows, cols))
+    Q = _sign_fixed_q(M, np.linalg.qr)
     if device is None:
-        return _sign_fixed_q(M, np.linalg.qr)
+        return Q
     import torch
-    Mt = torch.from_numpy(M).to(device=device, dtype=torch.float64)
-    return _sign_fixed_q(Mt, torch.linalg.qr)
+    return torch.from_numpy(np.ascontiguousarray(Q)).to(device=device, dtype=torch.float64)
 
 
 def spectral_matrix(m: int, n: int, sigma: np.ndarray, rng: np.random.Generator,

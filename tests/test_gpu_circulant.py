@@ -119,6 +119,12 @@ def test_decompose_parity(n, K):
     inf = d.info()
     assert inf["K_eff"] == len(dec.S)
     assert np.isclose(inf["norm_residual"], dec.norm_residual(), rtol=1e-9, atol=1e-12)
+    # eigenvalue lists (Alg. 2.3 step 4) directly: float64 on the device, kept
+    # as float32, so each part within its float32 rounding of the oracle's value
+    L = d.lists()
+    assert L.shape == dec.L.shape
+    tol = 2.0 ** -24 * np.abs(dec.L) + 1e-12 * np.max(np.abs(dec.L))
+    assert np.all(np.abs(L.real - dec.L.real) <= tol) and np.all(np.abs(L.imag - dec.L.imag) <= tol)
     got = host(c.approx_matmul(d, gpu(B)))
     assert rel(got, np.real(oc.apply_zeroth(dec, B))) < TOL_F32
 
