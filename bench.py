@@ -116,7 +116,7 @@ def rel_err(M, exact64):
 # kernel-name tag of a TimedLaunch -> (name of the kernel in a rocprofv3 trace,
 # dispatches per tag launch) for the headline step
 HEADLINE_KERNELS = {
-    "spmm_csr": ("spmm_bcast", 4),                                 # one dispatch per block of 4096 inner indices
+    "spmm_csr": ("spmm_narrow<16>", 1),
     "cd_apply_columns": ("cd_apply_kernel<14, false, false, true>", 1),
     "repitch": ("repitch_kernel", 1),
 }

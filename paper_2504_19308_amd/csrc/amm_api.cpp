@@ -219,29 +219,35 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     return blocked_apply(ctx, d, B, p, out, ctx->scratch[6].as<float>(), s);
   }
   if (is_sparse(d)) {
-    // The row gathers of the sparse part (and the column reads of a circulant
-    // residue) at a row pitch that is a large power of two all land on one L2
-    // channel: both read a copy of B at a spread pitch instead.  The residue
-    // goes first (it writes out), the sparse part then adds its rows.
-    const float* Bs = B;
-    int64_t ldb = p;
+    // The row gathers of the sparse part (and the column reads and writes of
+    // a circulant residue) at a row pitch that is a large power of two all
+    // land on one L2 channel: both read a copy of B at a spread pitch, the
+    // residue's product goes to a spread-pitch buffer, and the sparse part
+    // writes out = S B + that buffer.
     const int64_t sp = spread_pitch(p);
-    if (sp != p && d->nnz > 0 && ((uintptr_t)B % 16) == 0) {
+    const amm_dec* in = d->inner;
+    if (sp != p && d->nnz > 0 && ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0) {
       AMM_TRY(ctx->scratch[14].reserve((size_t)d->n * sp * sizeof(float)));
-      AMM_TRY(repitch_f32(B, d->n, p, ctx->scratch[14].as<float>(), sp, s));
-      Bs = ctx->scratch[14].as<float>();
-      ldb = sp;
+      float* Bs = ctx->scratch[14].as<float>();
+      AMM_TRY(repitch_f32(B, d->n, p, Bs, sp, s));
+      if (!acc && in && is_circ(in) && in->blocks.empty() && is_pow2(in->n) && in->K_eff > 0) {
+        AMM_TRY(ctx->scratch[15].reserve((size_t)d->m * sp * sizeof(float)));
+        float* Y = ctx->scratch[15].as<float>();
+        AMM_TRY(cd_apply_columns(ctx, log2_exact(in->n), in->K_eff, in->shifts.as<int32_t>(), in->L.as<float2>(), Bs,
+                                 p, Y, false, s, in->pairs_of(false), in->lists16(false), in->l16_inv, sp, sp));
+        return spmm_csr(d, Bs, sp, p, out, false, s, Y, sp);
+      }
+      if (in) {
+        AMM_TRY(left_apply(ctx, in, B, p, out, acc, s));
+        acc = true;
+      }
+      return spmm_csr(d, Bs, sp, p, out, acc, s);
     }
-    if (d->inner) {
-      if (is_circ(d->inner) && d->inner->blocks.empty() && is_pow2(d->inner->n) && d->inner->K_eff > 0)
-        AMM_TRY(cd_apply_columns(ctx, log2_exact(d->inner->n), d->inner->K_eff, d->inner->shifts.as<int32_t>(),
-                                 d->inner->L.as<float2>(), Bs, p, out, acc, s, d->inner->pairs_of(false),
-                                 d->inner->lists16(false), d->inner->l16_inv, ldb));
-      else
-        AMM_TRY(left_apply(ctx, d->inner, B, p, out, acc, s));
+    if (in) {
+      AMM_TRY(left_apply(ctx, in, B, p, out, acc, s));
       acc = true;
     }
-    return spmm_csr(d, Bs, ldb, p, out, acc, s);
+    return spmm_csr(d, B, p, p, out, acc, s);
   }
   if (is_sfft(d)) return sfft_left_apply(ctx, d, B, p, out, acc, s);
   if (is_circ(d)) return circ_columns(ctx, d, B, p, out, acc, s);

@@ -115,8 +115,9 @@ struct amm_ctx {
   int device = 0;
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[15];             // grow-only work areas for products (8-13: chirp-convolution path,
-                                       // 14: B at a spread row pitch for sparse products)
+  amm::DevBuf scratch[16];             // grow-only work areas for products (8-13: chirp-convolution path,
+                                       // 14, 15: B and the residue's product at a spread row pitch for
+                                       // sparse products)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
   amm::DevBuf rsvd[10];                     // grow-only float64 work areas of the randomized SVD
@@ -252,11 +253,12 @@ amm_status twiddles64(amm_ctx* ctx, int log2n, const double2** out);
 // L16 (optional, n >= 1024): the lists as float16 pairs scaled by a power of
 // two (l16_inv = its inverse); the spectral products then run in float16 with
 // float32 sums (see cd_apply_kernel).
-// ldb: row pitch of B in floats (0 = p); out is contiguous.
+// ldb, ldo: row pitches of B and out in floats (0 = p).
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
                             bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
-                            const __half2* L16 = nullptr, float l16_inv = 1.0f, int64_t ldb = 0);
+                            const __half2* L16 = nullptr, float l16_inv = 1.0f, int64_t ldb = 0,
+                            int64_t ldo = 0);
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
                          bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
@@ -372,9 +374,10 @@ amm_status sfft_first_order_term(amm_ctx* ctx, const amm_dec* dA, const amm_dec*
 // Sparse path
 amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
                           amm_dec* dec, float* R_out, hipStream_t s);
-// out (m x p, contiguous) (+)= S B, B with row pitch ldb (floats)
+// out (m x p, contiguous) (+)= S B, B with row pitch ldb (floats); with
+// `add` (row pitch ld_add; float4-aligned operands only) out = S B + add
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool accumulate,
-                    hipStream_t s);
+                    hipStream_t s, const float* add = nullptr, int64_t ld_add = 0);
 amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                            bool accumulate, hipStream_t s);
 

@@ -770,13 +770,13 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, int64_t ldx, float*
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,
                             bool accumulate, hipStream_t s, CdPairs pr, const __half2* L16, float l16_inv,
-                            int64_t ldb) {
+                            int64_t ldb, int64_t ldo) {
   const float2* tw = nullptr;
   AMM_TRY(twiddles32(ctx, log2n, &tw));
-  const int64_t ldx = ldb > 0 ? ldb : p;
+  const int64_t ldx = ldb > 0 ? ldb : p, ldy = ldo > 0 ? ldo : p;
   if (L16)
-    return dispatch_cd(false, log2n, B, ldx, out, p, p, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
-  return dispatch_cd(false, log2n, B, ldx, out, p, p, K, shifts, L, tw, accumulate, s, false, pr);
+    return dispatch_cd(false, log2n, B, ldx, out, ldy, p, K, shifts, L16, tw, accumulate, s, false, pr, true, l16_inv);
+  return dispatch_cd(false, log2n, B, ldx, out, ldy, p, K, shifts, L, tw, accumulate, s, false, pr);
 }
 
 amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t p, float* spec,

@@ -188,41 +188,49 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
   }
 }
 
-// The same product with the row's stored entries fetched sixteen at a time:
-// lane l of a row's 16 lanes loads entry base + l (one coalesced read of the
-// column indices and one of the values per row), and each entry is then
-// broadcast to the row's 16 lanes with ds_swizzle, so the index reads no
-// longer sit in front of every gather; eight gathers of B are in flight per
-// lane.  Needs the float4 path (p % 4 == 0, 16-byte aligned B and out).
-// A row's 16 lanes are one half of a 32-lane swizzle group; a row's lanes are
-// all active or all inactive together (they share the entry range), so a
-// broadcast never reads an inactive lane.
+// S B with S in CSR, float4 path (p, ldb, ldo % 4 == 0, 16-byte aligned B and
+// out).  Slices of 32 columns, 8 lanes per row (a float4 each), whole rows in
+// one pass: a slice of B is n x 128 bytes (2 MiB at n = 16384), held in one
+// XCD's L2 while that XCD sweeps the slice's rows (blocks are dealt so that
+// every XCD owns whole slices).  A row's stored entries come G at a time, one
+// or two per lane in one coalesced read of the indices and one of the values,
+// and are broadcast to the row's 8 lanes with ds_swizzle; the next G are read
+// before the current G rows of B are gathered.  With `add` the result is
+// out = S B + add (add with row pitch ld_add), else out (+)= S B.
 template <int J>
-__device__ __forceinline__ int bcast16(int v) {
-  // bit mode: source lane = (lane & 0x10) | J within each group of 32
-  return __builtin_amdgcn_ds_swizzle(v, 0x10 | (J << 5));
+__device__ __forceinline__ int bcast8(int v) {
+  // bit mode: source lane = (lane & 0x18) | J within each group of 32
+  return __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));
 }
 
 template <int H, int... J>
-__device__ __forceinline__ void spmm_round(std::integer_sequence<int, J...>, int my_c, int my_v, int cnt,
-                                           const float* __restrict__ B, int64_t ldb, int64_t c0, bool ok,
-                                           float4& acc) {
-  // broadcasts first, by every lane of the row (each reads its own group's
-  // lanes), and only then the guarded gathers
+__device__ __forceinline__ void narrow_round(std::integer_sequence<int, J...>, int my_c, int my_v, int cnt,
+                                             const float* __restrict__ B, int64_t ldb, int64_t c0, bool ok,
+                                             float4& acc) {
+  // entries 8 H + j of the round, held by lane j of the row's group
   int c[sizeof...(J)];
   float v[sizeof...(J)];
   float4 x[sizeof...(J)];
-  ((c[J] = bcast16<H * 8 + J>(my_c), v[J] = __int_as_float(bcast16<H * 8 + J>(my_v))), ...);
-  ((x[J] = (H * 8 + J < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)c[J] * ldb + c0)
+  ((c[J] = bcast8<J>(my_c), v[J] = __int_as_float(bcast8<J>(my_v))), ...);
+  ((x[J] = (8 * H + J < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)c[J] * ldb + c0)
                                    : float4{0.f, 0.f, 0.f, 0.f}),
    ...);
   ((acc.x += v[J] * x[J].x, acc.y += v[J] * x[J].y, acc.z += v[J] * x[J].z, acc.w += v[J] * x[J].w), ...);
 }
 
+constexpr int SWN = 32;   // columns per slice, narrow form
+constexpr int RPBN = 32;  // rows per block, narrow form
+constexpr int kNarrowRound = 16;   // entries per round (two per lane): 4.9 ms against 5.4 ms for 8 at n = 16384
+
+// G: entries per round (8 or 16: one or two per lane), the next round's
+// entries loaded before the current round's gathers.
+template <int G>
 __global__ void __launch_bounds__(256)
-spmm_bcast(const int32_t* __restrict__ rng, int stride, int blk, const int32_t* __restrict__ col,
-           const float* __restrict__ val, const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p,
-           float* __restrict__ out, int64_t ldo, int accumulate, int nslices, int rgroups) {
+spmm_narrow(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
+            const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p, float* __restrict__ out,
+            int64_t ldo, int accumulate, const float* __restrict__ add, int64_t ld_add, int nslices, int rgroups) {
+  static_assert(G == 8 || G == 16, "one or two entries per lane and round");
+  constexpr int H = G / 8;
   const int bid = blockIdx.x;
   int slice, rg;
   if ((nslices & 7) == 0) {
@@ -233,27 +241,48 @@ spmm_bcast(const int32_t* __restrict__ rng, int stride, int blk, const int32_t* 
     slice = bid / rgroups;
     rg = bid % rgroups;
   }
-  const int lane16 = threadIdx.x & 15;
-  const int64_t row = (int64_t)rg * RPB + (threadIdx.x >> 4);
-  const int64_t c0 = (int64_t)slice * SW + lane16 * 4;
-  if (row >= rows) return;            // the whole row's 16 lanes leave together
+  const int lane8 = threadIdx.x & 7;
+  const int64_t row = (int64_t)rg * RPBN + (threadIdx.x >> 3);
+  if (row >= rows) return;            // a row's 8 lanes leave together
+  const int64_t c0 = (int64_t)slice * SWN + lane8 * 4;
   const bool ok = c0 < p;             // lanes past the last column still serve the broadcasts
-  const int e0 = rng[row * stride + blk], e1 = rng[row * stride + blk + 1];
-  float4 acc{0.f, 0.f, 0.f, 0.f};
-  for (int base = e0; base < e1; base += 16) {
-    const int e = base + lane16;
-    int my_c = 0, my_v = 0;           // entries past the row's end add 0 x 0
+  const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
+  int nc[H], nv[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int e = e0 + 8 * h + lane8;
+    nc[h] = 0;
+    nv[h] = 0;
     if (e < e1) {
-      my_c = col[e];
-      my_v = __float_as_int(val[e]);
+      nc[h] = col[e];
+      nv[h] = __float_as_int(val[e]);
     }
-    const int cnt = min(16, e1 - base);
-    spmm_round<0>(std::make_integer_sequence<int, 8>{}, my_c, my_v, cnt, B, ldb, c0, ok, acc);
-    if (cnt > 8) spmm_round<1>(std::make_integer_sequence<int, 8>{}, my_c, my_v, cnt, B, ldb, c0, ok, acc);
+  }
+  float4 acc{0.f, 0.f, 0.f, 0.f};
+  for (int base = e0; base < e1; base += G) {
+    int cc[H], cv[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      cc[h] = nc[h];
+      cv[h] = nv[h];
+      const int e = base + G + 8 * h + lane8;
+      nc[h] = 0;
+      nv[h] = 0;
+      if (e < e1) {
+        nc[h] = col[e];
+        nv[h] = __float_as_int(val[e]);
+      }
+    }
+    narrow_round<0>(std::make_integer_sequence<int, 8>{}, cc[0], cv[0], e1 - base, B, ldb, c0, ok, acc);
+    if constexpr (H == 2)
+      narrow_round<1>(std::make_integer_sequence<int, 8>{}, cc[H - 1], cv[H - 1], e1 - base, B, ldb, c0, ok, acc);
   }
   if (!ok) return;
   float4* o = reinterpret_cast<float4*>(out + row * ldo + c0);
-  if (accumulate) {
+  if (add) {
+    const float4 z = *reinterpret_cast<const float4*>(add + row * ld_add + c0);
+    acc = float4{acc.x + z.x, acc.y + z.y, acc.z + z.z, acc.w + z.w};
+  } else if (accumulate) {
     const float4 z = *o;
     acc = float4{acc.x + z.x, acc.y + z.y, acc.z + z.z, acc.w + z.w};
   }
@@ -506,24 +535,31 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
 namespace {
 
 
+// out = S B (+ out if acc, or + add when add != nullptr: float4 path only)
 amm_status spmm_launch(const int32_t* row_ptr, const int32_t* col, const float* val, int64_t rows,
                        const float* B, int64_t ldb, int64_t p, float* out, int64_t ldo, bool acc, hipStream_t s,
-                       const int32_t* blk_ptr, int blocks) {
+                       const int32_t* blk_ptr, int blocks, const float* add = nullptr, int64_t ld_add = 0) {
   if (rows <= 0 || p <= 0) return AMM_OK;
   const int64_t nslices = (p + SW - 1) / SW, rgroups = (rows + RPB - 1) / RPB;
   if (nslices * rgroups > 0x7fffffff || rgroups > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
   if (blocks > 1 && !blk_ptr) return fail(AMM_EINVAL, "blocked SpMM without block ranges");
   const int vec = (p % 4 == 0 && ldb % 4 == 0 && ldo % 4 == 0 && ((uintptr_t)B % 16) == 0 &&
                    ((uintptr_t)out % 16) == 0) ? 1 : 0;
+  if (vec) {
+    const int64_t ns = (p + SWN - 1) / SWN, rgs = (rows + RPBN - 1) / RPBN;
+    if (ns * rgs > 0x7fffffff) return fail(AMM_EUNSUPPORTED, "SpMM grid too large");
+    if (add && (ld_add % 4 || ((uintptr_t)add % 16))) return fail(AMM_EINVAL, "SpMM addend not float4 aligned");
+    hipLaunchKernelGGL(spmm_narrow<kNarrowRound>, dim3((unsigned)(ns * rgs)), dim3(256), 0, s, row_ptr, col, val, B,
+                       ldb, rows, p, out, ldo, acc ? 1 : 0, add, ld_add, (int)ns, (int)rgs);
+    AMM_HIP(hipGetLastError());
+    return AMM_OK;
+  }
+  if (add) return fail(AMM_EINVAL, "SpMM with an addend needs the float4 path");
   const int32_t* rng = blocks <= 1 ? row_ptr : blk_ptr;
   const int stride = blocks <= 1 ? 1 : blocks + 1;
   for (int b = 0; b < std::max(blocks, 1); ++b) {
     const int a = (acc || b > 0) ? 1 : 0;
-    if (vec)
-      hipLaunchKernelGGL(spmm_bcast, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, rng, stride, b, col, val,
-                         B, ldb, rows, p, out, ldo, a, (int)nslices, (int)rgroups);
-    else
-      hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, rng, stride, b, col,
+    hipLaunchKernelGGL(spmm_slices, dim3((unsigned)(nslices * rgroups)), dim3(256), 0, s, rng, stride, b, col,
                          val, B, ldb, rows, p, out, ldo, a, (int)nslices, (int)rgroups, vec);
     AMM_HIP(hipGetLastError());
   }
@@ -540,9 +576,11 @@ amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val
                      blocks);
 }
 
-amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool acc, hipStream_t s) {
-  return spmm_raw(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, p, out, acc, s,
-                  d->csr_blk.as<int32_t>(), d->csr_blocks, ldb, p);
+amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool acc, hipStream_t s,
+                    const float* add, int64_t ld_add) {
+  TimedLaunch tl("spmm_csr", s);
+  return spmm_launch(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, ldb, p, out, p,
+                     acc, s, d->csr_blk.as<int32_t>(), d->csr_blocks, add, ld_add);
 }
 
 // out (rows x p) (+)= X S for X rows x n and S n x p sparse:
