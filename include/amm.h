@@ -253,6 +253,28 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
                              const float* B, int64_t n, int64_t p, float* out,
                              void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as amm_approx_matmul for truncated-SVD handles, through the split
+ * path only (dA of rank 32 or 64 with dB NULL or of rank 32/64, or rank 128
+ * with dB NULL or of rank 128; m, p and n multiples of 128).  Its
+ * intermediates live in one fixed array of 32 MiB per device (8 Mi floats,
+ * reserved on a device when the library's code is first loaded there -- at
+ * the latest by amm_ctx_create, which looks up its address -- and held until
+ * the process ends; the
+ * request's need is (S_G + 1) k_A p + (S_H + 1) k_B m + 64 floats for the
+ * split counts S the product picks), so the call allocates nothing and never
+ * synchronises.  Larger needs return AMM_EUNSUPPORTED, other handle kinds
+ * AMM_EUNSUPPORTED, a first-order request without A borrowed by dA or
+ * Delta B kept by dB AMM_ESTATE, a device on which no context was created
+ * AMM_ESTATE.  Every call on a device shares that device's array: calls that
+ * overlap on one device (two streams, two threads) race and must be ordered
+ * by the caller.  Nothing in the array needs to start at zero; each call
+ * overwrites what it reads. */
+amm_status amm_approx_matmul_static(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
+                                    const float* B, int64_t n, int64_t p, float* out,
+                                    void* stream);
+
 /* ---- batches of products ---------------------------------------------------- */
 
 /* Plan `count` zeroth-order products out_i = Atil_i B_i of truncated-SVD

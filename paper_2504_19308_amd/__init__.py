@@ -372,6 +372,17 @@ class Context:
             n, p, C.c_void_p(out.data_ptr()), _stream_ptr(self.torch, B.device)))
         return out
 
+    def approx_matmul_static(self, dA: Decomposition, B, out, dB: Decomposition | None = None):
+        """The product of truncated-SVD handles into a caller-provided `out`,
+        with no device allocation (amm_approx_matmul_static)."""
+        _need_f32_cuda(B, "B")
+        _need_f32_cuda(out, "out")
+        n, p = B.shape
+        _lib.check(_lib.load().amm_approx_matmul_static(
+            self.handle, dA.handle, dB.handle if dB is not None else None, C.c_void_p(B.data_ptr()),
+            n, p, C.c_void_p(out.data_ptr()), _stream_ptr(self.torch, B.device)))
+        return out
+
 
 def _make_autograd():
     import torch

@@ -382,6 +382,7 @@ amm_status amm_ctx_create(amm_ctx** ctx, int device) {
   AMM_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(AMM_EINVAL, "device %d out of range (%d devices)", device, count);
   AMM_HIP(hipSetDevice(device));
+  static_scratch_init(device);   // the fixed scratch's address on this device
   amm_ctx* c = new amm_ctx();
   c->device = device;
   *ctx = c;
@@ -1035,6 +1036,39 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   const float* dAres = nullptr;
   AMM_TRY(residual_of(ctx, dA, &dAres, s));
   return right_apply(ctx, dAres, dA->m, dB, out, true, s);
+}
+
+amm_status amm_approx_matmul_static(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B, int64_t n,
+                                    int64_t p, float* out, void* stream) {
+  if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");
+  if (n != dA->n) return fail(AMM_ESHAPE, "B has %lld rows, A has %lld columns", (long long)n, (long long)dA->n);
+  if (p < 0) return fail(AMM_ESHAPE, "negative column count");
+  if (p == 0) return AMM_OK;
+  if (!B || !out) return fail(AMM_EINVAL, "NULL argument");
+  if (dB && (dB->m != n || dB->n != p)) return fail(AMM_ESHAPE, "dB describes a %lldx%lld operand, B is %lldx%lld",
+                                                    (long long)dB->m, (long long)dB->n, (long long)n, (long long)p);
+  if (B == out) return fail(AMM_EINVAL, "out aliases B");
+  if (!is_tsvd(dA) || (dB && !is_tsvd(dB)))
+    return fail(AMM_EUNSUPPORTED, "the fixed-scratch product takes truncated-SVD handles only");
+  if (dB && !(dA->A_borrowed && dB->residual.ptr))
+    return fail(AMM_ESTATE, "first order needs A borrowed by dA and Delta B kept by dB");
+  const int ka = dA->K_eff, kb = dB ? dB->K_eff : 0;
+  if (!tsvd_split_shapes(dA->m, n, p, ka, kb))
+    return fail(AMM_EUNSUPPORTED, "the fixed-scratch product needs ranks 32/64 (or 128 with 0 or 128), m, p "
+                                  "multiples of 128 and n a multiple of 128");
+  const size_t need = tsvd_split_scratch(dA->m, n, p, ka, kb);
+  if (need > kStaticScratchFloats)
+    return fail(AMM_EUNSUPPORTED, "the product needs %zu scratch floats, more than the fixed %zu", need,
+                kStaticScratchFloats);
+  float* scr = nullptr;
+  AMM_TRY(static_scratch(ctx->device, &scr));
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  if (!dB)
+    return tsvd_split_product(dA->m, n, p, ka, 0, dA->V.as<float>(), dA->US.as<float>(), B, nullptr, nullptr,
+                              nullptr, scr, kStaticScratchFloats, out, s);
+  return tsvd_split_product(dA->m, n, p, ka, kb, dA->V.as<float>(), dA->US.as<float>(), dB->residual.as<float>(),
+                            dA->A_borrowed, dB->U.as<float>(), dB->VS.as<float>(), scr, kStaticScratchFloats, out, s);
 }
 
 amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X, const float* dY,

@@ -335,6 +335,13 @@ amm_status gemm_f64(int64_t M, int64_t N, int64_t Kd, double alpha, const double
 bool tsvd_fast_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb);
 bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb);
 size_t tsvd_split_scratch(int64_t m, int64_t n, int64_t p, int ka, int kb);
+// Fixed per-device scratch of amm_approx_matmul_static (floats).
+constexpr size_t kStaticScratchFloats = size_t{8} << 20;   // 32 MiB
+// Look up the device address of the fixed scratch on `device` (current);
+// once per device, from amm_ctx_create.
+void static_scratch_init(int device);
+// Its device address on `device`, or an error if the lookup failed or never ran.
+amm_status static_scratch(int device, float** out);
 amm_status tsvd_split_product(int64_t m, int64_t n, int64_t p, int ka, int kb, const float* V_A, const float* US_A,
                               const float* Y, const float* X, const float* U_B, const float* VS_B, float* scratch,
                               size_t scratch_floats, float* out, hipStream_t s);

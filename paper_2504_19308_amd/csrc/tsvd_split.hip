@@ -24,6 +24,9 @@
 // operand of MFMA s with reduction index c + 4g + s.  The four waves of a
 // workgroup split its reduction range and meet in LDS; workgroups split the
 // reduction S ways and leave S partials.
+#include <map>
+#include <mutex>
+
 #include "amm_internal.hpp"
 
 namespace amm {
@@ -451,6 +454,36 @@ bool tsvd_split_shapes(int64_t m, int64_t n, int64_t p, int ka, int kb) {
   return ranks && m > 0 && p > 0 && m % OT == 0 &&
          p % OT == 0 && n % (PW * 16 * DH) == 0 && n % (PW * 4 * DG) == 0 && n > 0 &&
          (m / OT) * (p / OT) < ((int64_t)1 << 31);
+}
+
+// ---- fixed device scratch for callers that cannot allocate -------------------
+// One array per device, for the whole process: the split partials and the
+// reduced G and H of amm_approx_matmul_static.  In host code `scratch` names a
+// host-side stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, looked up once per device (with that device current)
+// when a context is created there, and only that pointer reaches the kernels.
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+namespace {
+std::mutex g_static_mtx;
+std::map<int, std::pair<hipError_t, float*>> g_static;   // device -> (lookup status, address)
+}  // namespace
+
+void static_scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_static_mtx);
+  if (g_static.count(device)) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_static[device] = {e, e == hipSuccess ? static_cast<float*>(ptr) : nullptr};
+}
+
+amm_status static_scratch(int device, float** out) {
+  std::lock_guard<std::mutex> lk(g_static_mtx);
+  const auto it = g_static.find(device);
+  if (it == g_static.end()) return fail(AMM_ESTATE, "no context was created on device %d", device);
+  if (it->second.first != hipSuccess) return hip_fail(it->second.first, "hipGetSymbolAddress(scratch)");
+  *out = it->second.second;
+  return AMM_OK;
 }
 
 size_t tsvd_split_scratch(int64_t m, int64_t n, int64_t p, int ka, int kb) {
