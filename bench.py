@@ -310,7 +310,7 @@ def c5_headline(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
                          "kernels_ms": {kn: v[0] for kn, v in kt2.items()}})
         log(f"[bench] c5 {name}: {ms:.3f} ms, err {e:.3e}, kernels {variants[-1]['kernels_ms']}")
 
-    if not args.only or args.only == "c5":
+    if not args.no_variants and (not args.only or args.only == "c5"):
         variant(f"n={n} sparse0.5%+circulant K={K} first, float16 spectral products", dA, dB)
         dA32, tA32 = decompose_timed(A, False)
         dB32, tB32 = decompose_timed(B, False)

@@ -537,6 +537,257 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
   }
 }
 
+// ---- n = 16384, float16 products, columns: two column pairs per workgroup -----
+// At n = 16384 a float32 spectrum fills the LDS, so the kernel above holds one
+// packed column pair and streams every eigenvalue list once per pair.  This
+// form keeps two pairs (four real columns) per workgroup: the LDS holds one
+// float32 spectrum at a time for the transforms, and the other pair waits in
+// registers (its raw columns during the first forward transform, its
+// float16 spectrum during the first MAC, its finished columns during the
+// second inverse transform).  The MACs run one pair after the other, each
+// against that pair's doubled float16 spectrum (the affine reads of the
+// one-pair kernel; reading both pairs side by side with wrapped indices
+// measured slower, 2.0 against 1.3 ms for K = 64 at p = 16384).  Loads and
+// stores move 16 bytes per row (storing each pair as soon as it is done, 8
+// bytes per row, measured slower).  Each pair has its own power-of-two scale.
+// The kernel runs at the 128-register limit with a few spilled values outside
+// the MAC loop.
+
+// The thread's bins tid + q T of the float32 spectrum in LDS, scaled by the
+// power of two that puts the block's largest component in [2^14, 2^15) and
+// rounded to float16 words; returns the exponent of that scale.  Ends with a
+// barrier: every thread has read its bins.
+template <int LOG2N>
+__device__ __forceinline__ int spectrum_to_half(const float2* lds, float* red, uint32_t (&h)[CdCfg<LOG2N>::N /
+                                                                                       CdCfg<LOG2N>::T]) {
+  using Cfg = CdCfg<LOG2N>;
+  constexpr int T = Cfg::T, NV = Cfg::N / T;
+  float2 v[NV];
+  float mx = 0.f;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = lds[pad_bin(threadIdx.x + q * T)];
+    mx = fmaxf(mx, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = red[0];
+  for (int w = 1; w < T / 64; ++w) mx = fmaxf(mx, red[w]);
+  int ex = 0;
+  (void)frexpf(mx, &ex);
+  const int sh = min(max(15 - ex, -100), 100);
+  const float sx = ldexpf(1.0f, sh);
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    h[q] = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[q].x * sx, v[q].y * sx));
+  __syncthreads();
+  return sh;
+}
+
+// The float16 MAC of one packed column pair (C = 1) against the doubled,
+// unpadded spectrum hs (words 0 .. 2N-1, word q + N a copy of word q): the
+// same arithmetic as the float16 branch of cd_apply_kernel, whose lane owns
+// bins b1 = tid + i T and their mirrors.
+template <int LOG2N>
+__device__ __forceinline__ void mac_h16_doubled(const uint32_t* hs, const void* __restrict__ L, CdPairs pr, int K,
+                                                const int32_t* __restrict__ shifts,
+                                                float2 (&acc)[CdCfg<LOG2N>::N / CdCfg<LOG2N>::T]) {
+  using Cfg = CdCfg<LOG2N>;
+  constexpr int N = Cfg::N, T = Cfg::T, NV = N / T, BL = T, NH = NV / 2;
+  const int bl = threadIdx.x;
+  const uint32_t* Lw = reinterpret_cast<const uint32_t*>(L);
+  auto pair_bins = [&](int i, int& b1, int& b2) {
+    b1 = bl + i * BL;
+    b2 = b1 == 0 ? N / 2 : N - b1;
+  };
+  if (pr.npairs >= 0) {
+    for (int u = 0; u < pr.npairs; ++u) {
+      const int k = pr.pairs[u].x;
+      const int64_t Lt = (int64_t)pr.pairs[u].y * N;
+      // b1 -+ k step +BL with i; b2 -+ k step -BL (bases at i = NH-1); lane
+      // 0's partner of bin 0 is N/2.  Lists in two halves of the lane's bins
+      // (register pressure).
+      const int wx1 = bl - k + N, wy1 = bl + k;
+      const int wx2 = 2 * N - bl - (NH - 1) * BL - k, wy2 = N - bl - (NH - 1) * BL + k;
+#pragma unroll
+      for (int hb = 0; hb < NH; hb += NH / 2) {
+        uint32_t l1v[NH / 2], l2v[NH / 2];
+#pragma unroll
+        for (int j = 0; j < NH / 2; ++j) {
+          int b1, b2;
+          pair_bins(hb + j, b1, b2);
+          l1v[j] = Lw[Lt + b1];
+          l2v[j] = Lw[Lt + b2];
+        }
+#pragma unroll
+        for (int j = 0; j < NH / 2; ++j) {
+          const int i = hb + j;
+          const bool self = i == 0 && bl == 0;
+          const uint32_t l1 = l1v[j], l2 = l2v[j];
+          const uint32_t s1 = swap_halves(l1), s2 = swap_halves(l2);
+          const MulH p1{l1, s1}, p2{l2, s2};
+          const MulHc q1{self ? l1 : l2, self ? s1 : s2}, q2{self ? l2 : l1, self ? s2 : s1};
+          mac(acc[i], p1, hs[wx1 + i * BL]);
+          mac(acc[i], q1, hs[wy1 + i * BL]);
+          int ax = wx2 + (NH - 1 - i) * BL, ay = wy2 + (NH - 1 - i) * BL;
+          if (self) {
+            ax = N / 2 - k + N;
+            ay = N / 2 + k;
+          }
+          mac(acc[NH + i], p2, hs[ax]);
+          mac(acc[NH + i], q2, hs[ay]);
+        }
+      }
+    }
+    for (int v = 0; v < pr.nsingles; ++v) {
+      const int k = pr.singles[v].x;
+      const int64_t Lt = (int64_t)pr.singles[v].y * N;
+#pragma unroll
+      for (int i = 0; i < NH; ++i) {
+        int b1, b2;
+        pair_bins(i, b1, b2);
+        mac(acc[i], mul_plain(Lw[Lt + b1]), hs[b1 - k + N]);
+        mac(acc[NH + i], mul_plain(Lw[Lt + b2]), hs[b2 - k + N]);
+      }
+    }
+  } else {
+    for (int t = 0; t < K; ++t) {
+      const int k = shifts[t];
+      const int64_t Lt = (int64_t)t * N;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        int b1, b2;
+        pair_bins(i < NH ? i : i - NH, b1, b2);
+        const int b = i < NH ? b1 : b2;
+        mac(acc[i], mul_plain(Lw[Lt + b]), hs[b - k + N]);
+      }
+    }
+  }
+}
+
+template <int LOG2N>
+__global__ void __launch_bounds__(CdCfg<LOG2N>::T)
+cd_pair2_h16_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ out, int64_t ldo,
+                    int64_t extent, int K, const int32_t* __restrict__ shifts, const void* __restrict__ L,
+                    const float2* __restrict__ tw, int accumulate, CdPairs pr, float l16_inv) {
+  using Cfg = CdCfg<LOG2N>;
+  constexpr int N = Cfg::N, T = Cfg::T;
+  static_assert(Cfg::C == 1 && N % T == 0, "one float32 spectrum per LDS tile");
+  constexpr int NV = N / T, BL = T, NH = NV / 2;
+  __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
+  __shared__ float2 twl[Cfg::TWL], twh[Cfg::TWH];
+  __shared__ float red[T / 64];
+  for (int i = threadIdx.x; i < Cfg::TWL + Cfg::TWH; i += T) {
+    if (i < Cfg::TWL) twl[i] = tw[i];
+    else twh[i - Cfg::TWL] = tw[(i - Cfg::TWL) << Cfg::TWB];
+  }
+  const int nblk = gridDim.x;
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  int tile = xcd * ((nblk + 7) / 8) + slot;
+  if ((nblk & 7) != 0) tile = blockIdx.x;
+  const int64_t first = (int64_t)tile * 4;   // first real column
+  const int tid = threadIdx.x;
+
+  // ---- load: pair 0 (columns first, first + 1) into LDS, pair 1 kept --------
+  float2 keep[NV];
+  {
+    const bool whole = first + 3 < extent;
+#pragma unroll
+    for (int q0 = 0; q0 < NV; q0 += NV / 2) {   // two halves of the rows (register pressure)
+      float4 r[NV / 2];
+#pragma unroll
+      for (int j = 0; j < NV / 2; ++j) {
+        const float* src = X + (int64_t)(tid + (q0 + j) * T) * ldx + first;
+        if (whole) {
+          r[j] = *reinterpret_cast<const float4*>(src);
+        } else {
+          r[j] = float4{first < extent ? src[0] : 0.f, first + 1 < extent ? src[1] : 0.f,
+                        first + 2 < extent ? src[2] : 0.f, 0.f};
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NV / 2; ++j) {
+        lds[pad_bin(tid + (q0 + j) * T)] = float2{r[j].x, r[j].y};
+        keep[q0 + j] = float2{r[j].z, r[j].w};
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<-1, LOG2N, false>(lds, twl, twh);
+  uint32_t h0[NV];
+  const int sh0 = spectrum_to_half<LOG2N>(lds, red, h0);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) lds[pad_bin(tid + q * T)] = keep[q];
+  __syncthreads();
+  lds_fft<-1, LOG2N, false>(lds, twl, twh);
+  uint32_t h1[NV];
+  const int sh1 = spectrum_to_half<LOG2N>(lds, red, h1);
+  // ---- the MAC, one pair at a time against its doubled float16 spectrum -------
+  float2 acc[NV][2];
+  uint32_t* hs = reinterpret_cast<uint32_t*>(lds);
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    float2 a[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] = float2{0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const uint32_t w = pair == 0 ? h0[q] : h1[q];
+      hs[tid + q * T] = w;
+      hs[tid + q * T + N] = w;
+    }
+    __syncthreads();
+    mac_h16_doubled<LOG2N>(hs, L, pr, K, shifts, a);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i][pair] = a[i];
+  }
+  auto pair_bins = [&](int i, int& b1, int& b2) {
+    b1 = tid + i * BL;
+    b2 = b1 == 0 ? N / 2 : N - b1;
+  };
+
+  // ---- inverse transforms, pair 0 then pair 1; store 16 bytes per row --------
+  auto put = [&](int pair) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int b1, b2;
+      pair_bins(i < NH ? i : i - NH, b1, b2);
+      lds[pad_bin(i < NH ? b1 : b2)] = acc[i][pair];
+    }
+  };
+  put(0);
+  __syncthreads();
+  lds_fft<+1, LOG2N, false>(lds, twl, twh);
+  float2 res0[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) res0[q] = lds[pad_bin(tid + q * T)];
+  __syncthreads();
+  put(1);
+  __syncthreads();
+  lds_fft<+1, LOG2N, false>(lds, twl, twh);
+  const float s0 = ldexpf(l16_inv / (float)N, -sh0), s1 = ldexpf(l16_inv / (float)N, -sh1);
+  const bool whole = first + 3 < extent;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const float2 y1 = lds[pad_bin(tid + q * T)];
+    float4 y{res0[q].x * s0, res0[q].y * s0, y1.x * s1, y1.y * s1};
+    float* dst = out + (int64_t)(tid + q * T) * ldo + first;
+    if (whole) {
+      if (accumulate) {
+        const float4 z = *reinterpret_cast<const float4*>(dst);
+        y = float4{y.x + z.x, y.y + z.y, y.z + z.z, y.w + z.w};
+      }
+      *reinterpret_cast<float4*>(dst) = y;
+    } else {
+      const float yv[3] = {y.x, y.y, y.z};
+      for (int j = 0; j < 3; ++j)
+        if (first + j < extent) dst[j] = accumulate ? dst[j] + yv[j] : yv[j];
+    }
+  }
+}
+
 // ---- sides that are not powers of two (n <= 2048), fused ---------------------
 // The length-n DFT of sign s is Bluestein's chirp convolution,
 //   X[k] = ch_k sum_j (x_j ch_j) conj(ch_{k-j}),   ch_t = exp(s pi i t^2 / n),
@@ -706,6 +957,10 @@ amm_status launch_chirp(bool rows, const float* X, float* out, int64_t extent, i
   return AMM_OK;
 }
 
+#ifndef AMM_CD_ONEPAIR
+#define AMM_CD_ONEPAIR 0
+#endif
+
 template <int LOG2N, bool ROWS, bool H16>
 void launch_cd_kernel(dim3 grid, dim3 block, hipStream_t s, const float* X, int64_t ldx, float* out, int64_t ldo,
                       int64_t extent, int K, const int32_t* shifts, const void* L, const float2* tw, int acc, int vec4,
@@ -732,6 +987,16 @@ amm_status launch_cd(bool rows, const float* X, int64_t ldx, float* out, int64_t
     hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, true>), grid, block, 0, s, X, ldx, out, ldo, extent, 0,
                        shifts, L, tw, 0, vec4, pr, 1.0f);
   else if (h16) {
+    if constexpr (LOG2N == 14 && !AMM_CD_ONEPAIR) {
+      // two column pairs per workgroup (16-byte row accesses)
+      if (!rows && ldx % 4 == 0 && ldo % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)out % 16) == 0) {
+        const int64_t t4 = (extent + 3) / 4;
+        hipLaunchKernelGGL((cd_pair2_h16_kernel<LOG2N>), dim3((unsigned)t4), block, 0, s, X, ldx, out, ldo, extent, K,
+                           shifts, L, tw, a, pr, l16_inv);
+        AMM_HIP(hipGetLastError());
+        return AMM_OK;
+      }
+    }
     if constexpr (LOG2N >= kH16MinLog2) {
       if (rows)
         launch_cd_kernel<LOG2N, true, true>(grid, block, s, X, ldx, out, ldo, extent, K, shifts, L, tw, a, 0, pr,

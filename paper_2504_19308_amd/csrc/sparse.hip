@@ -188,49 +188,35 @@ spmm_slices(const int32_t* __restrict__ rng, int stride, int blk, const int32_t*
   }
 }
 
+constexpr int SWN = 32;   // columns per slice, narrow form
+constexpr int RPBN = 32;  // rows per block, narrow form
+// entries per round (two per lane): 4.75 ms against 5.3 ms for 8 at n = 16384
+// (cross-lane swizzles instead of the LDS hand-over: 4.95 ms)
+constexpr int kNarrowRound = 16;
+
 // S B with S in CSR, float4 path (p, ldb, ldo % 4 == 0, 16-byte aligned B and
 // out).  Slices of 32 columns, 8 lanes per row (a float4 each), whole rows in
 // one pass: a slice of B is n x 128 bytes (2 MiB at n = 16384), held in one
 // XCD's L2 while that XCD sweeps the slice's rows (blocks are dealt so that
-// every XCD owns whole slices).  A row's stored entries come G at a time, one
-// or two per lane in one coalesced read of the indices and one of the values,
-// and are broadcast to the row's 8 lanes with ds_swizzle; the next G are read
-// before the current G rows of B are gathered.  With `add` the result is
-// out = S B + add (add with row pitch ld_add), else out (+)= S B.
-template <int J>
-__device__ __forceinline__ int bcast8(int v) {
-  // bit mode: source lane = (lane & 0x18) | J within each group of 32
-  return __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));
-}
-
-template <int H, int... J>
-__device__ __forceinline__ void narrow_round(std::integer_sequence<int, J...>, int my_c, int my_v, int cnt,
-                                             const float* __restrict__ B, int64_t ldb, int64_t c0, bool ok,
-                                             float4& acc) {
-  // entries 8 H + j of the round, held by lane j of the row's group
-  int c[sizeof...(J)];
-  float v[sizeof...(J)];
-  float4 x[sizeof...(J)];
-  ((c[J] = bcast8<J>(my_c), v[J] = __int_as_float(bcast8<J>(my_v))), ...);
-  ((x[J] = (8 * H + J < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)c[J] * ldb + c0)
-                                   : float4{0.f, 0.f, 0.f, 0.f}),
-   ...);
-  ((acc.x += v[J] * x[J].x, acc.y += v[J] * x[J].y, acc.z += v[J] * x[J].z, acc.w += v[J] * x[J].w), ...);
-}
-
-constexpr int SWN = 32;   // columns per slice, narrow form
-constexpr int RPBN = 32;  // rows per block, narrow form
-constexpr int kNarrowRound = 16;   // entries per round (two per lane): 4.9 ms against 5.4 ms for 8 at n = 16384
-
-// G: entries per round (8 or 16: one or two per lane), the next round's
-// entries loaded before the current round's gathers.
+// every XCD owns whole slices), and each gathered row is one 128-byte line.
+// A row's stored entries come G at a time, one or two per lane, in one
+// coalesced read of the indices and one of the values, issued a round ahead;
+// each round's entries are handed to the row's lanes through LDS: every lane
+// stores its (column, value) pairs in its group's slot and every lane reads
+// the round back two entries at a time (the 8 lanes of a group read the same
+// address, a broadcast).  A wave's LDS operations complete in order, so the
+// group's stores are visible to its reads without a barrier; wave barriers
+// keep the compiler from moving them across each other.  With `add` the
+// result is out = S B + add (add with row pitch ld_add), else out (+)= S B.
 template <int G>
 __global__ void __launch_bounds__(256)
 spmm_narrow(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
-            const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p, float* __restrict__ out,
-            int64_t ldo, int accumulate, const float* __restrict__ add, int64_t ld_add, int nslices, int rgroups) {
+                const float* __restrict__ B, int64_t ldb, int64_t rows, int64_t p, float* __restrict__ out,
+                int64_t ldo, int accumulate, const float* __restrict__ add, int64_t ld_add, int nslices,
+                int rgroups) {
   static_assert(G == 8 || G == 16, "one or two entries per lane and round");
   constexpr int H = G / 8;
+  __shared__ __align__(16) int2 ent[256 / 8][G];
   const int bid = blockIdx.x;
   int slice, rg;
   if ((nslices & 7) == 0) {
@@ -242,10 +228,11 @@ spmm_narrow(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col
     rg = bid % rgroups;
   }
   const int lane8 = threadIdx.x & 7;
+  int2* my = ent[threadIdx.x >> 3];
   const int64_t row = (int64_t)rg * RPBN + (threadIdx.x >> 3);
   if (row >= rows) return;            // a row's 8 lanes leave together
   const int64_t c0 = (int64_t)slice * SWN + lane8 * 4;
-  const bool ok = c0 < p;             // lanes past the last column still serve the broadcasts
+  const bool ok = c0 < p;
   const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
   int nc[H], nv[H];
 #pragma unroll
@@ -260,11 +247,11 @@ spmm_narrow(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col
   }
   float4 acc{0.f, 0.f, 0.f, 0.f};
   for (int base = e0; base < e1; base += G) {
-    int cc[H], cv[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) my[8 * h + lane8] = int2{nc[h], nv[h]};
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      cc[h] = nc[h];
-      cv[h] = nv[h];
       const int e = base + G + 8 * h + lane8;
       nc[h] = 0;
       nv[h] = 0;
@@ -273,9 +260,27 @@ spmm_narrow(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col
         nv[h] = __float_as_int(val[e]);
       }
     }
-    narrow_round<0>(std::make_integer_sequence<int, 8>{}, cc[0], cv[0], e1 - base, B, ldb, c0, ok, acc);
-    if constexpr (H == 2)
-      narrow_round<1>(std::make_integer_sequence<int, 8>{}, cc[H - 1], cv[H - 1], e1 - base, B, ldb, c0, ok, acc);
+    const int cnt = e1 - base;
+    float4 x[G];
+    float v[G];
+#pragma unroll
+    for (int j = 0; j < G; j += 2) {
+      const int4 q = *reinterpret_cast<const int4*>(&my[j]);
+      v[j] = __int_as_float(q.y);
+      v[j + 1] = __int_as_float(q.w);
+      x[j] = (j < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)q.x * ldb + c0)
+                             : float4{0.f, 0.f, 0.f, 0.f};
+      x[j + 1] = (j + 1 < cnt && ok) ? *reinterpret_cast<const float4*>(B + (int64_t)q.z * ldb + c0)
+                                     : float4{0.f, 0.f, 0.f, 0.f};
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      acc.x += v[j] * x[j].x;
+      acc.y += v[j] * x[j].y;
+      acc.z += v[j] * x[j].z;
+      acc.w += v[j] * x[j].w;
+    }
   }
   if (!ok) return;
   float4* o = reinterpret_cast<float4*>(out + row * ldo + c0);

@@ -30,9 +30,10 @@ class _Lists:
         self.n, self.S, self.L = n, np.asarray(S, dtype=np.int64), np.asarray(L)
 
 
-def _pair_lists(n, K, rng, scale=1.0):
+def _pair_lists(n, K, rng, scale=1.0, singles=False):
     """K/2 pair classes {k, n-k} with random lists, L_{n-k}[p] = conj(L_k[-p])
-    (a real operator)."""
+    (a real operator); with singles also the self-paired frequencies 0 and
+    n/2, whose lists satisfy L[p] = conj(L[-p])."""
     neg = (-np.arange(n)) % n
     ks = rng.choice(np.arange(1, n // 2), K // 2, replace=False)
     S, L = [], []
@@ -40,7 +41,13 @@ def _pair_lists(n, K, rng, scale=1.0):
         v = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * scale
         S += [int(k), int(n - k)]
         L += [v, np.conj(v[neg])]
-    return S, np.array(L)
+    if singles:
+        for k in (0, n // 2):
+            v = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * scale
+            S.append(k)
+            L.append(0.5 * (v + np.conj(v[neg])))
+    order = np.argsort(S)
+    return [S[i] for i in order], np.array(L)[order]
 
 
 def _terms(n, S, L, B):
@@ -54,13 +61,17 @@ def _randn(n, p, seed):
     return torch.randn((n, p), generator=g, device="cuda", dtype=torch.float32)
 
 
-@pytest.mark.parametrize("n,K,p", [(1024, 6, 48), (4096, 10, 40), (8192, 4, 36), (16384, 64, 24)])
-def test_fp16_products_bound(n, K, p):
+@pytest.mark.parametrize("n,K,p,singles", [(1024, 6, 48, False), (4096, 10, 40, True), (8192, 4, 36, False),
+                                           (16384, 64, 24, False), (16384, 6, 28, True), (16384, 4, 26, True)])
+def test_fp16_products_bound(n, K, p, singles):
     """Imported lists (any scale: these are 1e-5 of unit size, below the
-    float16 normal range before scaling), float16 products on and off."""
-    note(f"fp16 products n={n} K={K} p={p}")
+    float16 normal range before scaling), float16 products on and off.
+    n = 16384 with p a multiple of 4 runs the two-pairs-per-workgroup kernel
+    (p = 28: seven tiles), other p the one-pair kernel; singles adds the
+    self-paired frequencies 0 and n/2."""
+    note(f"fp16 products n={n} K={K} p={p} singles={singles}")
     rng = np.random.default_rng(n + K)
-    S, L = _pair_lists(n, K, rng, scale=1e-5)
+    S, L = _pair_lists(n, K, rng, scale=1e-5, singles=singles)
     c = ctx()
     d = c.import_circulant(n, S, L)
     B = _randn(n, p, n + 3)
