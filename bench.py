@@ -38,11 +38,17 @@ VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2
 
 # HBM bytes per dispatch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # summarised in profiles/ (KiB per dispatch), with the scale factors a 256 MiB
-# elementwise copy gave (FETCH x2.0, WRITE x1.0).  A figure is reported only
+# elementwise copy gave (FETCH x2.0, WRITE x1.0; the spread-pitch copy of a
+# 1 GiB operand reads 524320 KiB and writes 1048576 KiB, the same factors).  A figure is reported only
 # while the kernel source still has the hash it had when the counters were
 # taken.
 TRAFFIC = {
-    # kernel tag: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch and the source they were taken on
+    # headline step, n = 16384 (profiles/sparse_circulant_n16384.md)
+    "spmm_csr": {"fetch_kib": 4945570.6, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
+                 "sha16": "83c8b69d32f711d3"},
+    "cd_apply_columns": {"fetch_kib": 934525.8, "write_kib": 1491414.2, "src": "paper_2504_19308_amd/csrc/cd_apply.hip",
+                         "sha16": "c9bfdc2a06b02240"},
+    # rank-32 first-order product, n = 4096 (profiles/tsvd_first_order_n4096.md)
     "panel": {"fetch_kib": 67709.3, "write_kib": 2048.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
               "sha16": "c7bac24a28d6757c"},
     "gemm_out": {"fetch_kib": 8746.7, "write_kib": 65536.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
@@ -117,7 +123,7 @@ def rel_err(M, exact64):
 # dispatches per tag launch) for the headline step
 HEADLINE_KERNELS = {
     "spmm_csr": ("spmm_narrow<16>", 1),
-    "cd_apply_columns": ("cd_apply_kernel<14, false, false, true>", 1),
+    "cd_apply_columns": ("cd_pair2_h16_kernel<14>", 1),
     "repitch": ("repitch_kernel", 1),
 }
 
