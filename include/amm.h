@@ -237,6 +237,25 @@ amm_status amm_dec_tsvd_factors(const amm_dec* dec, float* U_host,
 amm_status amm_dec_sparse_part(const amm_dec* dec, int32_t* row_ptr_host,
                                int32_t* col_host, float* val_host);
 
+/* Serialise a handle to a host buffer (a checkpoint of a decomposition made
+ * offline, as the paper treats the weights' decomposition, Sec. 4.5; its
+ * circulant lists, SVD factors and sparse arrays are the float32 values the
+ * products use, with their derived tables).  buf == NULL: *bytes receives the
+ * size needed.  Otherwise *bytes is buf's capacity (AMM_EINVAL if too small)
+ * and receives the size written.  Device -> host copies; synchronous.  A
+ * borrowed operand (A of a truncated SVD) is not included: pass it again to
+ * amm_dec_import.  The blob is plain host bytes (same-endian hosts). */
+amm_status amm_dec_export(const amm_dec* dec, void* buf, size_t* bytes);
+
+/* Rebuild a handle from amm_dec_export's bytes on ctx's device: every buffer
+ * is copied back verbatim, so products of the imported handle equal those of
+ * the exported one bit for bit.  A (device, may be NULL) is borrowed again by
+ * the nodes that borrowed an operand when exported (first-order left operands
+ * of the truncated-SVD kind).  AMM_EINVAL on a malformed or truncated blob,
+ * AMM_EUNSUPPORTED on another format version.  Synchronous. */
+amm_status amm_dec_import(amm_ctx* ctx, const void* buf, size_t bytes, const float* A,
+                          amm_dec** out);
+
 void amm_dec_destroy(amm_dec* dec);
 
 /* ---- product ------------------------------------------------------------ */

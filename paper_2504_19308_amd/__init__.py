@@ -106,6 +106,15 @@ class Decomposition:
         """Record sigma_{k+1} of an imported truncated SVD (for the Thm. 3.8 bound)."""
         _lib.check(_lib.load().amm_dec_set_sigma_next(self.handle, float(value)))
 
+    def export(self) -> bytes:
+        """The handle as a self-contained blob (amm_dec_export)."""
+        lib = _lib.load()
+        n = C.c_size_t(0)
+        _lib.check(lib.amm_dec_export(self.handle, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _lib.check(lib.amm_dec_export(self.handle, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
     def set_spectral_fp16(self, enable: bool = True):
         """Switch float16 spectral products on or off (circulant handles)."""
         _lib.check(_lib.load().amm_dec_set_spectral_fp16(self.handle, 1 if enable else 0))
@@ -238,6 +247,18 @@ class Context:
             res_ptr, float(norm_A), float(norm_residual), C.byref(h)))
         self.torch.cuda.synchronize()
         return Decomposition(self, h)
+
+    def import_blob(self, blob: bytes, A=None) -> Decomposition:
+        """A handle rebuilt from Decomposition.export() bytes (amm_dec_import);
+        A is borrowed again where the exported handle borrowed an operand."""
+        a_ptr = None
+        if A is not None:
+            _need_f32_cuda(A, "A")
+            a_ptr = C.c_void_p(A.data_ptr())
+        h = C.c_void_p()
+        buf = C.create_string_buffer(blob, len(blob))
+        _lib.check(_lib.load().amm_dec_import(self.handle, buf, len(blob), a_ptr, C.byref(h)))
+        return Decomposition(self, h, (A,) if A is not None else ())
 
     def import_tsvd(self, U, s, V, A=None) -> Decomposition:
         U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
