@@ -116,6 +116,29 @@ typedef struct {
 amm_status amm_ctx_create(amm_ctx** ctx, int device);
 void amm_ctx_destroy(amm_ctx* ctx);
 
+/* Device allocator supplied by the caller (e.g. a framework's caching
+ * allocator): alloc returns `bytes` of device memory on `device` (NULL on
+ * failure, reported as AMM_ENOMEM), free returns it.  Both must be callable
+ * from the thread that calls the library and stay valid while any buffer they
+ * made lives: until the context and every handle and plan made on it are
+ * destroyed.  free can be called while work queued earlier on the call's
+ * stream still reads the buffer (a work area grown inside a call, a handle
+ * destroyed after its last product was queued): the allocator must reuse
+ * memory in stream order (as torch's caching allocator does for the stream
+ * the library launches on) or wait for the device itself. */
+typedef struct {
+  void* (*alloc)(size_t bytes, int device, void* user);
+  void (*free)(void* ptr, size_t bytes, int device, void* user);
+  void* user;
+} amm_allocator;
+
+/* amm_ctx_create with every device buffer of the context, of the handles and
+ * plans made on it (component buffers, work areas, tables) taken from
+ * `alloc` instead of hipMalloc.  alloc == NULL: as amm_ctx_create.  The
+ * structure is copied.  The fixed scratch of amm_approx_matmul_static is
+ * not an allocation and is unaffected. */
+amm_status amm_ctx_create_with_allocator(amm_ctx** ctx, int device, const amm_allocator* alloc);
+
 /* Per-launch timing for measurement.  With timing enabled, every kernel that
  * a call on `ctx` enqueues is bracketed by hipEventRecord on the same stream.
  * amm_ctx_timings waits for the recorded events, then reports per kernel name

@@ -166,13 +166,41 @@ class BatchPlan:
 
 
 class Context:
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, allocator=None):
+        """allocator: None (hipMalloc), "torch" (torch's caching allocator on
+        the current stream), or a pair of Python callables
+        alloc(bytes, device) -> int address and free(address, bytes, device)
+        through which every device buffer of the context and of its handles
+        and plans is taken."""
         import torch
         self.torch = torch
         self.device = device
         lib = _lib.load()
         h = C.c_void_p()
-        _lib.check(lib.amm_ctx_create(C.byref(h), device))
+        if allocator is None:
+            _lib.check(lib.amm_ctx_create(C.byref(h), device))
+        else:
+            if allocator == "torch":
+                def py_alloc(nbytes, dev):
+                    return torch.cuda.caching_allocator_alloc(nbytes, dev)
+
+                def py_free(ptr, nbytes, dev):
+                    torch.cuda.caching_allocator_delete(ptr)
+            else:
+                py_alloc, py_free = allocator
+
+            def c_alloc(nbytes, dev, user):
+                try:
+                    return py_alloc(nbytes, dev) or None
+                except Exception:
+                    return None    # reported by the library as AMM_ENOMEM
+
+            def c_free(ptr, nbytes, dev, user):
+                py_free(ptr, nbytes, dev)
+
+            # the callbacks live as long as this object (handles keep it alive)
+            self._alloc = _lib.AmmAllocator(_lib.ALLOC_FN(c_alloc), _lib.FREE_FN(c_free), None)
+            _lib.check(lib.amm_ctx_create_with_allocator(C.byref(h), device, C.byref(self._alloc)))
         self.handle = h
 
     def close(self):

@@ -41,11 +41,20 @@ class AmmErrorEstimate(C.Structure):
                 ("spec_dA", C.c_double), ("spec_dB", C.c_double), ("mu_A", C.c_double), ("mu_B", C.c_double)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+
+
+class AmmAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 # name -> (restype, argtypes); every pointer is a plain void* / typed pointer
 SIGNATURES = {
     "amm_opts_default": (None, [C.POINTER(AmmOpts)]),
     "amm_last_error": (C.c_char_p, []),
     "amm_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "amm_ctx_create_with_allocator": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(AmmAllocator)]),
     "amm_ctx_destroy": (None, [C.c_void_p]),
     "amm_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "amm_ctx_timings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,

@@ -28,10 +28,24 @@ thread_local KernelTimer* g_timer = nullptr;
 
 namespace {
 // Routes the launches of one API call to the context's timer when enabled.
+// Per API call: the context's launch timer (if timing is on) and its
+// allocator for every device buffer the call makes.
 struct TimerScope {
   KernelTimer* prev;
-  explicit TimerScope(amm_ctx* ctx) : prev(g_timer) { g_timer = (ctx && ctx->timing) ? &ctx->timer : nullptr; }
-  ~TimerScope() { g_timer = prev; }
+  const AllocFns* prev_alloc;
+  explicit TimerScope(amm_ctx* ctx) : prev(g_timer), prev_alloc(g_alloc) {
+    g_timer = (ctx && ctx->timing) ? &ctx->timer : nullptr;
+    g_alloc = ctx ? &ctx->alloc : nullptr;
+  }
+  // calls on a handle alone allocate with the handle's allocator
+  explicit TimerScope(const amm_dec* d) : prev(g_timer), prev_alloc(g_alloc) {
+    g_timer = nullptr;
+    g_alloc = d ? &d->alloc : nullptr;
+  }
+  ~TimerScope() {
+    g_timer = prev;
+    g_alloc = prev_alloc;
+  }
 };
 }  // namespace
 
@@ -48,13 +62,22 @@ amm_status hip_fail(hipError_t e, const char* what) {
   return fail(AMM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+thread_local const AllocFns* g_alloc = nullptr;
+
 amm_status DevBuf::alloc(size_t b) {
   release();
+  fns = AllocFns{};
   if (b == 0) return AMM_OK;
-  hipError_t e = hipMalloc(&ptr, b);
-  if (e != hipSuccess) {
-    ptr = nullptr;
-    return hip_fail(e, "hipMalloc");
+  if (g_alloc && g_alloc->alloc) {
+    ptr = g_alloc->alloc(b, g_alloc->device, g_alloc->user);
+    if (!ptr) return fail(AMM_ENOMEM, "caller's allocator returned NULL for %zu bytes", b);
+    fns = *g_alloc;
+  } else {
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return hip_fail(e, "hipMalloc");
+    }
   }
   bytes = b;
   return AMM_OK;
@@ -376,8 +399,11 @@ void amm_opts_default(amm_opts* o) {
 
 const char* amm_last_error(void) { return g_msg; }
 
-amm_status amm_ctx_create(amm_ctx** ctx, int device) {
+amm_status amm_ctx_create(amm_ctx** ctx, int device) { return amm_ctx_create_with_allocator(ctx, device, nullptr); }
+
+amm_status amm_ctx_create_with_allocator(amm_ctx** ctx, int device, const amm_allocator* alloc) {
   if (!ctx) return fail(AMM_EINVAL, "ctx is NULL");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(AMM_EINVAL, "allocator needs both functions");
   int count = 0;
   AMM_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(AMM_EINVAL, "device %d out of range (%d devices)", device, count);
@@ -385,6 +411,7 @@ amm_status amm_ctx_create(amm_ctx** ctx, int device) {
   static_scratch_init(device);   // the fixed scratch's address on this device
   amm_ctx* c = new amm_ctx();
   c->device = device;
+  if (alloc) c->alloc = AllocFns{alloc->alloc, alloc->free, alloc->user, device};
   *ctx = c;
   return AMM_OK;
 }
@@ -605,6 +632,7 @@ extern "C" {
 amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_t* freqs,
                                     const double* eig, const float* residual, double norm_A,
                                     double norm_residual, amm_dec** out) {
+  TimerScope ts(ctx);
   if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
   if (!circ_side_ok(n)) return fail(AMM_EUNSUPPORTED, "circulant path needs n in [2, 16384], got %lld", (long long)n);
   if (K < 0 || K > n) return fail(AMM_EINVAL, "K = %d out of [0, n]", K);
@@ -667,6 +695,7 @@ amm_status amm_dec_import_circulant(amm_ctx* ctx, int64_t n, int K, const int32_
 
 amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const double* U,
                                const double* sigma, const double* V, const float* A, amm_dec** out) {
+  TimerScope ts(ctx);
   if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
   if (m <= 0 || n <= 0 || k < 0 || k > std::min(m, n)) return fail(AMM_ESHAPE, "bad SVD shape m=%lld n=%lld k=%d", (long long)m, (long long)n, k);
   if (k > 0 && (!U || !sigma || !V)) return fail(AMM_EINVAL, "NULL factor");
@@ -743,6 +772,7 @@ amm_status amm_dec_import_tsvd(amm_ctx* ctx, int64_t m, int64_t n, int k, const 
 amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
                                  const int32_t* row_ptr, const int32_t* col, const float* val,
                                  amm_dec* residue, const float* A, amm_dec** out) {
+  TimerScope ts(ctx);
   if (!ctx || !out) return fail(AMM_EINVAL, "NULL argument");
   if (m <= 0 || n <= 0 || nnz < 0 || nnz > m * n) return fail(AMM_ESHAPE, "bad sparse shape");
   if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(AMM_EINVAL, "NULL CSR array");
@@ -1222,6 +1252,7 @@ extern "C" {
 
 amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* dA, const float* const* B,
                                  const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
+  TimerScope ts(ctx);
   if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
   int k = 0;
   AMM_TRY(plan_check(count, dA, reinterpret_cast<const void* const*>(B), p, out, false, &k));
@@ -1270,6 +1301,7 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
 
 amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* const* dA, const void* const* B,
                                       const int64_t* p, float* const* out, void* stream, amm_batch_plan** plan) {
+  TimerScope ts(ctx);
   if (!ctx || !dA || !B || !p || !out || !plan) return fail(AMM_EINVAL, "NULL argument");
   int k = 0;
   AMM_TRY(plan_check(count, dA, B, p, out, true, &k));
@@ -1344,6 +1376,7 @@ double prior_of(double nA, double nB, double dA, double dB, int64_t n, int entri
 extern "C" {
 
 amm_status amm_dec_set_spectral_fp16(amm_dec* dec, int enable) {
+  TimerScope ts(static_cast<const amm_dec*>(dec));
   if (!dec) return fail(AMM_EINVAL, "NULL handle");
   amm_dec* c = is_sparse(dec) ? dec->inner : dec;
   if (!c || c->kind != AMM_CIRCULANT) return fail(AMM_EINVAL, "not a circulant handle (or sparse with a circulant residue)");
@@ -1382,6 +1415,7 @@ amm_status amm_dec_set_sigma_next(amm_dec* dec, double sigma_next) {
 
 amm_status amm_estimate_error(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* M, int64_t m,
                               int64_t p, int entries, void* stream, amm_error_estimate* out) {
+  TimerScope ts(ctx);
   if (!ctx || !dA || !dB || !out) return fail(AMM_EINVAL, "NULL argument");
   if (entries != AMM_ENTRIES_SIGNED && entries != AMM_ENTRIES_UNSIGNED_UNIFORM)
     return fail(AMM_EINVAL, "entries = %d", entries);
@@ -1430,6 +1464,7 @@ amm_status amm_estimate_error(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB
 
 amm_status amm_estimate_sketch(amm_ctx* ctx, const float* A, const float* B, const float* M, const float* G,
                                int64_t m, int64_t n, int64_t p, int64_t l, void* stream, double* est) {
+  TimerScope ts(ctx);
   if (!ctx || !A || !B || !M || !G || !est) return fail(AMM_EINVAL, "NULL argument");
   if (m <= 0 || n <= 0 || p <= 0 || l <= 0) return fail(AMM_ESHAPE, "empty sketch shape");
   AMM_HIP(hipSetDevice(ctx->device));

@@ -259,6 +259,12 @@ amm_status amm_dec_import(amm_ctx* ctx, const void* buf, size_t bytes, const flo
   if (version != kVersion) return fail(AMM_EUNSUPPORTED, "decomposition blob version %u", version);
   if (total != bytes) return fail(AMM_EINVAL, "blob size %zu, header says %llu", bytes, (unsigned long long)total);
   AMM_HIP(hipSetDevice(ctx->device));
+  // buffers come from the context's allocator (if it has one)
+  struct Scope {
+    const AllocFns* prev = g_alloc;
+    explicit Scope(const AllocFns* a) { g_alloc = a; }
+    ~Scope() { g_alloc = prev; }
+  } scope(&ctx->alloc);
   amm_dec* d = nullptr;
   AMM_TRY(read_node(r, ctx->device, A, &d, 0));
   if (r.left != 0) {

@@ -31,20 +31,42 @@ amm_status hip_fail(hipError_t e, const char* what);
   } while (0)
 
 // ---- device buffers ---------------------------------------------------------
+// Device allocations go through the allocator of the context the current API
+// call works for (amm_ctx_create_with_allocator), else hipMalloc; a buffer
+// keeps the functions it was allocated with and frees through them.
+struct AllocFns {
+  void* (*alloc)(size_t bytes, int device, void* user) = nullptr;
+  void (*free)(void* ptr, size_t bytes, int device, void* user) = nullptr;
+  void* user = nullptr;
+  int device = 0;
+};
+extern thread_local const AllocFns* g_alloc;
+
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  AllocFns fns{};
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes), fns(o.fns) { o.ptr = nullptr; o.bytes = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      ptr = o.ptr;
+      bytes = o.bytes;
+      fns = o.fns;
+      o.ptr = nullptr;
+      o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+      if (fns.free) fns.free(ptr, bytes, fns.device, fns.user);
+      else (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
   }
@@ -113,6 +135,7 @@ struct CdPairs {
 
 struct amm_ctx {
   int device = 0;
+  amm::AllocFns alloc;                 // caller's allocator (alloc == NULL: hipMalloc)
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
   amm::DevBuf scratch[16];             // grow-only work areas for products (8-13: chirp-convolution path,
@@ -126,6 +149,9 @@ struct amm_ctx {
 };
 
 struct amm_dec {
+  amm_dec() {
+    if (amm::g_alloc) alloc = *amm::g_alloc;   // the allocator of the call that makes the handle
+  }
   int kind = 0;
   int64_t m = 0, n = 0;
   int K = 0;
@@ -137,6 +163,7 @@ struct amm_dec {
   double sigma_next = NAN;   // truncated SVD: estimate of sigma_{k+1} = ||Delta A||_2
   std::vector<double> sigma64;  // truncated SVD: the kept singular values in float64 (host)
   int device = 0;
+  amm::AllocFns alloc;          // allocator of the context that made the handle
 
   // Fourier-domain sparsification: left role (rows of A conj(F) / n, CSR)
   // and its residual half spectrum ((n/2+1) x m, transposed); right role
