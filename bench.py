@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default="", help="run just one group of variants (profiling): c5, c2, c1, "
+    ap.add_argument("--only", default="", help="run just one group of variants (profiling): headline, power, exp, "
                                                "estimates, toeplitz, sfft, batch, layer, tables")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (reference for byte counters)")
@@ -131,7 +131,7 @@ HEADLINE_KERNELS = {
 def headline_roofline(kt, steps, n, nnz, K, list_bytes=4):
     """Roofline of the kernel with the largest time in the timed steps.
 
-    Algorithmic work per step (SURVEY 8(d) per-unit figures for the fused
+    Algorithmic work per step (per-unit figures of the fused
     steps): SpMM 2 nnz p flops, 8 nnz + 4 (n p + m p) bytes; circulant product
     p n (5 log2 n + 4 K) flops, 2 * 4 n p + K n list_bytes bytes; the spread
     pitch copy 2 * 4 n p bytes.  Per dispatch: the step's figure over the
@@ -179,7 +179,7 @@ def main():
     torch.backends.cuda.matmul.allow_tf32 = False
     ctx = Context(0)
     tm = Timer(torch)
-    rec, state = c5_headline(torch, ctx, tm, args)
+    rec, state = headline_sparse_circulant(torch, ctx, tm, args)
 
     if args.calib_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").normal_()
@@ -190,7 +190,7 @@ def main():
         del src, dst
 
     variants = list(state.pop("variants"))
-    cpu = None if args.no_cpu else cpu_baseline_c5(state)
+    cpu = None if args.no_cpu else cpu_baseline_headline(state)
     state.clear()
     torch.cuda.empty_cache()
     if not args.no_variants:
@@ -200,14 +200,14 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def c5_headline(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
+def headline_sparse_circulant(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
     """The headline step and the other n = 16384 variants (float32 spectral
     products, first order)."""
     from paper_2504_19308_amd import inputs
     n = args.n
     t0 = time.time()
     log(f"[bench] generating n={n} operands (sparse {frac:g} + rank-1024 decay)")
-    pair = inputs.workload_c5(n, device="cuda")
+    pair = inputs.workload_lowrank_sparse(n, device="cuda")
     A = pair.A.float().contiguous()
     B = pair.B.float().contiguous()
     del pair
@@ -314,9 +314,9 @@ def c5_headline(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
                          "speedup_vs_dense_fp32": dense_ms / ms, "dense_fp32_ms": dense_ms,
                          "err_vs_exact_sampled": e, "meets_1pct": e <= 0.01,
                          "kernels_ms": {kn: v[0] for kn, v in kt2.items()}})
-        log(f"[bench] c5 {name}: {ms:.3f} ms, err {e:.3e}, kernels {variants[-1]['kernels_ms']}")
+        log(f"[bench] headline {name}: {ms:.3f} ms, err {e:.3e}, kernels {variants[-1]['kernels_ms']}")
 
-    if not args.no_variants and (not args.only or args.only == "c5"):
+    if not args.no_variants and (not args.only or args.only == "headline"):
         variant(f"n={n} sparse0.5%+circulant K={K} first, float16 spectral products", dA, dB)
         dA32, tA32 = decompose_timed(A, False)
         dB32, tB32 = decompose_timed(B, False)
@@ -334,7 +334,7 @@ def c5_headline(torch, ctx, tm, args, K=64, frac=0.005, ncols=256):
     return rec, state
 
 
-def cpu_baseline_c5(state):
+def cpu_baseline_headline(state):
     """The float64 oracle's zeroth-order product (sparse rows, then the
     circulant spectral product) on the sampled output columns, with the
     device decomposition's kept entries and eigenvalue lists read back; the
@@ -374,13 +374,13 @@ def cpu_baseline_c5(state):
                       f"(this product uses no BLAS call: the FFT and the row loop run on one core)"}
 
 
-def c2_workload(torch, ctx, tm, only=""):
+def power_decay_workload(torch, ctx, tm, only=""):
     """n = 4096 square float32 operands Q1 diag(i^-1.5) Q2^T (Haar): the
     first-order truncated-SVD product of rank 32 (previously the headline),
     and the circulant / SVD / sparsified variants and error estimates."""
     from paper_2504_19308_amd import inputs
     n = 4096
-    pair = inputs.workload_c2(n, device="cuda")
+    pair = inputs.workload_power_decay(n, device="cuda")
     A = pair.A.float().contiguous()
     B = pair.B.float().contiguous()
     exact = A.double() @ B.double()
@@ -426,9 +426,9 @@ def c2_workload(torch, ctx, tm, only=""):
             "decompose_ms": {"A": tA, "B": tB},
             "end_to_end": {"ms": ms + tA + tB, "speedup_vs_dense_fp32": dense_ms / (ms + tA + tB)},
             "kernels_ms": {k: v[0] / 20 for k, v in kt.items()}, "roofline": roof}]
-    log(f"[bench] c2 tsvd k={kp} first: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, roofline "
+    log(f"[bench] power-decay tsvd k={kp} first: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, roofline "
         f"{roof['kernel']} {roof['frac']:.2f}")
-    res += c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA, dB)
+    res += power_decay_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA, dB)
     del A, B, exact, out, dA, dB
     torch.cuda.empty_cache()
     return res
@@ -467,7 +467,7 @@ def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False, list_by
             "frac": byts / t / HBM_PEAK}
 
 
-def c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
+def power_decay_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsvd32, dB_tsvd32):
     n = A.shape[0]
     res = []
     out = torch.empty_like(A)
@@ -497,7 +497,7 @@ def c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsv
                     "kernels_ms": {kn: v[0] for kn, v in kt.items()}, "roofline": roofs})
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
-    if not only or only == "c2":
+    if not only or only == "power":
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -525,7 +525,7 @@ def c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsv
             measure(f"tsvd k={k} first", dA, dB, B, ta + tb, exact, k=k)
         # sparsified operands: 1% Laplace(10) entries over the same low-rank decay
         from paper_2504_19308_amd import inputs
-        sp = inputs.workload_c2(n, device="cuda", with_sparse=True)
+        sp = inputs.workload_power_decay(n, device="cuda", with_sparse=True)
         As, Bs = sp.A.float().contiguous(), sp.B.float().contiguous()
         ex_s = As.double() @ Bs.double()
         for inner, K in (("tsvd", 32), ("circulant", 8)):
@@ -537,7 +537,7 @@ def c2_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, only, dA_tsv
             del dA, dB
         del As, Bs, ex_s
         torch.cuda.empty_cache()
-    if not only or only in ("c2", "estimates"):
+    if not only or only in ("power", "estimates"):
         res.append(estimate_variant(torch, ctx, A, B, exact, tm, dA_tsvd32, dB_tsvd32))
     return res
 
@@ -548,10 +548,10 @@ def run_variants(torch, ctx, tm, only):
         res.extend(tables_workload(torch, ctx))
         res.append(figures_workload(torch, ctx))
         return res
-    if not only or only in ("c2", "estimates"):
-        res.extend(c2_workload(torch, ctx, tm, only))
-    if not only or only == "c1":
-        res.extend(c1_workload(torch, ctx, tm))
+    if not only or only in ("power", "estimates"):
+        res.extend(power_decay_workload(torch, ctx, tm, only))
+    if not only or only == "exp":
+        res.extend(exp_decay_workload(torch, ctx, tm))
     if not only or only == "toeplitz":
         res.extend(toeplitz_workload(torch, ctx, tm))
         res.extend(toeplitz_workload(torch, ctx, tm, n=700, taus=(1e-2,)))
@@ -780,7 +780,7 @@ def estimate_variant(torch, ctx, A, B, exact, tm, dA, dB, l=32):
     return r
 
 
-def c1_workload(torch, ctx, tm, n=256, K=16):
+def exp_decay_workload(torch, ctx, tm, n=256, K=16):
     """n = 256: A, B = Q1 diag(exp(-i/20)) Q2^T + 1e-3 N(0, 1) (Haar Q, seeded,
     float64, rounded to float32 for the device); circulant K = 16 and
     truncated SVD k = 16, zeroth and first order.  Each product against the
@@ -791,7 +791,7 @@ def c1_workload(torch, ctx, tm, n=256, K=16):
     from oracle import product as op
     from oracle import tsvd as ot
     from paper_2504_19308_amd import inputs
-    pair = inputs.workload_c1(n)
+    pair = inputs.workload_exp_decay(n)
     Ah = pair.A.astype(np.float32).astype(np.float64)
     Bh = pair.B.astype(np.float32).astype(np.float64)
     A = torch.from_numpy(Ah).float().cuda()
@@ -823,7 +823,7 @@ def c1_workload(torch, ctx, tm, n=256, K=16):
             if kind == "circulant":
                 row["same_frequencies_as_oracle"] = same_sets
             res.append(row)
-            log(f"[bench] c1 {row['name']}: {ms:.4f} ms, err vs exact {row['err_vs_exact']:.3e}"
+            log(f"[bench] exp-decay {row['name']}: {ms:.4f} ms, err vs exact {row['err_vs_exact']:.3e}"
                 + (f", vs oracle {row['err_vs_oracle']:.2e}" if "err_vs_oracle" in row else ""))
     del A, B
     return res

@@ -295,6 +295,24 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
                              const float* B, int64_t n, int64_t p, float* out,
                              void* stream);
 
+/* amm_approx_matmul on operands with row pitches (Alg. 2.3 step 5 and
+ * eq. (2.1), (2.4) as above): B is n x p with row r at B + r ldb, out is
+ * m x p with row r at out + r ldo, e.g. column panels of larger row-major
+ * matrices.  ldb >= p and ldo >= p (AMM_ESHAPE otherwise); the two panels
+ * may share no element (AMM_EINVAL; with equal pitches the test is exact, so
+ * two column panels of one matrix are accepted, with different pitches the
+ * address ranges must be disjoint); columns between p and the pitch are
+ * neither read nor written.  ldb == ldo == p is amm_approx_matmul.  A zeroth-order
+ * product of a circulant handle with n a power of two, and of a sparse
+ * handle over such a circulant residue (16-byte aligned pointers, pitches and
+ * p multiples of 4), reads and writes at the pitches directly; other
+ * requests pass through packed copies in the context's scratch (one
+ * device-to-device 2-D copy each way).  Same stream and error behaviour as
+ * amm_approx_matmul. */
+amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
+                                     const float* B, int64_t n, int64_t p, int64_t ldb,
+                                     float* out, int64_t ldo, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product as amm_approx_matmul for truncated-SVD handles, through the split

@@ -27,6 +27,19 @@ def _stream_ptr(torch, device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _row_pitch(t, name):
+    """Row pitch of a float32 CUDA matrix whose rows are contiguous (a column
+    panel of a row-major matrix is one)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a 2-D tensor with contiguous rows")
+    return max(t.stride(0), t.shape[1])
+
+
 def _need_f32_cuda(t, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -409,16 +422,25 @@ class Context:
 
     # -- product ----------------------------------------------------------------
     def approx_matmul(self, dA: Decomposition, B, dB: Decomposition | None = None, out=None):
-        _need_f32_cuda(B, "B")
+        """out = Atil B (+ Delta A Btil).  B and out may be column panels of
+        larger row-major matrices (contiguous rows, any row pitch)."""
+        ldb = _row_pitch(B, "B")
         n, p = B.shape
         m = dA.info()["m"]
         if out is None:
             out = self.torch.empty((m, p), dtype=self.torch.float32, device=B.device)
+        ldo = _row_pitch(out, "out")
+        if tuple(out.shape) != (m, p):
+            raise ValueError(f"out must be {m} x {p}")
+        lib = _lib.load()
+        second = dB.handle if dB is not None else None
+        stream = _stream_ptr(self.torch, B.device)
+        if ldb == p and ldo == p:
+            _lib.check(lib.amm_approx_matmul(self.handle, dA.handle, second, C.c_void_p(B.data_ptr()), n, p,
+                                             C.c_void_p(out.data_ptr()), stream))
         else:
-            _need_f32_cuda(out, "out")
-        _lib.check(_lib.load().amm_approx_matmul(
-            self.handle, dA.handle, dB.handle if dB is not None else None, C.c_void_p(B.data_ptr()),
-            n, p, C.c_void_p(out.data_ptr()), _stream_ptr(self.torch, B.device)))
+            _lib.check(lib.amm_approx_matmul_strided(self.handle, dA.handle, second, C.c_void_p(B.data_ptr()), n, p,
+                                                     ldb, C.c_void_p(out.data_ptr()), ldo, stream))
         return out
 
     def approx_matmul_static(self, dA: Decomposition, B, out, dB: Decomposition | None = None):

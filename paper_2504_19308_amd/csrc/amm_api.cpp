@@ -104,14 +104,15 @@ bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 bool circ_side_ok(int64_t n) { return n >= 2 && n <= 16384; }
 
 amm_status circ_columns(amm_ctx* ctx, const amm_dec* b, const float* B, int64_t p, float* out, bool acc,
-                        hipStream_t s) {
+                        hipStream_t s, int64_t ldb = 0, int64_t ldo = 0) {
   if (b->K_eff == 0) {
     if (!acc) AMM_TRY(fill_f32(out, b->n * p, 0.f, s));
     return AMM_OK;
   }
   if (is_pow2(b->n))
     return cd_apply_columns(ctx, log2_exact(b->n), b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc,
-                            s, b->pairs_of(false), b->lists16(false), b->l16_inv);
+                            s, b->pairs_of(false), b->lists16(false), b->l16_inv, ldb, ldo);
+  if ((ldb && ldb != p) || (ldo && ldo != p)) return fail(AMM_EUNSUPPORTED, "strided operands need n a power of two");
   return cd_apply_general(ctx, (int)b->n, b->K_eff, b->shifts.as<int32_t>(), b->L.as<float2>(), B, p, out, acc, s,
                           b->lists16(false), b->l16_inv);
 }
@@ -252,7 +253,7 @@ amm_status left_apply(amm_ctx* ctx, const amm_dec* d, const float* B, int64_t p,
     if (sp != p && d->nnz > 0 && ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0) {
       AMM_TRY(ctx->scratch[14].reserve((size_t)d->n * sp * sizeof(float)));
       float* Bs = ctx->scratch[14].as<float>();
-      AMM_TRY(repitch_f32(B, d->n, p, Bs, sp, s));
+      AMM_TRY(repitch_f32(B, p, d->n, p, Bs, sp, s));
       if (!acc && in && is_circ(in) && in->blocks.empty() && is_pow2(in->n) && in->K_eff > 0) {
         AMM_TRY(ctx->scratch[15].reserve((size_t)d->m * sp * sizeof(float)));
         float* Y = ctx->scratch[15].as<float>();
@@ -1066,6 +1067,80 @@ amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB,
   const float* dAres = nullptr;
   AMM_TRY(residual_of(ctx, dA, &dAres, s));
   return right_apply(ctx, dAres, dA->m, dB, out, true, s);
+}
+
+namespace {
+// Whether two row panels of p floats (rows at a + i lda, i < ra, and at
+// b + k ldb, k < rb) share an element.  With one pitch and a whole-float
+// offset the test is exact (panels side by side in one matrix are disjoint);
+// otherwise the address ranges must be disjoint.
+bool panels_overlap(const float* a, int64_t ra, int64_t lda, const float* b, int64_t rb, int64_t ldb, int64_t p) {
+  const intptr_t diff = (intptr_t)b - (intptr_t)a;
+  if (lda == ldb && diff % (intptr_t)sizeof(float) == 0) {
+    const int64_t ld = lda, d = diff / (intptr_t)sizeof(float);
+    int64_t q = d / ld, r = d % ld;   // b = a + q ld + r, 0 <= r < ld
+    if (r < 0) {
+      r += ld;
+      q -= 1;
+    }
+    auto rows_meet = [&](int64_t lo) { return lo < ra && lo + rb > 0; };   // [lo, lo + rb) against [0, ra)
+    return (r < p && rows_meet(q)) || (ld - r < p && rows_meet(q + 1));
+  }
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)((ra - 1) * lda + p) * sizeof(float);
+  const uintptr_t b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)((rb - 1) * ldb + p) * sizeof(float);
+  return a0 < b1 && b0 < a1;
+}
+}  // namespace
+
+amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
+                                     int64_t n, int64_t p, int64_t ldb, float* out, int64_t ldo, void* stream) {
+  if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");
+  if (ldb < p || ldo < p) return fail(AMM_ESHAPE, "row pitches %lld, %lld below %lld columns", (long long)ldb,
+                                      (long long)ldo, (long long)p);
+  if (ldb == p && ldo == p) return amm_approx_matmul(ctx, dA, dB, B, n, p, out, stream);
+  if (n != dA->n) return fail(AMM_ESHAPE, "B has %lld rows, A has %lld columns", (long long)n, (long long)dA->n);
+  if (p == 0) return AMM_OK;
+  if (!B || !out) return fail(AMM_EINVAL, "NULL argument");
+  const int64_t m = dA->m;
+  if (panels_overlap(B, n, ldb, out, m, ldo, p)) return fail(AMM_EINVAL, "out overlaps B");
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  TimerScope ts(ctx);
+  const amm_dec* in = dA->inner;
+  const bool f4 = ((uintptr_t)B % 16) == 0 && ((uintptr_t)out % 16) == 0 && ldb % 4 == 0 && ldo % 4 == 0 && p % 4 == 0;
+  if (!dB && dA->blocks.empty() && is_circ(dA) && is_pow2(dA->n))
+    return circ_columns(ctx, dA, B, p, out, false, s, ldb, ldo);   // the product reads and writes at the pitches
+  if (!dB && dA->blocks.empty() && is_sparse(dA) && dA->nnz > 0 && f4 && in && is_circ(in) && in->blocks.empty() &&
+      is_pow2(in->n) && in->K_eff > 0) {
+    // B to a spread pitch (from ldb), the residue's product there, S B + it written at ldo
+    const int64_t sp = spread_pitch(p);
+    AMM_TRY(ctx->scratch[14].reserve((size_t)n * sp * sizeof(float)));
+    AMM_TRY(ctx->scratch[15].reserve((size_t)m * sp * sizeof(float)));
+    float* Bs = ctx->scratch[14].as<float>();
+    float* Y = ctx->scratch[15].as<float>();
+    AMM_TRY(repitch_f32(B, ldb, n, p, Bs, sp, s));
+    AMM_TRY(cd_apply_columns(ctx, log2_exact(in->n), in->K_eff, in->shifts.as<int32_t>(), in->L.as<float2>(), Bs, p, Y,
+                             false, s, in->pairs_of(false), in->lists16(false), in->l16_inv, sp, sp));
+    return spmm_csr(dA, Bs, sp, p, out, false, s, Y, sp, ldo);
+  }
+  // other kinds: packed copies in and out around the contiguous product
+  const float* Bp = B;
+  if (ldb != p) {
+    AMM_TRY(ctx->scratch[16].reserve((size_t)n * p * sizeof(float)));
+    AMM_HIP(hipMemcpy2DAsync(ctx->scratch[16].ptr, p * sizeof(float), B, ldb * sizeof(float), p * sizeof(float), n,
+                             hipMemcpyDeviceToDevice, s));
+    Bp = ctx->scratch[16].as<float>();
+  }
+  float* Op = out;
+  if (ldo != p) {
+    AMM_TRY(ctx->scratch[17].reserve((size_t)m * p * sizeof(float)));
+    Op = ctx->scratch[17].as<float>();
+  }
+  AMM_TRY(amm_approx_matmul(ctx, dA, dB, Bp, n, p, Op, stream));
+  if (ldo != p)
+    AMM_HIP(hipMemcpy2DAsync(out, ldo * sizeof(float), Op, p * sizeof(float), p * sizeof(float), m,
+                             hipMemcpyDeviceToDevice, s));
+  return AMM_OK;
 }
 
 amm_status amm_approx_matmul_static(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B, int64_t n,

@@ -138,9 +138,9 @@ struct amm_ctx {
   amm::AllocFns alloc;                 // caller's allocator (alloc == NULL: hipMalloc)
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[16];             // grow-only work areas for products (8-13: chirp-convolution path,
+  amm::DevBuf scratch[18];             // grow-only work areas for products (8-13: chirp-convolution path,
                                        // 14, 15: B and the residue's product at a spread row pitch for
-                                       // sparse products)
+                                       // sparse products; 16, 17: packed copies of strided operands)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
   amm::DevBuf rsvd[10];                     // grow-only float64 work areas of the randomized SVD
@@ -411,7 +411,7 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
 // out (m x p, contiguous) (+)= S B, B with row pitch ldb (floats); with
 // `add` (row pitch ld_add; float4-aligned operands only) out = S B + add
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool accumulate,
-                    hipStream_t s, const float* add = nullptr, int64_t ld_add = 0);
+                    hipStream_t s, const float* add = nullptr, int64_t ld_add = 0, int64_t ldo = 0);
 amm_status dense_times_csr(amm_ctx* ctx, const float* X, int64_t rows, const amm_dec* d, float* out,
                            bool accumulate, hipStream_t s);
 
@@ -433,7 +433,8 @@ amm_status transpose_acc_ld_f32(const float* Y, int64_t ldy, int64_t rows, int64
 // column slice's rows over the L2 channels (cols + 64 for multiples of 2048).
 int64_t spread_pitch(int64_t cols);
 // dst (rows x cols, row pitch ld_dst) = src (rows x cols, contiguous); float4 aligned
-amm_status repitch_f32(const float* src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst, hipStream_t s);
+amm_status repitch_f32(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst,
+                       hipStream_t s);
 amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
                            float* dX, float* dW, hipStream_t s);
 // Batched truncated-SVD products (tsvd_apply.hip)

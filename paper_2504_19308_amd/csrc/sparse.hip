@@ -373,24 +373,25 @@ amm_status transpose_acc_f32(const float* Y, int64_t rows, int64_t cols, float* 
 int64_t spread_pitch(int64_t cols) { return (cols >= 2048 && cols % 2048 == 0) ? cols + 64 : cols; }
 
 // dst (rows x cols, row pitch ld_dst) = src (rows x cols, contiguous)
-__global__ void repitch_kernel(const float4* __restrict__ src, int64_t rows, int64_t cols4, float4* __restrict__ dst,
-                               int64_t ld4) {
+__global__ void repitch_kernel(const float4* __restrict__ src, int64_t lds4, int64_t rows, int64_t cols4,
+                               float4* __restrict__ dst, int64_t ld4) {
   const int64_t total = rows * cols4;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / cols4, c = i - r * cols4;
-    dst[r * ld4 + c] = src[i];
+    dst[r * ld4 + c] = src[r * lds4 + c];
   }
 }
 
-amm_status repitch_f32(const float* src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst, hipStream_t s) {
+amm_status repitch_f32(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst,
+                       hipStream_t s) {
   if (rows <= 0 || cols <= 0) return AMM_OK;
-  if (cols % 4 || ld_dst % 4 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+  if (cols % 4 || ld_dst % 4 || ld_src % 4 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
     return fail(AMM_EINVAL, "repitch needs float4-aligned rows");
   TimedLaunch tl("repitch", s);
   const int64_t cols4 = cols / 4, total = rows * cols4;
   const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(repitch_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float4*>(src), rows, cols4,
-                     reinterpret_cast<float4*>(dst), ld_dst / 4);
+  hipLaunchKernelGGL(repitch_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float4*>(src), ld_src / 4,
+                     rows, cols4, reinterpret_cast<float4*>(dst), ld_dst / 4);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
@@ -582,10 +583,10 @@ amm_status spmm_raw(const int32_t* row_ptr, const int32_t* col, const float* val
 }
 
 amm_status spmm_csr(const amm_dec* d, const float* B, int64_t ldb, int64_t p, float* out, bool acc, hipStream_t s,
-                    const float* add, int64_t ld_add) {
+                    const float* add, int64_t ld_add, int64_t ldo) {
   TimedLaunch tl("spmm_csr", s);
-  return spmm_launch(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, ldb, p, out, p,
-                     acc, s, d->csr_blk.as<int32_t>(), d->csr_blocks, add, ld_add);
+  return spmm_launch(d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), d->m, B, ldb, p, out,
+                     ldo > 0 ? ldo : p, acc, s, d->csr_blk.as<int32_t>(), d->csr_blocks, add, ld_add);
 }
 
 // out (rows x p) (+)= X S for X rows x n and S n x p sparse:

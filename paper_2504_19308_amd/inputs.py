@@ -174,7 +174,7 @@ class Pair:
     name: str
 
 
-def workload_c1(n: int = 256) -> Pair:
+def workload_exp_decay(n: int = 256) -> Pair:
     """n=256 square float64, sigma_i = exp(-i/20), plus 1e-3 N(0,1) noise."""
     out = []
     for operand in (0, 1):
@@ -185,7 +185,7 @@ def workload_c1(n: int = 256) -> Pair:
     return Pair(out[0], out[1], f"haar-exp20-noise n={n}")
 
 
-def workload_c2(n: int = 4096, device=None, with_sparse: bool = False,
+def workload_power_decay(n: int = 4096, device=None, with_sparse: bool = False,
                 frac: float = 0.01, lap_scale: float = 10.0) -> Pair:
     """Square Haar operands with sigma_i = i^-1.5; optional 1% Laplace overlay."""
     out = []
@@ -206,7 +206,7 @@ def workload_c2(n: int = 4096, device=None, with_sparse: bool = False,
     return Pair(out[0], out[1], f"{tag} n={n}")
 
 
-def workload_c5(n: int = 16384, rank: int = 1024, frac: float = 0.005, lap_scale: float = 20.0,
+def workload_lowrank_sparse(n: int = 16384, rank: int = 1024, frac: float = 0.005, lap_scale: float = 20.0,
                 device=None) -> Pair:
     """Square operands S + R: R = Q1 diag(i^-1.5, i = 1..rank) Q2^T with thin
     Haar factors (the energy beyond rank 1024 of the full law is ~4e-7 of the

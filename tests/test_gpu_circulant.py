@@ -56,7 +56,7 @@ def test_apply_full_size_sampled(K):
     torch = torch_cuda()
     n = 4096
     note(f"cd apply full size n={n} K={K}")
-    pair = inputs.workload_c2(n, device="cuda")
+    pair = inputs.workload_power_decay(n, device="cuda")
     A = pair.A.float()
     B = pair.B.float()
     Ah = A.double().cpu().numpy()

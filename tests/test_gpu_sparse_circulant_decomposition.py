@@ -3,7 +3,7 @@ residue with sigma_i = i^-1.5), decomposed on the device as S + circulant_64(R)
 (eq. (2.4) with a truncated residue), checked against the float64 oracle.
 
 The sparse part is checked against the definition of the global top-nnz
-selection (reading G11 of the scope table: the round(f m n) entries of largest
+selection (as read here: the round(f m n) entries of largest
 |a|, ties to the smaller row-major index) without sorting 2^28 entries on the
 host: the stored values are A's entries at the stored positions, their count
 is round(f m n), every kept |a| is >= every dropped |a|, and at the threshold
@@ -30,11 +30,11 @@ class _Lists:
         self.n, self.S, self.L = n, np.asarray(S, dtype=np.int64), np.asarray(L)
 
 
-def test_c5_decomposition_against_oracle():
+def test_sparse_circulant_n16384_against_oracle():
     torch = torch_cuda()
     n, K, frac = 16384, 64, 0.005
-    note(f"c5 decomposition n={n} K={K} frac={frac}")
-    pair = inputs.workload_c5(n, device="cuda")
+    note(f"sparse + circulant decomposition n={n} K={K} frac={frac}")
+    pair = inputs.workload_lowrank_sparse(n, device="cuda")
     A = pair.A.float().contiguous()
     B = pair.B.float().contiguous()
     del pair

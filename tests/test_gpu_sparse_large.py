@@ -19,7 +19,7 @@ FRAC = 0.005
 def c5():
     torch = torch_cuda()
     note(f"sparse large: generating n={N} operand")
-    pair = inputs.workload_c5(N, device="cuda")
+    pair = inputs.workload_lowrank_sparse(N, device="cuda")
     A = pair.A.float().contiguous()
     del pair
     torch.cuda.empty_cache()
@@ -154,8 +154,8 @@ def test_c5_first_order_identity_sampled():
     Btil e_j and Atil (Delta B e_j) from the library's own zeroth-order
     products and everything else in float64."""
     torch = torch_cuda()
-    note("c5 first-order identity")
-    pair = inputs.workload_c5(N, device="cuda")
+    note("sparse + circulant first-order identity")
+    pair = inputs.workload_lowrank_sparse(N, device="cuda")
     A = pair.A.float().contiguous()
     B = pair.B.float().contiguous()
     del pair

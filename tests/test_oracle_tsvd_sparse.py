@@ -240,7 +240,7 @@ def test_thm38_equality_aligned_rank_one_residues():
 
 
 def test_frozen_pattern_keeps_zero_valued_entries():
-    """Reading G25: the frozen sparse structure is the kept index set Omega, so
+    """The frozen-structure reading: the frozen sparse structure is the kept index set Omega, so
     a kept entry whose value is exactly 0 stays in Omega and the projection
     P(G) = G o Omega keeps G there.  A has 5 nonzeros and 9 entries are kept,
     four of them zeros (ties at |a| = 0 go to the smallest row-major index)."""
