@@ -434,6 +434,18 @@ def power_decay_workload(torch, ctx, tm, only=""):
     return res
 
 
+def rsvd_excess(torch, d, M, sigma):
+    """||M - U S V^T||_F / (sum_{i > k} sigma_i^2)^(1/2) - 1 for the
+    device's rank-k factors of M (Eckart-Young: 0 for the exact truncation;
+    sigma the generator's singular values)."""
+    U, s, V = (torch.from_numpy(np.ascontiguousarray(x)).cuda().double() for x in d.tsvd_factors())
+    R = M.double() - (U * s) @ V.t()
+    tail = float(np.sqrt(np.sum(sigma[len(s):] ** 2)))
+    err = float(R.norm())
+    del U, V, R
+    return err / tail - 1.0
+
+
 def kernel_roof(name, ms_per_launch, n, p, K=0, k=0, nnz=0, first=False, list_bytes=8):
     """Roofline fraction of one kernel launch of a variant (algorithmic bytes
     and flops; the larger of the two times at peak decides the bound).
@@ -498,6 +510,8 @@ def power_decay_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, onl
         log(f"[bench] {name}: {ms:.4f} ms err {err:.3e}")
 
     if not only or only == "power":
+        from paper_2504_19308_amd import inputs
+        sigma = inputs.decay_power(n, 1.5)    # the generator's singular values
         # circulant
         for K in (8, 32, 128):
             dA, ta = dec(A, None, "circulant", K)
@@ -523,6 +537,8 @@ def power_decay_variants(torch, ctx, A, B, exact, tm, dense_ms, flops_equiv, onl
                 dB, tb = dec(B, None, "tsvd", k, seed=2)
             measure(f"tsvd k={k} zeroth", dA, None, B, ta, exact, k=k)
             measure(f"tsvd k={k} first", dA, dB, B, ta + tb, exact, k=k)
+            res[-2]["rsvd_excess"] = {"A": rsvd_excess(torch, dA, A, sigma), "B": rsvd_excess(torch, dB, B, sigma)}
+            log(f"[bench] power-decay rSVD k={k} excess ||A - A_k|| / tail - 1: {res[-2]['rsvd_excess']}")
         # sparsified operands: 1% Laplace(10) entries over the same low-rank decay
         from paper_2504_19308_amd import inputs
         sp = inputs.workload_power_decay(n, device="cuda", with_sparse=True)
@@ -944,7 +960,6 @@ def batch_workload(torch, ctx, tm, k=128, pcols=2048, count=64):
     plan.run(use_graph=False)
     kt = ctx.timings()
     ctx.set_timing(False)
-    del exact
     # dense FP32 baseline: the same 64 products with torch.matmul
     dense = []
     for (m, n) in shapes:
@@ -968,6 +983,9 @@ def batch_workload(torch, ctx, tm, k=128, pcols=2048, count=64):
     torch.cuda.empty_cache()
     plan16 = ctx.batch_plan(decs, B16)
     ms16 = statistics.median(tm.run(lambda: plan16.run(use_graph=True), 20, 3))
+    # error against the float64 product of the unrounded operands (bfloat16 B_i and factors both count)
+    errs16 = {f"{shapes[i][0]}x{shapes[i][1]}": rel_err(plan16.outs[i], exact[i]) for i in exact}
+    del exact
     ctx.set_timing(True)
     plan16.run(use_graph=False)
     kt16 = ctx.timings()
@@ -984,9 +1002,11 @@ def batch_workload(torch, ctx, tm, k=128, pcols=2048, count=64):
              "tflop_equiv_s": flops / (ms16 * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms16,
              "speedup_vs_dense_bf16": dense16_ms / ms16, "dense_bf16_ms": dense16_ms,
              "hbm_bytes_algorithmic": byts, "hbm_frac": byts / (ms16 * 1e-3) / HBM_PEAK,
+             "err_vs_exact": errs16, "meets_1pct": max(errs16.values()) <= 0.01,
              "plan": plan16.info(), "kernels_ms": {kn: v[0] for kn, v in kt16.items()},
              "precision": "bfloat16 factors and activations, float32 accumulation and output"}
-    log(f"[bench] batch bf16: {ms16:.3f} ms, dense bf16 {dense16_ms:.3f} ms, HBM frac {rec16['hbm_frac']:.2f}")
+    log(f"[bench] batch bf16: {ms16:.3f} ms, dense bf16 {dense16_ms:.3f} ms, HBM frac {rec16['hbm_frac']:.2f}, "
+        f"err {errs16}")
     plan16.close()
     del decs
     torch.cuda.empty_cache()

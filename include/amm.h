@@ -112,7 +112,10 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device` (made current for the call).
- * Owns per-size twiddle tables and scratch; not thread-safe. */
+ * Owns per-size twiddle tables and grow-only work areas; not thread-safe.
+ * Calls on one context share its work areas, so calls enqueued on different
+ * streams must be ordered by the caller (or use one context per stream);
+ * contexts never share work areas with each other. */
 amm_status amm_ctx_create(amm_ctx** ctx, int device);
 void amm_ctx_destroy(amm_ctx* ctx);
 

@@ -33,18 +33,22 @@ namespace {
 struct TimerScope {
   KernelTimer* prev;
   const AllocFns* prev_alloc;
-  explicit TimerScope(amm_ctx* ctx) : prev(g_timer), prev_alloc(g_alloc) {
+  DevBuf* prev_part;
+  explicit TimerScope(amm_ctx* ctx) : prev(g_timer), prev_alloc(g_alloc), prev_part(g_gemm_part) {
     g_timer = (ctx && ctx->timing) ? &ctx->timer : nullptr;
     g_alloc = ctx ? &ctx->alloc : nullptr;
+    g_gemm_part = ctx ? &ctx->gemm_part : nullptr;
   }
   // calls on a handle alone allocate with the handle's allocator
-  explicit TimerScope(const amm_dec* d) : prev(g_timer), prev_alloc(g_alloc) {
+  explicit TimerScope(const amm_dec* d) : prev(g_timer), prev_alloc(g_alloc), prev_part(g_gemm_part) {
     g_timer = nullptr;
     g_alloc = d ? &d->alloc : nullptr;
+    g_gemm_part = nullptr;
   }
   ~TimerScope() {
     g_timer = prev;
     g_alloc = prev_alloc;
+    g_gemm_part = prev_part;
   }
 };
 }  // namespace
@@ -63,6 +67,7 @@ amm_status hip_fail(hipError_t e, const char* what) {
 }
 
 thread_local const AllocFns* g_alloc = nullptr;
+thread_local DevBuf* g_gemm_part = nullptr;
 
 amm_status DevBuf::alloc(size_t b) {
   release();

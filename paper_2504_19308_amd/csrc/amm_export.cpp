@@ -262,9 +262,16 @@ amm_status amm_dec_import(amm_ctx* ctx, const void* buf, size_t bytes, const flo
   // buffers come from the context's allocator (if it has one)
   struct Scope {
     const AllocFns* prev = g_alloc;
-    explicit Scope(const AllocFns* a) { g_alloc = a; }
-    ~Scope() { g_alloc = prev; }
-  } scope(&ctx->alloc);
+    DevBuf* prev_part = g_gemm_part;
+    explicit Scope(amm_ctx* c) {
+      g_alloc = &c->alloc;
+      g_gemm_part = &c->gemm_part;
+    }
+    ~Scope() {
+      g_alloc = prev;
+      g_gemm_part = prev_part;
+    }
+  } scope(ctx);
   amm_dec* d = nullptr;
   AMM_TRY(read_node(r, ctx->device, A, &d, 0));
   if (r.left != 0) {

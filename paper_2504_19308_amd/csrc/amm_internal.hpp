@@ -103,6 +103,9 @@ struct KernelTimer {
   }
 };
 extern thread_local KernelTimer* g_timer;
+// split-K partial sums of the GEMMs: the work area of the context the current
+// API call works for (nullptr outside a context call)
+extern thread_local DevBuf* g_gemm_part;
 
 struct TimedLaunch {
   hipEvent_t b_ = nullptr;
@@ -143,7 +146,8 @@ struct amm_ctx {
                                        // sparse products; 16, 17: packed copies of strided operands)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
-  amm::DevBuf rsvd[10];                     // grow-only float64 work areas of the randomized SVD
+  amm::DevBuf rsvd[14];                     // grow-only work areas of the randomized SVD
+  amm::DevBuf gemm_part;                    // grow-only split-K partial sums
   amm::KernelTimer timer;
   bool timing = false;
 };
@@ -421,6 +425,12 @@ amm_status transpose_acc_f32(const float* Y, int64_t rows, int64_t cols, float* 
                              hipStream_t s);
 // sum of squares of count floats, accumulated in float64 (synchronises s)
 amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out);
+// l x l steps of the randomized SVD on the device (rsvd_small.hip)
+constexpr int kSmallEigMax = 96;
+amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, double* rinv, int* status,
+                          hipStream_t s);
+amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, double* isg, double* sgk,
+                    float* sigma_f, double* sig_sorted, hipStream_t s);
 // ||x - y||_F^2 and ||x||_F^2 of count floats, float64 (synchronises s)
 amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStream_t s, double* dd, double* xx);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);

@@ -159,12 +159,14 @@ __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restr
   *c = (beta == T(0)) ? s : s + beta * *c;
 }
 
-// Split-K workspace, grow-only and kept until the process ends (never freed
-// at exit, so no HIP call runs during static destruction).  Growing it frees
-// the old block with hipFree, which waits for work still using it.
-DevBuf& part_ws() {
-  static DevBuf* ws = new DevBuf();
-  return *ws;
+// Split-K workspace: the calling context's grow-only area.  Every library
+// entry point that multiplies sets it, so a GEMM outside a context call is an
+// internal error rather than a shared buffer that two contexts' streams could
+// race on.
+amm_status part_ws(DevBuf** ws) {
+  if (!g_gemm_part) return fail(AMM_EINVAL, "internal: split-K GEMM outside a context call");
+  *ws = g_gemm_part;
+  return AMM_OK;
 }
 
 template <typename T>
@@ -197,8 +199,10 @@ amm_status gemm_any(int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_
   splits = (K + k_split - 1) / k_split;
   T* part = nullptr;
   if (splits > 1) {
-    AMM_TRY(part_ws().reserve((size_t)splits * M * N * sizeof(T)));
-    part = part_ws().as<T>();
+    DevBuf* ws = nullptr;
+    AMM_TRY(part_ws(&ws));
+    AMM_TRY(ws->reserve((size_t)splits * M * N * sizeof(T)));
+    part = ws->as<T>();
   }
   if (gm > 65535 || splits > 65535) return fail(AMM_EUNSUPPORTED, "gemm grid too large");
   dim3 grid((unsigned)gn, (unsigned)gm, (unsigned)splits), block(NT);

@@ -1,0 +1,331 @@
+// The l x l steps of the randomized SVD (Alg. 2.1 with oversampling and
+// subspace iteration) on the device, one workgroup each, so the
+// decomposition makes no host round trip between its GEMMs:
+//
+//   chol_inv_kernel   Gram matrix G = Y^T Y of a sketch -> R^-1 with
+//                     G (+ shift) = R^T R (CholeskyQR's factor, inverted);
+//   gram_eig_kernel   G = B B^T of the projected operand -> eigenvectors W
+//                     and eigenvalues (parallel cyclic Jacobi), sorted into
+//                     the singular values and column order that the factor
+//                     assembly uses.
+//
+// Both hold their l x l matrices in LDS (l <= kSmallEigMax: two 96 x 97
+// float64 arrays at an odd row pitch, 146 KiB of the 160 KiB a workgroup may
+// use).  A larger sketch keeps the host path.
+#include <cmath>
+
+#include "amm_internal.hpp"
+
+namespace amm {
+namespace {
+
+constexpr int NT = 256;
+constexpr int LM = kSmallEigMax;
+constexpr int LS = LM * (LM + 1);   // an l x l array at the odd row pitch ld = l | 1
+
+// Row pitch of an l x l LDS array: odd, so that a column walk (lanes on
+// consecutive rows) spreads its 8-byte reads over the banks.
+__device__ __forceinline__ int pitch_of(int l) { return l | 1; }
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // 256 threads: four waves, shuffles inside a wave, LDS across waves
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// Upper Cholesky factor R of S (l x l at pitch ld, symmetric, only the upper
+// triangle is read; S = R^T R) by row elimination, applied at the same time
+// to E = I: the row operations that turn S into R turn I into R^-T (E S = R,
+// so E = R S^-1 = R^-T), with no serial back substitution.  On return the
+// upper part of S holds R and E (lower triangular) holds R^-T.  Returns
+// false (uniformly over the block) at a non-positive pivot.  Thread (g, c)
+// owns column c of the rows g, g + ng, ... (no division inside the loops).
+// One barrier per step: step j reads row j unscaled and scales on the fly;
+// the scaled row j is stored during step j + 1, when no thread reads it.
+__device__ bool cholesky_inv_lds(double* S, double* E, int l, int ld) {
+  const int ng = NT / l, g = (int)threadIdx.x / l, c = (int)threadIdx.x % l;
+  const bool active = g < ng;
+  if (active)
+    for (int a = g; a < l; a += ng) E[a * ld + c] = (a == c) ? 1.0 : 0.0;
+  int pend = -1;   // row whose scaled values thread (0, c) still has to store
+  double pend_s = 0.0, pend_e = 0.0;
+  for (int j = 0; j < l; ++j) {
+    __syncthreads();
+    if (g == 0 && pend >= 0) {
+      if (c >= pend) S[pend * ld + c] = pend_s;
+      if (c <= pend) E[pend * ld + c] = pend_e;
+    }
+    const double d = S[j * ld + j];
+    if (!(d > 0.0)) return false;
+    const double ir = 1.0 / sqrt(d);
+    if (active) {
+      const double xs = S[j * ld + c] * ir, xe = E[j * ld + c] * ir;   // row j of R and of R^-T
+      // rows a > j: minus R[j][a] times row j (S: columns >= a; E: columns
+      // <= j), four rows per pass; the loads are unconditional (rows past
+      // the end clamped) so all twelve are in flight together
+      for (int a0 = j + 1 + g; a0 < l; a0 += 4 * ng) {
+        double f[4], ts[4], te[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = min(a0 + u * ng, l - 1);
+          f[u] = S[j * ld + a] * ir;
+          ts[u] = S[a * ld + c];
+          te[u] = E[a * ld + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = a0 + u * ng;
+          if (a < l) {
+            if (c >= a) S[a * ld + c] = ts[u] - f[u] * xs;
+            else if (c <= j) E[a * ld + c] = te[u] - f[u] * xe;
+          }
+        }
+      }
+      if (g == 0) {
+        pend = j;
+        pend_s = xs;
+        pend_e = xe;
+      }
+    }
+  }
+  __syncthreads();
+  if (g == 0 && pend >= 0) {
+    if (c >= pend) S[pend * ld + c] = pend_s;
+    if (c <= pend) E[pend * ld + c] = pend_e;
+  }
+  __syncthreads();
+  return true;
+}
+
+// mode 0: G + shift (the first CholeskyQR pass, always shifted); mode 1: G,
+// shifted only if its plain factorisation fails.  shift = 11 (rows l +
+// l (l + 1)) u tr(G), u = 2^-53 (shifted CholeskyQR3, Fukaya et al. 2020).
+// rinv (l x l, row-major) receives R^-1 (zero below the diagonal).  On a
+// breakdown *status is set to 1 and rinv holds the identity.
+__global__ void __launch_bounds__(NT) chol_inv_kernel(const double* __restrict__ gram, int l, int64_t rows,
+                                                      int mode, double* __restrict__ rinv, int* __restrict__ status) {
+  __shared__ double S[LS];
+  __shared__ double E[LS];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, ld = pitch_of(l);
+  const int ng = NT / l, g = tid / l, c = tid % l;
+  auto load = [&](double shift) {
+    __syncthreads();
+    if (g < ng)
+      for (int i = g; i < l; i += ng) {
+        double v = 0.5 * (gram[i * l + c] + gram[c * l + i]);
+        if (i == c) v += shift;
+        S[i * ld + c] = v;
+      }
+  };
+  double tr = 0.0;
+  for (int i = tid; i < l; i += NT) tr += gram[i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * tr;
+  load(mode == 0 ? shift : 0.0);
+  bool ok = cholesky_inv_lds(S, E, l, ld);
+  if (!ok && mode != 0) {
+    load(shift);
+    ok = cholesky_inv_lds(S, E, l, ld);
+  }
+  if (!ok) {
+    if (tid == 0) *status = 1;
+    if (g < ng)
+      for (int i = g; i < l; i += ng) rinv[i * l + c] = (i == c) ? 1.0 : 0.0;
+    return;
+  }
+  // R^-1 = E^T (upper)
+  if (g < ng)
+    for (int i = g; i < l; i += ng) rinv[i * l + c] = (c >= i) ? E[c * ld + i] : 0.0;
+}
+
+// Player at seat `pos` of round `r` of a round-robin over `np` players (np
+// even): seat 0 keeps player 0, the others rotate.
+__device__ __forceinline__ int seat(int pos, int r, int np) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1); }
+
+// Eigen-decomposition of the symmetric G (l x l) by cyclic Jacobi with the
+// round-robin parallel ordering: each round rotates l/2 disjoint index pairs
+// at once (G <- J^T G J, W <- W J), a sweep is l - 1 rounds (every pair
+// once), sweeps run until the off-diagonal norm is <= 1e-16 ||G||_F.
+// Outputs, with the eigenvalues sorted descending (order[j] = index of the
+// j-th largest; ties by index):
+//   W (l x l) eigenvectors by original index; perm[j] = order[j];
+//   isg[i] = 1 / sqrt(lam_i) (0 for lam_i <= 0), by original index;
+//   sgk[j] = sqrt(lam_order[j]) for j < k (float64) and sigma_f (float32);
+//   sig_sorted[j] = sqrt(max(lam_order[j], 0)) for j < l.
+__global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__ gram, int l, int k,
+                                                      double* __restrict__ Wout, int32_t* __restrict__ perm,
+                                                      double* __restrict__ isg, double* __restrict__ sgk,
+                                                      float* __restrict__ sigma_f, double* __restrict__ sig_sorted) {
+  __shared__ double G[LS];
+  __shared__ double W[LS];
+  __shared__ double cs[LM / 2 + 1], sn[LM / 2 + 1];
+  __shared__ int pp[LM / 2 + 1], qq[LM / 2 + 1];
+  __shared__ double red[4];
+  __shared__ double lam[LM];
+  __shared__ int any_rot;
+  const int tid = threadIdx.x, ld = pitch_of(l);
+  // thread -> (row group g, column c): rows g, g + ng, ...; no division inside the loops
+  const int ng = NT / l, g = tid / l, c = tid % l;
+  const bool active = g < ng;
+  double f = 0.0;
+  if (active)
+    for (int i = g; i < l; i += ng) {
+      const double v = 0.5 * (gram[i * l + c] + gram[c * l + i]);
+      G[i * ld + c] = v;
+      W[i * ld + c] = (i == c) ? 1.0 : 0.0;
+      f += v * v;
+    }
+  const double fro = sqrt(block_sum(f, red));
+  const int np = l + (l & 1);   // an odd l gets a dummy player l (its pairs are skipped)
+  const int npairs = np / 2;
+  // Sweeps until one rotates no pair (every off-diagonal entry is at rounding
+  // level relative to its diagonal pair, which keeps small eigenvalues
+  // accurate too) or the off-diagonal norm is <= 1e-16 ||G||_F.
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double o = 0.0;
+    if (active)
+      for (int i = g; i < c; i += ng) o += G[i * ld + c] * G[i * ld + c];
+    o = block_sum(o, red);
+    if (!(sqrt(o) > 1e-16 * fro)) break;   // converged (or not a number: stop)
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      // rotation of each pair, from the 2 x 2 block it annihilates
+      if (tid < npairs) {
+        int rotated = 0;
+        int p = seat(tid, r, np), q = seat(np - 1 - tid, r, np);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double cc = 1.0, ss = 0.0;
+        if (q < l) {
+          const double apq = G[p * ld + q], app = G[p * ld + p], aqq = G[q * ld + q];
+          // rotate unless the pair is already decoupled to rounding: |a_pq| <= u sqrt(|a_pp a_qq|)
+          if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
+            rotated = 1;
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            cc = 1.0 / sqrt(t * t + 1.0);
+            ss = t * cc;
+          }
+        }
+        cs[tid] = cc;
+        sn[tid] = ss;
+        pp[tid] = p;
+        qq[tid] = q < l ? q : -1;
+        if (rotated) any_rot = 1;
+      }
+      __syncthreads();
+      // columns p, q of G and of W (G J, W J): thread row c, pairs g, g + ng, ...
+      // Four pairs per pass: their (disjoint) entries are all loaded before
+      // any is stored, so the LDS round trips overlap.
+      if (active)
+        for (int i0 = g; i0 < npairs; i0 += 4 * ng) {
+          int p[4], q[4];
+          double cc[4], ss[4], a[4], b[4], u[4], v[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = min(i0 + t * ng, npairs - 1);   // clamped: loads stay unconditional
+            const int pi = pp[i], qi = qq[i];
+            const double ci = cs[i], si = sn[i];
+            const bool on = i0 + t * ng < npairs && qi >= 0;
+            p[t] = on ? pi : 0;
+            q[t] = on ? qi : 0;
+            cc[t] = ci;
+            ss[t] = on ? si : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            a[t] = G[c * ld + p[t]];
+            b[t] = G[c * ld + q[t]];
+            u[t] = W[c * ld + p[t]];
+            v[t] = W[c * ld + q[t]];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (ss[t] == 0.0) continue;   // no rotation (or no pair): leave the entries
+            G[c * ld + p[t]] = cc[t] * a[t] - ss[t] * b[t];
+            G[c * ld + q[t]] = ss[t] * a[t] + cc[t] * b[t];
+            W[c * ld + p[t]] = cc[t] * u[t] - ss[t] * v[t];
+            W[c * ld + q[t]] = ss[t] * u[t] + cc[t] * v[t];
+          }
+        }
+      __syncthreads();
+      // rows p, q of G (J^T G): thread column c, four pairs per pass
+      if (active)
+        for (int i0 = g; i0 < npairs; i0 += 4 * ng) {
+          int p[4], q[4];
+          double cc[4], ss[4], a[4], b[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = min(i0 + t * ng, npairs - 1);   // clamped: loads stay unconditional
+            const int pi = pp[i], qi = qq[i];
+            const double ci = cs[i], si = sn[i];
+            const bool on = i0 + t * ng < npairs && qi >= 0;
+            p[t] = on ? pi : 0;
+            q[t] = on ? qi : 0;
+            cc[t] = ci;
+            ss[t] = on ? si : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            a[t] = G[p[t] * ld + c];
+            b[t] = G[q[t] * ld + c];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (ss[t] == 0.0) continue;
+            G[p[t] * ld + c] = cc[t] * a[t] - ss[t] * b[t];
+            G[q[t] * ld + c] = ss[t] * a[t] + cc[t] * b[t];
+          }
+        }
+      __syncthreads();
+    }
+    if (!any_rot) break;   // read after the round's last barrier: uniform
+  }
+  for (int i = tid; i < l; i += NT) lam[i] = G[i * ld + i];
+  __syncthreads();
+  for (int i = tid; i < l; i += NT) {
+    const double li = lam[i];
+    int rank = 0;
+    for (int j = 0; j < l; ++j) rank += (lam[j] > li || (lam[j] == li && j < i)) ? 1 : 0;
+    const double sg = sqrt(fmax(li, 0.0));
+    perm[rank] = i;
+    isg[i] = sg > 0.0 ? 1.0 / sg : 0.0;
+    sig_sorted[rank] = sg;
+    if (rank < k) {
+      sgk[rank] = sg;
+      sigma_f[rank] = (float)sg;
+    }
+  }
+  if (active)
+    for (int i = g; i < l; i += ng) Wout[i * l + c] = W[i * ld + c];
+}
+
+}  // namespace
+
+amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, double* rinv, int* status,
+                          hipStream_t s) {
+  if (l < 1 || l > kSmallEigMax) return fail(AMM_EUNSUPPORTED, "device CholeskyQR factor needs 1 <= l <= %d", kSmallEigMax);
+  TimedLaunch tl("rsvd_chol", s);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(NT), 0, s, gram, l, rows, mode, rinv, status);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, double* isg, double* sgk,
+                    float* sigma_f, double* sig_sorted, hipStream_t s) {
+  if (l < 1 || l > kSmallEigMax || k > l) return fail(AMM_EUNSUPPORTED, "device Gram eigensolver needs k <= l <= %d", kSmallEigMax);
+  TimedLaunch tl("rsvd_eig", s);
+  hipLaunchKernelGGL(gram_eig_kernel, dim3(1), dim3(NT), 0, s, gram, l, k, W, perm, isg, sgk, sigma_f, sig_sorted);
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+}  // namespace amm

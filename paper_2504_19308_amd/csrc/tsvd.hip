@@ -7,10 +7,14 @@
 // `power_iters` subspace iterations (Y <- A A^T Y with re-orthonormalisation),
 // both from the same reference; the leading k triplets are kept.
 //
-// Device work: the tall GEMMs (float64 MFMA) and the sketch generator.  Host
-// work is confined to l x l matrices (l = k + oversample): Cholesky factors
-// for the CholeskyQR2 orthonormalisation and a Jacobi eigensolver for the
-// small Gram matrix (Q^T A)(Q^T A)^T.
+// Device work: the tall GEMMs (float64 MFMA), the sketch generator and, for
+// l = k + oversample <= 96, the l x l steps as well (CholeskyQR factors and
+// the Jacobi eigensolver of the Gram matrix (Q^T A)(Q^T A)^T, one workgroup
+// each): the whole decomposition is enqueued without a host round trip and
+// read back once at the end.  Larger sketches do the l x l steps on the host.
+// Intermediate orthonormalisations of the subspace iteration take one
+// shifted CholeskyQR pass (they only need a well-conditioned basis of the
+// same span); the final basis takes three (shifted CholeskyQR3).
 //
 // The sketch entries are N(0,1) from Philox4x32-10 (Salmon et al., 2011) with
 // the Box-Muller transform: counter = (element pair index, seed), key fixed.
@@ -273,8 +277,10 @@ amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStre
   return AMM_OK;
 }
 
-amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
-                          const amm_opts* o, amm_dec* dec, hipStream_t s) {
+namespace {
+
+amm_status tsvd_decompose_host(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k,
+                               const amm_opts* o, amm_dec* dec, hipStream_t s) {
   const int64_t mn = std::min(m, n);
   const int l = (int)std::min<int64_t>(mn, (int64_t)k + std::max(o->oversample, 0));
   const int q = std::max(o->power_iters, 0);
@@ -384,6 +390,138 @@ amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   AMM_HIP(hipMemcpyAsync(dec->sigma.ptr, sig_f.data(), k * 4, hipMemcpyHostToDevice, s));
   AMM_HIP(hipStreamSynchronize(s));
   return AMM_OK;
+}
+
+// Orthonormalise the columns of *cur (rows x l) through `passes` CholeskyQR
+// passes on the device (the first shifted); each pass writes Q = Y R^-1 into
+// the other buffer and swaps the two.
+amm_status orthonormalise_dev(double** cur, double** alt, int64_t rows, int l, int passes, double* gram,
+                              double* rinv, int* status, hipStream_t s) {
+  for (int pass = 0; pass < passes; ++pass) {
+    AMM_TRY(gemm_f64(l, l, rows, 1.0, *cur, 1, l, *cur, l, 1, 0.0, gram, l, s));
+    AMM_TRY(chol_qr_factor(gram, l, rows, pass == 0 ? 0 : 1, rinv, status, s));
+    AMM_TRY(gemm_f64(rows, l, l, 1.0, *cur, l, 1, rinv, l, 1, 0.0, *alt, l, s));
+    std::swap(*cur, *alt);
+  }
+  return AMM_OK;
+}
+
+__global__ void set_i32(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// The decomposition with every step on the device (l <= kSmallEigMax) and a
+// single read-back of the singular values, the norm partial sums and the
+// breakdown flag at the end.
+amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k, int l, int q,
+                                 const amm_opts* o, amm_dec* dec, hipStream_t s) {
+  const int64_t mn = std::min(m, n);
+  DevBuf* ws = ctx->rsvd;
+  DevBuf &A64 = ws[0], &Om = ws[1], &Y = ws[2], &Z = ws[3], &Y2 = ws[4], &gram = ws[5], &Bs = ws[6];
+  DevBuf &Wd = ws[7], &Uf = ws[8], &Vf = ws[9], &Z2 = ws[10], &small = ws[11];
+  constexpr int kParts = 1024;
+  AMM_TRY(A64.reserve(m * n * sizeof(double)));
+  AMM_TRY(Om.reserve(n * l * sizeof(double)));
+  AMM_TRY(Y.reserve(m * l * sizeof(double)));
+  AMM_TRY(Y2.reserve(m * l * sizeof(double)));
+  AMM_TRY(Z.reserve(n * l * sizeof(double)));
+  AMM_TRY(Z2.reserve(n * l * sizeof(double)));
+  AMM_TRY(gram.reserve(l * l * sizeof(double)));
+  AMM_TRY(Bs.reserve(l * n * sizeof(double)));
+  AMM_TRY(Wd.reserve(l * l * sizeof(double)));
+  AMM_TRY(Uf.reserve(m * l * sizeof(double)));
+  AMM_TRY(Vf.reserve(n * l * sizeof(double)));
+  // small: [sig_sorted l | norm partials kParts | isg l | sgk l | rinv l*l] doubles, then perm l, status 1 int32
+  const size_t nd = (size_t)3 * l + kParts + (size_t)l * l;
+  AMM_TRY(small.reserve(nd * sizeof(double) + (l + 1) * sizeof(int32_t)));
+  double* sig_sorted = small.as<double>();
+  double* parts = sig_sorted + l;
+  double* isg = parts + kParts;
+  double* sgk = isg + l;
+  double* rinv = sgk + l;
+  int32_t* perm = reinterpret_cast<int32_t*>(rinv + (size_t)l * l);
+  int* status = perm + l;
+  hipLaunchKernelGGL(set_i32, dim3(1), dim3(64), 0, s, status, 0);
+  // ||A||_F partial sums (read with the results)
+  const int blocks = (int)std::min<int64_t>(kParts, (m * n + 255) / 256);
+  hipLaunchKernelGGL(sumsq_partial, dim3(blocks), dim3(256), 0, s, A, m * n, parts);
+  hipLaunchKernelGGL(widen_f32, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, A, A64.as<double>(), m * n);
+  const int64_t cnt = n * l;
+  hipLaunchKernelGGL(gaussian_sketch, dim3((unsigned)((cnt / 2 + 256) / 256)), dim3(256), 0, s, Om.as<double>(), cnt,
+                     o->seed);
+  AMM_HIP(hipGetLastError());
+  const double* Ad = A64.as<double>();
+  double *y = Y.as<double>(), *y2 = Y2.as<double>(), *z = Z.as<double>(), *z2 = Z2.as<double>();
+  // Y = A Omega
+  AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, Om.as<double>(), l, 1, 0.0, y, l, s));
+  AMM_TRY(orthonormalise_dev(&y, &y2, m, l, q > 0 ? 1 : 3, gram.as<double>(), rinv, status, s));
+  for (int it = 0; it < q; ++it) {
+    // Z = A^T Q, orthonormalise; Y = A Z, orthonormalise (three passes for the final basis)
+    AMM_TRY(gemm_f64(n, l, m, 1.0, Ad, 1, n, y, l, 1, 0.0, z, l, s));
+    AMM_TRY(orthonormalise_dev(&z, &z2, n, l, 1, gram.as<double>(), rinv, status, s));
+    AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, z, l, 1, 0.0, y, l, s));
+    AMM_TRY(orthonormalise_dev(&y, &y2, m, l, it + 1 == q ? 3 : 1, gram.as<double>(), rinv, status, s));
+  }
+  // Bs = Q^T A (l x n); its Gram matrix Bs Bs^T = W diag(lam) W^T
+  AMM_TRY(gemm_f64(l, n, m, 1.0, y, 1, l, Ad, n, 1, 0.0, Bs.as<double>(), n, s));
+  AMM_TRY(gemm_f64(l, l, n, 1.0, Bs.as<double>(), n, 1, Bs.as<double>(), 1, n, 0.0, gram.as<double>(), l, s));
+  AMM_TRY(gram_eig(gram.as<double>(), l, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted, s));
+  // U_full = Q W (m x l), V_full = Bs^T W diag(1/sig) (n x l); the leading k columns in descending order
+  AMM_TRY(gemm_f64(m, l, l, 1.0, y, l, 1, Wd.as<double>(), l, 1, 0.0, Uf.as<double>(), l, s));
+  AMM_TRY(gemm_f64(n, l, l, 1.0, Bs.as<double>(), 1, n, Wd.as<double>(), l, 1, 0.0, Vf.as<double>(), l, s));
+  hipLaunchKernelGGL(pick_columns, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s, Uf.as<double>(), m,
+                     (int64_t)l, perm, (const double*)nullptr, k, dec->U.as<float>(), dec->US.as<float>(), sgk);
+  hipLaunchKernelGGL(pick_columns, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, Vf.as<double>(), n,
+                     (int64_t)l, perm, isg, k, dec->V.as<float>(), dec->VS.as<float>(), sgk);
+  AMM_HIP(hipGetLastError());
+  AMM_TRY(transpose_f32(dec->VS.as<float>(), n, k, dec->VSt.as<float>(), s));
+  AMM_TRY(transpose_f32(dec->V.as<float>(), n, k, dec->Vt.as<float>(), s));
+  // one read-back: singular values, norm partial sums, breakdown flag
+  std::vector<double> h((size_t)l + blocks);
+  int st = 0;
+  AMM_HIP(hipMemcpyAsync(h.data(), sig_sorted, ((size_t)l + blocks) * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  double a2 = 0.0;
+  for (int b = 0; b < blocks; ++b) a2 += h[l + b];
+  dec->norm_A = std::sqrt(a2);
+  if (dec->norm_A == 0.0) {
+    // a zero operand has no nonzero singular triplet
+    dec->K_eff = 0;
+    dec->norm_residual = 0.0;
+    dec->sigma_next = 0.0;
+    return AMM_OK;
+  }
+  if (st != 0) return fail(AMM_EDEVICE, "CholeskyQR broke down (sketch rank-deficient)");
+  std::vector<double> sig_k(h.begin(), h.begin() + k);
+  double kept = 0.0;
+  for (double v : sig_k) kept += v * v;
+  dec->norm_residual = std::sqrt(std::max(dec->norm_A * dec->norm_A - kept, 0.0));
+  dec->sigma64 = sig_k;
+  // the sketch's (k+1)-th singular value estimates ||Delta A||_2 (Thm. 3.8)
+  if (k < l) dec->sigma_next = h[k];
+  else if (k == mn) dec->sigma_next = 0.0;
+  return AMM_OK;
+}
+
+}  // namespace
+
+amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k, const amm_opts* o, amm_dec* dec,
+                          hipStream_t s) {
+  const int64_t mn = std::min(m, n);
+  const int l = (int)std::min<int64_t>(mn, (int64_t)k + std::max(o->oversample, 0));
+  const int q = std::max(o->power_iters, 0);
+  if (k == 0 || l > kSmallEigMax) return tsvd_decompose_host(ctx, A, m, n, k, o, dec, s);
+  dec->K_eff = k;
+  const int64_t kk = std::max(k, 1);
+  AMM_TRY(dec->U.alloc(m * kk * 4));
+  AMM_TRY(dec->US.alloc(m * kk * 4));
+  AMM_TRY(dec->V.alloc(n * kk * 4));
+  AMM_TRY(dec->VS.alloc(n * kk * 4));
+  AMM_TRY(dec->VSt.alloc(n * kk * 4));
+  AMM_TRY(dec->Vt.alloc(n * kk * 4));
+  AMM_TRY(dec->sigma.alloc(kk * 4));
+  return tsvd_decompose_device(ctx, A, m, n, k, l, q, o, dec, s);
 }
 
 }  // namespace amm
