@@ -2,8 +2,8 @@
 //
 // With F[p, q] = exp(-2 pi i p q / n) (unnormalised) and W = F / sqrt(n):
 //   AB = (A W*)(W B) = (1/n) (A conj(F)) (F B).
-// Decomposition (float64 on the device, selection on the host as for the
-// circulant kind):
+// Decomposition (float64 on the device, the per-row / per-column closed
+// selection too):
 //   left role  (A, m x n, n = 2^a):  H = A conj(F) by rows; each row keeps the
 //     closed set of at most K frequencies {q, n-q} with the most energy;
 //     stored as CSR with values H / n (float32 complex), and the residual's
@@ -187,47 +187,271 @@ amm_status launch_cspmm(bool packed, const int32_t* ptr, const int32_t* idx, con
   return AMM_OK;
 }
 
-// Closed top-K of one energy vector (the select_closed rule, with a partial
-// sort of the pair classes: only the leading K/2 are needed)
-void closed_topk(const double* E, int n, int K, std::vector<int32_t>& out) {
-  out.clear();
-  K = std::min(K, n);
-  std::vector<int> singles{0};
-  if (n % 2 == 0 && n > 1) singles.push_back(n / 2);
-  std::vector<int> pairs;
-  pairs.reserve(n / 2);
-  for (int k = 1; k < (n + 1) / 2; ++k) pairs.push_back(k);
-  const size_t need = std::min<size_t>(pairs.size(), (size_t)(K / 2));
-  auto cmp = [&](int a, int b) {
-    const double ea = E[a] + E[n - a], eb = E[b] + E[n - b];
-    if (ea != eb) return ea > eb;
-    return a < b;
-  };
-  std::partial_sort(pairs.begin(), pairs.begin() + need, pairs.end(), cmp);
-  std::vector<std::vector<int>> subsets{{}};
-  for (int sgl : singles) subsets.push_back({sgl});
-  if (singles.size() == 2) subsets.push_back(singles);
-  bool have = false;
-  double best_total = 0.0;
-  size_t best_size = 0;
-  for (const auto& U : subsets) {
-    if ((int)U.size() > K) continue;
-    std::vector<int32_t> members(U.begin(), U.end());
-    const size_t np = std::min(need, (size_t)(K - (int)U.size()) / 2);
-    for (size_t i = 0; i < np; ++i) {
-      members.push_back(pairs[i]);
-      members.push_back(n - pairs[i]);
+// ---- closed top-K selection on the device ------------------------------------
+// One workgroup per vector (a row of H for the left role, a column of G for
+// the right role) applies the selection rule to its energies E (length len):
+// the kept set is closed under q -> len - q and holds at most K members;
+// among the candidates "singles U (a subset of {0, len/2}) plus the np
+// highest-energy pairs {k, len - k}" (ties to the smaller k) it keeps the one
+// with the most energy, then the larger one.  Pair energies go to LDS; the
+// need-th largest (need = min(#pairs, K/2)) is found by an 8-bit radix select
+// on their float64 bit patterns (nonnegative, so the patterns order like the
+// values); every candidate takes either the top need pairs or the top
+// need - 1, so the totals follow from that sum and the threshold value.
+// Output per vector (slot of K entries, ascending frequency):
+//   left role:  every member;
+//   right role: the class representatives q <= len/2 with weight 1 (a
+//               single) or 2 (a pair);
+// plus the member count, the kept energy and the vector's total energy.
+constexpr int kSelThreads = 256;
+constexpr int kSelMaxPairs = 8192;   // len <= 16384
+
+__device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+__device__ double sel_block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ int sel_block_count(int v, int* redi) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return redi[0] + redi[1] + redi[2] + redi[3];
+}
+
+// Exclusive prefix over the block's threads (in thread order) of v.
+__device__ int sel_block_exclusive(int v, int* redi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  __syncthreads();
+  if (lane == 63) redi[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += redi[w];
+  return base + incl - v;
+}
+
+__global__ void __launch_bounds__(kSelThreads) closed_topk_kernel(const double* __restrict__ E, int64_t count, int len,
+                                                                  int64_t vec_step, int64_t elem_stride, int K,
+                                                                  int slot, int right_role,
+                                                                  int32_t* __restrict__ slot_idx,
+                                                                  int32_t* __restrict__ slot_wt,
+                                                                  int32_t* __restrict__ slot_cnt,
+                                                                  double* __restrict__ kept_out,
+                                                                  double* __restrict__ total_out) {
+  __shared__ double pe[kSelMaxPairs];
+  __shared__ unsigned char flag[2 * kSelMaxPairs];
+  __shared__ int hist[256];
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ int sel_digit, sel_remaining;
+  const int64_t v = blockIdx.x;
+  if (v >= count) return;
+  const double* e = E + v * vec_step;
+  const int tid = threadIdx.x;
+  const int npairs = (len + 1) / 2 - 1;          // classes {k, len - k}, 1 <= k < (len + 1) / 2
+  const bool even = (len % 2 == 0) && len > 1;
+  const double e0 = e[0], eh = even ? e[(int64_t)(len / 2) * elem_stride] : 0.0;
+  double part = 0.0;
+  for (int k = 1 + tid; k <= npairs; k += kSelThreads) {
+    const double x = e[(int64_t)k * elem_stride] + e[(int64_t)(len - k) * elem_stride];
+    pe[k - 1] = x;
+    part += x;
+  }
+  for (int q = tid; q < len; q += kSelThreads) flag[q] = 0;
+  const double total = sel_block_sum(part, red) + e0 + eh;   // (its barriers also publish pe and flag)
+  const int Kc = min(K, len);
+  const int need = min(npairs, Kc / 2);
+  // the need-th largest pair energy T and how many of the pairs equal to T are taken
+  uint64_t prefix = 0, mask = 0;
+  int take_eq = 0;
+  double top = 0.0, T = 0.0;
+  if (need > 0) {
+    int remaining = need;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hist[tid] = 0;   // 256 threads, 256 bins
+      __syncthreads();
+      for (int k = tid; k < npairs; k += kSelThreads) {
+        const uint64_t b = dbits(pe[k]);
+        if ((b & mask) == prefix) atomicAdd(&hist[(b >> shift) & 255], 1);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        // lane L holds bins 255 - 4L .. 252 - 4L (descending digits); inclusive scan over lanes
+        int c4[4], s4 = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c4[u] = hist[255 - 4 * tid - u];
+          s4 += c4[u];
+        }
+        int incl = s4;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int t = __shfl_up(incl, off, 64);
+          if (tid >= off) incl += t;
+        }
+        const int excl = incl - s4;
+        // the lane whose range crosses `remaining` picks the digit
+        if (excl < remaining && incl >= remaining) {
+          int cum = excl;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (cum + c4[u] >= remaining && cum < remaining) {
+              sel_digit = 255 - 4 * tid - u;
+              sel_remaining = remaining - cum;
+            }
+            cum += c4[u];
+          }
+        }
+      }
+      __syncthreads();
+      prefix |= (uint64_t)sel_digit << shift;
+      mask |= (uint64_t)255 << shift;
+      remaining = sel_remaining;
+      __syncthreads();   // every thread has read the pick before the next pass rewrites it
     }
-    double total = 0.0;
-    for (int m : members) total += E[m];
-    if (!have || total > best_total || (total == best_total && members.size() > best_size)) {
-      have = true;
-      best_total = total;
-      best_size = members.size();
-      out = members;
+    take_eq = remaining;   // pairs equal to T among the top need (>= 1)
+    T = __longlong_as_double((long long)prefix);
+    double gt = 0.0;
+    for (int k = tid; k < npairs; k += kSelThreads)
+      if (dbits(pe[k]) > prefix) gt += pe[k];
+    top = sel_block_sum(gt, red) + (double)take_eq * T;   // energy of the top need pairs
+  }
+  // best candidate: singles U, then np = need or need - 1 pairs
+  double best = 0.0;
+  int best_size = -1, best_u = 0, best_np = 0;
+  for (int u = 0; u < 4; ++u) {
+    const bool has0 = (u & 1) != 0, hash = (u & 2) != 0;
+    if (hash && !even) continue;
+    const int us = (has0 ? 1 : 0) + (hash ? 1 : 0);
+    if (us > Kc) continue;
+    const int np = min(need, (Kc - us) / 2);
+    double tot = (has0 ? e0 : 0.0) + (hash ? eh : 0.0);
+    tot += (np == need) ? top : top - T;   // np is need or need - 1
+    const int size = us + 2 * np;
+    if (best_size < 0 || tot > best || (tot == best && size > best_size)) {
+      best = tot;
+      best_size = size;
+      best_u = u;
+      best_np = np;
     }
   }
-  std::sort(out.begin(), out.end());
+  // members: pairs above T, then the first (take_eq or take_eq - 1) pairs equal to T by index
+  const int take = (best_np == need) ? take_eq : take_eq - 1;
+  {
+    // contiguous chunk of pair indices per thread, so the ties are counted in index order
+    const int chunk = (npairs + kSelThreads - 1) / kSelThreads;
+    const int k0 = tid * chunk, k1 = min(npairs, k0 + chunk);
+    int eq = 0;
+    if (best_np > 0)
+      for (int k = k0; k < k1; ++k) eq += (dbits(pe[k]) == prefix) ? 1 : 0;
+    int before = sel_block_exclusive(eq, redi);
+    if (best_np > 0)
+      for (int k = k0; k < k1; ++k) {
+        const uint64_t b = dbits(pe[k]);
+        bool in = b > prefix;
+        if (b == prefix) in = before++ < take;
+        if (in) {
+          const int q = k + 1;
+          flag[q] = 2;                          // a pair's representative
+          if (!right_role) flag[len - q] = 2;
+        }
+      }
+  }
+  if (tid == 0) {
+    if (best_u & 1) flag[0] = 1;
+    if (best_u & 2) flag[len / 2] = 1;
+  }
+  __syncthreads();
+  // compaction in ascending frequency order
+  {
+    const int chunk = (len + kSelThreads - 1) / kSelThreads;
+    const int q0 = tid * chunk, q1 = min(len, q0 + chunk);
+    int c = 0;
+    for (int q = q0; q < q1; ++q) c += flag[q] ? 1 : 0;
+    int pos = sel_block_exclusive(c, redi);
+    for (int q = q0; q < q1; ++q)
+      if (flag[q]) {
+        slot_idx[v * slot + pos] = q;
+        if (right_role) slot_wt[v * slot + pos] = flag[q];
+        ++pos;
+      }
+    const int cnt = sel_block_count(c, redi);
+    if (tid == 0) {
+      slot_cnt[v] = cnt;
+      kept_out[v] = best;
+      total_out[v] = total;
+    }
+  }
+}
+
+// Slots of K entries per vector -> CSR (ptr from the counts' prefix sums).
+__global__ void slots_to_csr(const int32_t* __restrict__ slot_idx, const int32_t* __restrict__ slot_wt,
+                             const int32_t* __restrict__ ptr, int64_t count, int K, int32_t* __restrict__ idx,
+                             int32_t* __restrict__ wt) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (v >= count) return;
+  const int b = ptr[v], c = ptr[v + 1] - b;
+  for (int t = threadIdx.x; t < c; t += blockDim.x) {
+    idx[b + t] = slot_idx[v * K + t];
+    if (wt) wt[b + t] = slot_wt[v * K + t];
+  }
+}
+
+// Closed selection of `count` vectors of E; builds ptr/idx (and wt for the
+// right role) in d's buffers, returns the summed kept and total energies.
+amm_status select_closed_device(const double* E, int64_t count, int len, int64_t vec_step, int64_t elem_stride, int K,
+                                bool right_role, DevBuf& ptr_buf, DevBuf& idx_buf, DevBuf* wt_buf, int64_t* nnz_out,
+                                double* kept_sum, double* total_sum, hipStream_t s) {
+  const int slot = std::max(1, std::min(K, len));   // entries per vector at most
+  DevBuf slots, swt, cnt, kept, tot;
+  AMM_TRY(slots.alloc((size_t)count * slot * sizeof(int32_t)));
+  AMM_TRY(swt.alloc(right_role ? (size_t)count * slot * sizeof(int32_t) : 4));
+  AMM_TRY(cnt.alloc((size_t)count * sizeof(int32_t)));
+  AMM_TRY(kept.alloc((size_t)count * sizeof(double)));
+  AMM_TRY(tot.alloc((size_t)count * sizeof(double)));
+  {
+    TimedLaunch tl("sfft_select", s);
+    hipLaunchKernelGGL(closed_topk_kernel, dim3((unsigned)count), dim3(kSelThreads), 0, s, E, count, len, vec_step,
+                       elem_stride, K, slot, right_role ? 1 : 0, slots.as<int32_t>(), swt.as<int32_t>(), cnt.as<int32_t>(),
+                       kept.as<double>(), tot.as<double>());
+    AMM_HIP(hipGetLastError());
+  }
+  std::vector<int32_t> hc(count);
+  std::vector<double> hk(count), ht(count);
+  AMM_HIP(hipMemcpyAsync(hc.data(), cnt.ptr, count * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipMemcpyAsync(hk.data(), kept.ptr, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipMemcpyAsync(ht.data(), tot.ptr, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> ptr(count + 1, 0);
+  double ks = 0.0, ts = 0.0;
+  for (int64_t v = 0; v < count; ++v) {
+    ptr[v + 1] = ptr[v] + hc[v];
+    ks += hk[v];
+    ts += ht[v];
+  }
+  const int64_t nnz = ptr[count];
+  AMM_TRY(ptr_buf.alloc((count + 1) * sizeof(int32_t)));
+  AMM_TRY(idx_buf.alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+  if (wt_buf) AMM_TRY(wt_buf->alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+  AMM_HIP(hipMemcpyAsync(ptr_buf.ptr, ptr.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(slots_to_csr, dim3((unsigned)((count + 3) / 4)), dim3(64, 4), 0, s, slots.as<int32_t>(),
+                     swt.as<int32_t>(), ptr_buf.as<int32_t>(), count, slot, idx_buf.as<int32_t>(),
+                     wt_buf ? wt_buf->as<int32_t>() : (int32_t*)nullptr);
+  AMM_HIP(hipGetLastError());
+  AMM_HIP(hipStreamSynchronize(s));   // the slot buffers are released on return
+  *nnz_out = nnz;
+  *kept_sum = ks;
+  *total_sum = ts;
+  return AMM_OK;
 }
 
 int ilog2_exact(int64_t v) {
@@ -252,7 +476,6 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   AMM_TRY(z0.alloc(mn * sizeof(double2)));
   AMM_TRY(z1.alloc(mn * sizeof(double2)));
   AMM_TRY(E.alloc(mn * sizeof(double)));
-  std::vector<double> Eh(mn);
   const unsigned g = (unsigned)((mn + 255) / 256);
   double tot = 0.0;
   if (left) {
@@ -269,27 +492,11 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
     }
     hipLaunchKernelGGL(abs2_c64, dim3(g), dim3(256), 0, s, cur, E.as<double>(), mn);
     AMM_HIP(hipGetLastError());
-    AMM_HIP(hipMemcpyAsync(Eh.data(), E.ptr, mn * sizeof(double), hipMemcpyDeviceToHost, s));
-    AMM_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> ptr(m + 1, 0), idx, sel;
-    idx.reserve((size_t)m * std::min<int64_t>(K, n));
+    int64_t nnz = 0;
     double kept = 0.0;
-    for (int64_t i = 0; i < m; ++i) {
-      const double* Ei = Eh.data() + i * n;
-      closed_topk(Ei, (int)n, K, sel);
-      for (int q : sel) {
-        idx.push_back(q);
-        kept += Ei[q];
-      }
-      ptr[i + 1] = (int32_t)idx.size();
-    }
-    for (double v : Eh) tot += v;
-    const int64_t nnz = (int64_t)idx.size();
-    AMM_TRY(d->sf_rptr.alloc((m + 1) * sizeof(int32_t)));
-    AMM_TRY(d->sf_ridx.alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    AMM_TRY(select_closed_device(E.as<double>(), m, (int)n, n, 1, K, false, d->sf_rptr, d->sf_ridx, nullptr, &nnz,
+                                 &kept, &tot, s));
     AMM_TRY(d->sf_rval.alloc(std::max<int64_t>(nnz, 1) * sizeof(float2)));
-    AMM_HIP(hipMemcpyAsync(d->sf_rptr.ptr, ptr.data(), (m + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if (nnz) AMM_HIP(hipMemcpyAsync(d->sf_ridx.ptr, idx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(gather_entries, dim3((unsigned)((m + 3) / 4)), dim3(64, 4), 0, s, cur, d->sf_rptr.as<int32_t>(),
                        d->sf_ridx.as<int32_t>(), (const int32_t*)nullptr, m, n, (int64_t)1, 1.0 / (double)n,
                        d->sf_rval.as<float2>());
@@ -324,35 +531,12 @@ amm_status sfft_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
     }
     hipLaunchKernelGGL(abs2_c64, dim3(g), dim3(256), 0, s, cur, E.as<double>(), mn);
     AMM_HIP(hipGetLastError());
-    AMM_HIP(hipMemcpyAsync(Eh.data(), E.ptr, mn * sizeof(double), hipMemcpyDeviceToHost, s));
-    AMM_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> ptr(n + 1, 0), idx, wt, sel;
-    std::vector<double> col(m);
+    int64_t nr = 0;
     double kept = 0.0, total = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-      for (int64_t q = 0; q < m; ++q) col[q] = Eh[q * n + j];
-      closed_topk(col.data(), (int)m, K, sel);
-      for (int q : sel) {
-        kept += col[q];
-        if (q <= m / 2) {   // representative of its class
-          idx.push_back(q);
-          wt.push_back((q == 0 || 2 * q == m) ? 1 : 2);
-        }
-      }
-      for (int64_t q = 0; q < m; ++q) total += col[q];
-      ptr[j + 1] = (int32_t)idx.size();
-    }
-    const int64_t nr = (int64_t)idx.size();
-    AMM_TRY(d->sf_cptr.alloc((n + 1) * sizeof(int32_t)));
-    AMM_TRY(d->sf_cidx.alloc(std::max<int64_t>(nr, 1) * sizeof(int32_t)));
-    AMM_TRY(d->sf_cval.alloc(std::max<int64_t>(nr, 1) * sizeof(float2)));
     DevBuf wdev;
-    AMM_TRY(wdev.alloc(std::max<int64_t>(nr, 1) * sizeof(int32_t)));
-    AMM_HIP(hipMemcpyAsync(d->sf_cptr.ptr, ptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if (nr) {
-      AMM_HIP(hipMemcpyAsync(d->sf_cidx.ptr, idx.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      AMM_HIP(hipMemcpyAsync(wdev.ptr, wt.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    }
+    AMM_TRY(select_closed_device(E.as<double>(), n, (int)m, 1, n, K, true, d->sf_cptr, d->sf_cidx, &wdev, &nr, &kept,
+                                 &total, s));
+    AMM_TRY(d->sf_cval.alloc(std::max<int64_t>(nr, 1) * sizeof(float2)));
     // entry (column j, q): G[q * n + j]  -> row stride 1 (over j), index stride n
     hipLaunchKernelGGL(gather_entries, dim3((unsigned)((n + 3) / 4)), dim3(64, 4), 0, s, cur, d->sf_cptr.as<int32_t>(),
                        d->sf_cidx.as<int32_t>(), wdev.as<int32_t>(), n, (int64_t)1, n, 1.0, d->sf_cval.as<float2>());
