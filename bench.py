@@ -576,8 +576,8 @@ def run_variants(torch, ctx, tm, only):
     if not only or only == "batch":
         res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
-        res.append(layer_workload(torch, ctx, tm))
-        res.append(layer_workload(torch, ctx, tm, k=440))
+        res.extend(layer_workload(torch, ctx, tm))
+        res.extend(layer_workload(torch, ctx, tm, k=440))
     return res
 
 
@@ -1098,9 +1098,30 @@ def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
            "dense_fp32_ms": dense_ms, "forward_err_vs_exact": err, "decompose_ms": dec_ms,
            "kernels_ms": {kn: v[0] for kn, v in kt.items()}}
     log(f"[bench] layer fwd+bwd: {ms:.3f} ms, dense {dense_ms:.3f} ms, fwd err {err:.3e}")
-    del W, X, dY, Y, exact
+    del exact
+    # the same layer with bfloat16 activations and output gradient (the library
+    # widens them once and computes in float32; Y and dX come back in bfloat16)
+    X16, dY16 = X.bfloat16(), dY.bfloat16()
+    Y16 = torch.empty((n, pcols), dtype=torch.bfloat16, device="cuda")
+
+    def step16():
+        ctx.approx_matmul(d, X16, out=Y16)
+        ctx.approx_matmul_backward(d, X16, dY16)
+
+    ms16 = statistics.median(tm.run(step16, 10, 3))
+    W16 = W.bfloat16()
+    dense16_ms = statistics.median(tm.run(lambda: (W16 @ X16, W16.t() @ dY16, dY16 @ X16.t()), 5, 2))
+    exact16 = W.double() @ X16.double()
+    err16 = float((Y16.double() - exact16).norm() / exact16.norm())
+    rec16 = {"name": f"layer fwd+bwd tsvd k={k} bf16 activations (W {n}x{n}, X {n}x{pcols})", "ms": ms16,
+             "tflop_equiv_s": flops / (ms16 * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms16,
+             "speedup_vs_dense_bf16": dense16_ms / ms16, "dense_bf16_ms": dense16_ms,
+             "forward_err_vs_exact": err16,
+             "precision": "bfloat16 X, dY, Y and dX; float32 factors, arithmetic and dW"}
+    log(f"[bench] layer bf16 fwd+bwd: {ms16:.3f} ms, dense bf16 {dense16_ms:.3f} ms, fwd err {err16:.3e}")
+    del W, X, dY, Y, X16, dY16, Y16, W16, exact16
     torch.cuda.empty_cache()
-    return rec
+    return [rec, rec16]
 
 
 if __name__ == "__main__":

@@ -63,6 +63,17 @@ typedef enum {
  * AMM_TSVD, which then truncates the dense residue A - S. */
 enum { AMM_CIRCULANT = 1, AMM_TSVD = 2, AMM_SPARSE = 4, AMM_SFFT = 8 };
 
+/* Element types of described operands. */
+enum { AMM_F32 = 0, AMM_BF16 = 1, AMM_F16 = 2 };
+
+/* A row-major device matrix: element (r, c) at data + (r ld + c) elements
+ * of `dtype`; ld >= cols.  The caller owns the memory. */
+typedef struct {
+  void* data;
+  int64_t rows, cols, ld;
+  int dtype;
+} amm_matrix;
+
 typedef struct {
   double sparse_frac;  /* AMM_SPARSE: keep round(frac*m*n) entries of largest |a| */
   int64_t sparse_nnz;  /* AMM_SPARSE: if >= 0, overrides sparse_frac */
@@ -316,6 +327,17 @@ amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_
                                      const float* B, int64_t n, int64_t p, int64_t ldb,
                                      float* out, int64_t ldo, void* stream);
 
+/* amm_approx_matmul on described operands of any element type: B (n x p)
+ * and out (m x p), each float32, bfloat16 or float16, with its own pitch.
+ * The arithmetic is the float32 product's: 16-bit B is widened once into
+ * the context's scratch (exactly: every bfloat16 and float16 value is a
+ * float32 value), a 16-bit out receives the float32 result rounded once to
+ * nearest even.  All-float32 operands take amm_approx_matmul_strided.
+ * Shapes must conform (AMM_ESHAPE), dtype be one of the three (AMM_EINVAL),
+ * and B and out must not overlap (AMM_EINVAL). */
+amm_status amm_approx_matmul_ex(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const amm_matrix* B,
+                                const amm_matrix* out, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product as amm_approx_matmul for truncated-SVD handles, through the split
@@ -393,6 +415,15 @@ void amm_batch_plan_destroy(amm_batch_plan* plan);
  * formed from the column spectra of dY and X without the m x n product
  * dY X^T.  Circulant dWo needs p even.  Outputs are overwritten and must not
  * alias the inputs. */
+/* amm_approx_matmul_backward on described operands of any element type
+ * (see amm_approx_matmul_ex): X (n x p), dY (m x p), dX (n x p) and dWo
+ * (m x n) each float32, bfloat16 or float16 with its own pitch; dX or dWo
+ * may be NULL (not computed).  16-bit inputs are widened once, outputs are
+ * the float32 gradients rounded once. */
+amm_status amm_approx_matmul_backward_ex(amm_ctx* ctx, const amm_dec* dW, const amm_matrix* X,
+                                         const amm_matrix* dY, const amm_matrix* dX,
+                                         const amm_matrix* dW_out, void* stream);
+
 amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X,
                                       const float* dY, int64_t p, float* dX, float* dWo,
                                       void* stream);

@@ -27,6 +27,21 @@ def _stream_ptr(torch, device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _matrix(t, name):
+    """amm_matrix view of a CUDA tensor with contiguous rows (float32,
+    bfloat16 or float16)."""
+    import torch
+    codes = {torch.float32: _lib.AMM_F32, torch.bfloat16: _lib.AMM_BF16, torch.float16: _lib.AMM_F16}
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype not in codes:
+        raise TypeError(f"{name} must be float32, bfloat16 or float16")
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a 2-D tensor with contiguous rows")
+    return _lib.AmmMatrix(C.c_void_p(t.data_ptr()), t.shape[0], t.shape[1], max(t.stride(0), t.shape[1]),
+                          codes[t.dtype])
+
+
 def _row_pitch(t, name):
     """Row pitch of a float32 CUDA matrix whose rows are contiguous (a column
     panel of a row-major matrix is one)."""
@@ -369,7 +384,22 @@ class Context:
 
     # -- backward ---------------------------------------------------------------
     def approx_matmul_backward(self, dW: Decomposition, X, dY, need_dx: bool = True, need_dw: bool = True):
-        """(dX, dW) for Y = Wtil X with the truncation structure frozen."""
+        """(dX, dW) for Y = Wtil X with the truncation structure frozen.  16-bit
+        X and dY are widened once; dX comes back in X's type, dW in float32."""
+        torch = self.torch
+        if X.dtype != torch.float32 or dY.dtype != torch.float32:
+            inf = dW.info()
+            m, n = inf["m"], inf["n"]
+            p = X.shape[1]
+            dX = torch.empty((n, p), dtype=X.dtype, device=X.device) if need_dx else None
+            dWo = torch.empty((m, n), dtype=torch.float32, device=X.device) if need_dw else None
+            mx, my = _matrix(X, "X"), _matrix(dY, "dY")
+            mdx = _matrix(dX, "dX") if dX is not None else None
+            mdw = _matrix(dWo, "dW") if dWo is not None else None
+            _lib.check(_lib.load().amm_approx_matmul_backward_ex(
+                self.handle, dW.handle, C.byref(mx), C.byref(my), C.byref(mdx) if mdx is not None else None,
+                C.byref(mdw) if mdw is not None else None, _stream_ptr(torch, X.device)))
+            return dX, dWo
         _need_f32_cuda(X, "X")
         _need_f32_cuda(dY, "dY")
         inf = dW.info()
@@ -423,7 +453,18 @@ class Context:
     # -- product ----------------------------------------------------------------
     def approx_matmul(self, dA: Decomposition, B, dB: Decomposition | None = None, out=None):
         """out = Atil B (+ Delta A Btil).  B and out may be column panels of
-        larger row-major matrices (contiguous rows, any row pitch)."""
+        larger row-major matrices (contiguous rows, any row pitch), and
+        bfloat16 or float16 as well as float32 (the product is computed in
+        float32; out defaults to B's type)."""
+        torch = self.torch
+        if B.dtype != torch.float32 or (out is not None and out.dtype != torch.float32):
+            m = dA.info()["m"]
+            if out is None:
+                out = torch.empty((m, B.shape[1]), dtype=B.dtype, device=B.device)
+            mb, mo = _matrix(B, "B"), _matrix(out, "out")
+            _lib.check(_lib.load().amm_approx_matmul_ex(self.handle, dA.handle, dB.handle if dB is not None else None,
+                                                        C.byref(mb), C.byref(mo), _stream_ptr(torch, B.device)))
+            return out
         ldb = _row_pitch(B, "B")
         n, p = B.shape
         m = dA.info()["m"]

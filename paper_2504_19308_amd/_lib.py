@@ -41,6 +41,14 @@ class AmmErrorEstimate(C.Structure):
                 ("spec_dA", C.c_double), ("spec_dB", C.c_double), ("mu_A", C.c_double), ("mu_B", C.c_double)]
 
 
+AMM_F32, AMM_BF16, AMM_F16 = 0, 1, 2
+
+
+class AmmMatrix(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("rows", C.c_int64), ("cols", C.c_int64), ("ld", C.c_int64),
+                ("dtype", C.c_int)]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
 
@@ -94,6 +102,10 @@ SIGNATURES = {
     "amm_batch_plan_destroy": (None, [C.c_void_p]),
     "amm_approx_matmul_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amm_approx_matmul_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AmmMatrix),
+                                       C.POINTER(AmmMatrix), C.c_void_p]),
+    "amm_approx_matmul_backward_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AmmMatrix), C.POINTER(AmmMatrix),
+                                                C.POINTER(AmmMatrix), C.POINTER(AmmMatrix), C.c_void_p]),
     "amm_estimate_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                      C.c_int, C.c_void_p, C.POINTER(AmmErrorEstimate)]),
     "amm_estimate_sketch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,

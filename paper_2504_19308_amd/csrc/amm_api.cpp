@@ -1148,6 +1148,119 @@ amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_
   return AMM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+bool dtype_ok(int t) { return t == AMM_F32 || t == AMM_BF16 || t == AMM_F16; }
+size_t dtype_size(int t) { return t == AMM_F32 ? 4 : 2; }
+
+amm_status check_matrix(const amm_matrix* M, const char* name, int64_t rows, int64_t cols) {
+  if (!M) return fail(AMM_EINVAL, "%s is NULL", name);
+  if (!dtype_ok(M->dtype)) return fail(AMM_EINVAL, "%s: unknown element type %d", name, M->dtype);
+  if (M->rows != rows || M->cols != cols)
+    return fail(AMM_ESHAPE, "%s is %lldx%lld, expected %lldx%lld", name, (long long)M->rows, (long long)M->cols,
+                (long long)rows, (long long)cols);
+  if (M->ld < cols) return fail(AMM_ESHAPE, "%s: pitch %lld below %lld columns", name, (long long)M->ld, (long long)cols);
+  if (rows > 0 && cols > 0 && !M->data) return fail(AMM_EINVAL, "%s has no data", name);
+  return AMM_OK;
+}
+
+// byte ranges of two described matrices meet
+bool matrices_overlap(const amm_matrix* a, const amm_matrix* b) {
+  if (!a || !b || a->rows == 0 || a->cols == 0 || b->rows == 0 || b->cols == 0) return false;
+  const uintptr_t a0 = (uintptr_t)a->data, a1 = a0 + (uintptr_t)((a->rows - 1) * a->ld + a->cols) * dtype_size(a->dtype);
+  const uintptr_t b0 = (uintptr_t)b->data, b1 = b0 + (uintptr_t)((b->rows - 1) * b->ld + b->cols) * dtype_size(b->dtype);
+  return a0 < b1 && b0 < a1;
+}
+
+// A float32 packed view of M: M itself when it already is one, else a
+// widened copy in `buf`.
+amm_status packed_input(const amm_matrix* M, DevBuf& buf, const float** out, hipStream_t s) {
+  if (M->dtype == AMM_F32 && M->ld == M->cols) {
+    *out = static_cast<const float*>(M->data);
+    return AMM_OK;
+  }
+  AMM_TRY(buf.reserve((size_t)M->rows * M->cols * sizeof(float)));
+  AMM_TRY(cast_matrix(M->data, M->dtype, M->ld, M->rows, M->cols, buf.ptr, AMM_F32, M->cols, s));
+  *out = buf.as<float>();
+  return AMM_OK;
+}
+
+// Where a float32 result for M is written: M itself when packed float32,
+// else `buf` (copied out by finish_output).
+amm_status packed_output(const amm_matrix* M, DevBuf& buf, float** out) {
+  if (M->dtype == AMM_F32 && M->ld == M->cols) {
+    *out = static_cast<float*>(M->data);
+    return AMM_OK;
+  }
+  AMM_TRY(buf.reserve((size_t)M->rows * M->cols * sizeof(float)));
+  *out = buf.as<float>();
+  return AMM_OK;
+}
+
+amm_status finish_output(const amm_matrix* M, const float* res, hipStream_t s) {
+  if (res == M->data) return AMM_OK;
+  return cast_matrix(res, AMM_F32, M->cols, M->rows, M->cols, M->data, M->dtype, M->ld, s);
+}
+}  // namespace
+
+extern "C" {
+
+amm_status amm_approx_matmul_ex(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const amm_matrix* B,
+                                const amm_matrix* out, void* stream) {
+  if (!ctx || !dA || !B || !out) return fail(AMM_EINVAL, "NULL argument");
+  const int64_t n = dA->n, p = B->cols, m = dA->m;
+  AMM_TRY(check_matrix(B, "B", n, p));
+  AMM_TRY(check_matrix(out, "out", m, p));
+  if (p == 0) return AMM_OK;
+  if (matrices_overlap(B, out)) return fail(AMM_EINVAL, "out overlaps B");
+  if (B->dtype == AMM_F32 && out->dtype == AMM_F32)
+    return amm_approx_matmul_strided(ctx, dA, dB, static_cast<const float*>(B->data), n, p, B->ld,
+                                     static_cast<float*>(out->data), out->ld, stream);
+  if (dB && (dB->m != n || dB->n != p)) return fail(AMM_ESHAPE, "dB describes a %lldx%lld operand, B is %lldx%lld",
+                                                    (long long)dB->m, (long long)dB->n, (long long)n, (long long)p);
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  TimerScope ts(ctx);
+  const float* Bp = nullptr;
+  float* Op = nullptr;
+  AMM_TRY(packed_input(B, ctx->scratch[16], &Bp, s));
+  AMM_TRY(packed_output(out, ctx->scratch[17], &Op));
+  AMM_TRY(amm_approx_matmul(ctx, dA, dB, Bp, n, p, Op, stream));
+  return finish_output(out, Op, s);
+}
+
+amm_status amm_approx_matmul_backward_ex(amm_ctx* ctx, const amm_dec* dW, const amm_matrix* X, const amm_matrix* dY,
+                                         const amm_matrix* dX, const amm_matrix* dW_out, void* stream) {
+  if (!ctx || !dW || !X || !dY) return fail(AMM_EINVAL, "NULL argument");
+  const int64_t m = dW->m, n = dW->n, p = X->cols;
+  AMM_TRY(check_matrix(X, "X", n, p));
+  AMM_TRY(check_matrix(dY, "dY", m, p));
+  if (dX) AMM_TRY(check_matrix(dX, "dX", n, p));
+  if (dW_out) AMM_TRY(check_matrix(dW_out, "dW", m, n));
+  if (!dX && !dW_out) return AMM_OK;
+  for (const amm_matrix* o : {dX, dW_out})
+    if (o && (matrices_overlap(o, X) || matrices_overlap(o, dY))) return fail(AMM_EINVAL, "an output overlaps an input");
+  if (dX && dW_out && matrices_overlap(dX, dW_out)) return fail(AMM_EINVAL, "dX overlaps dW");
+  hipStream_t s = (hipStream_t)stream;
+  AMM_HIP(hipSetDevice(ctx->device));
+  TimerScope ts(ctx);
+  const float *Xp = nullptr, *Yp = nullptr;
+  float *dXp = nullptr, *dWp = nullptr;
+  AMM_TRY(packed_input(X, ctx->scratch[16], &Xp, s));
+  AMM_TRY(packed_input(dY, ctx->scratch[18], &Yp, s));
+  if (dX) AMM_TRY(packed_output(dX, ctx->scratch[17], &dXp));
+  if (dW_out) AMM_TRY(packed_output(dW_out, ctx->scratch[19], &dWp));
+  AMM_TRY(amm_approx_matmul_backward(ctx, dW, Xp, Yp, p, dXp, dWp, stream));
+  if (dX) AMM_TRY(finish_output(dX, dXp, s));
+  if (dW_out) AMM_TRY(finish_output(dW_out, dWp, s));
+  return AMM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 amm_status amm_approx_matmul_static(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B, int64_t n,
                                     int64_t p, float* out, void* stream) {
   if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");

@@ -141,9 +141,10 @@ struct amm_ctx {
   amm::AllocFns alloc;                 // caller's allocator (alloc == NULL: hipMalloc)
   std::map<int, amm::DevBuf> tw32;     // per log2 n: n float2, exp(-2 pi i m / n)
   std::map<int, amm::DevBuf> tw64;     // per log2 n: n double2
-  amm::DevBuf scratch[18];             // grow-only work areas for products (8-13: chirp-convolution path,
+  amm::DevBuf scratch[20];             // grow-only work areas for products (8-13: chirp-convolution path,
                                        // 14, 15: B and the residue's product at a spread row pitch for
-                                       // sparse products; 16, 17: packed copies of strided operands)
+                                       // sparse products; 16-19: packed float32 copies of strided or
+                                       // 16-bit operands)
   std::map<int64_t, amm::DevBuf> chirp64;   // per (n, sign): float64 spectrum of the chirp kernel
   std::map<int, amm::DevBuf> chirp32;       // per n: float32 chirp and kernel spectra of the fused product
   amm::DevBuf rsvd[14];                     // grow-only work areas of the randomized SVD
@@ -443,6 +444,10 @@ amm_status transpose_acc_ld_f32(const float* Y, int64_t ldy, int64_t rows, int64
 // column slice's rows over the L2 channels (cols + 64 for multiples of 2048).
 int64_t spread_pitch(int64_t cols);
 // dst (rows x cols, row pitch ld_dst) = src (rows x cols, contiguous); float4 aligned
+// Element-wise copy between row-major matrices of element types
+// AMM_F32 / AMM_BF16 / AMM_F16 (widening exact, narrowing rounds to nearest even).
+amm_status cast_matrix(const void* src, int src_dtype, int64_t src_ld, int64_t rows, int64_t cols, void* dst,
+                       int dst_dtype, int64_t dst_ld, hipStream_t s);
 amm_status repitch_f32(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst, int64_t ld_dst,
                        hipStream_t s);
 amm_status approx_backward(amm_ctx* ctx, const amm_dec* d, const float* X, const float* dY, int64_t p,
