@@ -128,6 +128,15 @@ typedef struct {
  * streams must be ordered by the caller (or use one context per stream);
  * contexts never share work areas with each other. */
 amm_status amm_ctx_create(amm_ctx** ctx, int device);
+
+/* Debug mode (also on when the environment variable AMM_DEBUG is set to
+ * anything but "0" at context creation): every product, gradient,
+ * decomposition and batch run of the context first checks that the matrix
+ * pointers it is given are device memory of the context's device
+ * (AMM_EINVAL otherwise, before any launch), and afterwards synchronises
+ * its stream, so a device fault is reported by the call that caused it
+ * (AMM_EDEVICE).  Costs a host round trip per call. */
+amm_status amm_ctx_set_debug(amm_ctx* ctx, int enable);
 void amm_ctx_destroy(amm_ctx* ctx);
 
 /* Device allocator supplied by the caller (e.g. a framework's caching

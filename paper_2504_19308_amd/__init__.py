@@ -242,6 +242,12 @@ class Context:
         except Exception:
             pass
 
+    def set_debug(self, enable: bool = True):
+        """Check argument pointers and synchronise after every call (see
+        amm_ctx_set_debug; also on when AMM_DEBUG is set)."""
+        _lib.check(_lib.load().amm_ctx_set_debug(self.handle, 1 if enable else 0))
+        return self
+
     # -- per-launch timing (HIP events on the launch stream) --------------------
     def set_timing(self, enable: bool = True):
         _lib.check(_lib.load().amm_ctx_set_timing(self.handle, 1 if enable else 0))

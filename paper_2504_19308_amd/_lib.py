@@ -65,6 +65,7 @@ SIGNATURES = {
     "amm_ctx_create_with_allocator": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(AmmAllocator)]),
     "amm_ctx_destroy": (None, [C.c_void_p]),
     "amm_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "amm_ctx_set_debug": (C.c_int, [C.c_void_p, C.c_int]),
     "amm_ctx_timings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                   C.POINTER(C.c_int)]),
     "amm_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_int,

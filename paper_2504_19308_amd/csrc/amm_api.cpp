@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -418,6 +419,10 @@ amm_status amm_ctx_create_with_allocator(amm_ctx** ctx, int device, const amm_al
   amm_ctx* c = new amm_ctx();
   c->device = device;
   if (alloc) c->alloc = AllocFns{alloc->alloc, alloc->free, alloc->user, device};
+  {
+    const char* e = std::getenv("AMM_DEBUG");
+    c->debug = e && *e && std::strcmp(e, "0") != 0;
+  }
   *ctx = c;
   return AMM_OK;
 }
@@ -820,7 +825,7 @@ amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n, int64_t nnz
   return AMM_OK;
 }
 
-amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int kind, int K,
+static amm_status decompose_body(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int kind, int K,
                          const amm_opts* opts, void* stream, amm_dec** out) {
   if (!ctx || !A || !out) return fail(AMM_EINVAL, "NULL argument");
   if (m <= 0 || n <= 0) return fail(AMM_ESHAPE, "empty operand");
@@ -980,7 +985,7 @@ amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int
   return fail(AMM_EINVAL, "bad kind %d", kind);
 }
 
-amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
+static amm_status matmul_body(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
                              int64_t n, int64_t p, float* out, void* stream) {
   if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");
   if (n != dA->n) return fail(AMM_ESHAPE, "B has %lld rows, A has %lld columns", (long long)n, (long long)dA->n);
@@ -1097,7 +1102,7 @@ bool panels_overlap(const float* a, int64_t ra, int64_t lda, const float* b, int
 }
 }  // namespace
 
-amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
+static amm_status strided_body(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
                                      int64_t n, int64_t p, int64_t ldb, float* out, int64_t ldo, void* stream) {
   if (!ctx || !dA) return fail(AMM_EINVAL, "NULL argument");
   if (ldb < p || ldo < p) return fail(AMM_ESHAPE, "row pitches %lld, %lld below %lld columns", (long long)ldb,
@@ -1294,7 +1299,7 @@ amm_status amm_approx_matmul_static(amm_ctx* ctx, const amm_dec* dA, const amm_d
                             dA->A_borrowed, dB->U.as<float>(), dB->VS.as<float>(), scr, kStaticScratchFloats, out, s);
 }
 
-amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X, const float* dY,
+static amm_status backward_body(amm_ctx* ctx, const amm_dec* dW, const float* X, const float* dY,
                                       int64_t p, float* dX, float* dW_out, void* stream) {
   if (!ctx || !dW || !X || !dY) return fail(AMM_EINVAL, "NULL argument");
   if (p <= 0) return fail(AMM_ESHAPE, "X has no columns");
@@ -1520,7 +1525,7 @@ amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* co
   return plan_finish(bp, s, plan);
 }
 
-amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream) {
+static amm_status batch_run_body(amm_batch_plan* plan, int use_graph, void* stream) {
   if (!plan) return fail(AMM_EINVAL, "NULL plan");
   hipStream_t s = (hipStream_t)stream;
   TimerScope ts(plan->ctx);
@@ -1727,6 +1732,85 @@ amm_status amm_choose_rank(const amm_dec* dA, const amm_dec* dB, double tau, int
     return AMM_OK;
   }
   return fail(AMM_EUNSUPPORTED, "rank choice for two circulant or two truncated-SVD handles");
+}
+
+}  // extern "C"
+
+// ---- debug mode: argument pointers checked, every call synchronised ----------
+namespace {
+
+// In debug mode a pointer the device would dereference must be device (or
+// managed, or mapped host) memory reachable from the context's device.
+amm_status debug_pointer(const amm_ctx* ctx, const void* ptr, const char* name) {
+  if (!ctx || !ctx->debug || !ptr) return AMM_OK;
+  hipPointerAttribute_t a{};
+  const hipError_t e = hipPointerGetAttributes(&a, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();   // the query's failure is not a device error
+    return fail(AMM_EINVAL, "%s (%p) is not device memory", name, ptr);
+  }
+  const bool device_side = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+                           (a.type == hipMemoryTypeHost && a.devicePointer);
+  if (!device_side) return fail(AMM_EINVAL, "%s (%p) is not device memory", name, ptr);
+  if (a.type == hipMemoryTypeDevice && a.device != ctx->device)
+    return fail(AMM_EINVAL, "%s lives on device %d, the context on device %d", name, a.device, ctx->device);
+  return AMM_OK;
+}
+
+// In debug mode wait for the call's work and report any device error as the call's.
+amm_status debug_finish(const amm_ctx* ctx, hipStream_t s, amm_status st, const char* what) {
+  if (!ctx || !ctx->debug || st != AMM_OK) return st;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(AMM_EDEVICE, "%s: device error after the call: %s", what, hipGetErrorString(e));
+  return AMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amm_status amm_ctx_set_debug(amm_ctx* ctx, int enable) {
+  if (!ctx) return fail(AMM_EINVAL, "NULL context");
+  ctx->debug = enable != 0;
+  return AMM_OK;
+}
+
+amm_status amm_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int kind, int K, const amm_opts* opts,
+                         void* stream, amm_dec** out) {
+  AMM_TRY(debug_pointer(ctx, A, "A"));
+  return debug_finish(ctx, (hipStream_t)stream, decompose_body(ctx, A, m, n, kind, K, opts, stream, out),
+                      "amm_decompose");
+}
+
+amm_status amm_approx_matmul(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B, int64_t n, int64_t p,
+                             float* out, void* stream) {
+  AMM_TRY(debug_pointer(ctx, B, "B"));
+  AMM_TRY(debug_pointer(ctx, out, "out"));
+  return debug_finish(ctx, (hipStream_t)stream, matmul_body(ctx, dA, dB, B, n, p, out, stream), "amm_approx_matmul");
+}
+
+amm_status amm_approx_matmul_strided(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B, int64_t n,
+                                     int64_t p, int64_t ldb, float* out, int64_t ldo, void* stream) {
+  AMM_TRY(debug_pointer(ctx, B, "B"));
+  AMM_TRY(debug_pointer(ctx, out, "out"));
+  return debug_finish(ctx, (hipStream_t)stream, strided_body(ctx, dA, dB, B, n, p, ldb, out, ldo, stream),
+                      "amm_approx_matmul_strided");
+}
+
+amm_status amm_approx_matmul_backward(amm_ctx* ctx, const amm_dec* dW, const float* X, const float* dY, int64_t p,
+                                      float* dX, float* dW_out, void* stream) {
+  AMM_TRY(debug_pointer(ctx, X, "X"));
+  AMM_TRY(debug_pointer(ctx, dY, "dY"));
+  AMM_TRY(debug_pointer(ctx, dX, "dX"));
+  AMM_TRY(debug_pointer(ctx, dW_out, "dW"));
+  return debug_finish(ctx, (hipStream_t)stream, backward_body(ctx, dW, X, dY, p, dX, dW_out, stream),
+                      "amm_approx_matmul_backward");
+}
+
+amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream) {
+  return debug_finish(plan ? plan->ctx : nullptr, (hipStream_t)stream, batch_run_body(plan, use_graph, stream),
+                      "amm_batch_run");
 }
 
 }  // extern "C"

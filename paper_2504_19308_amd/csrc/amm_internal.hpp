@@ -151,6 +151,7 @@ struct amm_ctx {
   amm::DevBuf gemm_part;                    // grow-only split-K partial sums
   amm::KernelTimer timer;
   bool timing = false;
+  bool debug = false;                  // check argument pointers, synchronise after every call
 };
 
 struct amm_dec {
