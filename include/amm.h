@@ -396,7 +396,11 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
  * intermediate V_i^T B_i is accumulated in float32 and enters the second
  * product as a hi + lo pair of bfloat16 values, so the rounding of the stored
  * components is the only bfloat16 loss.  Shapes: rank 32, 64 or 128, m_i and
- * p[i] multiples of 128, n_i a multiple of 32; up to 256 entries. */
+ * p[i] multiples of 128, n_i a multiple of 32; up to 256 entries.
+ * Circulant handles (all entries circulant, power-of-two sides or square
+ * blocks of side 64 .. 16384): the batched launches read the bfloat16 B_i
+ * directly and widen them exactly in the load, everything after is the
+ * float32 (or float16-list) product of the float32 plan. */
 amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* const* dA,
                                       const void* const* B, const int64_t* p, float* const* out,
                                       void* stream, amm_batch_plan** plan);
@@ -408,6 +412,23 @@ amm_status amm_batch_run(amm_batch_plan* plan, int use_graph, void* stream);
  * of one run in ms. */
 amm_status amm_batch_info(const amm_batch_plan* plan, int* target_blocks, int* panel_blocks,
                           int* out_blocks, double* tuned_ms);
+/* Circulant plans: the schedule the plan's tuner kept.  Power-of-two block
+ * products with sides 64 .. 16384 can run as batched launches over a job
+ * table (one launch per side, list precision and accumulation phase -- a
+ * column-blocked operand's second and later blocks accumulate in later
+ * phases), the rest one launch sequence per entry; the tuner times both
+ * (a warm-up and three runs each) at plan creation and keeps the faster.
+ * job_table: 1 if the job-table launches were kept; launches: kernel
+ * launch sequences per run; entry_ms, table_ms: the tuner's time of one run
+ * in each mode (-1 when not timed; bfloat16 plans time only the job table).
+ * AMM_ESTATE for a truncated-SVD plan. */
+amm_status amm_batch_circulant_schedule(const amm_batch_plan* plan, int* job_table, int* launches,
+                                        double* entry_ms, double* table_ms);
+/* Override the tuner: job_table 1 runs the batched launches (AMM_EUNSUPPORTED
+ * if no entry is eligible), 0 every entry by itself (AMM_EUNSUPPORTED for a
+ * bfloat16 plan); the plan's graph is captured again.  Waits for the plan's
+ * own stream; work the caller enqueued with the old schedule may still run. */
+amm_status amm_batch_circulant_set_mode(amm_batch_plan* plan, int job_table);
 void amm_batch_plan_destroy(amm_batch_plan* plan);
 
 /* ---- backward ------------------------------------------------------------ */

@@ -181,6 +181,17 @@ class BatchPlan:
         _lib.check(_lib.load().amm_batch_info(self.handle, C.byref(t), C.byref(pb), C.byref(ob), C.byref(ms)))
         return {"target_blocks": t.value, "panel_blocks": pb.value, "out_blocks": ob.value, "tuned_ms": ms.value}
 
+    def set_circulant_mode(self, job_table: bool):
+        _lib.check(_lib.load().amm_batch_circulant_set_mode(self.handle, 1 if job_table else 0))
+        return self
+
+    def circulant_schedule(self) -> dict:
+        """The circulant plan's tuned schedule (see amm_batch_circulant_schedule)."""
+        jt, nl, e, t = C.c_int(), C.c_int(), C.c_double(), C.c_double()
+        _lib.check(_lib.load().amm_batch_circulant_schedule(self.handle, C.byref(jt), C.byref(nl), C.byref(e),
+                                                           C.byref(t)))
+        return {"job_table": bool(jt.value), "launches": nl.value, "entry_ms": e.value, "table_ms": t.value}
+
     def close(self):
         if self.handle:
             _lib.load().amm_batch_plan_destroy(self.handle)

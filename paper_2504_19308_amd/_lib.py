@@ -101,6 +101,9 @@ SIGNATURES = {
     "amm_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_double)]),
     "amm_batch_plan_destroy": (None, [C.c_void_p]),
+    "amm_batch_circulant_set_mode": (C.c_int, [C.c_void_p, C.c_int]),
+    "amm_batch_circulant_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "amm_approx_matmul_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_void_p, C.c_void_p, C.c_void_p]),
     "amm_approx_matmul_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AmmMatrix),

@@ -1325,8 +1325,108 @@ namespace {
 // circulant entries: the zeroth-order product of each entry in turn, blocked
 // operands through the plan-owned scratch (so a captured graph never points
 // into the context's growable buffers)
-amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
+// The job table of a circulant plan: every power-of-two block product with
+// side in [64, 16384] becomes one job (row blocks write their valid rows,
+// column blocks read theirs and accumulate from the second block on, one
+// launch phase per block index); other entries stay per-entry launches.
+amm_status circ_build_jobs(amm_batch_plan* bp, bool x_bf16) {
+  struct Key {
+    int log2n, h16, phase;
+    bool operator<(const Key& o) const {
+      if (log2n != o.log2n) return log2n < o.log2n;
+      if (h16 != o.h16) return h16 < o.h16;
+      return phase < o.phase;
+    }
+  };
+  std::map<Key, std::vector<CdJob>> groups;
   for (size_t i = 0; i < bp->items.size(); ++i) {
+    const amm_dec* d = bp->decs[i];
+    const auto& it = bp->items[i];
+    const int64_t sd = d->blocks.empty() ? d->n : std::min(d->m, d->n);
+    const int l2 = is_pow2(sd) ? log2_exact(sd) : -1;
+    if (l2 < 0 || cd_tile_columns(l2) == 0) {
+      if (x_bf16) return fail(AMM_EUNSUPPORTED, "entry %zu: side %lld outside the batched launches", i, (long long)sd);
+      bp->cloose.push_back((int)i);
+      continue;
+    }
+    const size_t esz = x_bf16 ? 2 : 4;
+    const char* X = static_cast<const char*>(x_bf16 ? it.B16 : static_cast<const void*>(it.B));
+    const int64_t p = it.p;
+    auto job = [&](const amm_dec* b, const char* Xb, float* ob, int rows_in, int rows_out, int acc) {
+      CdJob j{};
+      j.X = Xb;
+      j.out = ob;
+      j.ldx = p;
+      j.ldo = p;
+      j.extent = p;
+      j.shifts = b->shifts.as<int32_t>();
+      j.L = b->lists16(false) ? static_cast<const void*>(b->lists16(false)) : static_cast<const void*>(b->L.as<float2>());
+      j.pr = b->pairs_of(false);
+      j.l16_inv = b->l16_inv;
+      j.K = b->K_eff;
+      j.accumulate = acc;
+      j.x_bf16 = x_bf16 ? 1 : 0;
+      const size_t xal = x_bf16 ? 8 : 16;
+      j.vec4 = (p % 4 == 0 && ((uintptr_t)Xb % xal) == 0 && ((uintptr_t)ob % 16) == 0) ? 1 : 0;
+      j.rows_in = rows_in;
+      j.rows_out = rows_out;
+      return j;
+    };
+    if (d->blocks.empty()) {
+      groups[{l2, d->lists16(false) != nullptr, 0}].push_back(job(d, X, it.out, (int)sd, (int)sd, 0));
+      continue;
+    }
+    for (size_t jb = 0; jb < d->blocks.size(); ++jb) {
+      const amm_dec* b = d->blocks[jb];
+      const int64_t lo = (int64_t)jb * sd;
+      const int h = b->lists16(false) != nullptr;
+      if (d->block_rows) {
+        const int valid = (int)std::min<int64_t>(sd, d->m - lo);
+        groups[{l2, h, 0}].push_back(job(b, X, it.out + lo * p, (int)sd, valid, 0));
+      } else {
+        const int valid = (int)std::min<int64_t>(sd, d->n - lo);
+        groups[{l2, h, (int)jb}].push_back(job(b, X + (size_t)lo * p * esz, it.out, valid, (int)sd, jb > 0 ? 1 : 0));
+      }
+    }
+  }
+  // phases in order (the map's order is side, precision, phase: accumulation
+  // phases of one group follow their first phase)
+  for (auto& kv : groups) {
+    amm_batch_plan::CircGroup g{kv.first.log2n, kv.first.h16 != 0, (int)bp->cjobs_host.size(), (int)kv.second.size(), 0};
+    const int tc = cd_tile_columns(g.log2n);
+    for (auto& j : kv.second) {
+      j.tile0 = g.tiles;
+      g.tiles += (int)((j.extent + tc - 1) / tc);
+      bp->cjobs_host.push_back(j);
+    }
+    bp->cgroups.push_back(g);
+  }
+  if (!bp->cjobs_host.empty()) {
+    AMM_TRY(bp->cjobs.alloc(bp->cjobs_host.size() * sizeof(CdJob)));
+    AMM_HIP(hipMemcpy(bp->cjobs.ptr, bp->cjobs_host.data(), bp->cjobs_host.size() * sizeof(CdJob),
+                      hipMemcpyHostToDevice));
+  }
+  return AMM_OK;
+}
+
+amm_status circ_one(amm_batch_plan* bp, size_t i, hipStream_t s);
+
+amm_status circ_job_launches(amm_batch_plan* bp, hipStream_t s) {
+  const CdJob* jobs = bp->cjobs.as<CdJob>();
+  for (const auto& g : bp->cgroups)
+    AMM_TRY(cd_apply_jobs(bp->ctx, g.log2n, g.h16, jobs + g.first_job, g.njobs, g.tiles, s));
+  for (int i : bp->cloose) AMM_TRY(circ_one(bp, (size_t)i, s));
+  return AMM_OK;
+}
+
+amm_status circ_launches(amm_batch_plan* bp, hipStream_t s) {
+  if (bp->circ_mode == 1) return circ_job_launches(bp, s);
+  for (size_t i = 0; i < bp->items.size(); ++i) AMM_TRY(circ_one(bp, i, s));
+  return AMM_OK;
+}
+
+amm_status circ_one(amm_batch_plan* bp, size_t i, hipStream_t s) {
+  {
     const amm_dec* d = bp->decs[i];
     const auto& it = bp->items[i];
     if (!d->blocks.empty()) {
@@ -1356,6 +1456,28 @@ amm_status plan_launch(amm_batch_plan* bp, hipStream_t s) {
 // Autotune the reduction split policy by timing each candidate on the caller's
 // stream, then capture the two launches once on a plan-owned stream; runs
 // replay the graph.  Deletes the plan on failure.
+// (Re)capture the plan's launches into its graph on its own stream.
+amm_status plan_capture(amm_batch_plan* bp) {
+  if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+  if (bp->graph) (void)hipGraphDestroy(bp->graph);
+  bp->exec = nullptr;
+  bp->graph = nullptr;
+  KernelTimer* saved = g_timer;
+  g_timer = nullptr;
+  amm_status st = AMM_OK;
+  if (hipStreamBeginCapture(bp->own, hipStreamCaptureModeThreadLocal) != hipSuccess) st = fail(AMM_EDEVICE, "capture");
+  if (st == AMM_OK) {
+    amm_status ls = plan_launch(bp, bp->own);
+    hipError_t ce = hipStreamEndCapture(bp->own, &bp->graph);
+    if (ls != AMM_OK) st = ls;
+    else if (ce != hipSuccess) st = hip_fail(ce, "hipStreamEndCapture");
+  }
+  if (st == AMM_OK && hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = fail(AMM_EDEVICE, "hipGraphInstantiate");
+  g_timer = saved;
+  return st;
+}
+
 amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan) {
   const int candidates[] = {256, 512, 1024, 2048, 4096};
   double best = 1e30;
@@ -1364,13 +1486,23 @@ amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan)
   amm_status st = AMM_OK;
   if (hipEventCreate(&e0) != hipSuccess) st = fail(AMM_EDEVICE, "event");
   if (st == AMM_OK && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); st = fail(AMM_EDEVICE, "event"); }
-  if (st == AMM_OK && bp->launches) {   // nothing to tune: time one run
-    (void)hipEventRecord(e0, s);
-    st = plan_launch(bp, s);
-    (void)hipEventRecord(e1, s);
-    float ms = 0.f;
-    if (st == AMM_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
-    best = 3.0 * ms;
+  if (st == AMM_OK && bp->launches) {
+    // circulant plans: time the per-entry launches and the job-table launches
+    // (a warm-up and three runs each) and keep the faster; bfloat16 plans
+    // have only the job table
+    for (int mode = bp->bf16 ? 1 : 0; mode <= (bp->cgroups.empty() ? 0 : 1) && st == AMM_OK; ++mode) {
+      bp->circ_mode = mode;
+      st = plan_launch(bp, s);
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && st == AMM_OK; ++r) st = plan_launch(bp, s);
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (st == AMM_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+      bp->circ_ms[mode] = ms / 3.0;
+    }
+    const bool table = bp->circ_ms[1] >= 0.0 && (bp->circ_ms[0] < 0.0 || bp->circ_ms[1] <= bp->circ_ms[0]);
+    bp->circ_mode = table ? 1 : 0;
+    best = 3.0 * bp->circ_ms[bp->circ_mode];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   } else if (st == AMM_OK) {
@@ -1392,20 +1524,7 @@ amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan)
   if (st == AMM_OK) st = plan_build(bp, best_t);
   bp->tuned_ms = best / 3.0;
   if (st == AMM_OK && hipStreamCreateWithFlags(&bp->own, hipStreamNonBlocking) != hipSuccess) st = fail(AMM_EDEVICE, "stream");
-  if (st == AMM_OK) {
-    KernelTimer* saved = g_timer;
-    g_timer = nullptr;
-    if (hipStreamBeginCapture(bp->own, hipStreamCaptureModeThreadLocal) != hipSuccess) st = fail(AMM_EDEVICE, "capture");
-    if (st == AMM_OK) {
-      amm_status ls = plan_launch(bp, bp->own);
-      hipError_t ce = hipStreamEndCapture(bp->own, &bp->graph);
-      if (ls != AMM_OK) st = ls;
-      else if (ce != hipSuccess) st = hip_fail(ce, "hipStreamEndCapture");
-    }
-    if (st == AMM_OK && hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
-      st = fail(AMM_EDEVICE, "hipGraphInstantiate");
-    g_timer = saved;
-  }
+  if (st == AMM_OK) st = plan_capture(bp);
   if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "sync");
   if (st != AMM_OK) {
     delete bp;
@@ -1423,9 +1542,11 @@ amm_status plan_check(int count, const amm_dec* const* dA, const void* const* B,
   for (int i = 0; i < count; ++i) {
     const amm_dec* d = dA[i];
     if (!d || !B[i] || !out[i]) return fail(AMM_EINVAL, "NULL entry %d", i);
-    if (!bf16 && d->kind == AMM_CIRCULANT && dA[0]->kind == AMM_CIRCULANT) {
+    if (d->kind == AMM_CIRCULANT && dA[0]->kind == AMM_CIRCULANT) {
       if (p[i] <= 0) return fail(AMM_ESHAPE, "entry %d has no columns", i);
       const int64_t side = d->blocks.empty() ? d->n : std::min(d->m, d->n);
+      if (bf16 && !(is_pow2(side) && cd_tile_columns(log2_exact(side)) > 0))
+        return fail(AMM_EUNSUPPORTED, "entry %d: bfloat16 circulant plans need power-of-two sides in [64, 16384]", i);
       if (!is_pow2(side) && !(side >= 3 && side <= kChirpFusedMax))
         return fail(AMM_EUNSUPPORTED, "entry %d: circulant plans need power-of-two sides or sides up to %d", i,
                     kChirpFusedMax);
@@ -1486,6 +1607,7 @@ amm_status amm_batch_plan_create(amm_ctx* ctx, int count, const amm_dec* const* 
       }
     }
     amm_status st = bp->partials.alloc(scratch * sizeof(float));
+    if (st == AMM_OK) st = circ_build_jobs(bp, false);
     if (st != AMM_OK) {
       delete bp;
       return st;
@@ -1508,6 +1630,26 @@ amm_status amm_batch_plan_create_bf16(amm_ctx* ctx, int count, const amm_dec* co
   bp->ctx = ctx;
   bp->k = k;
   bp->bf16 = true;
+  if (dA[0]->kind == AMM_CIRCULANT) {
+    // bfloat16 B_i read by the batched launches (widened in the load), float32 products
+    bp->launches = true;
+    amm_status st = AMM_OK;
+    for (int i = 0; i < count && st == AMM_OK; ++i) {
+      amm_batch_plan::Item it{dA[i]->m, dA[i]->n, p[i], nullptr, nullptr, nullptr, out[i]};
+      it.B16 = B[i];
+      bp->items.push_back(it);
+      bp->decs.push_back(dA[i]);
+      const int64_t sd = dA[i]->blocks.empty() ? dA[i]->n : std::min(dA[i]->m, dA[i]->n);
+      const float2* tw = nullptr;
+      st = twiddles32(ctx, log2_exact(sd), &tw);
+    }
+    if (st == AMM_OK) st = circ_build_jobs(bp, true);
+    if (st != AMM_OK) {
+      delete bp;
+      return st;
+    }
+    return plan_finish(bp, (hipStream_t)stream, plan);
+  }
   std::vector<const float*> V, US;
   for (int i = 0; i < count; ++i) {
     amm_batch_plan::Item it{dA[i]->m, dA[i]->n, p[i], nullptr, nullptr, nullptr, out[i]};
@@ -1534,6 +1676,30 @@ static amm_status batch_run_body(amm_batch_plan* plan, int use_graph, void* stre
     return AMM_OK;
   }
   return plan_launch(plan, s);
+}
+
+amm_status amm_batch_circulant_set_mode(amm_batch_plan* plan, int job_table) {
+  if (!plan) return fail(AMM_EINVAL, "NULL plan");
+  if (!plan->launches) return fail(AMM_ESTATE, "not a circulant plan");
+  if (job_table && plan->cgroups.empty()) return fail(AMM_EUNSUPPORTED, "no entry runs in the batched launches");
+  if (!job_table && plan->bf16) return fail(AMM_EUNSUPPORTED, "bfloat16 plans run only the batched launches");
+  TimerScope ts(plan->ctx);
+  AMM_HIP(hipSetDevice(plan->ctx->device));
+  AMM_HIP(hipStreamSynchronize(plan->own));
+  plan->circ_mode = job_table ? 1 : 0;
+  return plan_capture(plan);
+}
+
+amm_status amm_batch_circulant_schedule(const amm_batch_plan* plan, int* job_table, int* launches,
+                                        double* entry_ms, double* table_ms) {
+  if (!plan) return fail(AMM_EINVAL, "NULL plan");
+  if (!plan->launches) return fail(AMM_ESTATE, "not a circulant plan");
+  if (job_table) *job_table = plan->circ_mode;
+  if (launches)
+    *launches = plan->circ_mode == 1 ? (int)(plan->cgroups.size() + plan->cloose.size()) : (int)plan->items.size();
+  if (entry_ms) *entry_ms = plan->circ_ms[0];
+  if (table_ms) *table_ms = plan->circ_ms[1];
+  return AMM_OK;
 }
 
 amm_status amm_batch_info(const amm_batch_plan* plan, int* target_blocks, int* panel_blocks, int* out_blocks,

@@ -134,6 +134,23 @@ struct CdPairs {
   int nsingles = 0;
 };
 
+// One product of a batched circulant launch (column mode): out (N x extent)
+// (+)= Atil X for one square block, over the launch's workgroups tile0 ..
+// tile0 + tiles - 1.  Rows of X at or past rows_in read as zero (the padded
+// last block of a column-blocked operand); rows of out at or past rows_out
+// are not written (the overhang of a row-blocked one).
+struct CdJob {
+  const void* X;            // float32, or bfloat16 when x_bf16
+  float* out;
+  int64_t ldx, ldo, extent;
+  const int32_t* shifts;
+  const void* L;            // float2 lists, or the float16 ones of a float16 launch
+  CdPairs pr;
+  float l16_inv;
+  int K, accumulate, vec4, x_bf16;
+  int rows_in, rows_out;
+  int tile0;
+};
 }  // namespace amm
 
 struct amm_ctx {
@@ -266,6 +283,20 @@ struct amm_batch_plan {
   int* ostart = nullptr;
   int* rstart = nullptr;
   int red_blocks = 0;
+  // circulant plans: batched launches over a job table, one per (side,
+  // list precision, accumulation phase) group, and the entries they do not
+  // cover (other sides) launched one by one
+  struct CircGroup {
+    int log2n;
+    bool h16;
+    int first_job, njobs, tiles;
+  };
+  std::vector<amm::CdJob> cjobs_host;
+  std::vector<CircGroup> cgroups;
+  std::vector<int> cloose;
+  amm::DevBuf cjobs;
+  int circ_mode = 0;            // 0: every entry launched by itself; 1: the job-table launches
+  double circ_ms[2] = {-1.0, -1.0};   // tuner's time of one run in each mode (-1: not timed)
   hipStream_t own = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -292,6 +323,11 @@ amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shift
                             bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},
                             const __half2* L16 = nullptr, float l16_inv = 1.0f, int64_t ldb = 0,
                             int64_t ldo = 0);
+// Batched column-mode products over a job table (device memory, sorted by
+// tile0, covering workgroups 0 .. tiles - 1); cd_tile_columns: real columns
+// per workgroup at side 2^log2n (0 outside 64 .. 16384).
+amm_status cd_apply_jobs(amm_ctx* ctx, int log2n, bool h16, const CdJob* jobs, int njobs, int tiles, hipStream_t s);
+int cd_tile_columns(int log2n);
 amm_status cd_apply_rows(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                          const float2* L, const float* X, int64_t rows, float* out,
                          bool accumulate, hipStream_t s, CdPairs pr = CdPairs{},

@@ -199,13 +199,48 @@ __device__ __forceinline__ void read_h(const uint32_t* hs, int w, uint32_t (&x)[
   }
 }
 
-template <int LOG2N, bool ROWS, bool SPEC = false, bool H16 = false>
+// JOBS: a batched launch; each workgroup takes its product's operands from
+// the job table (jobs sorted by tile0) instead of the arguments.
+template <int LOG2N, bool ROWS, bool SPEC = false, bool H16 = false, bool JOBS = false>
 __global__ void __launch_bounds__(CdCfg<LOG2N>::T)
 cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ out, int64_t ldo, int64_t extent,
                 int K, const int32_t* __restrict__ shifts, const void* __restrict__ L,
-                const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr, float l16_inv) {
+                const float2* __restrict__ tw, int accumulate, int vec4, CdPairs pr, float l16_inv,
+                const CdJob* __restrict__ jobs = nullptr, int njobs = 0) {
   using Cfg = CdCfg<LOG2N>;
   constexpr int N = Cfg::N, C = Cfg::C, T = Cfg::T;
+  const uint16_t* Xh = nullptr;   // bfloat16 rows (batched launches)
+  int rows_in = N, rows_out = N;
+  int job_tile = 0;
+  if constexpr (JOBS) {
+    // the launch's tiles in XCD-aware order (consecutive tiles, which share a
+    // product's lists, on one XCD), then the last job with tile0 <= that tile
+    int gt = blockIdx.x;
+    if ((gridDim.x & 7) == 0) gt = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile0 <= gt) lo = mid;
+      else hi = mid - 1;
+    }
+    const CdJob& J = jobs[lo];
+    if (J.x_bf16) Xh = static_cast<const uint16_t*>(J.X);
+    else X = static_cast<const float*>(J.X);
+    out = J.out;
+    ldx = J.ldx;
+    ldo = J.ldo;
+    extent = J.extent;
+    K = J.K;
+    shifts = J.shifts;
+    L = J.L;
+    pr = J.pr;
+    l16_inv = J.l16_inv;
+    accumulate = J.accumulate;
+    vec4 = J.vec4;
+    rows_in = J.rows_in;
+    rows_out = J.rows_out;
+    job_tile = gt - J.tile0;
+  }
   __shared__ __align__(16) float2 lds[Cfg::LDS_SLOTS];
   __shared__ float2 twl[Cfg::TWL], twh[Cfg::TWH];
   __shared__ float red[(T + 63) / 64];
@@ -222,6 +257,7 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
   const int per = (nblk + 7) / 8;
   int tile = xcd * per + slot;
   if ((nblk & 7) != 0) tile = blockIdx.x;   // only remap when it is a bijection
+  if constexpr (JOBS) tile = job_tile;      // batched: consecutive tiles of one product
   const int64_t first = (int64_t)tile * 2 * C;  // first real column / row
 
   // ---- load -----------------------------------------------------------------
@@ -236,8 +272,20 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
         const int e = threadIdx.x + q * T;
         const int row = e / V, v = e % V;
         const int64_t c = first + 4 * v;
-        r[q] = (e < TOT && c < extent) ? *reinterpret_cast<const float4*>(X + (int64_t)row * ldx + c)
-                                       : float4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (JOBS) {
+          const bool in = e < TOT && c < extent && row < rows_in;
+          if (Xh) {
+            // four bfloat16 values (8 bytes) widened exactly
+            const uint2 h = in ? *reinterpret_cast<const uint2*>(Xh + (int64_t)row * ldx + c) : uint2{0u, 0u};
+            r[q] = float4{__uint_as_float(h.x << 16), __uint_as_float(h.x & 0xFFFF0000u), __uint_as_float(h.y << 16),
+                          __uint_as_float(h.y & 0xFFFF0000u)};
+          } else {
+            r[q] = in ? *reinterpret_cast<const float4*>(X + (int64_t)row * ldx + c) : float4{0.f, 0.f, 0.f, 0.f};
+          }
+        } else {
+          r[q] = (e < TOT && c < extent) ? *reinterpret_cast<const float4*>(X + (int64_t)row * ldx + c)
+                                         : float4{0.f, 0.f, 0.f, 0.f};
+        }
       }
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
@@ -248,7 +296,14 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
       for (int e = threadIdx.x; e < N * 2 * C; e += T) {
         const int rc = e % (2 * C), row = e / (2 * C);
         const int64_t c = first + rc;
-        ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = c < extent ? X[(int64_t)row * ldx + c] : 0.f;
+        float x = 0.f;
+        if constexpr (JOBS) {
+          if (c < extent && row < rows_in)
+            x = Xh ? __uint_as_float((uint32_t)Xh[(int64_t)row * ldx + c] << 16) : X[(int64_t)row * ldx + c];
+        } else {
+          x = c < extent ? X[(int64_t)row * ldx + c] : 0.f;
+        }
+        ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] = x;
       }
     }
   } else {
@@ -502,7 +557,7 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
         const int e = threadIdx.x + q * T;
         const int row = e / V, v = e % V;
         const int64_t c = first + 4 * v;
-        if (e < TOT && c < extent) {
+        if (e < TOT && c < extent && (!JOBS || row < rows_out)) {
           float4 y = *reinterpret_cast<const float4*>(&lds[pad_bin(row) * C + 2 * v]);
           y = float4{y.x * scale, y.y * scale, y.z * scale, y.w * scale};
           float4* o = reinterpret_cast<float4*>(out + (int64_t)row * ldo + c);
@@ -517,7 +572,7 @@ cd_apply_kernel(const float* __restrict__ X, int64_t ldx, float* __restrict__ ou
       for (int e = threadIdx.x; e < N * 2 * C; e += T) {
         const int rc = e % (2 * C), row = e / (2 * C);
         const int64_t c = first + rc;
-        if (c < extent) {
+        if (c < extent && (!JOBS || row < rows_out)) {
           const float v = ldsf[(pad_bin(row) * C + (rc >> 1)) * 2 + (rc & 1)] * scale;
           float* o = out + (int64_t)row * ldo + c;
           *o = accumulate ? *o + v : v;
@@ -1030,7 +1085,51 @@ amm_status dispatch_cd(bool rows, int log2n, const float* X, int64_t ldx, float*
   }
 }
 
+template <int LOG2N>
+amm_status launch_cd_jobs(bool h16, const CdJob* jobs, int njobs, int tiles, const float2* tw, hipStream_t s) {
+  using Cfg = CdCfg<LOG2N>;
+  dim3 grid((unsigned)tiles), block(Cfg::T);
+  TimedLaunch tl("cd_apply_batched", s);
+  if (h16) {
+    if constexpr (LOG2N >= kH16MinLog2)
+      hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, false, true, true>), grid, block, 0, s, (const float*)nullptr,
+                         (int64_t)0, (float*)nullptr, (int64_t)0, (int64_t)0, 0, (const int32_t*)nullptr,
+                         (const void*)nullptr, tw, 0, 0, CdPairs{}, 1.0f, jobs, njobs);
+    else
+      return fail(AMM_EUNSUPPORTED, "float16 spectral products need n >= %d", 1 << kH16MinLog2);
+  } else {
+    hipLaunchKernelGGL((cd_apply_kernel<LOG2N, false, false, false, true>), grid, block, 0, s, (const float*)nullptr,
+                       (int64_t)0, (float*)nullptr, (int64_t)0, (int64_t)0, 0, (const int32_t*)nullptr,
+                       (const void*)nullptr, tw, 0, 0, CdPairs{}, 1.0f, jobs, njobs);
+  }
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
 }  // namespace
+
+int cd_tile_columns(int log2n) {
+  switch (log2n) {
+#define AMM_CASE(L2) \
+  case L2: return 2 * CdCfg<L2>::C;
+    AMM_CASE(6) AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12) AMM_CASE(13) AMM_CASE(14)
+#undef AMM_CASE
+    default: return 0;
+  }
+}
+
+amm_status cd_apply_jobs(amm_ctx* ctx, int log2n, bool h16, const CdJob* jobs, int njobs, int tiles, hipStream_t s) {
+  if (njobs <= 0 || tiles <= 0) return AMM_OK;
+  const float2* tw = nullptr;
+  AMM_TRY(twiddles32(ctx, log2n, &tw));
+  switch (log2n) {
+#define AMM_CASE(L2) \
+  case L2: return launch_cd_jobs<L2>(h16, jobs, njobs, tiles, tw, s);
+    AMM_CASE(6) AMM_CASE(7) AMM_CASE(8) AMM_CASE(9) AMM_CASE(10) AMM_CASE(11) AMM_CASE(12) AMM_CASE(13) AMM_CASE(14)
+#undef AMM_CASE
+    default: return fail(AMM_EUNSUPPORTED, "batched circulant launches need 64 <= n <= 16384");
+  }
+}
 
 amm_status cd_apply_columns(amm_ctx* ctx, int log2n, int K, const int32_t* shifts,
                             const float2* L, const float* B, int64_t p, float* out,

@@ -122,3 +122,76 @@ def test_mixed_batch_is_rejected():
     B = gpu(np.ones((128, 128)))
     with pytest.raises(AmmError):
         c.batch_plan([dc, dt], [B, B])
+
+
+def test_circulant_batch_job_table_matches_entry_launches():
+    """The batched job-table launches against the per-entry launches, bit for
+    bit, on square, row-blocked and column-blocked entries (partial last
+    blocks, odd column counts, a zero-rank entry, float16 lists) next to a
+    side that only runs per entry; graph replays of the job table; and the
+    tuner's report."""
+    torch = torch_cuda()
+    c = ctx()
+    shapes = [(64, 64, 5, 40), (200, 64, 4, 33), (64, 150, 3, 17), (256, 256, 8, 128), (128, 512, 6, 64),
+              (1024, 1024, 0, 24), (2500, 1024, 6, 24), (1024, 2500, 6, 20), (300, 300, 5, 20)]
+    decs, Bs = [], []
+    for i, (m, n, K, p) in enumerate(shapes):
+        A = _rect_toeplitz(m, n, 80 + i)
+        decs.append(c.decompose(gpu(A), "circulant", K))
+        Bs.append(gpu(np.random.default_rng(90 + i).standard_normal((n, p))))
+    A = _rect_toeplitz(1024, 1024, 99)
+    decs.append(c.decompose(gpu(A), "circulant", 12, spectral_fp16=True))
+    Bs.append(gpu(np.random.default_rng(98).standard_normal((1024, 48))))
+    plan = c.batch_plan(decs, Bs)
+    sched = plan.circulant_schedule()
+    note(f"  schedule {sched}")
+    assert sched["entry_ms"] > 0 and sched["table_ms"] > 0
+    results = {}
+    for mode in (False, True):
+        plan.set_circulant_mode(mode)
+        assert plan.circulant_schedule()["job_table"] == mode
+        for o in plan.outs:
+            o.fill_(float("nan"))
+        results[mode] = [o.clone() for o in plan.run(use_graph=False)]
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(results[False], results[True])):
+        assert torch.equal(a, b), f"entry {i} differs between the schedules"
+    assert float(results[True][5].abs().max()) == 0.0          # zero rank: zero product
+    for i in (0, 3):                                            # square entries against the oracle
+        m, n, K, p = shapes[i]
+        Ah = _rect_toeplitz(m, n, 80 + i)
+        want = np.real(oc.apply_zeroth(oc.CirculantDecomp(Ah, K), host(Bs[i])))
+        assert rel(host(results[True][i]), want) < TOL_F32
+    for rep in range(3):
+        for o in plan.outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run(use_graph=True)
+        torch.cuda.synchronize()
+        for o, e in zip(plan.outs, results[True]):
+            assert torch.equal(o, e), f"replay {rep} differs"
+
+
+def test_circulant_batch_bf16():
+    """bfloat16 B_i through the job table: equal to the float32 plan on the
+    widened values; sides the batched launches do not cover are refused."""
+    from paper_2504_19308_amd import AmmError
+    torch = torch_cuda()
+    c = ctx()
+    shapes = [(256, 256, 8, 64), (600, 256, 5, 36), (256, 700, 4, 40), (1024, 1024, 10, 96)]
+    decs, B16 = [], []
+    for i, (m, n, K, p) in enumerate(shapes):
+        A = _rect_toeplitz(m, n, 70 + i)
+        decs.append(c.decompose(gpu(A), "circulant", K, spectral_fp16=(n == 1024)))
+        B16.append(gpu(np.random.default_rng(75 + i).standard_normal((n, p))).bfloat16())
+    plan16 = c.batch_plan(decs, B16)
+    assert plan16.circulant_schedule()["job_table"] and plan16.circulant_schedule()["entry_ms"] < 0
+    out16 = [o.clone() for o in plan16.run(use_graph=True)]
+    plan32 = c.batch_plan(decs, [b.float() for b in B16]).set_circulant_mode(True)
+    out32 = plan32.run(use_graph=False)
+    torch.cuda.synchronize()
+    for a, b in zip(out16, out32):
+        assert torch.equal(a, b)
+    odd = c.decompose(gpu(_rect_toeplitz(300, 300, 5)), "circulant", 4)
+    with pytest.raises(AmmError):
+        c.batch_plan([odd], [gpu(np.ones((300, 8))).bfloat16()])
