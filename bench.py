@@ -163,6 +163,11 @@ def headline_roofline(kt, steps, n, nnz, K, list_bytes=4):
     top = max(rows.values(), key=lambda r: r["ms_per_step"])
     out = dict(top)
     out["traffic"] = traffic_bytes(top["tag"])
+    if top["tag"] == "spmm_csr":
+        # what actually bounds the row gather: every entry reads its slice of a B row through L2
+        g = 4.0 * nnz * p / HEADLINE_KERNELS["spmm_csr"][1]
+        out["l2_gather"] = {"bytes": g, "achieved_TBs": g / (top["avg_us"] * 1e-6) / 1e12,
+                            "note": "4 nnz p bytes of B rows gathered through L2 per product (47x the HBM bytes)"}
     out["per_kernel"] = rows
     return out
 
