@@ -44,17 +44,17 @@ VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2
 # taken.
 TRAFFIC = {
     # headline step, n = 16384 (profiles/sparse_circulant_n16384.md)
-    "spmm_csr": {"fetch_kib": 4945570.6, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
-                 "sha16": "83c8b69d32f711d3"},
-    "cd_apply_columns": {"fetch_kib": 934525.8, "write_kib": 1491414.2, "src": "paper_2504_19308_amd/csrc/cd_apply.hip",
-                         "sha16": "c9bfdc2a06b02240"},
+    "spmm_csr": {"fetch_kib": 4956767.7, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
+                 "sha16": "90dfd0f5f5c05146"},
+    "cd_apply_columns": {"fetch_kib": 932867.2, "write_kib": 1495888.8, "src": "paper_2504_19308_amd/csrc/cd_apply.hip",
+                         "sha16": "9e3111996e8eca06"},
+    "repitch": {"fetch_kib": 524311.0, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
+                "sha16": "90dfd0f5f5c05146"},
     # rank-32 first-order product, n = 4096 (profiles/tsvd_first_order_n4096.md)
-    "panel": {"fetch_kib": 67709.3, "write_kib": 2048.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
-              "sha16": "c7bac24a28d6757c"},
-    "gemm_out": {"fetch_kib": 8746.7, "write_kib": 65536.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
-                 "sha16": "c7bac24a28d6757c"},
-    "reduce": {"fetch_kib": 1036.0, "write_kib": 1024.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
-               "sha16": "c7bac24a28d6757c"},
+    "panel": {"fetch_kib": 67707.2, "write_kib": 2048.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
+              "sha16": "1c062e58b9095c9e"},
+    "gemm_out": {"fetch_kib": 8746.5, "write_kib": 65536.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
+                 "sha16": "1c062e58b9095c9e"},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -158,7 +158,7 @@ def headline_roofline(kt, steps, n, nnz, K, list_bytes=4):
             r = {"bound": "hbm", "achieved": b1 / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
         r["frac"] = r["achieved"] / r["peak"]
         r.update(kernel=kname, tag=tag, dispatches_per_step=nd, avg_us=t * 1e6, ms_per_step=ms / steps,
-                 algorithmic_bytes=b1, algorithmic_flops=f1)
+                 algorithmic_bytes=b1, algorithmic_flops=f1, traffic=traffic_bytes(tag))
         rows[tag] = r
     top = max(rows.values(), key=lambda r: r["ms_per_step"])
     out = dict(top)
