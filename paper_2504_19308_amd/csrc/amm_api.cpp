@@ -584,24 +584,29 @@ amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
   float mx = 0.f;
   for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
   const float tol = 1e-5f * mx + 1e-30f;
-  // adjoint lists on the host
+  // adjoint lists on the host: La_t[p] = conj(L_t[(p + k) mod n]) (the index
+  // wraps once, so the two ranges run without a modulo)
   std::vector<float2> La((size_t)K * n);
   std::vector<int64_t> ka(K);
   for (int t = 0; t < K; ++t) {
     const int64_t k = d->freqs[t];
-    ka[t] = (n - k) % n;
-    for (int64_t p = 0; p < n; ++p) {
-      const float2 v = Lh[(size_t)t * n + (p + k) % n];
-      La[(size_t)t * n + p] = float2{v.x, -v.y};
-    }
+    ka[t] = k == 0 ? 0 : n - k;
+    const float2* src = Lh.data() + (size_t)t * n;
+    float2* dst = La.data() + (size_t)t * n;
+    for (int64_t p = 0; p < n - k; ++p) dst[p] = float2{src[p + k].x, -src[p + k].y};
+    for (int64_t p = n - k; p < n; ++p) dst[p] = float2{src[p + k - n].x, -src[p + k - n].y};
   }
-  // L_b[p] == conj(L_a[-p]) for every p
+  // L_b[p] == conj(L_a[-p]) for every p (index -p is 0 at p = 0, else n - p)
   auto mirror = [&](const std::vector<float2>& Ls, int ta, int tb) {
-    for (int64_t p = 0; p < n; ++p) {
-      const float2 a = Ls[(size_t)ta * n + (n - p) % n], b = Ls[(size_t)tb * n + p];
-      if (std::fabs(b.x - a.x) > tol || std::fabs(b.y + a.y) > tol) return false;
+    const float2* la = Ls.data() + (size_t)ta * n;
+    const float2* lb = Ls.data() + (size_t)tb * n;
+    if (std::fabs(lb[0].x - la[0].x) > tol || std::fabs(lb[0].y + la[0].y) > tol) return false;
+    bool ok = true;
+    for (int64_t p = 1; p < n; ++p) {
+      const float2 a = la[n - p], b = lb[p];
+      ok &= !(std::fabs(b.x - a.x) > tol || std::fabs(b.y + a.y) > tol);
     }
-    return true;
+    return ok;
   };
   std::vector<int2> pairs, singles, pairs_a, singles_a;
   for (int pass = 0; pass < 2; ++pass) {
@@ -1078,29 +1083,6 @@ static amm_status matmul_body(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB
   AMM_TRY(residual_of(ctx, dA, &dAres, s));
   return right_apply(ctx, dAres, dA->m, dB, out, true, s);
 }
-
-namespace {
-// Whether two row panels of p floats (rows at a + i lda, i < ra, and at
-// b + k ldb, k < rb) share an element.  With one pitch and a whole-float
-// offset the test is exact (panels side by side in one matrix are disjoint);
-// otherwise the address ranges must be disjoint.
-bool panels_overlap(const float* a, int64_t ra, int64_t lda, const float* b, int64_t rb, int64_t ldb, int64_t p) {
-  const intptr_t diff = (intptr_t)b - (intptr_t)a;
-  if (lda == ldb && diff % (intptr_t)sizeof(float) == 0) {
-    const int64_t ld = lda, d = diff / (intptr_t)sizeof(float);
-    int64_t q = d / ld, r = d % ld;   // b = a + q ld + r, 0 <= r < ld
-    if (r < 0) {
-      r += ld;
-      q -= 1;
-    }
-    auto rows_meet = [&](int64_t lo) { return lo < ra && lo + rb > 0; };   // [lo, lo + rb) against [0, ra)
-    return (r < p && rows_meet(q)) || (ld - r < p && rows_meet(q + 1));
-  }
-  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)((ra - 1) * lda + p) * sizeof(float);
-  const uintptr_t b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)((rb - 1) * ldb + p) * sizeof(float);
-  return a0 < b1 && b0 < a1;
-}
-}  // namespace
 
 static amm_status strided_body(amm_ctx* ctx, const amm_dec* dA, const amm_dec* dB, const float* B,
                                      int64_t n, int64_t p, int64_t ldb, float* out, int64_t ldo, void* stream) {

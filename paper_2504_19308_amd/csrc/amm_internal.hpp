@@ -8,6 +8,8 @@
 #include <map>
 #include <string>
 #include <vector>
+
+#include "host_logic.hpp"
 #include <cmath>
 
 #include "amm.h"
@@ -383,10 +385,6 @@ amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shif
 amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
                            bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s);
 
-// Closed-set frequency selection (host), same reading as documented in amm.h.
-std::vector<int32_t> select_closed(const std::vector<double>& E, int K);
-// energy kept by select_closed(E, K) for every K = 0..n
-std::vector<double> retained_all(const std::vector<double>& E);
 
 // Dense float32 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C, with
 // general element strides (row-major or transposed views).

@@ -202,76 +202,6 @@ amm_status transform_axis(double2*& cur, double2*& tmp, int log2n, bool columns,
 
 }  // namespace
 
-std::vector<int32_t> select_closed(const std::vector<double>& E, int K) {
-  // Among frequency sets closed under k -> n-k with at most K members, keep
-  // the one with the largest total energy.  Singleton classes are {0} and
-  // {n/2}; every other class is a pair, so for each subset of singletons the
-  // best completion is the top pairs by E[k] + E[n-k] (ties: smaller k).
-  const int n = (int)E.size();
-  std::vector<int> singles{0};
-  if (n % 2 == 0 && n > 1) singles.push_back(n / 2);
-  std::vector<int> pairs;
-  for (int k = 1; k < (n + 1) / 2; ++k) pairs.push_back(k);
-  std::stable_sort(pairs.begin(), pairs.end(), [&](int a, int b) {
-    const double ea = E[a] + E[n - a], eb = E[b] + E[n - b];
-    if (ea != eb) return ea > eb;
-    return a < b;
-  });
-  std::vector<std::vector<int>> subsets{{}};
-  for (int sgl : singles) subsets.push_back({sgl});
-  if (singles.size() == 2) subsets.push_back(singles);
-  bool have = false;
-  double best_total = 0.0;
-  size_t best_size = 0;
-  std::vector<int32_t> best;
-  for (const auto& U : subsets) {
-    if ((int)U.size() > K) continue;
-    std::vector<int32_t> members(U.begin(), U.end());
-    const int np = (K - (int)U.size()) / 2;
-    for (int i = 0; i < np && i < (int)pairs.size(); ++i) {
-      members.push_back(pairs[i]);
-      members.push_back(n - pairs[i]);
-    }
-    double total = 0.0;
-    for (int m : members) total += E[m];
-    if (!have || total > best_total || (total == best_total && members.size() > best_size)) {
-      have = true;
-      best_total = total;
-      best_size = members.size();
-      best = members;
-    }
-  }
-  std::sort(best.begin(), best.end());
-  return best;
-}
-
-std::vector<double> retained_all(const std::vector<double>& E) {
-  // R[K] = energy kept by select_closed(E, K) for K = 0..n, from prefix sums of
-  // the sorted pair energies (the same candidate sets as select_closed)
-  const int n = (int)E.size();
-  std::vector<int> singles{0};
-  if (n % 2 == 0 && n > 1) singles.push_back(n / 2);
-  std::vector<double> pe;
-  for (int k = 1; k < (n + 1) / 2; ++k) pe.push_back(E[k] + E[n - k]);
-  std::sort(pe.begin(), pe.end(), [](double a, double b) { return a > b; });
-  std::vector<double> pre(pe.size() + 1, 0.0);
-  for (size_t i = 0; i < pe.size(); ++i) pre[i + 1] = pre[i] + pe[i];
-  std::vector<std::pair<int, double>> subsets{{0, 0.0}};
-  for (int sgl : singles) subsets.push_back({1, E[sgl]});
-  if (singles.size() == 2) subsets.push_back({2, E[singles[0]] + E[singles[1]]});
-  std::vector<double> R(n + 1, 0.0);
-  for (int K = 0; K <= n; ++K) {
-    double best = 0.0;
-    for (const auto& u : subsets) {
-      if (u.first > K) continue;
-      const size_t np = std::min<size_t>((size_t)(K - u.first) / 2, pe.size());
-      best = std::max(best, u.second + pre[np]);
-    }
-    R[K] = best;
-  }
-  return R;
-}
-
 // float16 copies of L and Ladj, scaled by the power of two that puts the
 // largest list component in [2^13, 2^14) (the lists of a small residue would
 // otherwise sit among the float16 subnormals); l16_inv undoes the scale.

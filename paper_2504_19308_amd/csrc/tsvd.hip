@@ -130,80 +130,6 @@ __global__ void pick_columns(const double* __restrict__ src, int64_t rows, int64
   out_scaled[idx] = (float)(v * sig[j]);
 }
 
-// ---- host l x l linear algebra ---------------------------------------------------
-// Cholesky G = R^T R (upper R); returns false if not positive definite.
-bool cholesky_upper(std::vector<double>& G, int l) {
-  for (int j = 0; j < l; ++j) {
-    double d = G[j * l + j];
-    for (int k = 0; k < j; ++k) d -= G[k * l + j] * G[k * l + j];
-    if (!(d > 0.0)) return false;
-    d = std::sqrt(d);
-    G[j * l + j] = d;
-    for (int i = j + 1; i < l; ++i) {
-      double v = G[j * l + i];
-      for (int k = 0; k < j; ++k) v -= G[k * l + j] * G[k * l + i];
-      G[j * l + i] = v / d;
-    }
-    for (int i = 0; i < j; ++i) G[j * l + i] = 0.0;
-  }
-  return true;
-}
-
-// inverse of an upper-triangular R (row-major)
-std::vector<double> inv_upper(const std::vector<double>& R, int l) {
-  std::vector<double> X(l * l, 0.0);
-  for (int j = 0; j < l; ++j) {
-    X[j * l + j] = 1.0 / R[j * l + j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s += R[i * l + k] * X[k * l + j];
-      X[i * l + j] = -s / R[i * l + i];
-    }
-  }
-  return X;
-}
-
-// cyclic Jacobi: G = W diag(lam) W^T
-void jacobi_eig(std::vector<double> G, int l, std::vector<double>& lam, std::vector<double>& W) {
-  W.assign(l * l, 0.0);
-  for (int i = 0; i < l; ++i) W[i * l + i] = 1.0;
-  double fro = 0.0;
-  for (double v : G) fro += v * v;
-  fro = std::sqrt(fro);
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < l; ++i)
-      for (int j = i + 1; j < l; ++j) off += G[i * l + j] * G[i * l + j];
-    if (std::sqrt(off) <= 1e-16 * fro) break;
-    for (int p = 0; p < l; ++p)
-      for (int q = p + 1; q < l; ++q) {
-        const double apq = G[p * l + q];
-        if (apq == 0.0) continue;
-        const double app = G[p * l + p], aqq = G[q * l + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < l; ++k) {
-          const double gkp = G[k * l + p], gkq = G[k * l + q];
-          G[k * l + p] = c * gkp - s * gkq;
-          G[k * l + q] = s * gkp + c * gkq;
-        }
-        for (int k = 0; k < l; ++k) {
-          const double gpk = G[p * l + k], gqk = G[q * l + k];
-          G[p * l + k] = c * gpk - s * gqk;
-          G[q * l + k] = s * gpk + c * gqk;
-        }
-        for (int k = 0; k < l; ++k) {
-          const double wkp = W[k * l + p], wkq = W[k * l + q];
-          W[k * l + p] = c * wkp - s * wkq;
-          W[k * l + q] = s * wkp + c * wkq;
-        }
-      }
-  }
-  lam.resize(l);
-  for (int i = 0; i < l; ++i) lam[i] = G[i * l + i];
-}
-
 // Orthonormalise the columns of Y (rows x l, row-major) in place into Q via
 // CholeskyQR2 (a shifted first pass guards against a numerically rank-deficient
 // sketch).  tmp: rows x l scratch.
