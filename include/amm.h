@@ -137,6 +137,16 @@ amm_status amm_ctx_create(amm_ctx** ctx, int device);
  * its stream, so a device fault is reported by the call that caused it
  * (AMM_EDEVICE).  Costs a host round trip per call. */
 amm_status amm_ctx_set_debug(amm_ctx* ctx, int enable);
+
+/* Tune cache: batch plans of this context look their tuned choice (the
+ * split target of a truncated-SVD plan, the schedule of a circulant plan) up
+ * in the text file `path`, keyed by the device's architecture and compute
+ * units and every entry's shape, rank or kept frequencies and list
+ * precision, and skip their timing runs on a hit; a miss tunes and appends
+ * one line.  NULL or "" turns it off (the default unless AMM_TUNE_CACHE is
+ * set at context creation).  A file that cannot be read or written only
+ * disables the cache.  Processes may share one file (single-line appends). */
+amm_status amm_ctx_set_tune_cache(amm_ctx* ctx, const char* path);
 void amm_ctx_destroy(amm_ctx* ctx);
 
 /* Device allocator supplied by the caller (e.g. a framework's caching
@@ -429,6 +439,8 @@ amm_status amm_batch_circulant_schedule(const amm_batch_plan* plan, int* job_tab
  * bfloat16 plan); the plan's graph is captured again.  Waits for the plan's
  * own stream; work the caller enqueued with the old schedule may still run. */
 amm_status amm_batch_circulant_set_mode(amm_batch_plan* plan, int job_table);
+/* 1 if the plan's tuned choice came from the context's tune cache. */
+amm_status amm_batch_tuned_from_cache(const amm_batch_plan* plan, int* from_cache);
 void amm_batch_plan_destroy(amm_batch_plan* plan);
 
 /* ---- backward ------------------------------------------------------------ */

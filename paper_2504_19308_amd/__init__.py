@@ -179,7 +179,10 @@ class BatchPlan:
     def info(self) -> dict:
         t, pb, ob, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
         _lib.check(_lib.load().amm_batch_info(self.handle, C.byref(t), C.byref(pb), C.byref(ob), C.byref(ms)))
-        return {"target_blocks": t.value, "panel_blocks": pb.value, "out_blocks": ob.value, "tuned_ms": ms.value}
+        fc = C.c_int()
+        _lib.check(_lib.load().amm_batch_tuned_from_cache(self.handle, C.byref(fc)))
+        return {"target_blocks": t.value, "panel_blocks": pb.value, "out_blocks": ob.value, "tuned_ms": ms.value,
+                "from_cache": bool(fc.value)}
 
     def set_circulant_mode(self, job_table: bool):
         _lib.check(_lib.load().amm_batch_circulant_set_mode(self.handle, 1 if job_table else 0))
@@ -252,6 +255,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tune_cache(self, path):
+        """Batch plans look their tuned choice up in (and add it to) this
+        text file; None turns the cache off (see amm_ctx_set_tune_cache)."""
+        _lib.check(_lib.load().amm_ctx_set_tune_cache(self.handle, None if path is None else str(path).encode()))
+        return self
 
     def set_debug(self, enable: bool = True):
         """Check argument pointers and synchronise after every call (see

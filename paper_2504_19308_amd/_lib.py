@@ -66,6 +66,8 @@ SIGNATURES = {
     "amm_ctx_destroy": (None, [C.c_void_p]),
     "amm_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "amm_ctx_set_debug": (C.c_int, [C.c_void_p, C.c_int]),
+    "amm_ctx_set_tune_cache": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "amm_batch_tuned_from_cache": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "amm_ctx_timings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                   C.POINTER(C.c_int)]),
     "amm_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_int,

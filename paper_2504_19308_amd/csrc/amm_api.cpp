@@ -422,6 +422,8 @@ amm_status amm_ctx_create_with_allocator(amm_ctx** ctx, int device, const amm_al
   {
     const char* e = std::getenv("AMM_DEBUG");
     c->debug = e && *e && std::strcmp(e, "0") != 0;
+    const char* tc = std::getenv("AMM_TUNE_CACHE");
+    if (tc) c->tune_cache = tc;
   }
   *ctx = c;
   return AMM_OK;
@@ -1438,6 +1440,77 @@ amm_status plan_launch(amm_batch_plan* bp, hipStream_t s) {
 // Autotune the reduction split policy by timing each candidate on the caller's
 // stream, then capture the two launches once on a plan-owned stream; runs
 // replay the graph.  Deletes the plan on failure.
+// ---- tune cache ----------------------------------------------------------------
+// A plan's tuned choice keyed by everything the timing depended on: the
+// device (architecture, compute units), the plan kind and every entry's
+// shape, rank or kept frequencies and list precision.  One text line per
+// entry: "AMMTUNE1 <key> <choice> <ms> <ms_entry> <ms_table>"; the last line
+// for a key wins, appends are single writes.
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t plan_key(const amm_batch_plan* bp) {
+  uint64_t h = 1469598103934665603ull;
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, bp->ctx->device) == hipSuccess) {
+    h = fnv1a(h, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+    h = fnv1a(h, &prop.multiProcessorCount, sizeof(int));
+  }
+  const int head[3] = {bp->launches ? 1 : 0, bp->bf16 ? 1 : 0, bp->k};
+  h = fnv1a(h, head, sizeof(head));
+  for (size_t i = 0; i < bp->items.size(); ++i) {
+    const auto& it = bp->items[i];
+    const int64_t dims[3] = {it.m, it.n, it.p};
+    h = fnv1a(h, dims, sizeof(dims));
+    if (bp->launches) {
+      const amm_dec* d = bp->decs[i];
+      const amm_dec* b = d->blocks.empty() ? d : d->blocks[0];
+      const int info[3] = {b->K_eff, b->lists16(false) ? 1 : 0, (int)d->blocks.size()};
+      h = fnv1a(h, info, sizeof(info));
+    }
+  }
+  return h;
+}
+
+bool tune_lookup(const std::string& path, uint64_t key, int* choice, double* ms, double* ms0, double* ms1) {
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    unsigned long long k = 0;
+    int c = 0;
+    double a = 0, b = 0, e = 0;
+    if (std::sscanf(line, "AMMTUNE1 %llx %d %lf %lf %lf", &k, &c, &a, &b, &e) == 5 && k == key) {
+      *choice = c;
+      *ms = a;
+      *ms0 = b;
+      *ms1 = e;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& path, uint64_t key, int choice, double ms, double ms0, double ms1) {
+  if (path.empty()) return;
+  char line[256];
+  const int len = std::snprintf(line, sizeof(line), "AMMTUNE1 %016llx %d %.6g %.6g %.6g\n", (unsigned long long)key,
+                                choice, ms, ms0, ms1);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;   // the cache is an optimisation: a file that cannot be written is skipped
+  (void)std::fwrite(line, 1, (size_t)len, f);
+  std::fclose(f);
+}
+
 // (Re)capture the plan's launches into its graph on its own stream.
 amm_status plan_capture(amm_batch_plan* bp) {
   if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
@@ -1466,9 +1539,30 @@ amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan)
   int best_t = 1024;
   hipEvent_t e0, e1;
   amm_status st = AMM_OK;
-  if (hipEventCreate(&e0) != hipSuccess) st = fail(AMM_EDEVICE, "event");
-  if (st == AMM_OK && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); st = fail(AMM_EDEVICE, "event"); }
-  if (st == AMM_OK && bp->launches) {
+  const uint64_t key = plan_key(bp);
+  int cached = 0;
+  double cms = 0, c0 = -1, c1 = -1;
+  const bool hit = tune_lookup(bp->ctx->tune_cache, key, &cached, &cms, &c0, &c1) &&
+                   (bp->launches ? (cached == 0 || cached == 1) && !(cached == 1 && bp->cgroups.empty()) &&
+                                       !(cached == 0 && bp->bf16)
+                                 : cached > 0);
+  if (hit) {
+    // the choice a tuning run stored for this device and these shapes
+    bp->from_cache = true;
+    if (bp->launches) {
+      bp->circ_mode = cached;
+      bp->circ_ms[0] = c0;
+      bp->circ_ms[1] = c1;
+    } else {
+      best_t = cached;
+    }
+    best = 3.0 * cms;
+  }
+  if (!hit && hipEventCreate(&e0) != hipSuccess) st = fail(AMM_EDEVICE, "event");
+  if (!hit && st == AMM_OK && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); st = fail(AMM_EDEVICE, "event"); }
+  if (hit) {
+    // nothing to time
+  } else if (st == AMM_OK && bp->launches) {
     // circulant plans: time the per-entry launches and the job-table launches
     // (a warm-up and three runs each) and keep the faster; bfloat16 plans
     // have only the job table
@@ -1505,6 +1599,9 @@ amm_status plan_finish(amm_batch_plan* bp, hipStream_t s, amm_batch_plan** plan)
   }
   if (st == AMM_OK) st = plan_build(bp, best_t);
   bp->tuned_ms = best / 3.0;
+  if (st == AMM_OK && !hit)
+    tune_store(bp->ctx->tune_cache, key, bp->launches ? bp->circ_mode : best_t, bp->tuned_ms, bp->circ_ms[0],
+               bp->circ_ms[1]);
   if (st == AMM_OK && hipStreamCreateWithFlags(&bp->own, hipStreamNonBlocking) != hipSuccess) st = fail(AMM_EDEVICE, "stream");
   if (st == AMM_OK) st = plan_capture(bp);
   if (st == AMM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(AMM_EDEVICE, "sync");
@@ -1917,6 +2014,18 @@ amm_status debug_finish(const amm_ctx* ctx, hipStream_t s, amm_status st, const 
 }  // namespace
 
 extern "C" {
+
+amm_status amm_ctx_set_tune_cache(amm_ctx* ctx, const char* path) {
+  if (!ctx) return fail(AMM_EINVAL, "NULL context");
+  ctx->tune_cache = path ? path : "";
+  return AMM_OK;
+}
+
+amm_status amm_batch_tuned_from_cache(const amm_batch_plan* plan, int* from_cache) {
+  if (!plan || !from_cache) return fail(AMM_EINVAL, "NULL argument");
+  *from_cache = plan->from_cache ? 1 : 0;
+  return AMM_OK;
+}
 
 amm_status amm_ctx_set_debug(amm_ctx* ctx, int enable) {
   if (!ctx) return fail(AMM_EINVAL, "NULL context");

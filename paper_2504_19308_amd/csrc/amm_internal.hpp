@@ -170,7 +170,8 @@ struct amm_ctx {
   amm::DevBuf gemm_part;                    // grow-only split-K partial sums
   amm::KernelTimer timer;
   bool timing = false;
-  bool debug = false;                  // check argument pointers, synchronise after every call
+  bool debug = false;
+  std::string tune_cache;              // file of tuned batch-plan choices ("" = none)                  // check argument pointers, synchronise after every call
 };
 
 struct amm_dec {
@@ -299,6 +300,7 @@ struct amm_batch_plan {
   amm::DevBuf cjobs;
   int circ_mode = 0;            // 0: every entry launched by itself; 1: the job-table launches
   double circ_ms[2] = {-1.0, -1.0};   // tuner's time of one run in each mode (-1: not timed)
+  bool from_cache = false;      // the tuned choice came from the context's tune cache
   hipStream_t own = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
