@@ -396,47 +396,6 @@ amm_status repitch_f32(const float* src, int64_t ld_src, int64_t rows, int64_t c
   return AMM_OK;
 }
 
-// ---- element type conversion ------------------------------------------------
-__device__ __forceinline__ float load_as_f32(const void* p, int dtype, int64_t i) {
-  if (dtype == AMM_BF16) return __uint_as_float((uint32_t)static_cast<const uint16_t*>(p)[i] << 16);
-  if (dtype == AMM_F16) return __half2float(static_cast<const __half*>(p)[i]);
-  return static_cast<const float*>(p)[i];
-}
-
-__device__ __forceinline__ void store_from_f32(void* p, int dtype, int64_t i, float v) {
-  if (dtype == AMM_BF16) {
-    const uint32_t b = __float_as_uint(v);
-    uint16_t h;
-    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) h = (uint16_t)((b >> 16) | 0x40u);   // NaN stays NaN
-    else h = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);                                      // nearest even
-    static_cast<uint16_t*>(p)[i] = h;
-  } else if (dtype == AMM_F16) {
-    static_cast<__half*>(p)[i] = __float2half_rn(v);
-  } else {
-    static_cast<float*>(p)[i] = v;
-  }
-}
-
-__global__ void cast_matrix_kernel(const void* __restrict__ src, int sdt, int64_t sld, int64_t rows, int64_t cols,
-                                   void* __restrict__ dst, int ddt, int64_t dld) {
-  // blockIdx.y strides over rows, threads over the columns of a row
-  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x)
-      store_from_f32(dst, ddt, r * dld + c, load_as_f32(src, sdt, r * sld + c));
-}
-
-amm_status cast_matrix(const void* src, int src_dtype, int64_t src_ld, int64_t rows, int64_t cols, void* dst,
-                       int dst_dtype, int64_t dst_ld, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return AMM_OK;
-  TimedLaunch tl("cast_matrix", s);
-  const unsigned gx = (unsigned)std::min<int64_t>((cols + 255) / 256, 64);
-  const unsigned gy = (unsigned)std::min<int64_t>(rows, 8192);
-  hipLaunchKernelGGL(cast_matrix_kernel, dim3(gx, gy), dim3(256), 0, s, src, src_dtype, src_ld, rows, cols, dst,
-                     dst_dtype, dst_ld);
-  AMM_HIP(hipGetLastError());
-  return AMM_OK;
-}
-
 amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   if (count <= 0) return AMM_OK;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
