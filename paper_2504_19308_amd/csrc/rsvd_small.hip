@@ -12,7 +12,9 @@
 // Both hold their l x l matrices in LDS (l <= kSmallEigMax: two 96 x 97
 // float64 arrays at an odd row pitch, 146 KiB of the 160 KiB a workgroup may
 // use).  A larger sketch keeps the host path.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "amm_internal.hpp"
 
@@ -308,6 +310,136 @@ __global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__
     for (int i = g; i < l; i += ng) Wout[i * l + c] = W[i * ld + c];
 }
 
+// ---- sketches above 96 columns ---------------------------------------------------
+// G (l x l, pitch ld) + shift on the diagonal, shift = 11 (rows l + l (l + 1))
+// u tr(G): the first CholeskyQR pass's, as in the one-workgroup form.  One
+// workgroup.
+__global__ void __launch_bounds__(NT) add_shift_kernel(double* __restrict__ G, int l, int64_t ld, int64_t rows) {
+  __shared__ double red[4];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += NT) tr += G[i * ld + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * tr;
+  for (int i = threadIdx.x; i < l; i += NT) G[i * ld + i] += shift;
+}
+
+// Cholesky factor of the b x b diagonal block at G (pitch ldg, b <= 64):
+// R_jj (upper) into R (pitch ldr), R_jj^-T (lower) into E (pitch b).  A
+// non-positive pivot sets *status.
+constexpr int kCholBlock = 64;
+__global__ void __launch_bounds__(NT) chol_block_kernel(const double* __restrict__ G, int64_t ldg, int b,
+                                                        double* __restrict__ R, int64_t ldr, double* __restrict__ E,
+                                                        int* __restrict__ status) {
+  __shared__ double S[kCholBlock * (kCholBlock + 1)];
+  __shared__ double X[kCholBlock * (kCholBlock + 1)];
+  const int tid = threadIdx.x, ld = pitch_of(b);
+  const int ng = NT / b, g = tid / b, c = tid % b;
+  if (g < ng)
+    for (int i = g; i < b; i += ng) S[i * ld + c] = 0.5 * (G[i * ldg + c] + G[c * ldg + i]);
+  const bool ok = cholesky_inv_lds(S, X, b, ld);
+  if (!ok) {
+    if (tid == 0) *status = 1;
+    if (g < ng)
+      for (int i = g; i < b; i += ng) {
+        R[i * ldr + c] = (i == c) ? 1.0 : 0.0;
+        E[i * b + c] = (i == c) ? 1.0 : 0.0;
+      }
+    return;
+  }
+  if (g < ng)
+    for (int i = g; i < b; i += ng) {
+      R[i * ldr + c] = (c >= i) ? S[i * ld + c] : 0.0;
+      E[i * b + c] = (c <= i) ? X[i * ld + c] : 0.0;
+    }
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ p, int64_t count, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void identity_f64_kernel(double* __restrict__ p, int l) {
+  const int64_t n = (int64_t)l * l;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (i / l == i % l) ? 1.0 : 0.0;
+}
+
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[3 * (threadIdx.x >> 6)] = a;
+    red[3 * (threadIdx.x >> 6) + 1] = b;
+    red[3 * (threadIdx.x >> 6) + 2] = c;
+  }
+  __syncthreads();
+  a = red[0] + red[3] + red[6] + red[9];
+  b = red[1] + red[4] + red[7] + red[10];
+  c = red[2] + red[5] + red[8] + red[11];
+}
+
+// One round of one-sided (Hestenes) Jacobi on the columns of the symmetric
+// positive semi-definite M (l x l; column j contiguous at M + j l): the
+// workgroup of pair i rotates columns p, q of M and of V so that they become
+// orthogonal, unless they already are to the rounding of their dot product
+// (|m_p . m_q| <= tol ||m_p|| ||m_q||, tol = l u); any rotation sets *rotated.  At convergence
+// M = G V with orthogonal columns: V holds the eigenvectors of G and the
+// column norms of M its eigenvalues.
+__global__ void __launch_bounds__(NT) ojac_round_kernel(double* __restrict__ M, double* __restrict__ V, int l, int r,
+                                                        int np, double tol, int* __restrict__ rotated) {
+  __shared__ double red[12];
+  int p = seat(blockIdx.x, r, np), q = seat(np - 1 - blockIdx.x, r, np);
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+  if (q >= l) return;   // the dummy player of an odd l (uniform over the block)
+  double* mp = M + (int64_t)p * l;
+  double* mq = M + (int64_t)q * l;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < l; k += NT) {
+    const double x = mp[k], y = mq[k];
+    a += x * x;
+    b += y * y;
+    c += x * y;
+  }
+  block_sum3(a, b, c, red);
+  if (!(fabs(c) > tol * sqrt(a * b))) return;   // orthogonal to rounding (or not a number)
+  const double zeta = (b - a) / (2.0 * c);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  double* vp = V + (int64_t)p * l;
+  double* vq = V + (int64_t)q * l;
+  for (int k = threadIdx.x; k < l; k += NT) {
+    const double x = mp[k], y = mq[k];
+    mp[k] = cs * x - sn * y;
+    mq[k] = sn * x + cs * y;
+    const double u = vp[k], w = vq[k];
+    vp[k] = cs * u - sn * w;
+    vq[k] = sn * u + cs * w;
+  }
+  if (threadIdx.x == 0) atomicOr(rotated, 1);
+}
+
+// lam[j] = || column j of M || (one workgroup per column)
+__global__ void __launch_bounds__(NT) col_norms_kernel(const double* __restrict__ M, int l, double* __restrict__ lam) {
+  __shared__ double red[4];
+  const double* m = M + (int64_t)blockIdx.x * l;
+  double a = 0.0;
+  for (int k = threadIdx.x; k < l; k += NT) a += m[k] * m[k];
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) lam[blockIdx.x] = sqrt(a);
+}
+
+__global__ void set_flag_kernel(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
 }  // namespace
 
 amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, double* rinv, int* status,
@@ -325,6 +457,92 @@ amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, 
   TimedLaunch tl("rsvd_eig", s);
   hipLaunchKernelGGL(gram_eig_kernel, dim3(1), dim3(NT), 0, s, gram, l, k, W, perm, isg, sgk, sigma_f, sig_sorted);
   AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+
+// ---- sketches above 96 columns: blocked CholeskyQR, one-sided Jacobi ------------
+
+int chol_blocks(int l) { return (l + kCholBlock - 1) / kCholBlock; }
+
+// Upper Cholesky factor R of G (+ the shift when `shift`; G l x l, overwritten
+// by the trailing updates) in blocks of 64.  The passes after a shifted one
+// factor a basis whose condition the shift has bounded, so they run unshifted
+// (a non-positive pivot there sets *status, which the caller reports).  Blocks: each diagonal block in one workgroup (R_jj and
+// R_jj^-T into E, 64 x 64 per block), the block row of R beside it by one
+// GEMM with R_jj^-T, the trailing matrix by one more.
+amm_status chol_qr_blocked(double* G, int l, int64_t rows, bool shift, double* R, double* E, int* status,
+                           hipStream_t s) {
+  const int nb = chol_blocks(l);
+  if (shift) hipLaunchKernelGGL(add_shift_kernel, dim3(1), dim3(NT), 0, s, G, l, (int64_t)l, rows);
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)l * l + 255) / 256, 4096)), dim3(256),
+                     0, s, R, (int64_t)l * l, 0.0);
+  AMM_HIP(hipGetLastError());
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * kCholBlock, b = std::min(kCholBlock, l - j0), j1 = j0 + b;
+    double* Ej = E + (size_t)jb * kCholBlock * kCholBlock;
+    {
+      TimedLaunch tl("rsvd_chol", s);
+      hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(NT), 0, s, G + (int64_t)j0 * l + j0, (int64_t)l, b,
+                         R + (int64_t)j0 * l + j0, (int64_t)l, Ej, status);
+      AMM_HIP(hipGetLastError());
+    }
+    if (j1 < l) {
+      const int w = l - j1;
+      // R[j0:j1, j1:l] = R_jj^-T G[j0:j1, j1:l]
+      AMM_TRY(gemm_f64(b, w, b, 1.0, Ej, b, 1, G + (int64_t)j0 * l + j1, l, 1, 0.0, R + (int64_t)j0 * l + j1, l, s));
+      // G[j1:l, j1:l] -= R[j0:j1, j1:l]^T R[j0:j1, j1:l]
+      AMM_TRY(gemm_f64(w, w, b, -1.0, R + (int64_t)j0 * l + j1, 1, l, R + (int64_t)j0 * l + j1, l, 1, 1.0,
+                       G + (int64_t)j1 * l + j1, l, s));
+    }
+  }
+  return AMM_OK;
+}
+
+// Q = Y R^-1 by block columns: Q_j = Y_j X_jj - Q_{<j} (R_{<j, j} X_jj), X_jj =
+// R_jj^-1 = (R_jj^-T)^T.  P: scratch of l x 64.
+amm_status chol_qr_apply(const double* Y, int64_t rows, int l, const double* R, const double* E, double* Q, double* P,
+                         hipStream_t s) {
+  const int nb = chol_blocks(l);
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * kCholBlock, b = std::min(kCholBlock, l - j0);
+    const double* Ej = E + (size_t)jb * kCholBlock * kCholBlock;   // X_jj(i, k) = Ej[k b + i]
+    AMM_TRY(gemm_f64(rows, b, b, 1.0, Y + j0, l, 1, Ej, 1, b, 0.0, Q + j0, l, s));
+    if (j0 > 0) {
+      AMM_TRY(gemm_f64(j0, b, b, 1.0, R + j0, l, 1, Ej, 1, b, 0.0, P, b, s));
+      AMM_TRY(gemm_f64(rows, b, j0, -1.0, Q, l, 1, P, b, 1, 1.0, Q + j0, l, s));
+    }
+  }
+  return AMM_OK;
+}
+
+// Eigen-decomposition of the symmetric positive semi-definite G (l x l,
+// overwritten) by one-sided Jacobi sweeps (round-robin pairs, one launch per
+// round) until a sweep rotates nothing (at most 40): V (l x l) receives the
+// eigenvectors as contiguous columns, lam_host the eigenvalues (unsorted).
+amm_status gram_eig_large(double* G, int l, double* V, double* lam, int* flag, std::vector<double>& lam_host,
+                          int* sweeps_out, hipStream_t s) {
+  const int np = l + (l & 1);
+  hipLaunchKernelGGL(identity_f64_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)l * l + 255) / 256, 4096)),
+                     dim3(256), 0, s, V, l);
+  AMM_HIP(hipGetLastError());
+  const double tol = std::max(1e-15, l * 1.1102230246251565e-16);
+  int sweep = 0, h = 1;
+  TimedLaunch tl("rsvd_eig", s);
+  for (; sweep < 40 && h; ++sweep) {
+    hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, flag);
+    for (int r = 0; r < np - 1; ++r)
+      hipLaunchKernelGGL(ojac_round_kernel, dim3((unsigned)(np / 2)), dim3(NT), 0, s, G, V, l, r, np, tol, flag);
+    AMM_HIP(hipGetLastError());
+    AMM_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMM_HIP(hipStreamSynchronize(s));
+  }
+  hipLaunchKernelGGL(col_norms_kernel, dim3((unsigned)l), dim3(NT), 0, s, G, l, lam);
+  AMM_HIP(hipGetLastError());
+  lam_host.resize(l);
+  AMM_HIP(hipMemcpyAsync(lam_host.data(), lam, l * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  if (sweeps_out) *sweeps_out = sweep;
   return AMM_OK;
 }
 

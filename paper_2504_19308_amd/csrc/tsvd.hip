@@ -321,12 +321,27 @@ amm_status tsvd_decompose_host(amm_ctx* ctx, const float* A, int64_t m, int64_t 
 // Orthonormalise the columns of *cur (rows x l) through `passes` CholeskyQR
 // passes on the device (the first shifted); each pass writes Q = Y R^-1 into
 // the other buffer and swaps the two.
+// Work of the l x l steps: rinv (l x l) for sketches up to 96 columns; R
+// (l x l), the inverse diagonal blocks E and a panel P for larger ones.
+struct SmallWork {
+  double* rinv;
+  double* R;
+  double* E;
+  double* P;
+  int* status;
+};
+
 amm_status orthonormalise_dev(double** cur, double** alt, int64_t rows, int l, int passes, double* gram,
-                              double* rinv, int* status, hipStream_t s) {
+                              const SmallWork& w, hipStream_t s) {
   for (int pass = 0; pass < passes; ++pass) {
     AMM_TRY(gemm_f64(l, l, rows, 1.0, *cur, 1, l, *cur, l, 1, 0.0, gram, l, s));
-    AMM_TRY(chol_qr_factor(gram, l, rows, pass == 0 ? 0 : 1, rinv, status, s));
-    AMM_TRY(gemm_f64(rows, l, l, 1.0, *cur, l, 1, rinv, l, 1, 0.0, *alt, l, s));
+    if (l <= kSmallEigMax) {
+      AMM_TRY(chol_qr_factor(gram, l, rows, pass == 0 ? 0 : 1, w.rinv, w.status, s));
+      AMM_TRY(gemm_f64(rows, l, l, 1.0, *cur, l, 1, w.rinv, l, 1, 0.0, *alt, l, s));
+    } else {
+      AMM_TRY(chol_qr_blocked(gram, l, rows, pass == 0, w.R, w.E, w.status, s));
+      AMM_TRY(chol_qr_apply(*cur, rows, l, w.R, w.E, *alt, w.P, s));
+    }
     std::swap(*cur, *alt);
   }
   return AMM_OK;
@@ -336,15 +351,16 @@ __global__ void set_i32(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-// The decomposition with every step on the device (l <= kSmallEigMax) and a
-// single read-back of the singular values, the norm partial sums and the
-// breakdown flag at the end.
+// The decomposition with every step on the device and, for sketches up to 96
+// columns, a single read-back of the singular values, the norm partial sums
+// and the breakdown flag at the end (larger sketches read the flag of each
+// Jacobi sweep and the eigenvalues, which they sort on the host).
 amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k, int l, int q,
                                  const amm_opts* o, amm_dec* dec, hipStream_t s) {
   const int64_t mn = std::min(m, n);
   DevBuf* ws = ctx->rsvd;
   DevBuf &A64 = ws[0], &Om = ws[1], &Y = ws[2], &Z = ws[3], &Y2 = ws[4], &gram = ws[5], &Bs = ws[6];
-  DevBuf &Wd = ws[7], &Uf = ws[8], &Vf = ws[9], &Z2 = ws[10], &small = ws[11];
+  DevBuf &Wd = ws[7], &Uf = ws[8], &Vf = ws[9], &Z2 = ws[10], &small = ws[11], &big = ws[12];
   constexpr int kParts = 1024;
   AMM_TRY(A64.reserve(m * n * sizeof(double)));
   AMM_TRY(Om.reserve(n * l * sizeof(double)));
@@ -367,6 +383,17 @@ amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_
   double* rinv = sgk + l;
   int32_t* perm = reinterpret_cast<int32_t*>(rinv + (size_t)l * l);
   int* status = perm + l;
+  SmallWork w{rinv, nullptr, nullptr, nullptr, status};
+  const bool large = l > kSmallEigMax;
+  if (large) {
+    // R (l x l), E (64 x 64 per diagonal block), P (l x 64), the sweep flag
+    const size_t nr = (size_t)l * l, ne = (size_t)chol_blocks(l) * 64 * 64, npn = (size_t)l * 64;
+    AMM_TRY(big.reserve((nr + ne + npn) * sizeof(double) + 16));
+    w.R = big.as<double>();
+    w.E = w.R + nr;
+    w.P = w.E + ne;
+  }
+  int* flag = large ? reinterpret_cast<int*>(w.P + (size_t)l * 64) : nullptr;
   hipLaunchKernelGGL(set_i32, dim3(1), dim3(64), 0, s, status, 0);
   // ||A||_F partial sums (read with the results)
   const int blocks = (int)std::min<int64_t>(kParts, (m * n + 255) / 256);
@@ -380,21 +407,51 @@ amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_
   double *y = Y.as<double>(), *y2 = Y2.as<double>(), *z = Z.as<double>(), *z2 = Z2.as<double>();
   // Y = A Omega
   AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, Om.as<double>(), l, 1, 0.0, y, l, s));
-  AMM_TRY(orthonormalise_dev(&y, &y2, m, l, q > 0 ? 1 : 3, gram.as<double>(), rinv, status, s));
+  AMM_TRY(orthonormalise_dev(&y, &y2, m, l, q > 0 ? 1 : 3, gram.as<double>(), w, s));
   for (int it = 0; it < q; ++it) {
     // Z = A^T Q, orthonormalise; Y = A Z, orthonormalise (three passes for the final basis)
     AMM_TRY(gemm_f64(n, l, m, 1.0, Ad, 1, n, y, l, 1, 0.0, z, l, s));
-    AMM_TRY(orthonormalise_dev(&z, &z2, n, l, 1, gram.as<double>(), rinv, status, s));
+    AMM_TRY(orthonormalise_dev(&z, &z2, n, l, 1, gram.as<double>(), w, s));
     AMM_TRY(gemm_f64(m, l, n, 1.0, Ad, n, 1, z, l, 1, 0.0, y, l, s));
-    AMM_TRY(orthonormalise_dev(&y, &y2, m, l, it + 1 == q ? 3 : 1, gram.as<double>(), rinv, status, s));
+    AMM_TRY(orthonormalise_dev(&y, &y2, m, l, it + 1 == q ? 3 : 1, gram.as<double>(), w, s));
   }
   // Bs = Q^T A (l x n); its Gram matrix Bs Bs^T = W diag(lam) W^T
   AMM_TRY(gemm_f64(l, n, m, 1.0, y, 1, l, Ad, n, 1, 0.0, Bs.as<double>(), n, s));
   AMM_TRY(gemm_f64(l, l, n, 1.0, Bs.as<double>(), n, 1, Bs.as<double>(), 1, n, 0.0, gram.as<double>(), l, s));
-  AMM_TRY(gram_eig(gram.as<double>(), l, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted, s));
+  // W element (i, j) = component i of eigenvector j: row-major from the one-workgroup solver,
+  // contiguous eigenvectors (column-major) from the one-sided Jacobi
+  int64_t w_rs = l, w_cs = 1;
+  if (!large) {
+    AMM_TRY(gram_eig(gram.as<double>(), l, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted, s));
+  } else {
+    std::vector<double> lam;
+    AMM_TRY(gram_eig_large(gram.as<double>(), l, Wd.as<double>(), rinv, flag, lam, nullptr, s));
+    // descending order (ties by index), sigma = sqrt(lam), 1/sigma, the leading k
+    std::vector<int32_t> order(l);
+    for (int i = 0; i < l; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] > lam[b]; });
+    std::vector<double> ss(l), inv(l), sk(std::max(k, 1));
+    std::vector<float> sf(std::max(k, 1));
+    for (int j = 0; j < l; ++j) ss[j] = std::sqrt(std::max(lam[order[j]], 0.0));
+    for (int i = 0; i < l; ++i) {
+      const double sg = std::sqrt(std::max(lam[i], 0.0));
+      inv[i] = sg > 0.0 ? 1.0 / sg : 0.0;
+    }
+    for (int j = 0; j < k; ++j) {
+      sk[j] = ss[j];
+      sf[j] = (float)ss[j];
+    }
+    AMM_HIP(hipMemcpyAsync(perm, order.data(), l * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    AMM_HIP(hipMemcpyAsync(isg, inv.data(), l * sizeof(double), hipMemcpyHostToDevice, s));
+    AMM_HIP(hipMemcpyAsync(sgk, sk.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    AMM_HIP(hipMemcpyAsync(sig_sorted, ss.data(), l * sizeof(double), hipMemcpyHostToDevice, s));
+    AMM_HIP(hipMemcpyAsync(dec->sigma.ptr, sf.data(), k * sizeof(float), hipMemcpyHostToDevice, s));
+    w_rs = 1;
+    w_cs = l;
+  }
   // U_full = Q W (m x l), V_full = Bs^T W diag(1/sig) (n x l); the leading k columns in descending order
-  AMM_TRY(gemm_f64(m, l, l, 1.0, y, l, 1, Wd.as<double>(), l, 1, 0.0, Uf.as<double>(), l, s));
-  AMM_TRY(gemm_f64(n, l, l, 1.0, Bs.as<double>(), 1, n, Wd.as<double>(), l, 1, 0.0, Vf.as<double>(), l, s));
+  AMM_TRY(gemm_f64(m, l, l, 1.0, y, l, 1, Wd.as<double>(), w_rs, w_cs, 0.0, Uf.as<double>(), l, s));
+  AMM_TRY(gemm_f64(n, l, l, 1.0, Bs.as<double>(), 1, n, Wd.as<double>(), w_rs, w_cs, 0.0, Vf.as<double>(), l, s));
   hipLaunchKernelGGL(pick_columns, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s, Uf.as<double>(), m,
                      (int64_t)l, perm, (const double*)nullptr, k, dec->U.as<float>(), dec->US.as<float>(), sgk);
   hipLaunchKernelGGL(pick_columns, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, Vf.as<double>(), n,
@@ -432,12 +489,15 @@ amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_
 
 }  // namespace
 
+constexpr int kLargeSketchMax = 2048;
+
 amm_status tsvd_decompose(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int k, const amm_opts* o, amm_dec* dec,
                           hipStream_t s) {
   const int64_t mn = std::min(m, n);
   const int l = (int)std::min<int64_t>(mn, (int64_t)k + std::max(o->oversample, 0));
   const int q = std::max(o->power_iters, 0);
-  if (k == 0 || l > kSmallEigMax) return tsvd_decompose_host(ctx, A, m, n, k, o, dec, s);
+  // the host path remains for k = 0 (nothing to keep) and sketches beyond kLargeSketchMax
+  if (k == 0 || l > kLargeSketchMax) return tsvd_decompose_host(ctx, A, m, n, k, o, dec, s);
   dec->K_eff = k;
   const int64_t kk = std::max(k, 1);
   AMM_TRY(dec->U.alloc(m * kk * 4));
