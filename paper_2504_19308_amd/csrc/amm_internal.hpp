@@ -470,14 +470,15 @@ amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, dou
 amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, double* isg, double* sgk,
                     float* sigma_f, double* sig_sorted, hipStream_t s);
 // larger sketches: blocked CholeskyQR (E: chol_blocks(l) blocks of 64 x 64,
-// P: l x 64) and one-sided Jacobi (one launch per round)
+// P: l x 64) and block one-sided Jacobi on the Cholesky factor (one launch
+// per round of block pairs)
 int chol_blocks(int l);
 amm_status chol_qr_blocked(double* G, int l, int64_t rows, bool shift, double* R, double* E, int* status,
-                           hipStream_t s);
+                           hipStream_t s, double* shift_out = nullptr);
 amm_status chol_qr_apply(const double* Y, int64_t rows, int l, const double* R, const double* E, double* Q, double* P,
                          hipStream_t s);
-amm_status gram_eig_large(double* G, int l, double* V, double* lam, int* flag, std::vector<double>& lam_host,
-                          int* sweeps_out, hipStream_t s);
+amm_status gram_eig_large(double* G, int l, int64_t rows, double* R, double* E, double* W, double* dev, int* flag,
+                          int* status, std::vector<double>& lam_host, int* sweeps_out, hipStream_t s);
 // ||x - y||_F^2 and ||x||_F^2 of count floats, float64 (synchronises s)
 amm_status diff_sumsq_f32(const float* x, const float* y, int64_t count, hipStream_t s, double* dd, double* xx);
 amm_status transpose_f32(const float* src, int64_t rows, int64_t cols, float* dst, hipStream_t s);

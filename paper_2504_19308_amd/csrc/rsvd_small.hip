@@ -314,13 +314,15 @@ __global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__
 // G (l x l, pitch ld) + shift on the diagonal, shift = 11 (rows l + l (l + 1))
 // u tr(G): the first CholeskyQR pass's, as in the one-workgroup form.  One
 // workgroup.
-__global__ void __launch_bounds__(NT) add_shift_kernel(double* __restrict__ G, int l, int64_t ld, int64_t rows) {
+__global__ void __launch_bounds__(NT) add_shift_kernel(double* __restrict__ G, int l, int64_t ld, int64_t rows,
+                                                       double* __restrict__ shift_out) {
   __shared__ double red[4];
   double tr = 0.0;
   for (int i = threadIdx.x; i < l; i += NT) tr += G[i * ld + i];
   tr = block_sum(tr, red);
   const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * tr;
   for (int i = threadIdx.x; i < l; i += NT) G[i * ld + i] += shift;
+  if (shift_out && threadIdx.x == 0) *shift_out = shift;
 }
 
 // Cholesky factor of the b x b diagonal block at G (pitch ldg, b <= 64):
@@ -358,82 +360,191 @@ __global__ void fill_f64_kernel(double* __restrict__ p, int64_t count, double v)
     p[i] = v;
 }
 
-__global__ void identity_f64_kernel(double* __restrict__ p, int l) {
-  const int64_t n = (int64_t)l * l;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = (i / l == i % l) ? 1.0 : 0.0;
-}
-
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
-    c += __shfl_xor(c, off, 64);
+// One round of block one-sided (Hestenes) Jacobi on the columns of M (l x l;
+// column j contiguous at M + j l).  The columns form blocks of BS; the
+// workgroup of block pair (P, Q) of round r stages their (up to) 2 BS columns
+// in LDS (dynamic, 2 BS (l | 1) doubles: one batch of loads), forms their
+// Gram matrix H = M_c^T M_c, runs one cyclic two-sided Jacobi sweep on H
+// (rotating a pair unless |h_pq| <= tol sqrt(h_pp h_qq)) while accumulating
+// the rotations in J, and writes M_c J back.  Any rotation sets *rotated.
+// Repeated sweeps until none rotates leave every column pair orthogonal to
+// tol: M V with V orthogonal and never formed.  Slots past column l stay zero
+// and are never rotated.
+template <int BS>
+__global__ void __launch_bounds__(NT) bjac_round_kernel(double* __restrict__ M, int l, int nb, int r, int npb,
+                                                        double tol, int* __restrict__ rotated) {
+  constexpr int W = 2 * BS;   // slots; W * W <= NT
+  static_assert(W * W <= NT && W % 4 == 0, "block shape");
+  extern __shared__ double X[];   // W x lp: slot a's column at X + a lp
+  __shared__ double H[W * (W + 1)], J[W * (W + 1)];
+  __shared__ int col[W];
+  __shared__ int total_rot;
+  int P = seat(blockIdx.x, r, npb), Q = seat(npb - 1 - blockIdx.x, r, npb);
+  if (P >= nb || Q >= nb) return;   // the dummy block of an odd count (uniform over the workgroup)
+  const int tid = threadIdx.x, lp = l | 1;   // odd pitch: the W slots of one row fall in distinct banks
+  if (tid < W) {
+    const int c = (tid < BS ? P * BS + tid : Q * BS + tid - BS);
+    col[tid] = c < l ? c : -1;
+  }
+  if (tid == 0) total_rot = 0;
+  __syncthreads();
+  // Each block's columns are one contiguous range of M: eight loads in flight
+  // per thread per batch, then their LDS stores; the slots of a partial
+  // block's missing columns are zero.
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int blk = h == 0 ? P : Q, wb = min(BS, l - blk * BS);
+    const double* src = M + (int64_t)blk * BS * l;
+    const int count = wb * l;
+    for (int base = 0; base < count; base += 8 * NT) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + tid + u * NT;
+        v[u] = idx < count ? src[idx] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + tid + u * NT;
+        if (idx < count) {
+          const int sl = idx / l, k = idx - sl * l;
+          X[(h * BS + sl) * lp + k] = v[u];
+        }
+      }
+    }
+    for (int idx = count + tid; idx < BS * l; idx += NT) {
+      const int sl = idx / l, k = idx - sl * l;
+      X[(h * BS + sl) * lp + k] = 0.0;
+    }
   }
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[3 * (threadIdx.x >> 6)] = a;
-    red[3 * (threadIdx.x >> 6) + 1] = b;
-    red[3 * (threadIdx.x >> 6) + 2] = c;
+  // H = M_c^T M_c in 4 x 4 tiles: thread (tile, split) sums rows split,
+  // split + S, ... of its tile (the S splits of a tile are adjacent lanes,
+  // reduced by shuffles)
+  {
+    constexpr int TI = W / 4, S = NT / (TI * TI);
+    static_assert(S <= 64 && (S & (S - 1)) == 0, "tile split");
+    const int tile = tid / S, sp = tid % S, ti = tile / TI, tj = tile % TI;
+    double acc[4][4] = {};
+    for (int k = sp; k < l; k += S) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = X[(4 * ti + u) * lp + k];
+        b[u] = X[(4 * tj + u) * lp + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int off = 1; off < S; off <<= 1)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += __shfl_xor(acc[u][v], off, 64);
+    if (sp == 0)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int hi = 4 * ti + u, hj = 4 * tj + v;
+          H[hi * (W + 1) + hj] = acc[u][v];
+          J[hi * (W + 1) + hj] = (hi == hj) ? 1.0 : 0.0;
+        }
+  }
+  // One cyclic Jacobi sweep on H, rotations accumulated in J (new column p =
+  // c x_p - s x_q, new column q = s x_p + c x_q; H <- J_r^T H J_r, J <- J
+  // J_r).  Thread (i, j) computes the rotations of the pairs holding i and j
+  // itself (bitwise the same as every other thread that computes them), so
+  // a round needs only the barriers around its stores.  One sweep per visit:
+  // the outer sweeps converge in about as many visits as with a fully
+  // diagonalised H, at a fraction of the inner rounds.
+  const int i = tid / W, j = tid % W;
+  const bool el = tid < W * W;
+  for (int rr = 0; rr < W - 1; ++rr) {
+    __syncthreads();
+    double hn = 0.0, jn = 0.0;
+    if (el) {
+      double cs2[2], cp2[2];
+      int pt2[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int x = e == 0 ? i : j;
+        // position of slot x in the round-robin seating of round rr, its partner's slot
+        const int pos = x == 0 ? 0 : (x - 1 - rr + 2 * (W - 1)) % (W - 1) + 1;
+        const int y = seat(W - 1 - pos, rr, W);
+        const int p = min(x, y), q = max(x, y);
+        const double hpp = H[p * (W + 1) + p], hqq = H[q * (W + 1) + q], hpq = H[p * (W + 1) + q];
+        double cc = 1.0, ss = 0.0;
+        if (fabs(hpq) > tol * sqrt(hpp * hqq)) {
+          const double zeta = (hqq - hpp) / (2.0 * hpq);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          cc = 1.0 / sqrt(1.0 + t * t);
+          ss = cc * t;
+          total_rot = 1;
+        }
+        cs2[e] = cc;
+        cp2[e] = x == p ? -ss : ss;
+        pt2[e] = y;
+      }
+      const int pi = pt2[0], pj = pt2[1];
+      const double si = cs2[0], ti = cp2[0], sj = cs2[1], tj = cp2[1];
+      hn = si * (sj * H[i * (W + 1) + j] + tj * H[i * (W + 1) + pj]) +
+           ti * (sj * H[pi * (W + 1) + j] + tj * H[pi * (W + 1) + pj]);
+      jn = sj * J[i * (W + 1) + j] + tj * J[i * (W + 1) + pj];
+    }
+    __syncthreads();
+    if (el) {
+      H[i * (W + 1) + j] = hn;
+      J[i * (W + 1) + j] = jn;
+    }
   }
   __syncthreads();
-  a = red[0] + red[3] + red[6] + red[9];
-  b = red[1] + red[4] + red[7] + red[10];
-  c = red[2] + red[5] + red[8] + red[11];
+  if (!total_rot) return;   // read after the last barrier: uniform
+  if (tid == 0) atomicOr(rotated, 1);
+  // M_c <- M_c J from the staged copy: thread (group of 4 output columns,
+  // row), NT / (W / 4) consecutive rows per pass; each staged value feeds 4
+  // outputs
+  constexpr int G4 = W / 4, RP = NT / G4;
+  const int bg = tid / RP, rsub = tid % RP;
+  double jc[W][4];
+#pragma unroll
+  for (int a = 0; a < W; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) jc[a][v] = J[a * (W + 1) + 4 * bg + v];
+  int cb[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) cb[v] = col[4 * bg + v];
+  for (int k = rsub; k < l; k += RP) {
+    double y[4] = {};
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const double x = X[a * lp + k];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) y[v] += x * jc[a][v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (cb[v] >= 0) M[(int64_t)cb[v] * l + k] = y[v];
+  }
 }
 
-// One round of one-sided (Hestenes) Jacobi on the columns of the symmetric
-// positive semi-definite M (l x l; column j contiguous at M + j l): the
-// workgroup of pair i rotates columns p, q of M and of V so that they become
-// orthogonal, unless they already are to the rounding of their dot product
-// (|m_p . m_q| <= tol ||m_p|| ||m_q||, tol = l u); any rotation sets *rotated.  At convergence
-// M = G V with orthogonal columns: V holds the eigenvectors of G and the
-// column norms of M its eigenvalues.
-__global__ void __launch_bounds__(NT) ojac_round_kernel(double* __restrict__ M, double* __restrict__ V, int l, int r,
-                                                        int np, double tol, int* __restrict__ rotated) {
-  __shared__ double red[12];
-  int p = seat(blockIdx.x, r, np), q = seat(np - 1 - blockIdx.x, r, np);
-  if (p > q) {
-    const int t = p;
-    p = q;
-    q = t;
-  }
-  if (q >= l) return;   // the dummy player of an odd l (uniform over the block)
-  double* mp = M + (int64_t)p * l;
-  double* mq = M + (int64_t)q * l;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < l; k += NT) {
-    const double x = mp[k], y = mq[k];
-    a += x * x;
-    b += y * y;
-    c += x * y;
-  }
-  block_sum3(a, b, c, red);
-  if (!(fabs(c) > tol * sqrt(a * b))) return;   // orthogonal to rounding (or not a number)
-  const double zeta = (b - a) / (2.0 * c);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-  double* vp = V + (int64_t)p * l;
-  double* vq = V + (int64_t)q * l;
-  for (int k = threadIdx.x; k < l; k += NT) {
-    const double x = mp[k], y = mq[k];
-    mp[k] = cs * x - sn * y;
-    mq[k] = sn * x + cs * y;
-    const double u = vp[k], w = vq[k];
-    vp[k] = cs * u - sn * w;
-    vq[k] = sn * u + cs * w;
-  }
-  if (threadIdx.x == 0) atomicOr(rotated, 1);
-}
-
-// lam[j] = || column j of M || (one workgroup per column)
-__global__ void __launch_bounds__(NT) col_norms_kernel(const double* __restrict__ M, int l, double* __restrict__ lam) {
+// Column j of M (l x l, contiguous columns) = sigma_j u_j with sigma_j^2 the
+// eigenvalue of G + shift: lam[j] = max(||m_j||^2 - shift, 0) and column j of
+// W = m_j / ||m_j|| (one workgroup per column).
+__global__ void __launch_bounds__(NT) eig_finish_kernel(const double* __restrict__ M, int l,
+                                                        const double* __restrict__ shift, double* __restrict__ W,
+                                                        double* __restrict__ lam) {
   __shared__ double red[4];
   const double* m = M + (int64_t)blockIdx.x * l;
   double a = 0.0;
   for (int k = threadIdx.x; k < l; k += NT) a += m[k] * m[k];
   a = block_sum(a, red);
-  if (threadIdx.x == 0) lam[blockIdx.x] = sqrt(a);
+  const double inv = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+  for (int k = threadIdx.x; k < l; k += NT) W[(int64_t)blockIdx.x * l + k] = m[k] * inv;
+  if (threadIdx.x == 0) lam[blockIdx.x] = fmax(a - *shift, 0.0);
 }
 
 __global__ void set_flag_kernel(int* p) {
@@ -472,9 +583,9 @@ int chol_blocks(int l) { return (l + kCholBlock - 1) / kCholBlock; }
 // R_jj^-T into E, 64 x 64 per block), the block row of R beside it by one
 // GEMM with R_jj^-T, the trailing matrix by one more.
 amm_status chol_qr_blocked(double* G, int l, int64_t rows, bool shift, double* R, double* E, int* status,
-                           hipStream_t s) {
+                           hipStream_t s, double* shift_out) {
   const int nb = chol_blocks(l);
-  if (shift) hipLaunchKernelGGL(add_shift_kernel, dim3(1), dim3(NT), 0, s, G, l, (int64_t)l, rows);
+  if (shift) hipLaunchKernelGGL(add_shift_kernel, dim3(1), dim3(NT), 0, s, G, l, (int64_t)l, rows, shift_out);
   hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)l * l + 255) / 256, 4096)), dim3(256),
                      0, s, R, (int64_t)l * l, 0.0);
   AMM_HIP(hipGetLastError());
@@ -516,28 +627,47 @@ amm_status chol_qr_apply(const double* Y, int64_t rows, int l, const double* R, 
   return AMM_OK;
 }
 
-// Eigen-decomposition of the symmetric positive semi-definite G (l x l,
-// overwritten) by one-sided Jacobi sweeps (round-robin pairs, one launch per
-// round) until a sweep rotates nothing (at most 40): V (l x l) receives the
-// eigenvectors as contiguous columns, lam_host the eigenvalues (unsorted).
-amm_status gram_eig_large(double* G, int l, double* V, double* lam, int* flag, std::vector<double>& lam_host,
-                          int* sweeps_out, hipStream_t s) {
-  const int np = l + (l & 1);
-  hipLaunchKernelGGL(identity_f64_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)l * l + 255) / 256, 4096)),
-                     dim3(256), 0, s, V, l);
-  AMM_HIP(hipGetLastError());
+// Eigen-decomposition of the symmetric positive semi-definite G = B B^T (l x
+// l, the Gram matrix of `rows`-long rows; overwritten): G + shift = R^T R by
+// the blocked Cholesky factorisation (R into R, E its scratch), then block
+// one-sided Jacobi on the columns of R^T (the rows of R, contiguous in the
+// row-major R; the lower-triangular orientation converges in about half the
+// sweeps of the same iteration on G): R^T V = U Sigma with U the eigenvectors
+// of G and Sigma^2 - shift its eigenvalues.  Sweeps (8-column blocks, 4 above
+// 1024 columns; round-robin block pairs, one launch per round) run until one
+// rotates nothing (at most 40).  W (l x l) receives the eigenvectors as contiguous
+// columns, lam_host the eigenvalues (unsorted); dev (2 + l doubles) is device
+// scratch.
+amm_status gram_eig_large(double* G, int l, int64_t rows, double* R, double* E, double* W, double* dev, int* flag,
+                          int* status, std::vector<double>& lam_host, int* sweeps_out, hipStream_t s) {
+  double* shift = dev;
+  double* lam = dev + 2;
+  AMM_TRY(chol_qr_blocked(G, l, rows, true, R, E, status, s, shift));
+  // 8-column blocks while the staged pair fits in LDS (l <= 1024), 4 beyond
+  const int BS = l <= 1024 ? 8 : 4;
+  const int nb = (l + BS - 1) / BS, npb = nb + (nb & 1);
+  const size_t lds = (size_t)2 * BS * (l | 1) * sizeof(double);
+  if (lds > 140 * 1024) return fail(AMM_EUNSUPPORTED, "sketch of %d columns too wide for the device eigensolver", l);
+  const void* kern = BS == 8 ? (const void*)bjac_round_kernel<8> : (const void*)bjac_round_kernel<4>;
+  if (lds > 64 * 1024) AMM_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   const double tol = std::max(1e-15, l * 1.1102230246251565e-16);
   int sweep = 0, h = 1;
   TimedLaunch tl("rsvd_eig", s);
   for (; sweep < 40 && h; ++sweep) {
     hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, flag);
-    for (int r = 0; r < np - 1; ++r)
-      hipLaunchKernelGGL(ojac_round_kernel, dim3((unsigned)(np / 2)), dim3(NT), 0, s, G, V, l, r, np, tol, flag);
+    for (int r = 0; r < npb - 1; ++r) {
+      if (BS == 8)
+        hipLaunchKernelGGL(bjac_round_kernel<8>, dim3((unsigned)(npb / 2)), dim3(NT), lds, s, R, l, nb, r, npb, tol,
+                           flag);
+      else
+        hipLaunchKernelGGL(bjac_round_kernel<4>, dim3((unsigned)(npb / 2)), dim3(NT), lds, s, R, l, nb, r, npb, tol,
+                           flag);
+    }
     AMM_HIP(hipGetLastError());
     AMM_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     AMM_HIP(hipStreamSynchronize(s));
   }
-  hipLaunchKernelGGL(col_norms_kernel, dim3((unsigned)l), dim3(NT), 0, s, G, l, lam);
+  hipLaunchKernelGGL(eig_finish_kernel, dim3((unsigned)l), dim3(NT), 0, s, R, l, shift, W, lam);
   AMM_HIP(hipGetLastError());
   lam_host.resize(l);
   AMM_HIP(hipMemcpyAsync(lam_host.data(), lam, l * sizeof(double), hipMemcpyDeviceToHost, s));

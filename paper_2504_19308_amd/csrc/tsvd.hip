@@ -425,7 +425,7 @@ amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_
     AMM_TRY(gram_eig(gram.as<double>(), l, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted, s));
   } else {
     std::vector<double> lam;
-    AMM_TRY(gram_eig_large(gram.as<double>(), l, Wd.as<double>(), rinv, flag, lam, nullptr, s));
+    AMM_TRY(gram_eig_large(gram.as<double>(), l, n, w.R, w.E, Wd.as<double>(), rinv, flag, status, lam, nullptr, s));
     // descending order (ties by index), sigma = sqrt(lam), 1/sigma, the leading k
     std::vector<int32_t> order(l);
     for (int i = 0; i < l; ++i) order[i] = i;
