@@ -7,11 +7,14 @@
 // `power_iters` subspace iterations (Y <- A A^T Y with re-orthonormalisation),
 // both from the same reference; the leading k triplets are kept.
 //
-// Device work: the tall GEMMs (float64 MFMA), the sketch generator and, for
-// l = k + oversample <= 96, the l x l steps as well (CholeskyQR factors and
-// the Jacobi eigensolver of the Gram matrix (Q^T A)(Q^T A)^T, one workgroup
-// each): the whole decomposition is enqueued without a host round trip and
-// read back once at the end.  Larger sketches do the l x l steps on the host.
+// Device work: the tall GEMMs (float64 MFMA), the sketch generator and the
+// l x l steps.  For l = k + oversample <= 96 the CholeskyQR factors and the
+// Jacobi eigensolver of the Gram matrix (Q^T A)(Q^T A)^T run in one
+// workgroup each: the whole decomposition is enqueued without a host round
+// trip and read back once at the end.  Up to 2048 columns a blocked
+// CholeskyQR and a block one-sided Jacobi on the Cholesky factor take over
+// (one flag read per Jacobi sweep, the eigenvalues sorted on the host);
+// beyond that, and for k = 0, the l x l steps run on the host.
 // Intermediate orthonormalisations of the subspace iteration take one
 // shifted CholeskyQR pass (they only need a well-conditioned basis of the
 // same span); the final basis takes three (shifted CholeskyQR3).
