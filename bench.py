@@ -588,7 +588,7 @@ def run_variants(torch, ctx, tm, only):
         res.extend(batch_workload(torch, ctx, tm))
     if not only or only == "layer":
         res.extend(layer_workload(torch, ctx, tm))
-        res.extend(layer_workload(torch, ctx, tm, k=440))
+        res.extend(layer_workload(torch, ctx, tm, k=440, oversample=64, power_iters=3))
     return res
 
 
@@ -1101,11 +1101,14 @@ def batch_circulant(torch, ctx, tm, shapes, B16, count, pcols, dense_ms, flops, 
     return recs
 
 
-def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
+def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192, oversample=16, power_iters=2):
     """Differentiable layer Y = approx(W) X, W 4096x4096 with sigma_i = i^-1.2,
     X 4096x8192 and dY N(0,1): forward + backward (dX, dW), truncated SVD of
-    rank 128 with the structure frozen; dense FP32 forward + 2 backward GEMMs
-    as the baseline."""
+    rank k with the structure frozen; dense FP32 forward + 2 backward GEMMs
+    as the baseline.  At rank 440 the exact truncation leaves 0.9907 % of
+    ||W||_F, so the randomized SVD needs a small excess: 64 extra columns and
+    3 subspace iterations (excess 1.8e-3 in a float64 simulation, against
+    1.5e-2 with 16 and 2)."""
     from paper_2504_19308_amd import inputs
     W = inputs.spectral_matrix(n, n, inputs.decay_power(n, 1.2), inputs.rng_of(4, 0), device="cuda").float()
     g = torch.Generator(device="cuda")
@@ -1113,7 +1116,7 @@ def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
     X = torch.randn((n, pcols), generator=g, device="cuda")
     dY = torch.randn((n, pcols), generator=g, device="cuda")
     t0 = time.perf_counter()
-    d = ctx.decompose(W, "tsvd", k, seed=7)
+    d = ctx.decompose(W, "tsvd", k, seed=7, oversample=oversample, power_iters=power_iters)
     torch.cuda.synchronize()
     dec_ms = (time.perf_counter() - t0) * 1e3
     Y = torch.empty((n, pcols), device="cuda")
@@ -1133,7 +1136,8 @@ def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
     flops = 3 * 2.0 * n * n * pcols
     rec = {"name": f"layer fwd+bwd tsvd k={k} (W {n}x{n}, X {n}x{pcols})", "ms": ms,
            "tflop_equiv_s": flops / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
-           "dense_fp32_ms": dense_ms, "forward_err_vs_exact": err, "decompose_ms": dec_ms,
+           "dense_fp32_ms": dense_ms, "forward_err_vs_exact": err, "meets_1pct": err <= 0.01,
+           "decompose_ms": dec_ms, "rsvd": {"oversample": oversample, "power_iters": power_iters},
            "kernels_ms": {kn: v[0] for kn, v in kt.items()}}
     log(f"[bench] layer fwd+bwd: {ms:.3f} ms, dense {dense_ms:.3f} ms, fwd err {err:.3e}")
     del exact
@@ -1154,7 +1158,7 @@ def layer_workload(torch, ctx, tm, k=128, n=4096, pcols=8192):
     rec16 = {"name": f"layer fwd+bwd tsvd k={k} bf16 activations (W {n}x{n}, X {n}x{pcols})", "ms": ms16,
              "tflop_equiv_s": flops / (ms16 * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms16,
              "speedup_vs_dense_bf16": dense16_ms / ms16, "dense_bf16_ms": dense16_ms,
-             "forward_err_vs_exact": err16,
+             "forward_err_vs_exact": err16, "meets_1pct": err16 <= 0.01,
              "precision": "bfloat16 X, dY, Y and dX; float32 factors, arithmetic and dW"}
     log(f"[bench] layer bf16 fwd+bwd: {ms16:.3f} ms, dense bf16 {dense16_ms:.3f} ms, fwd err {err16:.3e}")
     del W, X, dY, Y, X16, dY16, Y16, W16, exact16
