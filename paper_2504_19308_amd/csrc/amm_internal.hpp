@@ -467,8 +467,8 @@ amm_status sumsq_f32(const float* x, int64_t count, hipStream_t s, double* out);
 constexpr int kSmallEigMax = 96;
 amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, double* rinv, int* status,
                           hipStream_t s);
-amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, double* isg, double* sgk,
-                    float* sigma_f, double* sig_sorted, hipStream_t s);
+amm_status gram_eig(const double* gram, int l, int64_t rows, int k, double* W, int32_t* perm, double* isg,
+                    double* sgk, float* sigma_f, double* sig_sorted, int* status, hipStream_t s);
 // larger sketches: blocked CholeskyQR (E: chol_blocks(l) blocks of 64 x 64,
 // P: l x 64) and block one-sided Jacobi on the Cholesky factor (one launch
 // per round of block pairs)

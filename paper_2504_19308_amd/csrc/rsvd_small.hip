@@ -38,6 +38,29 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// S[i][c] = (G[i][c] + G[c][i]) / 2, plus `shift` on the diagonal, for
+// i, c < n (G at pitch ldg) into LDS at pitch ld.  Thread (g, c) takes rows
+// g, g + ng, ...: eight rows' loads (clamped addresses, so unconditional) are
+// in flight before their stores, where a plain loop would wait for each.
+__device__ void load_sym_lds(const double* __restrict__ G, int64_t ldg, int n, double shift, double* S, int ld) {
+  const int ng = NT / n, g = (int)threadIdx.x / n, c = (int)threadIdx.x % n;
+  if (g >= ng) return;
+  for (int i0 = g; i0 < n; i0 += 8 * ng) {
+    double u[8], v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = min(i0 + t * ng, n - 1);
+      u[t] = G[i * ldg + c];
+      v[t] = G[c * ldg + i];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = i0 + t * ng;
+      if (i < n) S[i * ld + c] = 0.5 * (u[t] + v[t]) + (i == c ? shift : 0.0);
+    }
+  }
+}
+
 // Upper Cholesky factor R of S (l x l at pitch ld, symmetric, only the upper
 // triangle is read; S = R^T R) by row elimination, applied at the same time
 // to E = I: the row operations that turn S into R turn I into R^-T (E S = R,
@@ -102,6 +125,111 @@ __device__ bool cholesky_inv_lds(double* S, double* E, int l, int ld) {
   return true;
 }
 
+// The same factorisation held in registers, for l <= 64: thread (wave w,
+// lane c) keeps column c of rows w, w + 4, ..., w + 60 of S (s[16]) and of E
+// (e[16]); rows and columns past l are the identity (a block-diagonal
+// padding that the factor keeps).  Step j: the wave holding row j takes the
+// pivot from lane j, scales the row and publishes rows j of R and of E
+// through LDS (double-buffered: a buffer is rewritten two steps later, after
+// a barrier every reader has passed, so one barrier per step); every thread
+// then subtracts R[j][a] times them from its rows a > j.  Every register
+// index is a constant of the unrolled loops.  Returns false (uniformly) at a
+// non-positive pivot.
+constexpr int LR = 64;
+__device__ bool cholesky_inv_regs(double (&s)[16], double (&e)[16], int l, double (*Rrow)[LR], double (*Erow)[LR],
+                                  int* fail_flag) {
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) e[m] = (w + 4 * m == c) ? 1.0 : 0.0;
+  if (threadIdx.x == 0) *fail_flag = 0;
+  __syncthreads();
+  // step j = 4 mm + w4: the register index mm is a constant of the unrolled
+  // outer loop, the inner loop stays rolled (a quarter of the code)
+#pragma unroll
+  for (int mm = 0; mm < LR / 4; ++mm) {
+    if (4 * mm >= l) break;
+    for (int w4 = 0; w4 < 4; ++w4) {
+      const int j = 4 * mm + w4;
+      if (j >= l) break;   // uniform
+      const int buf = j & 1;
+      if (w == w4) {
+        const double v = s[mm];
+        const double d = __shfl(v, j, 64);
+        if (!(d > 0.0) && c == 0) *fail_flag = 1;
+        const double ir = 1.0 / sqrt(d);   // not a number after a failed pivot: the flag decides
+        const double rv = c >= j ? v * ir : 0.0;
+        const double ev = e[mm] * ir;
+        s[mm] = rv;
+        e[mm] = ev;
+        Rrow[buf][c] = rv;
+        Erow[buf][c] = ev;
+      }
+      __syncthreads();
+      const double rc = Rrow[buf][c], ec = Erow[buf][c];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        if (w + 4 * m > j) {   // uniform over the wave
+          const double f = Rrow[buf][w + 4 * m];
+          s[m] -= f * rc;
+          e[m] -= f * ec;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const bool ok = *fail_flag == 0;
+  __syncthreads();   // every thread has read the flag before a retry clears it
+  return ok;
+}
+
+// Rows w + 4 m, column c of G (pitch ldg; + shift on the diagonal) into s;
+// the identity past l.
+__device__ __forceinline__ void load_gram_regs(double (&s)[16], const double* __restrict__ gram, int64_t ldg, int l,
+                                               double shift) {
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cc = min(c, l - 1);
+  double u[16], v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {   // clamped addresses: all 32 loads in flight together
+    const int ac = min(w + 4 * m, l - 1);
+    u[m] = gram[ac * ldg + cc];
+    v[m] = gram[cc * ldg + ac];
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int a = w + 4 * m;
+    s[m] = (a < l && c < l) ? 0.5 * (u[m] + v[m]) + (a == c ? shift : 0.0) : (a == c ? 1.0 : 0.0);
+  }
+}
+
+// chol_inv_kernel's contract for l <= 64, with the factorisation in registers.
+__global__ void __launch_bounds__(NT) chol_inv_reg_kernel(const double* __restrict__ gram, int l, int64_t rows,
+                                                          int mode, double* __restrict__ rinv,
+                                                          int* __restrict__ status) {
+  __shared__ double Rrow[2][LR], Erow[2][LR];
+  __shared__ double red[4];
+  __shared__ int fail_flag;
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += NT) tr += gram[i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * tr;
+  double s[16], e[16];
+  load_gram_regs(s, gram, l, l, mode == 0 ? shift : 0.0);
+  bool ok = cholesky_inv_regs(s, e, l, Rrow, Erow, &fail_flag);
+  if (!ok && mode != 0) {
+    load_gram_regs(s, gram, l, l, shift);
+    ok = cholesky_inv_regs(s, e, l, Rrow, Erow, &fail_flag);
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int a = w + 4 * m;
+    // R^-1 = E^T (upper): rinv[c][a] = E[a][c] for a >= c; the identity on a breakdown
+    if (a < l && c < l) rinv[c * l + a] = ok ? (a >= c ? e[m] : 0.0) : (a == c ? 1.0 : 0.0);
+  }
+  if (!ok && threadIdx.x == 0) *status = 1;
+}
+
 // mode 0: G + shift (the first CholeskyQR pass, always shifted); mode 1: G,
 // shifted only if its plain factorisation fails.  shift = 11 (rows l +
 // l (l + 1)) u tr(G), u = 2^-53 (shifted CholeskyQR3, Fukaya et al. 2020).
@@ -116,12 +244,7 @@ __global__ void __launch_bounds__(NT) chol_inv_kernel(const double* __restrict__
   const int ng = NT / l, g = tid / l, c = tid % l;
   auto load = [&](double shift) {
     __syncthreads();
-    if (g < ng)
-      for (int i = g; i < l; i += ng) {
-        double v = 0.5 * (gram[i * l + c] + gram[c * l + i]);
-        if (i == c) v += shift;
-        S[i * ld + c] = v;
-      }
+    load_sym_lds(gram, l, l, shift, S, ld);
   };
   double tr = 0.0;
   for (int i = tid; i < l; i += NT) tr += gram[i * l + i];
@@ -148,156 +271,175 @@ __global__ void __launch_bounds__(NT) chol_inv_kernel(const double* __restrict__
 // even): seat 0 keeps player 0, the others rotate.
 __device__ __forceinline__ int seat(int pos, int r, int np) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1); }
 
-// Eigen-decomposition of the symmetric G (l x l) by cyclic Jacobi with the
-// round-robin parallel ordering: each round rotates l/2 disjoint index pairs
-// at once (G <- J^T G J, W <- W J), a sweep is l - 1 rounds (every pair
-// once), sweeps run until the off-diagonal norm is <= 1e-16 ||G||_F.
-// Outputs, with the eigenvalues sorted descending (order[j] = index of the
-// j-th largest; ties by index):
-//   W (l x l) eigenvectors by original index; perm[j] = order[j];
+// Lane-exchange steps of a butterfly over 4 or 8 adjacent lanes (DPP: quad
+// permutations [1,0,3,2] and [2,3,0,1], then the mirror within 8 lanes),
+// applied to both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int LPP>
+__device__ __forceinline__ double lane_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (LPP == 8) v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the 8
+  return v;
+}
+
+// One sweep (np - 1 rounds) of one-sided Jacobi on the rows of S (l x l at
+// pitch ld): lane li of pair group pi rotates elements li, li + LPP, ...
+// (at most EM of them) of the pair's rows p, q, both held in registers; the
+// LPP lanes of a pair are adjacent in one wave and reduce the dot products by
+// a butterfly (commutative at every step, so every one of them computes the
+// same rotation).  A rotation sets *any_rot.
+template <int LPP, int EM>
+__device__ void ojac_sweep(double* S, int ld, int l, int np, int pi, int li, bool on, double tol, int* any_rot) {
+  for (int r = 0; r < np - 1; ++r) {
+    __syncthreads();
+    if (!on) continue;
+    int p = seat(pi, r, np), q = seat(np - 1 - pi, r, np);
+    if (p > q) {
+      const int t = p;
+      p = q;
+      q = t;
+    }
+    if (q >= l) continue;   // the dummy row of an odd l (uniform over the pair's lanes)
+    double x[EM], y[EM];
+#pragma unroll
+    for (int t = 0; t < EM; ++t) {   // clamped loads (all in flight together), zeroed past the row
+      const int e = li + t * LPP, ec = min(e, l - 1);
+      const double xv = S[p * ld + ec], yv = S[q * ld + ec];
+      x[t] = e < l ? xv : 0.0;
+      y[t] = e < l ? yv : 0.0;
+    }
+    double a = 0.0, b = 0.0, d = 0.0;
+#pragma unroll
+    for (int t = 0; t < EM; ++t) {
+      a += x[t] * x[t];
+      b += y[t] * y[t];
+      d += x[t] * y[t];
+    }
+    a = lane_sum<LPP>(a);
+    b = lane_sum<LPP>(b);
+    d = lane_sum<LPP>(d);
+    if (!(fabs(d) > tol * sqrt(a * b))) continue;   // orthogonal to rounding (or not a number)
+    const double zeta = (b - a) / (2.0 * d);
+    const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+    for (int u = 0; u < EM; ++u) {
+      const int e = li + u * LPP;
+      if (e < l) {
+        S[p * ld + e] = cs * x[u] - sn * y[u];
+        S[q * ld + e] = sn * x[u] + cs * y[u];
+      }
+    }
+    if (li == 0) *any_rot = 1;
+  }
+}
+
+// Eigen-decomposition of the symmetric positive semi-definite G = B B^T (l x
+// l, the Gram matrix of `rows`-long rows) through its Cholesky factor:
+// G + delta I = R^T R with delta = 11 (rows l + l (l + 1)) u tr(G), which keeps
+// the factorisation defined for a singular G and moves no eigenvector; then
+// one-sided (Hestenes) Jacobi on the rows of R (the columns of R^T): each
+// round rotates l/2 disjoint row pairs (round-robin ordering, a group of LPP
+// adjacent lanes per pair, dot products reduced by shuffles, both rows held
+// in registers) until they are orthogonal to tol = max(1e-15, l u); a sweep
+// is l - 1 rounds, sweeps run until one rotates nothing (at most 40).  Then
+// R^T V = U Sigma: row j of R holds sigma_j u_j, so the eigenvalues are
+// ||row_j||^2 - delta and the eigenvectors the normalised rows, with no
+// rotation matrix formed.  On the triangular factor the sweeps are about
+// half those of the same iteration on G.  Outputs, with the eigenvalues
+// sorted descending (order[j] = index of the j-th largest; ties by index):
+//   W (l x l, row-major) eigenvectors by original index, W[i l + j] =
+//   component i of eigenvector j; perm[j] = order[j];
 //   isg[i] = 1 / sqrt(lam_i) (0 for lam_i <= 0), by original index;
 //   sgk[j] = sqrt(lam_order[j]) for j < k (float64) and sigma_f (float32);
 //   sig_sorted[j] = sqrt(max(lam_order[j], 0)) for j < l.
-__global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__ gram, int l, int k,
+// A failed factorisation (G not positive semi-definite to rounding) sets
+// *status and leaves W = I and zero eigenvalues.
+__global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__ gram, int l, int64_t rows, int k,
                                                       double* __restrict__ Wout, int32_t* __restrict__ perm,
                                                       double* __restrict__ isg, double* __restrict__ sgk,
-                                                      float* __restrict__ sigma_f, double* __restrict__ sig_sorted) {
-  __shared__ double G[LS];
-  __shared__ double W[LS];
-  __shared__ double cs[LM / 2 + 1], sn[LM / 2 + 1];
-  __shared__ int pp[LM / 2 + 1], qq[LM / 2 + 1];
+                                                      float* __restrict__ sigma_f, double* __restrict__ sig_sorted,
+                                                      int* __restrict__ status) {
+  __shared__ double S[LS];
+  __shared__ double E[LS];   // R^-T from the factorisation (not used here)
+  __shared__ double Rrow[2][LR], Erow[2][LR];
   __shared__ double red[4];
-  __shared__ double lam[LM];
-  __shared__ int any_rot;
+  __shared__ double lam[LM], inv_norm[LM];
+  __shared__ int any_rot, fail_flag;
   const int tid = threadIdx.x, ld = pitch_of(l);
-  // thread -> (row group g, column c): rows g, g + ng, ...; no division inside the loops
   const int ng = NT / l, g = tid / l, c = tid % l;
   const bool active = g < ng;
-  double f = 0.0;
-  if (active)
-    for (int i = g; i < l; i += ng) {
-      const double v = 0.5 * (gram[i * l + c] + gram[c * l + i]);
-      G[i * ld + c] = v;
-      W[i * ld + c] = (i == c) ? 1.0 : 0.0;
-      f += v * v;
+  double tr = 0.0;
+  for (int i = tid; i < l; i += NT) tr += gram[i * l + i];
+  tr = block_sum(tr, red);
+  const double delta = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * tr;
+  bool ok;
+  if (l <= LR) {
+    // factor in registers, then R (upper) into S
+    double sr[16], er[16];
+    load_gram_regs(sr, gram, l, l, delta);
+    ok = cholesky_inv_regs(sr, er, l, Rrow, Erow, &fail_flag);
+    const int cr = tid & 63, wr = tid >> 6;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int a = wr + 4 * m;
+      if (a < l && cr < l) S[a * ld + cr] = ok ? (cr >= a ? sr[m] : 0.0) : (a == cr ? 1.0 : 0.0);
     }
-  const double fro = sqrt(block_sum(f, red));
-  const int np = l + (l & 1);   // an odd l gets a dummy player l (its pairs are skipped)
-  const int npairs = np / 2;
-  // Sweeps until one rotates no pair (every off-diagonal entry is at rounding
-  // level relative to its diagonal pair, which keeps small eigenvalues
-  // accurate too) or the off-diagonal norm is <= 1e-16 ||G||_F.
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double o = 0.0;
+  } else {
+    load_sym_lds(gram, l, l, delta, S, ld);
+    ok = cholesky_inv_lds(S, E, l, ld);
+    // R: the upper part of S; clear the rest (identity on a breakdown)
     if (active)
-      for (int i = g; i < c; i += ng) o += G[i * ld + c] * G[i * ld + c];
-    o = block_sum(o, red);
-    if (!(sqrt(o) > 1e-16 * fro)) break;   // converged (or not a number: stop)
-    if (tid == 0) any_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < np - 1; ++r) {
-      // rotation of each pair, from the 2 x 2 block it annihilates
-      if (tid < npairs) {
-        int rotated = 0;
-        int p = seat(tid, r, np), q = seat(np - 1 - tid, r, np);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double cc = 1.0, ss = 0.0;
-        if (q < l) {
-          const double apq = G[p * ld + q], app = G[p * ld + p], aqq = G[q * ld + q];
-          // rotate unless the pair is already decoupled to rounding: |a_pq| <= u sqrt(|a_pp a_qq|)
-          if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) {
-            rotated = 1;
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            cc = 1.0 / sqrt(t * t + 1.0);
-            ss = t * cc;
-          }
-        }
-        cs[tid] = cc;
-        sn[tid] = ss;
-        pp[tid] = p;
-        qq[tid] = q < l ? q : -1;
-        if (rotated) any_rot = 1;
-      }
-      __syncthreads();
-      // columns p, q of G and of W (G J, W J): thread row c, pairs g, g + ng, ...
-      // Four pairs per pass: their (disjoint) entries are all loaded before
-      // any is stored, so the LDS round trips overlap.
-      if (active)
-        for (int i0 = g; i0 < npairs; i0 += 4 * ng) {
-          int p[4], q[4];
-          double cc[4], ss[4], a[4], b[4], u[4], v[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int i = min(i0 + t * ng, npairs - 1);   // clamped: loads stay unconditional
-            const int pi = pp[i], qi = qq[i];
-            const double ci = cs[i], si = sn[i];
-            const bool on = i0 + t * ng < npairs && qi >= 0;
-            p[t] = on ? pi : 0;
-            q[t] = on ? qi : 0;
-            cc[t] = ci;
-            ss[t] = on ? si : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            a[t] = G[c * ld + p[t]];
-            b[t] = G[c * ld + q[t]];
-            u[t] = W[c * ld + p[t]];
-            v[t] = W[c * ld + q[t]];
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (ss[t] == 0.0) continue;   // no rotation (or no pair): leave the entries
-            G[c * ld + p[t]] = cc[t] * a[t] - ss[t] * b[t];
-            G[c * ld + q[t]] = ss[t] * a[t] + cc[t] * b[t];
-            W[c * ld + p[t]] = cc[t] * u[t] - ss[t] * v[t];
-            W[c * ld + q[t]] = ss[t] * u[t] + cc[t] * v[t];
-          }
-        }
-      __syncthreads();
-      // rows p, q of G (J^T G): thread column c, four pairs per pass
-      if (active)
-        for (int i0 = g; i0 < npairs; i0 += 4 * ng) {
-          int p[4], q[4];
-          double cc[4], ss[4], a[4], b[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int i = min(i0 + t * ng, npairs - 1);   // clamped: loads stay unconditional
-            const int pi = pp[i], qi = qq[i];
-            const double ci = cs[i], si = sn[i];
-            const bool on = i0 + t * ng < npairs && qi >= 0;
-            p[t] = on ? pi : 0;
-            q[t] = on ? qi : 0;
-            cc[t] = ci;
-            ss[t] = on ? si : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            a[t] = G[p[t] * ld + c];
-            b[t] = G[q[t] * ld + c];
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (ss[t] == 0.0) continue;
-            G[p[t] * ld + c] = cc[t] * a[t] - ss[t] * b[t];
-            G[q[t] * ld + c] = ss[t] * a[t] + cc[t] * b[t];
-          }
-        }
-      __syncthreads();
-    }
-    if (!any_rot) break;   // read after the round's last barrier: uniform
+      for (int i = g; i < l; i += ng)
+        if (!ok)
+          S[i * ld + c] = (i == c) ? 1.0 : 0.0;
+        else if (c < i)
+          S[i * ld + c] = 0.0;
   }
-  for (int i = tid; i < l; i += NT) lam[i] = G[i * ld + i];
+  if (!ok && tid == 0) *status = 1;
+  const double shift = ok ? delta : 1.0;
+  const int np = l + (l & 1);   // an odd l gets a dummy row l (its pairs are skipped)
+  const int npairs = np / 2, LPP = npairs <= NT / 8 ? 8 : 4;
+  const int pi = tid / LPP, li = tid % LPP;
+  const bool on = ok && pi < npairs;
+  const double tol = fmax(1e-15, l * 1.1102230246251565e-16);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    // uniform branch: every thread takes the same sweep (and its barriers)
+    if (l <= 32)
+      ojac_sweep<8, 4>(S, ld, l, np, pi, li, on, tol, &any_rot);
+    else if (LPP == 8)
+      ojac_sweep<8, 8>(S, ld, l, np, pi, li, on, tol, &any_rot);
+    else
+      ojac_sweep<4, (LM + 3) / 4>(S, ld, l, np, pi, li, on, tol, &any_rot);
+    __syncthreads();
+    const int rot = any_rot;
+    __syncthreads();   // every thread has read any_rot before it is cleared
+    if (!rot) break;
+  }
+  // eigenvalues ||row_j||^2 - shift, eigenvectors the normalised rows
+  for (int j = tid / 64; j < l; j += NT / 64) {
+    double a = 0.0;
+    for (int e = tid % 64; e < l; e += 64) a += S[j * ld + e] * S[j * ld + e];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (tid % 64 == 0) {
+      lam[j] = fmax(a - shift, 0.0);
+      inv_norm[j] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+    }
+  }
   __syncthreads();
   for (int i = tid; i < l; i += NT) {
-    const double li = lam[i];
+    const double li2 = lam[i];
     int rank = 0;
-    for (int j = 0; j < l; ++j) rank += (lam[j] > li || (lam[j] == li && j < i)) ? 1 : 0;
-    const double sg = sqrt(fmax(li, 0.0));
+    for (int j = 0; j < l; ++j) rank += (lam[j] > li2 || (lam[j] == li2 && j < i)) ? 1 : 0;
+    const double sg = sqrt(li2);
     perm[rank] = i;
     isg[i] = sg > 0.0 ? 1.0 / sg : 0.0;
     sig_sorted[rank] = sg;
@@ -307,7 +449,7 @@ __global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__
     }
   }
   if (active)
-    for (int i = g; i < l; i += ng) Wout[i * l + c] = W[i * ld + c];
+    for (int i = g; i < l; i += ng) Wout[i * l + c] = S[c * ld + i] * inv_norm[c];
 }
 
 // ---- sketches above 96 columns ---------------------------------------------------
@@ -325,34 +467,29 @@ __global__ void __launch_bounds__(NT) add_shift_kernel(double* __restrict__ G, i
   if (shift_out && threadIdx.x == 0) *shift_out = shift;
 }
 
-// Cholesky factor of the b x b diagonal block at G (pitch ldg, b <= 64):
-// R_jj (upper) into R (pitch ldr), R_jj^-T (lower) into E (pitch b).  A
-// non-positive pivot sets *status.
+// Cholesky factor of the b x b diagonal block at G (pitch ldg, b <= 64), in
+// registers: R_jj (upper) into R (pitch ldr), R_jj^-T (lower) into E (pitch
+// b).  A non-positive pivot sets *status (R_jj = E = I).
 constexpr int kCholBlock = 64;
+static_assert(kCholBlock <= LR, "diagonal blocks factor in registers");
 __global__ void __launch_bounds__(NT) chol_block_kernel(const double* __restrict__ G, int64_t ldg, int b,
                                                         double* __restrict__ R, int64_t ldr, double* __restrict__ E,
                                                         int* __restrict__ status) {
-  __shared__ double S[kCholBlock * (kCholBlock + 1)];
-  __shared__ double X[kCholBlock * (kCholBlock + 1)];
-  const int tid = threadIdx.x, ld = pitch_of(b);
-  const int ng = NT / b, g = tid / b, c = tid % b;
-  if (g < ng)
-    for (int i = g; i < b; i += ng) S[i * ld + c] = 0.5 * (G[i * ldg + c] + G[c * ldg + i]);
-  const bool ok = cholesky_inv_lds(S, X, b, ld);
-  if (!ok) {
-    if (tid == 0) *status = 1;
-    if (g < ng)
-      for (int i = g; i < b; i += ng) {
-        R[i * ldr + c] = (i == c) ? 1.0 : 0.0;
-        E[i * b + c] = (i == c) ? 1.0 : 0.0;
-      }
-    return;
-  }
-  if (g < ng)
-    for (int i = g; i < b; i += ng) {
-      R[i * ldr + c] = (c >= i) ? S[i * ld + c] : 0.0;
-      E[i * b + c] = (c <= i) ? X[i * ld + c] : 0.0;
+  __shared__ double Rrow[2][LR], Erow[2][LR];
+  __shared__ int fail_flag;
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double sr[16], er[16];
+  load_gram_regs(sr, G, ldg, b, 0.0);
+  const bool ok = cholesky_inv_regs(sr, er, b, Rrow, Erow, &fail_flag);
+  if (!ok && threadIdx.x == 0) *status = 1;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int a = w + 4 * m;
+    if (a < b && c < b) {
+      R[a * ldr + c] = ok ? (c >= a ? sr[m] : 0.0) : (a == c ? 1.0 : 0.0);
+      E[a * b + c] = ok ? (c <= a ? er[m] : 0.0) : (a == c ? 1.0 : 0.0);
     }
+  }
 }
 
 __global__ void fill_f64_kernel(double* __restrict__ p, int64_t count, double v) {
@@ -557,16 +694,20 @@ amm_status chol_qr_factor(const double* gram, int l, int64_t rows, int mode, dou
                           hipStream_t s) {
   if (l < 1 || l > kSmallEigMax) return fail(AMM_EUNSUPPORTED, "device CholeskyQR factor needs 1 <= l <= %d", kSmallEigMax);
   TimedLaunch tl("rsvd_chol", s);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(NT), 0, s, gram, l, rows, mode, rinv, status);
+  if (l <= LR)
+    hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(NT), 0, s, gram, l, rows, mode, rinv, status);
+  else
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(NT), 0, s, gram, l, rows, mode, rinv, status);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }
 
-amm_status gram_eig(const double* gram, int l, int k, double* W, int32_t* perm, double* isg, double* sgk,
-                    float* sigma_f, double* sig_sorted, hipStream_t s) {
+amm_status gram_eig(const double* gram, int l, int64_t rows, int k, double* W, int32_t* perm, double* isg,
+                    double* sgk, float* sigma_f, double* sig_sorted, int* status, hipStream_t s) {
   if (l < 1 || l > kSmallEigMax || k > l) return fail(AMM_EUNSUPPORTED, "device Gram eigensolver needs k <= l <= %d", kSmallEigMax);
   TimedLaunch tl("rsvd_eig", s);
-  hipLaunchKernelGGL(gram_eig_kernel, dim3(1), dim3(NT), 0, s, gram, l, k, W, perm, isg, sgk, sigma_f, sig_sorted);
+  hipLaunchKernelGGL(gram_eig_kernel, dim3(1), dim3(NT), 0, s, gram, l, rows, k, W, perm, isg, sgk, sigma_f,
+                     sig_sorted, status);
   AMM_HIP(hipGetLastError());
   return AMM_OK;
 }

@@ -425,7 +425,8 @@ amm_status tsvd_decompose_device(amm_ctx* ctx, const float* A, int64_t m, int64_
   // contiguous eigenvectors (column-major) from the one-sided Jacobi
   int64_t w_rs = l, w_cs = 1;
   if (!large) {
-    AMM_TRY(gram_eig(gram.as<double>(), l, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted, s));
+    AMM_TRY(gram_eig(gram.as<double>(), l, n, k, Wd.as<double>(), perm, isg, sgk, dec->sigma.as<float>(), sig_sorted,
+                     status, s));
   } else {
     std::vector<double> lam;
     AMM_TRY(gram_eig_large(gram.as<double>(), l, n, w.R, w.E, Wd.as<double>(), rinv, flag, status, lam, nullptr, s));
