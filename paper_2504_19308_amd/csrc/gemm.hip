@@ -34,7 +34,9 @@ template <> struct Mfma<double> {
   }
 };
 
-constexpr int BK = 16;
+// k-slab depth: 16 float32 or 32 float64 values (64 B rows of a slab either way)
+template <typename T>
+constexpr int kBK = sizeof(T) == 8 ? 32 : 16;
 constexpr int NT = 256;
 
 // BM, BN in {32, 64, 128}; each wave: (BM/2) x (BN/2) = TM x TN MFMA tiles.
@@ -43,6 +45,7 @@ __global__ void __launch_bounds__(NT)
 gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A, int64_t a_rs,
             int64_t a_cs, const T* __restrict__ B, int64_t b_rs, int64_t b_cs, T beta,
             T* __restrict__ C, int64_t ldc, int64_t k_split, T* __restrict__ part) {
+  constexpr int BK = kBK<T>;
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int APT = BM * BK / NT;  // A elements per thread per slab
   constexpr int BPT = BN * BK / NT;
@@ -153,8 +156,17 @@ __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restr
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t i = idx / N, j = idx % N;
+  // eight partials' loads in flight at a time (a plain loop waits for each)
   T s = 0;
-  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * M * N + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
   T* c = C + i * ldc + j;
   *c = (beta == T(0)) ? s : s + beta * *c;
 }
@@ -188,9 +200,12 @@ amm_status gemm_any(int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_
   // split K when the output grid cannot fill the chip
   int64_t splits = 1;
   const int64_t target = 1024;
+  constexpr int BK = kBK<T>;
   if (gm * gn < target && K >= 512) {
     splits = (target + gm * gn - 1) / (gm * gn);
-    const int64_t maxs = K / 256;
+    // float64: down to two slabs per split (small outputs such as an l x l
+    // Gram matrix are latency-bound); float32: at least 256 per split
+    const int64_t maxs = sizeof(T) == 8 ? K / (2 * BK) : K / 256;
     if (splits > maxs) splits = maxs;
     if (splits < 1) splits = 1;
   }
