@@ -400,6 +400,13 @@ def power_decay_workload(torch, ctx, tm, only=""):
     dense_ms = statistics.median(tm.run(lambda: torch.matmul(A, B), 25, 5))
     out = torch.empty((n, n), dtype=torch.float32, device="cuda")
     kp = 32
+    # the context's first decomposition grows its work areas: timed apart, the
+    # steady-state calls below are the ones a stream of decompositions sees
+    t0 = time.perf_counter()
+    dA = ctx.decompose(A, "tsvd", kp, seed=1)
+    torch.cuda.synchronize()
+    tA_first = (time.perf_counter() - t0) * 1e3
+    del dA
     t0 = time.perf_counter()
     dA = ctx.decompose(A, "tsvd", kp, seed=1)
     torch.cuda.synchronize()
@@ -434,8 +441,9 @@ def power_decay_workload(torch, ctx, tm, only=""):
     res = [{"name": f"n={n} tsvd k={kp} first (both operands rank {kp})", "ms": ms,
             "tflop_equiv_s": flops_equiv / (ms * 1e-3) / 1e12, "speedup_vs_dense_fp32": dense_ms / ms,
             "dense_fp32_ms": dense_ms, "err_vs_exact": err, "meets_1pct": err <= 0.01,
-            "decompose_ms": {"A": tA, "B": tB},
-            "end_to_end": {"ms": ms + tA + tB, "speedup_vs_dense_fp32": dense_ms / (ms + tA + tB)},
+            "decompose_ms": {"A": tA, "B": tB, "A_first_call": tA_first},
+            "end_to_end": {"ms": ms + tA + tB, "speedup_vs_dense_fp32": dense_ms / (ms + tA + tB),
+                           "note": "steady-state decompositions of A and B plus one first-order product"},
             "kernels_ms": {k: v[0] / 20 for k, v in kt.items()}, "roofline": roof}]
     log(f"[bench] power-decay tsvd k={kp} first: {ms:.4f} ms (dense {dense_ms:.3f}), err {err:.3e}, roofline "
         f"{roof['kernel']} {roof['frac']:.2f}")
