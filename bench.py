@@ -240,6 +240,10 @@ def headline_sparse_circulant(torch, ctx, tm, args, K=64, frac=0.005, ncols=256)
 
     # ---- headline: zeroth order, float16 spectral products -------------------
     # (the zeroth-order product needs neither Delta A nor B's decomposition)
+    # the context's first decomposition grows its work areas (4 GiB of float64
+    # spectra at n = 16384): timed apart from the steady-state call
+    dA, tA_first = decompose_timed(A, True, keep=False)
+    del dA
     dA, tA = decompose_timed(A, True, keep=False)
     info = dA.info()
     step = lambda: ctx.approx_matmul(dA, B, out=out)
@@ -294,13 +298,13 @@ def headline_sparse_circulant(torch, ctx, tm, args, K=64, frac=0.005, ncols=256)
         "dense_fp32_ms": dense_ms,
         "dense_bf16_ms": dense_bf16_ms,
         "speedup_vs_dense_fp32": dense_ms / ms_step,
-        "decompose_ms": {"A": tA},
+        "decompose_ms": {"A": tA, "A_first_call": tA_first},
         "end_to_end": {
             "ms": ms_step + tA,
             "tflop_equiv_s": flops_equiv / ((ms_step + tA) * 1e-3) / 1e12,
             "speedup_vs_dense_fp32": dense_ms / (ms_step + tA),
-            "note": "decomposition of A (sparse part, circulant lists; Delta A not formed) plus one product: the "
-                    "zeroth-order product needs nothing else",
+            "note": "steady-state decomposition of A (sparse part, circulant lists; Delta A not formed) plus one "
+                    "product: the zeroth-order product needs nothing else",
         },
         "roofline": roof,
     }

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamm.so")
 
-SOURCES = ["amm_api.cpp", "amm_export.cpp", "host_logic.cpp", "cd_apply.hip", "cd_decomp.hip", "gemm.hip", "sparse.hip", "cast.hip", "tsvd.hip", "rsvd_small.hip", "tsvd_apply.hip", "tsvd_split.hip", "tsvd_bf16.hip", "sfft.hip", "cd_general.hip", "backward.hip"]
+SOURCES = ["amm_api.cpp", "amm_export.cpp", "host_logic.cpp", "cd_apply.hip", "cd_decomp.hip", "gemm.hip", "sparse.hip", "csc_build.hip", "cast.hip", "tsvd.hip", "rsvd_small.hip", "tsvd_apply.hip", "tsvd_split.hip", "tsvd_bf16.hip", "sfft.hip", "cd_general.hip", "backward.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -821,7 +821,7 @@ amm_status amm_dec_import_sparse(amm_ctx* ctx, int64_t m, int64_t n, int64_t nnz
     delete d;
     return hip_fail(e, "import sparse");
   }
-  if ((st = build_csc(d)) != AMM_OK) {
+  if ((st = build_csc(d, nullptr)) != AMM_OK) {
     delete d;
     return st;
   }

@@ -510,6 +510,8 @@ amm_status batch_convert_bf16(amm_batch_plan* bp, const std::vector<const float*
 amm_status batch_build_bf16(amm_batch_plan* bp, int target_blocks);
 amm_status batch_launch_bf16(const amm_batch_plan* bp, hipStream_t s);
 // Build the CSC copy of a CSR part held on the device (host transpose).
-amm_status build_csc(amm_dec* d);
+// column-major copy of a sparse part and the block ranges of both (csc_build.hip)
+constexpr int64_t kSpBlock = 4096;   // inner indices per block of a blocked sparse product
+amm_status build_csc(amm_dec* d, hipStream_t s);
 
 }  // namespace amm

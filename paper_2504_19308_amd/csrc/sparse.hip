@@ -403,70 +403,6 @@ amm_status fill_f32(float* p, int64_t count, float v, hipStream_t s) {
   return AMM_OK;
 }
 
-namespace {
-
-constexpr int64_t kSpBlock = 4096;   // inner indices per block of a blocked SpMM
-
-// Entry ranges per block of kSpBlock inner indices for rows whose indices are
-// sorted: (blocks + 1) offsets per row, or blocks = 1 when the inner dimension
-// is short (up to 8192, where the whole slice of B stays in an XCD's L2) or a
-// row is unsorted.
-amm_status block_ranges(const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx, int64_t rows,
-                        int64_t inner, amm::DevBuf* out, int* blocks) {
-  *blocks = 1;
-  if (inner <= 2 * kSpBlock) return AMM_OK;
-  for (int64_t i = 0; i < rows; ++i)
-    for (int32_t e = ptr[i] + 1; e < ptr[i + 1]; ++e)
-      if (idx[e] < idx[e - 1]) return AMM_OK;
-  const int nb = (int)((inner + kSpBlock - 1) / kSpBlock);
-  std::vector<int32_t> h((size_t)rows * (nb + 1));
-  for (int64_t i = 0; i < rows; ++i) {
-    int32_t e = ptr[i];
-    for (int b = 0; b < nb; ++b) {
-      while (e < ptr[i + 1] && idx[e] < (int64_t)b * kSpBlock) ++e;
-      h[(size_t)i * (nb + 1) + b] = e;
-    }
-    h[(size_t)i * (nb + 1) + nb] = ptr[i + 1];
-  }
-  AMM_TRY(out->alloc(h.size() * 4));
-  AMM_HIP(hipMemcpy(out->ptr, h.data(), h.size() * 4, hipMemcpyHostToDevice));
-  *blocks = nb;
-  return AMM_OK;
-}
-
-}  // namespace
-
-amm_status build_csc(amm_dec* d) {
-  const int64_t m = d->m, n = d->n, nnz = d->nnz;
-  std::vector<int32_t> rp(m + 1), cl(std::max<int64_t>(nnz, 1));
-  std::vector<float> vl(std::max<int64_t>(nnz, 1));
-  AMM_HIP(hipMemcpy(rp.data(), d->row_ptr.ptr, (m + 1) * 4, hipMemcpyDeviceToHost));
-  if (nnz) {
-    AMM_HIP(hipMemcpy(cl.data(), d->col.ptr, nnz * 4, hipMemcpyDeviceToHost));
-    AMM_HIP(hipMemcpy(vl.data(), d->val.ptr, nnz * 4, hipMemcpyDeviceToHost));
-  }
-  std::vector<int32_t> cp(n + 1, 0), rr(std::max<int64_t>(nnz, 1));
-  std::vector<float> cv(std::max<int64_t>(nnz, 1));
-  for (int64_t e = 0; e < nnz; ++e) cp[cl[e] + 1]++;
-  for (int64_t c = 0; c < n; ++c) cp[c + 1] += cp[c];
-  std::vector<int32_t> fillp(cp.begin(), cp.end() - 1);
-  for (int64_t i = 0; i < m; ++i)
-    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const int32_t at = fillp[cl[e]]++;
-      rr[at] = (int32_t)i;
-      cv[at] = vl[e];
-    }
-  AMM_TRY(d->csc_ptr.alloc((n + 1) * 4));
-  AMM_TRY(d->csc_row.alloc(rr.size() * 4));
-  AMM_TRY(d->csc_val.alloc(cv.size() * 4));
-  AMM_HIP(hipMemcpy(d->csc_ptr.ptr, cp.data(), (n + 1) * 4, hipMemcpyHostToDevice));
-  AMM_HIP(hipMemcpy(d->csc_row.ptr, rr.data(), rr.size() * 4, hipMemcpyHostToDevice));
-  AMM_HIP(hipMemcpy(d->csc_val.ptr, cv.data(), cv.size() * 4, hipMemcpyHostToDevice));
-  AMM_TRY(block_ranges(rp, cl, m, n, &d->csr_blk, &d->csr_blocks));
-  AMM_TRY(block_ranges(cp, rr, n, m, &d->csc_blk, &d->csc_blocks));
-  return AMM_OK;
-}
-
 amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t nnz,
                           amm_dec* d, float* R, hipStream_t s) {
   (void)ctx;
@@ -532,8 +468,7 @@ amm_status sparse_extract(amm_ctx* ctx, const float* A, int64_t m, int64_t n, in
   hipLaunchKernelGGL(fill_rows, dim3((unsigned)m), dim3(256), 0, s, A, n, T, take.as<int32_t>(),
                      d->row_ptr.as<int32_t>(), d->col.as<int32_t>(), d->val.as<float>(), R);
   AMM_HIP(hipGetLastError());
-  AMM_HIP(hipStreamSynchronize(s));
-  AMM_TRY(build_csc(d));
+  AMM_TRY(build_csc(d, s));
   // norms for reporting: ||A||_F^2 = ||S||^2 + ||R||^2 is left to the caller
   return AMM_OK;
 }
