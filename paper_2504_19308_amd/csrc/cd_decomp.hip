@@ -18,6 +18,7 @@
 // Delta A = A - sum_{t} R_{k_t} D^{k_t} (step 6) without the O(K n^2) sum.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "amm_internal.hpp"
 #include "fft_core.hpp"
@@ -71,6 +72,86 @@ __global__ void fft64_pass(const double2* __restrict__ in, double2* __restrict__
 }
 
 // E_part[chunk][k] = sum over rows p of the chunk of |Ahat[p, (p - k) mod n]|^2
+// One Stockham pass of radix R = 16 R2 (R2 = 2 ... 16) as two levels in a
+// workgroup of 16 lanes x 16: with r = r1 + 16 r2 and q = a + R2 b,
+//   X[q] = sum_r1 w16^(r1 b) w_R^(r1 a) [sum_r2 v[r1 + 16 r2] w_R2^(r2 a)],
+// thread (lane, r1) loads its R2 inputs, applies the stage twiddles, takes the
+// R2-point DFT and the w_R^(r1 a) twiddles; one LDS exchange; thread (lane, a)
+// takes the 16-point DFT over r1 and stores X[a + R2 b].  Half the global
+// round trips of two radix-16 passes.  The 16 lanes run along the contiguous
+// index: MODE 0, 16 consecutive vectors (bs = 1, batch % 16 == 0); MODE 1,
+// 16 consecutive groups j of one vector (es = 1, (n / R) % 16 == 0, Ns >= 16,
+// so the outputs of a given q are contiguous too); MODE 2, the same with
+// Ns = 1, whose outputs (j R + q) are staged through LDS and stored as one
+// contiguous run of 16 R elements.
+template <int R2, int SIGN, int MODE>
+__global__ void __launch_bounds__(256)
+fft64_pass2(const double2* __restrict__ in, double2* __restrict__ out, int n, int Ns, int64_t es, int64_t bs,
+            int64_t batch, const double2* __restrict__ tw, double scale) {
+  constexpr int R = 16 * R2, P = 17;   // LDS pitch over r1 (odd in 16-byte units)
+  __shared__ double2 sh[16 * R2 * P];
+  const int c = threadIdx.x & 15, r1 = threadIdx.x >> 4;
+  const int64_t nb = n / R;
+  int64_t b, j, j0 = 0;
+  if constexpr (MODE == 0) {
+    const int64_t gpb = batch / 16;
+    j = blockIdx.x / gpb;
+    b = (blockIdx.x % gpb) * 16 + c;
+  } else {
+    const int64_t per = nb / 16;
+    b = blockIdx.x / per;
+    j0 = (blockIdx.x % per) * 16;
+    j = j0 + c;
+  }
+  const int k = (int)(j & (Ns - 1));
+  const double2* src = in + b * bs;
+  double2 v[R2];
+#pragma unroll
+  for (int r2 = 0; r2 < R2; ++r2) v[r2] = src[(j + (int64_t)(r1 + 16 * r2) * nb) * es];
+  if (Ns > 1) {
+    const int step = n / (Ns * R);
+#pragma unroll
+    for (int r2 = 0; r2 < R2; ++r2) {
+      double2 w = tw[(unsigned)((r1 + 16 * r2) * k * step)];
+      if (SIGN > 0) w.y = -w.y;
+      v[r2] = cmul(v[r2], w);
+    }
+  }
+  dftR<R2, SIGN>(v);
+  const int inner = n / R;
+#pragma unroll
+  for (int a = 1; a < R2; ++a) {
+    double2 w = tw[(unsigned)(r1 * a * inner)];
+    if (SIGN > 0) w.y = -w.y;
+    v[a] = cmul(v[a], w);
+  }
+#pragma unroll
+  for (int a = 0; a < R2; ++a) sh[(c * R2 + a) * P + r1] = v[a];
+  __syncthreads();
+  const int a = threadIdx.x >> 4;   // second level: thread (lane, a), a < R2
+  double2 z[16];
+  if (a < R2) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) z[t] = sh[(c * R2 + a) * P + t];
+    dftR<16, SIGN>(z);              // z[bq] = X[a + R2 bq]
+  }
+  double2* dst = out + b * bs;
+  if constexpr (MODE == 2) {
+    __syncthreads();
+    if (a < R2)
+#pragma unroll
+      for (int bq = 0; bq < 16; ++bq) sh[c * R + a + R2 * bq] = z[bq];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 16 * R; idx += 256) dst[j0 * R + idx] = cscale(sh[idx], scale);
+  } else {
+    if (a < R2) {
+      const int64_t base = (j - k) * R + k;
+#pragma unroll
+      for (int bq = 0; bq < 16; ++bq) dst[(base + (int64_t)(a + R2 * bq) * Ns) * es] = cscale(z[bq], scale);
+    }
+  }
+}
+
 __global__ void energy_partial(const double2* __restrict__ Ahat, int n, int rows_per_chunk,
                                double* __restrict__ part) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,16 +254,68 @@ amm_status launch_pass(int log2r, const double2* in, double2* out, int n, int Ns
 
 }  // namespace
 
+namespace {
+
+template <int SIGN, int MODE>
+amm_status launch_pass2(int log2r, const double2* in, double2* out, int n, int Ns, int64_t es, int64_t bs,
+                        int64_t batch, const double2* tw, double scale, hipStream_t s) {
+  const int64_t groups = (int64_t)(n >> log2r) * batch;   // one workgroup per 16 groups
+  dim3 grid((unsigned)(groups / 16)), block(256);
+  switch (log2r) {
+    case 8: hipLaunchKernelGGL((fft64_pass2<16, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
+    case 7: hipLaunchKernelGGL((fft64_pass2<8, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
+    case 6: hipLaunchKernelGGL((fft64_pass2<4, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
+    case 5: hipLaunchKernelGGL((fft64_pass2<2, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
+    default: return fail(AMM_EUNSUPPORTED, "bad two-level radix");
+  }
+  AMM_HIP(hipGetLastError());
+  return AMM_OK;
+}
+
+template <int SIGN>
+amm_status launch_any2(int log2r, int mode, const double2* in, double2* out, int n, int Ns, int64_t es,
+                       int64_t bs, int64_t batch, const double2* tw, double scale, hipStream_t s) {
+  if (mode == 0) return launch_pass2<SIGN, 0>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
+  if (mode == 1) return launch_pass2<SIGN, 1>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
+  return launch_pass2<SIGN, 2>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
+}
+
+}  // namespace
+
+// Passes of up to 256 points as two levels in a workgroup (fft64_pass2)
+// where the lanes can run along a contiguous index: columns of 16 or more
+// vectors at unit batch stride, or rows with at least 16 groups per pass;
+// radix-16 passes (and one smaller) otherwise and for the last few bits.
 amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
                            bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s) {
   const int n = 1 << log2n;
+  const bool cols2 = batch_fast && bs == 1 && batch % 16 == 0;
+  const bool rows2 = !batch_fast && es == 1;
+  std::vector<std::pair<int, bool>> plan;   // (log2 radix, two-level)
+  for (int bits = log2n; bits > 0;) {
+    const int lr2 = std::min({8, bits, rows2 ? log2n - 4 : 8});
+    if ((cols2 || rows2) && lr2 >= 5) {
+      plan.push_back({lr2, true});
+      bits -= lr2;
+    } else {
+      const int lr = std::min(4, bits);
+      plan.push_back({lr, false});
+      bits -= lr;
+    }
+  }
   int Ns = 1;
-  const int stages = stage_count(log2n);
-  for (int st = 0; st < stages; ++st) {
-    const int lr = stage_log2r(log2n, st);
-    const double sc = (st == stages - 1) ? scale : 1.0;
-    if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
-    else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
+  for (size_t st = 0; st < plan.size(); ++st) {
+    const int lr = plan[st].first;
+    const double sc = (st + 1 == plan.size()) ? scale : 1.0;
+    if (plan[st].second) {
+      const int mode = cols2 ? 0 : (Ns == 1 ? 2 : 1);
+      if (mode == 1 && Ns < 16) return fail(AMM_EUNSUPPORTED, "internal: two-level row pass needs Ns >= 16");
+      if (sign < 0) AMM_TRY(launch_any2<-1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, s));
+      else AMM_TRY(launch_any2<+1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, s));
+    } else {
+      if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
+      else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
+    }
     std::swap(cur, tmp);
     Ns <<= lr;
   }
