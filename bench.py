@@ -44,12 +44,12 @@ VALU_F32_PEAK = 78.6e12      # flop/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2
 # taken.
 TRAFFIC = {
     # headline step, n = 16384 (profiles/sparse_circulant_n16384.md)
-    "spmm_csr": {"fetch_kib": 4950131.4, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
-                 "sha16": "37ae9fe74ed71a5d"},
-    "cd_apply_columns": {"fetch_kib": 934016.5, "write_kib": 1496529.2, "src": "paper_2504_19308_amd/csrc/cd_apply.hip",
+    "spmm_csr": {"fetch_kib": 4951227.7, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
+                 "sha16": "39a5120168007452"},
+    "cd_apply_columns": {"fetch_kib": 933873.5, "write_kib": 1495623.8, "src": "paper_2504_19308_amd/csrc/cd_apply.hip",
                          "sha16": "9e3111996e8eca06"},
-    "repitch": {"fetch_kib": 524305.9, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
-                "sha16": "37ae9fe74ed71a5d"},
+    "repitch": {"fetch_kib": 524306.1, "write_kib": 1048576.0, "src": "paper_2504_19308_amd/csrc/sparse.hip",
+                "sha16": "39a5120168007452"},
     # rank-32 first-order product, n = 4096 (profiles/tsvd_first_order_n4096.md)
     "panel": {"fetch_kib": 67707.2, "write_kib": 2048.0, "src": "paper_2504_19308_amd/csrc/tsvd_split.hip",
               "sha16": "1c062e58b9095c9e"},
