@@ -15,6 +15,7 @@
 #include <cstring>
 #include <vector>
 
+#include <functional>
 #include <map>
 
 #include "amm_internal.hpp"
@@ -572,47 +573,23 @@ namespace amm {
 // Pair structure of a closed frequency set (see CdPairs), for the lists L
 // (shifts k_t) and for the adjoint lists Ladj_t[p] = conj(L_t[p + k_t])
 // (shifts -k_t).  Left unset (plain loop) when the set is not closed or the
-// lists are not those of a real operator to float32 rounding.
-amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
+// lists are not those of a real operator to float32 rounding: `mirror(pass,
+// ta, tb)` tells whether list tb of the pass (0: L, 1: Ladj) is the mirrored
+// conjugate of list ta, L_b[p] = conj(L_a[-p]) to the tolerance.
+amm_status cd_pair_tables(amm_dec* d, const std::function<bool(int, int, int)>& mirror) {
   d->npairs = d->npairs_adj = -1;
   d->nsingles = d->nsingles_adj = 0;
   const int64_t n = d->n;
   const int K = d->K_eff;
-  if (K == 0 || (int64_t)Lh.size() < (int64_t)K * n) return AMM_OK;
+  if (K == 0) return AMM_OK;
   std::map<int64_t, int> idx;
   for (int t = 0; t < K; ++t) idx[d->freqs[t]] = t;
   for (int t = 0; t < K; ++t)
     if (!idx.count((n - d->freqs[t]) % n)) return AMM_OK;
-  float mx = 0.f;
-  for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
-  const float tol = 1e-5f * mx + 1e-30f;
-  // adjoint lists on the host: La_t[p] = conj(L_t[(p + k) mod n]) (the index
-  // wraps once, so the two ranges run without a modulo)
-  std::vector<float2> La((size_t)K * n);
   std::vector<int64_t> ka(K);
-  for (int t = 0; t < K; ++t) {
-    const int64_t k = d->freqs[t];
-    ka[t] = k == 0 ? 0 : n - k;
-    const float2* src = Lh.data() + (size_t)t * n;
-    float2* dst = La.data() + (size_t)t * n;
-    for (int64_t p = 0; p < n - k; ++p) dst[p] = float2{src[p + k].x, -src[p + k].y};
-    for (int64_t p = n - k; p < n; ++p) dst[p] = float2{src[p + k - n].x, -src[p + k - n].y};
-  }
-  // L_b[p] == conj(L_a[-p]) for every p (index -p is 0 at p = 0, else n - p)
-  auto mirror = [&](const std::vector<float2>& Ls, int ta, int tb) {
-    const float2* la = Ls.data() + (size_t)ta * n;
-    const float2* lb = Ls.data() + (size_t)tb * n;
-    if (std::fabs(lb[0].x - la[0].x) > tol || std::fabs(lb[0].y + la[0].y) > tol) return false;
-    bool ok = true;
-    for (int64_t p = 1; p < n; ++p) {
-      const float2 a = la[n - p], b = lb[p];
-      ok &= !(std::fabs(b.x - a.x) > tol || std::fabs(b.y + a.y) > tol);
-    }
-    return ok;
-  };
+  for (int t = 0; t < K; ++t) ka[t] = d->freqs[t] == 0 ? 0 : n - d->freqs[t];
   std::vector<int2> pairs, singles, pairs_a, singles_a;
   for (int pass = 0; pass < 2; ++pass) {
-    const std::vector<float2>& Ls = pass == 0 ? Lh : La;
     auto& P = pass == 0 ? pairs : pairs_a;
     auto& S = pass == 0 ? singles : singles_a;
     std::map<int64_t, int> at;
@@ -621,10 +598,10 @@ amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
       const int64_t k = kv.first, kk = (n - k) % n;
       const int t = kv.second, tt = at[kk];
       if (k == kk) {
-        if (!mirror(Ls, t, t)) return AMM_OK;
+        if (!mirror(pass, t, t)) return AMM_OK;
         S.push_back(int2{(int)k, t});
       } else if (k < kk) {
-        if (!mirror(Ls, t, tt)) return AMM_OK;
+        if (!mirror(pass, t, tt)) return AMM_OK;
         P.push_back(int2{(int)k, t});
       }
     }
@@ -641,6 +618,45 @@ amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
   d->npairs_adj = (int)pairs_a.size();
   d->nsingles_adj = (int)singles_a.size();
   return AMM_OK;
+}
+
+// The same with the mirror test on host copies of the lists (imported
+// eigenvalues).
+amm_status cd_build_pairs(amm_dec* d, const std::vector<float2>& Lh) {
+  const int64_t n = d->n;
+  const int K = d->K_eff;
+  if (K == 0 || (int64_t)Lh.size() < (int64_t)K * n) {
+    d->npairs = d->npairs_adj = -1;
+    d->nsingles = d->nsingles_adj = 0;
+    return AMM_OK;
+  }
+  float mx = 0.f;
+  for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
+  const float tol = 1e-5f * mx + 1e-30f;
+  // adjoint lists on the host: La_t[p] = conj(L_t[(p + k) mod n]) (the index
+  // wraps once, so the two ranges run without a modulo)
+  std::vector<float2> La((size_t)K * n);
+  for (int t = 0; t < K; ++t) {
+    const int64_t k = d->freqs[t];
+    const float2* src = Lh.data() + (size_t)t * n;
+    float2* dst = La.data() + (size_t)t * n;
+    for (int64_t p = 0; p < n - k; ++p) dst[p] = float2{src[p + k].x, -src[p + k].y};
+    for (int64_t p = n - k; p < n; ++p) dst[p] = float2{src[p + k - n].x, -src[p + k - n].y};
+  }
+  // L_b[p] == conj(L_a[-p]) for every p (index -p is 0 at p = 0, else n - p)
+  auto mirror = [&](int pass, int ta, int tb) {
+    const std::vector<float2>& Ls = pass == 0 ? Lh : La;
+    const float2* la = Ls.data() + (size_t)ta * n;
+    const float2* lb = Ls.data() + (size_t)tb * n;
+    if (std::fabs(lb[0].x - la[0].x) > tol || std::fabs(lb[0].y + la[0].y) > tol) return false;
+    bool ok = true;
+    for (int64_t p = 1; p < n; ++p) {
+      const float2 a = la[n - p], b = lb[p];
+      ok &= !(std::fabs(b.x - a.x) > tol || std::fabs(b.y + a.y) > tol);
+    }
+    return ok;
+  };
+  return cd_pair_tables(d, mirror);
 }
 
 }  // namespace amm

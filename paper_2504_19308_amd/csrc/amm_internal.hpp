@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "host_logic.hpp"
@@ -346,10 +347,17 @@ amm_status cd_spectrum_columns(amm_ctx* ctx, int log2n, const float* B, int64_t 
 // Builds dec->pair_buf from host copies of the lists when the frequency set
 // is closed and the lists satisfy L_{n-k}[p] = conj(L_k[-p]).
 amm_status cd_build_pairs(amm_dec* dec, const std::vector<float2>& L_host);
+// The same with the lists on the device only (the mirror test and the
+// largest list component |x|, |y| computed there; *mx receives the latter).
+amm_status cd_build_pairs_dev(amm_dec* dec, float* mx, hipStream_t s);
+// The table builder shared by both: mirror(pass, ta, tb) is the list test.
+amm_status cd_pair_tables(amm_dec* d, const std::function<bool(int, int, int)>& mirror);
 
 // float16 copies of dec->L and dec->Ladj (host copy of L given) with a
 // power-of-two scale; sets dec->fp16 and dec->l16_inv.
 amm_status cd_make_half_lists(amm_dec* dec, const std::vector<float2>& L_host, hipStream_t s);
+// the same given the largest list component
+amm_status cd_make_half_lists_mx(amm_dec* dec, float mx, hipStream_t s);
 
 amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K,
                         bool keep_residual, amm_dec* dec, hipStream_t s, bool fp16 = false);

@@ -18,6 +18,7 @@
 // Delta A = A - sum_{t} R_{k_t} D^{k_t} (step 6) without the O(K n^2) sum.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "amm_internal.hpp"
@@ -150,6 +151,33 @@ fft64_pass2(const double2* __restrict__ in, double2* __restrict__ out, int n, in
       for (int bq = 0; bq < 16; ++bq) dst[(base + (int64_t)(a + R2 * bq) * Ns) * es] = cscale(z[bq], scale);
     }
   }
+}
+
+// *out = max over the list entries of max(|x|, |y|), as the bits of a
+// non-negative float (integer order = float order)
+__global__ void list_absmax(const float2* __restrict__ L, int64_t count, unsigned* __restrict__ out) {
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fmaxf(fabsf(L[i].x), fabsf(L[i].y)));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// Check (pass, ta, tb) of blockIdx.y: *fail = 1 unless list tb of the pass
+// (L, or Ladj for pass 1) is the mirrored conjugate of list ta,
+// L_b[p] = conj(L_a[-p]), to tol at every p.
+__global__ void mirror_check(const float2* __restrict__ L, const float2* __restrict__ La, int64_t n,
+                             const int4* __restrict__ checks, float tol, int* __restrict__ fail) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int4 ck = checks[blockIdx.y];
+  const float2* Ls = ck.x == 0 ? L : La;
+  const float2 a = Ls[(int64_t)ck.y * n + (p == 0 ? 0 : n - p)], b = Ls[(int64_t)ck.z * n + p];
+  if (fabsf(b.x - a.x) > tol || fabsf(b.y + a.y) > tol) atomicOr(fail, 1);
+}
+
+__global__ void zero_words(unsigned* p, int count) {
+  if (threadIdx.x < count) p[threadIdx.x] = 0u;
 }
 
 __global__ void energy_partial(const double2* __restrict__ Ahat, int n, int rows_per_chunk,
@@ -341,10 +369,14 @@ amm_status transform_axis(double2*& cur, double2*& tmp, int log2n, bool columns,
 amm_status cd_make_half_lists(amm_dec* dec, const std::vector<float2>& Lh, hipStream_t s) {
   float mx = 0.f;
   for (const float2& v : Lh) mx = std::max(mx, std::max(std::fabs(v.x), std::fabs(v.y)));
+  return cd_make_half_lists_mx(dec, mx, s);
+}
+
+amm_status cd_make_half_lists_mx(amm_dec* dec, float mx, hipStream_t s) {
   int ex = 0;
   (void)std::frexp(mx, &ex);                         // mx < 2^ex
   const int sh = std::min(std::max(14 - ex, -100), 100);
-  const int64_t cnt = (int64_t)Lh.size();
+  const int64_t cnt = (int64_t)dec->K_eff * dec->n;
   AMM_TRY(dec->L16.alloc(cnt * sizeof(__half2)));
   AMM_TRY(dec->Ladj16.alloc(cnt * sizeof(__half2)));
   const float sc = std::ldexp(1.0f, sh);
@@ -355,6 +387,54 @@ amm_status cd_make_half_lists(amm_dec* dec, const std::vector<float2>& Lh, hipSt
   AMM_HIP(hipGetLastError());
   dec->l16_inv = std::ldexp(1.0f, -sh);
   dec->fp16 = true;
+  return AMM_OK;
+}
+
+// Pair tables from the device lists: the largest component (for the
+// tolerance 1e-5 max + 1e-30, as with host lists), then every mirror test the
+// closed set needs in one launch and one flag.
+amm_status cd_build_pairs_dev(amm_dec* dec, float* mx, hipStream_t s) {
+  const int64_t n = dec->n;
+  const int K = dec->K_eff;
+  *mx = 0.f;
+  dec->npairs = dec->npairs_adj = -1;
+  dec->nsingles = dec->nsingles_adj = 0;
+  if (K == 0) return AMM_OK;
+  DevBuf words;
+  AMM_TRY(words.alloc(2 * sizeof(unsigned)));
+  unsigned* w = words.as<unsigned>();
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, w, 2);
+  const int64_t cnt = (int64_t)K * n;
+  hipLaunchKernelGGL(list_absmax, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 2048)), dim3(256), 0, s,
+                     dec->L.as<float2>(), cnt, w);
+  AMM_HIP(hipGetLastError());
+  unsigned bits = 0;
+  AMM_HIP(hipMemcpyAsync(&bits, w, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  std::memcpy(mx, &bits, sizeof(float));
+  // the tests the closed set needs (recorded; the tables assume they pass)
+  std::vector<int4> checks;
+  AMM_TRY(cd_pair_tables(dec, [&](int pass, int ta, int tb) {
+    checks.push_back(int4{pass, ta, tb, 0});
+    return true;
+  }));
+  if (dec->npairs < 0 || checks.empty()) return AMM_OK;   // not closed
+  DevBuf ck;
+  AMM_TRY(ck.alloc(checks.size() * sizeof(int4)));
+  AMM_HIP(hipMemcpyAsync(ck.ptr, checks.data(), checks.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  const float tol = 1e-5f * *mx + 1e-30f;
+  hipLaunchKernelGGL(mirror_check, dim3((unsigned)((n + 255) / 256), (unsigned)checks.size()), dim3(256), 0, s,
+                     dec->L.as<float2>(), dec->Ladj.as<float2>(), n, ck.as<int4>(), tol,
+                     reinterpret_cast<int*>(w + 1));
+  AMM_HIP(hipGetLastError());
+  unsigned failed = 0;
+  AMM_HIP(hipMemcpyAsync(&failed, w + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  AMM_HIP(hipStreamSynchronize(s));
+  if (failed) {
+    dec->npairs = dec->npairs_adj = -1;
+    dec->nsingles = dec->nsingles_adj = 0;
+    dec->pair_buf.release();
+  }
   return AMM_OK;
 }
 
@@ -420,11 +500,9 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_re
     hipLaunchKernelGGL(gather_lists, dim3((unsigned)((n + 255) / 256), (unsigned)Ke), dim3(256), 0, s,
                        cur, n, dec->shifts.as<int32_t>(), dec->L.as<float2>(), dec->Ladj.as<float2>());
     AMM_HIP(hipGetLastError());
-    std::vector<float2> Lh((size_t)Ke * n);
-    AMM_HIP(hipMemcpyAsync(Lh.data(), dec->L.ptr, Lh.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
-    AMM_HIP(hipStreamSynchronize(s));
-    AMM_TRY(cd_build_pairs(dec, Lh));
-    if (fp16 && n >= 1024 && (pow2 || n <= kChirpFusedMax)) AMM_TRY(cd_make_half_lists(dec, Lh, s));
+    float mx = 0.f;
+    AMM_TRY(cd_build_pairs_dev(dec, &mx, s));
+    if (fp16 && n >= 1024 && (pow2 || n <= kChirpFusedMax)) AMM_TRY(cd_make_half_lists_mx(dec, mx, s));
   }
 
   // spectral concentration of Delta A (circulant residual theorem of Sec. 3):
