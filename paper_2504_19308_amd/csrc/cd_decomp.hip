@@ -177,7 +177,7 @@ __global__ void mirror_check(const float2* __restrict__ L, const float2* __restr
 }
 
 __global__ void zero_words(unsigned* p, int count) {
-  if (threadIdx.x < count) p[threadIdx.x] = 0u;
+  if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
 }
 
 __global__ void energy_partial(const double2* __restrict__ Ahat, int n, int rows_per_chunk,

@@ -396,12 +396,14 @@ __global__ void __launch_bounds__(NT) gram_eig_kernel(const double* __restrict__
     load_sym_lds(gram, l, l, delta, S, ld);
     ok = cholesky_inv_lds(S, E, l, ld);
     // R: the upper part of S; clear the rest (identity on a breakdown)
-    if (active)
-      for (int i = g; i < l; i += ng)
+    if (active) {
+      for (int i = g; i < l; i += ng) {
         if (!ok)
           S[i * ld + c] = (i == c) ? 1.0 : 0.0;
         else if (c < i)
           S[i * ld + c] = 0.0;
+      }
+    }
   }
   if (!ok && tid == 0) *status = 1;
   const double shift = ok ? delta : 1.0;
