@@ -393,7 +393,7 @@ amm_status cd_apply_rows_general(amm_ctx* ctx, int n, int K, const int32_t* shif
 // vector b at b*bs + e*es); sign -1: exp(-2 pi i jk/n), +1: its conjugate;
 // `scale` multiplies the result, which ends in `cur` (buffers swapped).
 amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
-                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s);
+                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s, const float* real_src = nullptr);
 
 
 // Dense float32 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C, with

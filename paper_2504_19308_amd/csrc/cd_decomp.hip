@@ -84,11 +84,13 @@ __global__ void fft64_pass(const double2* __restrict__ in, double2* __restrict__
 // 16 consecutive groups j of one vector (es = 1, (n / R) % 16 == 0, Ns >= 16,
 // so the outputs of a given q are contiguous too); MODE 2, the same with
 // Ns = 1, whose outputs (j R + q) are staged through LDS and stored as one
-// contiguous run of 16 R elements.
+// contiguous run of 16 R elements.  With `rin` the input is real float32 at
+// the same positions (the first pass over a real operand, which then needs no
+// widened copy).
 template <int R2, int SIGN, int MODE>
 __global__ void __launch_bounds__(256)
 fft64_pass2(const double2* __restrict__ in, double2* __restrict__ out, int n, int Ns, int64_t es, int64_t bs,
-            int64_t batch, const double2* __restrict__ tw, double scale) {
+            int64_t batch, const double2* __restrict__ tw, double scale, const float* __restrict__ rin) {
   constexpr int R = 16 * R2, P = 17;   // LDS pitch over r1 (odd in 16-byte units)
   __shared__ double2 sh[16 * R2 * P];
   const int c = threadIdx.x & 15, r1 = threadIdx.x >> 4;
@@ -105,10 +107,16 @@ fft64_pass2(const double2* __restrict__ in, double2* __restrict__ out, int n, in
     j = j0 + c;
   }
   const int k = (int)(j & (Ns - 1));
-  const double2* src = in + b * bs;
   double2 v[R2];
+  if (rin) {
+    const float* rsrc = rin + b * bs;
 #pragma unroll
-  for (int r2 = 0; r2 < R2; ++r2) v[r2] = src[(j + (int64_t)(r1 + 16 * r2) * nb) * es];
+    for (int r2 = 0; r2 < R2; ++r2) v[r2] = double2{(double)rsrc[(j + (int64_t)(r1 + 16 * r2) * nb) * es], 0.0};
+  } else {
+    const double2* src = in + b * bs;
+#pragma unroll
+    for (int r2 = 0; r2 < R2; ++r2) v[r2] = src[(j + (int64_t)(r1 + 16 * r2) * nb) * es];
+  }
   if (Ns > 1) {
     const int step = n / (Ns * R);
 #pragma unroll
@@ -286,14 +294,14 @@ namespace {
 
 template <int SIGN, int MODE>
 amm_status launch_pass2(int log2r, const double2* in, double2* out, int n, int Ns, int64_t es, int64_t bs,
-                        int64_t batch, const double2* tw, double scale, hipStream_t s) {
+                        int64_t batch, const double2* tw, double scale, const float* rin, hipStream_t s) {
   const int64_t groups = (int64_t)(n >> log2r) * batch;   // one workgroup per 16 groups
   dim3 grid((unsigned)(groups / 16)), block(256);
   switch (log2r) {
-    case 8: hipLaunchKernelGGL((fft64_pass2<16, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
-    case 7: hipLaunchKernelGGL((fft64_pass2<8, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
-    case 6: hipLaunchKernelGGL((fft64_pass2<4, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
-    case 5: hipLaunchKernelGGL((fft64_pass2<2, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale); break;
+    case 8: hipLaunchKernelGGL((fft64_pass2<16, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, rin); break;
+    case 7: hipLaunchKernelGGL((fft64_pass2<8, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, rin); break;
+    case 6: hipLaunchKernelGGL((fft64_pass2<4, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, rin); break;
+    case 5: hipLaunchKernelGGL((fft64_pass2<2, SIGN, MODE>), grid, block, 0, s, in, out, n, Ns, es, bs, batch, tw, scale, rin); break;
     default: return fail(AMM_EUNSUPPORTED, "bad two-level radix");
   }
   AMM_HIP(hipGetLastError());
@@ -302,10 +310,11 @@ amm_status launch_pass2(int log2r, const double2* in, double2* out, int n, int N
 
 template <int SIGN>
 amm_status launch_any2(int log2r, int mode, const double2* in, double2* out, int n, int Ns, int64_t es,
-                       int64_t bs, int64_t batch, const double2* tw, double scale, hipStream_t s) {
-  if (mode == 0) return launch_pass2<SIGN, 0>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
-  if (mode == 1) return launch_pass2<SIGN, 1>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
-  return launch_pass2<SIGN, 2>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, s);
+                       int64_t bs, int64_t batch, const double2* tw, double scale, const float* rin,
+                       hipStream_t s) {
+  if (mode == 0) return launch_pass2<SIGN, 0>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, rin, s);
+  if (mode == 1) return launch_pass2<SIGN, 1>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, rin, s);
+  return launch_pass2<SIGN, 2>(log2r, in, out, n, Ns, es, bs, batch, tw, scale, rin, s);
 }
 
 }  // namespace
@@ -315,7 +324,8 @@ amm_status launch_any2(int log2r, int mode, const double2* in, double2* out, int
 // vectors at unit batch stride, or rows with at least 16 groups per pass;
 // radix-16 passes (and one smaller) otherwise and for the last few bits.
 amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, int64_t bs, int64_t batch,
-                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s) {
+                           bool batch_fast, int sign, double scale, const double2* tw, hipStream_t s,
+                           const float* real_src) {
   const int n = 1 << log2n;
   const bool cols2 = batch_fast && bs == 1 && batch % 16 == 0;
   const bool rows2 = !batch_fast && es == 1;
@@ -331,6 +341,13 @@ amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, 
       bits -= lr;
     }
   }
+  // a real input that the first pass cannot read directly is widened into cur first
+  if (real_src && !plan[0].second) {
+    const int64_t count = (batch - 1) * bs + ((int64_t)n - 1) * es + 1;
+    hipLaunchKernelGGL(widen_real, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, real_src, cur, count);
+    AMM_HIP(hipGetLastError());
+    real_src = nullptr;
+  }
   int Ns = 1;
   for (size_t st = 0; st < plan.size(); ++st) {
     const int lr = plan[st].first;
@@ -338,8 +355,9 @@ amm_status fft64_transform(double2*& cur, double2*& tmp, int log2n, int64_t es, 
     if (plan[st].second) {
       const int mode = cols2 ? 0 : (Ns == 1 ? 2 : 1);
       if (mode == 1 && Ns < 16) return fail(AMM_EUNSUPPORTED, "internal: two-level row pass needs Ns >= 16");
-      if (sign < 0) AMM_TRY(launch_any2<-1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, s));
-      else AMM_TRY(launch_any2<+1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, s));
+      const float* rin = st == 0 ? real_src : nullptr;
+      if (sign < 0) AMM_TRY(launch_any2<-1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, rin, s));
+      else AMM_TRY(launch_any2<+1>(lr, mode, cur, tmp, n, Ns, es, bs, batch, tw, sc, rin, s));
     } else {
       if (sign < 0) AMM_TRY(launch_pass<-1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
       else AMM_TRY(launch_pass<+1>(lr, cur, tmp, n, Ns, es, bs, batch, tw, sc, batch_fast, s));
@@ -456,9 +474,14 @@ amm_status cd_decompose(amm_ctx* ctx, const float* A, int n, int K, bool keep_re
   AMM_TRY(z1.alloc(nn * sizeof(double2)));
   double2* cur = z0.as<double2>();
   double2* tmp = z1.as<double2>();
-  hipLaunchKernelGGL(widen_real, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, cur, nn);
-  AMM_HIP(hipGetLastError());
-  AMM_TRY(xform(cur, tmp, /*columns=*/true, -1, 1.0));
+  if (pow2) {
+    // the first column pass reads A (real float32) directly
+    AMM_TRY(fft64_transform(cur, tmp, log2n, n, 1, n, true, -1, 1.0, tw, s, A));
+  } else {
+    hipLaunchKernelGGL(widen_real, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, cur, nn);
+    AMM_HIP(hipGetLastError());
+    AMM_TRY(xform(cur, tmp, /*columns=*/true, -1, 1.0));
+  }
   AMM_TRY(xform(cur, tmp, /*columns=*/false, +1, 1.0 / n));
 
   // energies ||R_k||_F^2
